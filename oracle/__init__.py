@@ -1,0 +1,214 @@
+"""FP64 CPU oracle for NOMAD SGD (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may import
+this package.  The HIP product path neither imports nor links it.
+
+The arithmetic lives in ``nomad_oracle.c`` (plain C, IEEE double, single thread); this
+module only builds it with gcc and marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nomad_oracle.c")
+_LIB = os.path.join(_HERE, "libnomad_oracle.so")
+_lib = None
+
+OK, EINVAL, ENOMEM, EDEADLOCK = 0, -1, -2, -3
+
+
+class Stats(C.Structure):
+    _fields_ = [("updates", C.c_int64), ("visits", C.c_int64), ("violations", C.c_int64),
+                ("hops", C.c_int64)]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no fast-math: IEEE semantics are part of the contract)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = C.CDLL(_LIB)
+        i32, i64, u64, dbl = C.c_int32, C.c_int64, C.c_uint64, C.c_double
+        P = C.c_void_p
+        lib.orc_splitmix64.restype = u64
+        lib.orc_splitmix64.argtypes = [u64]
+        lib.orc_owner0.restype = i32
+        lib.orc_owner0.argtypes = [u64, i64, i32]
+        lib.orc_step.restype = dbl
+        lib.orc_step.argtypes = [dbl, dbl, dbl, dbl]
+        lib.orc_update.restype = None
+        lib.orc_update.argtypes = [i32, P, P, dbl, dbl, dbl]
+        lib.orc_partition.restype = C.c_int
+        lib.orc_partition.argtypes = [i64, i64, P, i32, P]
+        common = [i64, i64, i64, P, P, P, i32, dbl, dbl, dbl, dbl, i32, u64]
+        lib.orc_train_ring.restype = C.c_int
+        lib.orc_train_ring.argtypes = common + [i32, i32, P, P, P]
+        lib.orc_train_ring_interleaved.restype = C.c_int
+        lib.orc_train_ring_interleaved.argtypes = common + [i32, i32, u64, P, P, P]
+        lib.orc_train_perm.restype = C.c_int
+        lib.orc_train_perm.argtypes = common + [i32, i32, u64, P, P, P]
+        lib.orc_train_uniform.restype = C.c_int
+        lib.orc_train_uniform.argtypes = common + [i64, u64, P, P, P, P]
+        lib.orc_replay.restype = C.c_int
+        lib.orc_replay.argtypes = common + [i64, P, P, P, P, P, P, P]
+        lib.orc_rmse.restype = C.c_int
+        lib.orc_rmse.argtypes = [i64, i64, i64, P, P, P, i32, P, P, P]
+        lib.orc_objective.restype = C.c_int
+        lib.orc_objective.argtypes = [i64, i64, i64, P, P, P, i32, dbl, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _coo(row, col, val):
+    row = np.ascontiguousarray(np.asarray(row, dtype=np.int32))
+    col = np.ascontiguousarray(np.asarray(col, dtype=np.int32))
+    val = np.ascontiguousarray(np.asarray(val, dtype=np.float32))
+    assert row.shape == col.shape == val.shape
+    return row, col, val
+
+
+def _factors(X, rows, k):
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    assert X.shape == (rows, k), (X.shape, rows, k)
+    return X
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _check(rc):
+    if rc != OK:
+        raise OracleError({EINVAL: "invalid input", ENOMEM: "out of memory",
+                           EDEADLOCK: "schedule cannot progress"}.get(rc, str(rc)))
+
+
+@dataclass
+class Hyper:
+    k: int
+    lam: float
+    alpha: float
+    beta: float
+    gamma: float
+
+
+def splitmix64(x: int) -> int:
+    return int(_load().orc_splitmix64(x & 0xFFFFFFFFFFFFFFFF))
+
+
+def owner0(seed: int, j: int, p: int) -> int:
+    return int(_load().orc_owner0(seed, j, p))
+
+
+def step(alpha, beta, gamma, t) -> float:
+    return float(_load().orc_step(alpha, beta, gamma, float(t)))
+
+
+def update(w, h, r, s, lam):
+    """One SGD update; returns (w', h') as new float64 arrays."""
+    w = np.array(w, dtype=np.float64)
+    h = np.array(h, dtype=np.float64)
+    _load().orc_update(w.size, _p(w), _p(h), float(r), float(s), float(lam))
+    return w, h
+
+
+def partition(m, row, p):
+    row = np.ascontiguousarray(np.asarray(row, dtype=np.int32))
+    out = np.zeros(p + 1, dtype=np.int64)
+    _check(_load().orc_partition(m, row.size, _p(row), p, _p(out)))
+    return out
+
+
+def train_ring(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, epoch0=0,
+               interleave_seed=None):
+    """Fixed token-passing order; with interleave_seed, the same orders under a random
+    asynchronous interleaving.  Returns (W, H, stats)."""
+    row, col, val = _coo(row, col, val)
+    W = _factors(W0, m, hp.k)
+    H = _factors(H0, n, hp.k)
+    st = Stats()
+    lib = _load()
+    args = (m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha, hp.beta, hp.gamma,
+            p, seed, epoch0, epochs)
+    if interleave_seed is None:
+        _check(lib.orc_train_ring(*args, _p(W), _p(H), C.byref(st)))
+    else:
+        _check(lib.orc_train_ring_interleaved(*args, interleave_seed, _p(W), _p(H), C.byref(st)))
+    return W, H, st
+
+
+def train_perm(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, sched_seed, epoch0=0):
+    row, col, val = _coo(row, col, val)
+    W = _factors(W0, m, hp.k)
+    H = _factors(H0, n, hp.k)
+    st = Stats()
+    _check(_load().orc_train_perm(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha,
+                                  hp.beta, hp.gamma, p, seed, epoch0, epochs, sched_seed, _p(W), _p(H),
+                                  C.byref(st)))
+    return W, H, st
+
+
+def train_uniform(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, max_updates, sched_seed,
+                  visit_count=None):
+    row, col, val = _coo(row, col, val)
+    W = _factors(W0, m, hp.k)
+    H = _factors(H0, n, hp.k)
+    if visit_count is None:
+        visit_count = np.zeros(p * n, dtype=np.int32)
+    assert visit_count.dtype == np.int32 and visit_count.size == p * n
+    st = Stats()
+    _check(_load().orc_train_uniform(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha,
+                                     hp.beta, hp.gamma, p, seed, int(max_updates), sched_seed,
+                                     _p(visit_count), _p(W), _p(H), C.byref(st)))
+    return W, H, st
+
+
+def replay(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, tq, tj, tt, tseq):
+    row, col, val = _coo(row, col, val)
+    W = _factors(W0, m, hp.k)
+    H = _factors(H0, n, hp.k)
+    tq, tj, tt, tseq = (np.ascontiguousarray(np.asarray(a, dtype=np.int32)) for a in (tq, tj, tt, tseq))
+    st = Stats()
+    _check(_load().orc_replay(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha, hp.beta,
+                              hp.gamma, p, seed, tq.size, _p(tq), _p(tj), _p(tt), _p(tseq), _p(W), _p(H),
+                              C.byref(st)))
+    return W, H, st
+
+
+def rmse(m, n, row, col, val, W, H) -> float:
+    row, col, val = _coo(row, col, val)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    out = C.c_double()
+    _check(_load().orc_rmse(m, n, row.size, _p(row), _p(col), _p(val), W.shape[1], _p(W), _p(H),
+                            C.byref(out)))
+    return out.value
+
+
+def objective(m, n, row, col, val, W, H, lam) -> float:
+    row, col, val = _coo(row, col, val)
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    out = C.c_double()
+    _check(_load().orc_objective(m, n, row.size, _p(row), _p(col), _p(val), W.shape[1], float(lam),
+                                 _p(W), _p(H), C.byref(out)))
+    return out.value

@@ -1,0 +1,635 @@
+/*
+ * NOMAD oracle -- a plain, slow, FP64 CPU implementation of what the NOMAD hot path
+ * computes (Yun, Yu, Hsieh, Vishwanathan, Dhillon: "NOMAD: Non-locking, stOchastic
+ * Multi-machine algorithm for Asynchronous and Decentralized matrix completion").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library.  The product path (the HIP library) never
+ * calls it, includes it, or shares a line of code, a header or a table with it.
+ *
+ * Everything is IEEE double precision, single threaded, written for readability:
+ * no blocking, fusion or reordering beyond what the paper states.
+ *
+ * What each function follows:
+ *   orc_update       -- SGD updates eq. (w_update)/(h_update), section 2.3, applied to the
+ *                       per-rating loss of eq. (obj_fcn) in its simplified per-rating form.
+ *                       Readings: descent direction (the printed bracket is the negative
+ *                       gradient of the squared loss, so the update adds it), w_i (not w_j)
+ *                       in the h-update, one residual shared by both updates, and the h
+ *                       step uses the pre-update w_i (simultaneous update).
+ *   orc_step         -- step-size schedule eq. (stepsize_method), section 5.1, with the
+ *                       exponent generalised to gamma (the paper uses 1.5).
+ *   orc_partition    -- row partition I_1..I_p of section 3.1, in the "same number of
+ *                       ratings per set" form given in that section's footnote.
+ *   orc_owner0       -- initial uniformly random queue of each item (Algorithm 1, queue
+ *                       initialisation), realised by the splitmix64 mixing function
+ *                       (Steele, Lea, Flood 2014; Vigna's splitmix64.c).
+ *   orc_train_ring   -- Algorithm 1 with a fixed token-passing order: every worker q at
+ *                       sub-step s works on the items first placed at worker (q+s) mod p,
+ *                       in ascending item order; items move from worker q to q-1.
+ *   orc_train_ring_interleaved -- the same per-worker and per-item orders executed under
+ *                       a random asynchronous interleaving (serializability, section 1
+ *                       and section 4.4).
+ *   orc_train_perm   -- Algorithm 1 with the random-permutation circulation of section 3.4:
+ *                       each item visits every worker holding its ratings once per epoch, in
+ *                       uniformly random order, workers take turns at random.
+ *   orc_train_uniform -- Algorithm 1 literally: recipient uniform over all p workers, t is
+ *                       the per-(worker,item) visit count, stop after a number of updates.
+ *   orc_replay       -- re-execute a recorded sequence of (worker, item, t, seq) visits.
+ *   orc_rmse / orc_objective -- test RMSE of section 5.1 and J(W,H) of eq. (obj_fcn),
+ *                       with FP64 dot products and Neumaier-compensated sums.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_EDEADLOCK (-3)
+
+typedef struct {
+    int64_t updates;     /* SGD updates applied */
+    int64_t visits;      /* (worker, item) visits that applied at least one update */
+    int64_t violations;  /* updates whose row or item was not owned by the worker */
+    int64_t hops;        /* item transfers between workers */
+} orc_stats;
+
+/* ------------------------------------------------------------------------------- */
+/* Counter-based mixing function splitmix64 (published definition).                 */
+/* ------------------------------------------------------------------------------- */
+uint64_t orc_splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Worker whose queue receives item j at start-up: uniform over 0..p-1. */
+int32_t orc_owner0(uint64_t seed, int64_t j, int32_t p)
+{
+    return (int32_t)(orc_splitmix64(seed ^ (uint64_t)j) % (uint64_t)p);
+}
+
+/* s_t = alpha / (1 + beta * t^gamma). */
+double orc_step(double alpha, double beta, double gamma, double t)
+{
+    return alpha / (1.0 + beta * pow(t, gamma));
+}
+
+/* One SGD update on rating r of (w, h) with step s. */
+void orc_update(int32_t k, double *w, double *h, double r, double s, double lambda)
+{
+    double d = 0.0;
+    for (int32_t l = 0; l < k; ++l) d += w[l] * h[l];
+    double e = r - d;
+    for (int32_t l = 0; l < k; ++l) {
+        double wl = w[l], hl = h[l];
+        w[l] = wl + s * (e * hl - lambda * wl);
+        h[l] = hl + s * (e * wl - lambda * hl);
+    }
+}
+
+/* row_start[q] = smallest i with (#ratings in rows < i) >= ceil(q*nnz/p), q = 1..p-1;
+ * row_start[0] = 0 and row_start[p] = m. */
+int orc_partition(int64_t m, int64_t nnz, const int32_t *row, int32_t p, int64_t *row_start)
+{
+    if (p <= 0 || m < 0 || nnz < 0) return ORC_EINVAL;
+    int64_t *deg = (int64_t *)calloc((size_t)m + 1, sizeof(int64_t));
+    if (!deg) return ORC_ENOMEM;
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (row[e] < 0 || row[e] >= m) { free(deg); return ORC_EINVAL; }
+        deg[row[e]]++;
+    }
+    row_start[0] = 0;
+    row_start[p] = m;
+    int64_t i = 0, prefix = 0; /* prefix = #ratings in rows < i */
+    for (int32_t q = 1; q < p; ++q) {
+        int64_t target = (q * nnz + p - 1) / p; /* ceil(q*nnz/p) */
+        while (prefix < target) { prefix += deg[i]; ++i; }
+        row_start[q] = i;
+    }
+    free(deg);
+    return ORC_OK;
+}
+
+/* Worker that owns row i: the q with row_start[q] <= i < row_start[q+1]. */
+static int32_t worker_of_row(const int64_t *row_start, int32_t p, int64_t i)
+{
+    int32_t lo = 0, hi = p - 1;
+    while (lo < hi) {
+        int32_t mid = (lo + hi + 1) / 2;
+        if (row_start[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    /* skip empty workers that share the same start */
+    while (lo + 1 < p && row_start[lo + 1] <= i) ++lo;
+    return lo;
+}
+
+/* ------------------------------------------------------------------------------- */
+/* The partitioned data: each worker's ratings grouped by item, ascending row.       */
+/* ------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t i, j, q, s; /* row, item, owning worker, ring sub-step (g(j) - q) mod p */
+    double r;
+} rating;
+
+typedef struct {
+    int32_t q, j;       /* worker and item */
+    int64_t begin, end; /* its ratings: ratings[begin..end) */
+    int32_t v;          /* ordinal of this visit among the item's visits in one ring epoch */
+} visit;
+
+typedef struct {
+    int64_t m, n, nnz;
+    int32_t p;
+    int64_t *row_start;
+    rating *ratings;  /* sorted by (q, s, j, i) */
+    visit *visits;    /* one per nonempty (q, j), in the same order */
+    int64_t nvisit;
+    int64_t *wvis;    /* worker q's visits: visits[wvis[q]..wvis[q+1]) */
+    int32_t *nhold;   /* number of workers holding ratings of item j */
+    /* per item, its visits in ring order: ivis[istart[j]..istart[j+1]) index visits[] */
+    int64_t *istart, *ivis;
+} layout;
+
+static int cmp_qsji(const void *a, const void *b)
+{
+    const rating *x = (const rating *)a, *y = (const rating *)b;
+    if (x->q != y->q) return x->q < y->q ? -1 : 1;
+    if (x->s != y->s) return x->s < y->s ? -1 : 1;
+    if (x->j != y->j) return x->j < y->j ? -1 : 1;
+    if (x->i != y->i) return x->i < y->i ? -1 : 1;
+    return 0;
+}
+
+static void layout_free(layout *L)
+{
+    free(L->row_start); free(L->ratings); free(L->visits); free(L->wvis);
+    free(L->nhold); free(L->istart); free(L->ivis);
+    memset(L, 0, sizeof(*L));
+}
+
+static int layout_build(layout *L, int64_t m, int64_t n, int64_t nnz, const int32_t *row,
+                        const int32_t *col, const float *val, int32_t p, uint64_t seed)
+{
+    memset(L, 0, sizeof(*L));
+    if (p <= 0 || m < 0 || n < 0 || nnz < 0) return ORC_EINVAL;
+    L->m = m; L->n = n; L->nnz = nnz; L->p = p;
+    L->row_start = (int64_t *)malloc(sizeof(int64_t) * ((size_t)p + 1));
+    L->ratings = (rating *)malloc(sizeof(rating) * ((size_t)nnz + 1));
+    L->wvis = (int64_t *)calloc((size_t)p + 1, sizeof(int64_t));
+    L->nhold = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    L->istart = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!L->row_start || !L->ratings || !L->wvis || !L->nhold || !L->istart) {
+        layout_free(L); return ORC_ENOMEM;
+    }
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (row[e] < 0 || row[e] >= m || col[e] < 0 || col[e] >= n) { layout_free(L); return ORC_EINVAL; }
+    }
+    int rc = orc_partition(m, nnz, row, p, L->row_start);
+    if (rc) { layout_free(L); return rc; }
+    for (int64_t e = 0; e < nnz; ++e) {
+        rating *x = &L->ratings[e];
+        x->i = row[e]; x->j = col[e]; x->r = (double)val[e];
+        x->q = worker_of_row(L->row_start, p, row[e]);
+        int32_t g = orc_owner0(seed, col[e], p);
+        x->s = (int32_t)(((int64_t)g - x->q + p) % p);
+    }
+    qsort(L->ratings, (size_t)nnz, sizeof(rating), cmp_qsji);
+    /* duplicates are not allowed: Omega is a set of (i, j) positions */
+    for (int64_t e = 1; e < nnz; ++e) {
+        if (L->ratings[e].i == L->ratings[e - 1].i && L->ratings[e].j == L->ratings[e - 1].j) {
+            layout_free(L); return ORC_EINVAL;
+        }
+    }
+    /* visits: maximal runs of equal (q, j) */
+    int64_t nv = 0;
+    for (int64_t e = 0; e < nnz; ++e)
+        if (e == 0 || L->ratings[e].q != L->ratings[e - 1].q || L->ratings[e].j != L->ratings[e - 1].j) ++nv;
+    L->visits = (visit *)malloc(sizeof(visit) * ((size_t)nv + 1));
+    L->ivis = (int64_t *)malloc(sizeof(int64_t) * ((size_t)nv + 1));
+    if (!L->visits || !L->ivis) { layout_free(L); return ORC_ENOMEM; }
+    nv = 0;
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (e == 0 || L->ratings[e].q != L->ratings[e - 1].q || L->ratings[e].j != L->ratings[e - 1].j) {
+            if (nv > 0) L->visits[nv - 1].end = e;
+            L->visits[nv].q = L->ratings[e].q;
+            L->visits[nv].j = L->ratings[e].j;
+            L->visits[nv].begin = e;
+            ++nv;
+        }
+    }
+    if (nv > 0) L->visits[nv - 1].end = nnz;
+    L->nvisit = nv;
+    for (int64_t v = 0; v < nv; ++v) { L->wvis[L->visits[v].q + 1]++; L->nhold[L->visits[v].j]++; }
+    for (int32_t q = 0; q < p; ++q) L->wvis[q + 1] += L->wvis[q];
+    /* per item: its visits ordered by ring sub-step (the order the ring schedule meets them) */
+    for (int64_t j = 0; j < n; ++j) L->istart[j + 1] = L->istart[j] + L->nhold[j];
+    int64_t *fill = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!fill) { layout_free(L); return ORC_ENOMEM; }
+    for (int64_t v = 0; v < nv; ++v) {
+        int32_t j = L->visits[v].j;
+        L->ivis[L->istart[j] + fill[j]++] = v;
+    }
+    /* insertion sort each item's visits by sub-step s (distinct per item) */
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t a = L->istart[j], b = L->istart[j + 1];
+        for (int64_t x = a + 1; x < b; ++x) {
+            int64_t key = L->ivis[x];
+            int32_t ks = L->ratings[L->visits[key].begin].s;
+            int64_t y = x - 1;
+            while (y >= a && L->ratings[L->visits[L->ivis[y]].begin].s > ks) {
+                L->ivis[y + 1] = L->ivis[y]; --y;
+            }
+            L->ivis[y + 1] = key;
+        }
+        for (int64_t x = a; x < b; ++x) L->visits[L->ivis[x]].v = (int32_t)(x - a);
+    }
+    free(fill);
+    return ORC_OK;
+}
+
+/* Apply one visit: worker q holding item j runs SGD over its ratings of j. */
+static void apply_visit(const layout *L, const visit *V, int32_t k, double *W, double *H,
+                        double lambda, double s, int32_t holder_ok, orc_stats *st)
+{
+    double *h = H + (int64_t)V->j * k;
+    for (int64_t e = V->begin; e < V->end; ++e) {
+        const rating *x = &L->ratings[e];
+        int own_row = (x->i >= L->row_start[V->q] && x->i < L->row_start[V->q + 1]);
+        if (st && (!own_row || !holder_ok)) st->violations++;
+        orc_update(k, W + (int64_t)x->i * k, h, x->r, s, lambda);
+        if (st) st->updates++;
+    }
+    if (st && V->end > V->begin) st->visits++;
+}
+
+static int check_common(int32_t k, int32_t p, int32_t epochs)
+{
+    return (k <= 0 || p <= 0 || epochs < 0) ? ORC_EINVAL : ORC_OK;
+}
+
+/* Fixed token-passing order.  For e in epochs, s in 0..p-1, q in 0..p-1: worker q
+ * processes, in ascending item order, the items of group (q+s) mod p; t = epoch0 + e
+ * (every rating is updated exactly once per epoch). */
+int orc_train_ring(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                   const float *val, int32_t k, double lambda, double alpha, double beta,
+                   double gamma, int32_t p, uint64_t seed, int32_t epoch0, int32_t epochs,
+                   double *W, double *H, orc_stats *st)
+{
+    int rc = check_common(k, p, epochs);
+    if (rc) return rc;
+    layout L;
+    rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
+    if (rc) return rc;
+    if (st) memset(st, 0, sizeof(*st));
+    /* cursor[q] walks worker q's visits, which are sorted by sub-step */
+    int64_t *cursor = (int64_t *)malloc(sizeof(int64_t) * ((size_t)p + 1));
+    if (!cursor) { layout_free(&L); return ORC_ENOMEM; }
+    for (int32_t e = 0; e < epochs; ++e) {
+        double s_t = orc_step(alpha, beta, gamma, (double)(epoch0 + e));
+        for (int32_t q = 0; q < p; ++q) cursor[q] = L.wvis[q];
+        for (int32_t sub = 0; sub < p; ++sub) {
+            for (int32_t q = 0; q < p; ++q) {
+                while (cursor[q] < L.wvis[q + 1] &&
+                       L.ratings[L.visits[cursor[q]].begin].s == sub) {
+                    apply_visit(&L, &L.visits[cursor[q]], k, W, H, lambda, s_t, 1, st);
+                    cursor[q]++;
+                }
+            }
+        }
+    }
+    free(cursor);
+    layout_free(&L);
+    return ORC_OK;
+}
+
+/* The ring schedule's per-worker and per-item orders, executed under a random
+ * interleaving of the workers: a worker may take its next visit as soon as the item's
+ * previous visit (in ring order) is done.  Serializability says the result equals
+ * orc_train_ring bit for bit. */
+int orc_train_ring_interleaved(int64_t m, int64_t n, int64_t nnz, const int32_t *row,
+                               const int32_t *col, const float *val, int32_t k, double lambda,
+                               double alpha, double beta, double gamma, int32_t p, uint64_t seed,
+                               int32_t epoch0, int32_t epochs, uint64_t interleave_seed,
+                               double *W, double *H, orc_stats *st)
+{
+    int rc = check_common(k, p, epochs);
+    if (rc) return rc;
+    layout L;
+    rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
+    if (rc) return rc;
+    if (st) memset(st, 0, sizeof(*st));
+    int64_t *pos = (int64_t *)calloc((size_t)p, sizeof(int64_t));  /* visits done by q, all epochs */
+    int64_t *done = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t)); /* visits done on item j */
+    int32_t *live = (int32_t *)malloc(sizeof(int32_t) * (size_t)p);
+    if (!pos || !done || !live) { free(pos); free(done); free(live); layout_free(&L); return ORC_ENOMEM; }
+    int32_t nlive = 0;
+    for (int32_t q = 0; q < p; ++q)
+        if (L.wvis[q + 1] > L.wvis[q] && epochs > 0) live[nlive++] = q;
+    uint64_t ctr = 0;
+    int64_t misses = 0;
+    while (nlive > 0) {
+        int32_t pick = (int32_t)(orc_splitmix64(interleave_seed + ctr++) % (uint64_t)nlive);
+        int32_t q = live[pick];
+        int64_t per = L.wvis[q + 1] - L.wvis[q];
+        int64_t e = pos[q] / per;
+        const visit *V = &L.visits[L.wvis[q] + pos[q] % per];
+        int64_t ticket = e * L.nhold[V->j] + V->v;
+        if (done[V->j] != ticket) {
+            if (++misses > 64LL * p + 1024) {
+                /* scan: is any live worker able to move? */
+                int any = 0;
+                for (int32_t x = 0; x < nlive && !any; ++x) {
+                    int32_t qq = live[x];
+                    int64_t pp = L.wvis[qq + 1] - L.wvis[qq];
+                    const visit *VV = &L.visits[L.wvis[qq] + pos[qq] % pp];
+                    if (done[VV->j] == (pos[qq] / pp) * L.nhold[VV->j] + VV->v) any = 1;
+                }
+                if (!any) { rc = ORC_EDEADLOCK; break; }
+                misses = 0;
+            }
+            continue;
+        }
+        misses = 0;
+        apply_visit(&L, V, k, W, H, lambda, orc_step(alpha, beta, gamma, (double)(epoch0 + e)), 1, st);
+        done[V->j]++;
+        pos[q]++;
+        if (pos[q] == per * epochs) live[pick] = live[--nlive];
+    }
+    free(pos); free(done); free(live);
+    layout_free(&L);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------- */
+/* Asynchronous emulation: FIFO queue per worker (linked through next[]), a seeded   */
+/* scheduler picks uniformly among workers whose queue is not empty.                 */
+/* ------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t *head, *tail, *next; /* per-worker FIFO of items; next[j] links items */
+    int32_t *ne, *ne_pos;        /* list of workers with a non-empty queue */
+    int32_t nne;
+} queues;
+
+static int queues_init(queues *Q, int32_t p, int64_t n)
+{
+    Q->head = (int32_t *)malloc(sizeof(int32_t) * (size_t)p);
+    Q->tail = (int32_t *)malloc(sizeof(int32_t) * (size_t)p);
+    Q->next = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    Q->ne = (int32_t *)malloc(sizeof(int32_t) * (size_t)p);
+    Q->ne_pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)p);
+    if (!Q->head || !Q->tail || !Q->next || !Q->ne || !Q->ne_pos) return ORC_ENOMEM;
+    for (int32_t q = 0; q < p; ++q) { Q->head[q] = Q->tail[q] = -1; Q->ne_pos[q] = -1; }
+    Q->nne = 0;
+    return ORC_OK;
+}
+
+static void queues_free(queues *Q)
+{
+    free(Q->head); free(Q->tail); free(Q->next); free(Q->ne); free(Q->ne_pos);
+}
+
+static void q_push(queues *Q, int32_t q, int32_t j)
+{
+    Q->next[j] = -1;
+    if (Q->tail[q] < 0) {
+        Q->head[q] = Q->tail[q] = j;
+        Q->ne_pos[q] = Q->nne;
+        Q->ne[Q->nne++] = q;
+    } else {
+        Q->next[Q->tail[q]] = j;
+        Q->tail[q] = j;
+    }
+}
+
+static int32_t q_pop(queues *Q, int32_t q)
+{
+    int32_t j = Q->head[q];
+    Q->head[q] = Q->next[j];
+    if (Q->head[q] < 0) {
+        Q->tail[q] = -1;
+        int32_t at = Q->ne_pos[q], last = Q->ne[--Q->nne];
+        Q->ne[at] = last; Q->ne_pos[last] = at; Q->ne_pos[q] = -1;
+    }
+    return j;
+}
+
+/* Index (into L->visits) of worker q's visit of item j, or -1 if q holds no rating of j. */
+static int64_t find_visit(const layout *L, int32_t j, int32_t q)
+{
+    for (int64_t x = L->istart[j]; x < L->istart[j + 1]; ++x)
+        if (L->visits[L->ivis[x]].q == q) return L->ivis[x];
+    return -1;
+}
+
+/* Random-permutation circulation.  Each item starts at worker owner0(j); on every pop
+ * the worker processes its ratings of the item (once per epoch), then sends it to a
+ * uniformly random holder of the item's ratings that it has not visited in its current
+ * epoch; when every holder has been visited, the item's epoch advances (t = epoch0 +
+ * item epoch) and all holders become eligible again.  Items retire after `epochs`. */
+int orc_train_perm(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                   const float *val, int32_t k, double lambda, double alpha, double beta,
+                   double gamma, int32_t p, uint64_t seed, int32_t epoch0, int32_t epochs,
+                   uint64_t sched_seed, double *W, double *H, orc_stats *st)
+{
+    int rc = check_common(k, p, epochs);
+    if (rc) return rc;
+    layout L;
+    rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
+    if (rc) return rc;
+    if (st) memset(st, 0, sizeof(*st));
+    queues Q;
+    int32_t *ep = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));
+    int32_t *left = (int32_t *)calloc((size_t)n + 1, sizeof(int32_t));   /* holders not yet visited */
+    uint8_t *seen = (uint8_t *)calloc((size_t)L.nvisit + 1, 1);          /* per visit: done this epoch */
+    int32_t *holder = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
+    int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * ((size_t)p + 1));
+    if (queues_init(&Q, p, n) || !ep || !left || !seen || !holder || !cand) {
+        queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand);
+        layout_free(&L); return ORC_ENOMEM;
+    }
+    uint64_t ctr = 0;
+    for (int64_t j = 0; j < n; ++j) {
+        left[j] = L.nhold[j];
+        holder[j] = -1;
+        if (L.nhold[j] > 0 && epochs > 0) {
+            holder[j] = orc_owner0(seed, j, p);
+            q_push(&Q, holder[j], (int32_t)j);
+        }
+    }
+    while (Q.nne > 0) {
+        int32_t q = Q.ne[orc_splitmix64(sched_seed + ctr++) % (uint64_t)Q.nne];
+        int32_t j = q_pop(&Q, q);
+        int64_t vi = find_visit(&L, j, q);
+        if (vi >= 0 && !seen[vi]) {
+            apply_visit(&L, &L.visits[vi], k, W, H, lambda,
+                        orc_step(alpha, beta, gamma, (double)(epoch0 + ep[j])), holder[j] == q, st);
+            seen[vi] = 1;
+            left[j]--;
+        }
+        if (left[j] == 0) {
+            ep[j]++;
+            if (ep[j] == epochs) { holder[j] = -1; continue; }
+            left[j] = L.nhold[j];
+            for (int64_t x = L.istart[j]; x < L.istart[j + 1]; ++x) seen[L.ivis[x]] = 0;
+        }
+        int32_t nc = 0;
+        for (int64_t x = L.istart[j]; x < L.istart[j + 1]; ++x)
+            if (!seen[L.ivis[x]]) cand[nc++] = L.ivis[x];
+        int32_t dst = L.visits[cand[orc_splitmix64(sched_seed + ctr++) % (uint64_t)nc]].q;
+        holder[j] = dst;
+        if (st) st->hops++;
+        q_push(&Q, dst, j);
+    }
+    queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand);
+    layout_free(&L);
+    return ORC_OK;
+}
+
+/* Algorithm 1 literally: recipient uniform over all p workers; t = number of earlier
+ * updates of the (i, j) pair = earlier visits of item j to worker q (visit_count, p*n
+ * entries, in/out, may carry over from an earlier call); stop once `max_updates`
+ * updates were applied (checked after each visit). */
+int orc_train_uniform(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                      const float *val, int32_t k, double lambda, double alpha, double beta,
+                      double gamma, int32_t p, uint64_t seed, int64_t max_updates,
+                      uint64_t sched_seed, int32_t *visit_count, double *W, double *H,
+                      orc_stats *st)
+{
+    int rc = check_common(k, p, 0);
+    if (rc) return rc;
+    layout L;
+    rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
+    if (rc) return rc;
+    if (st) memset(st, 0, sizeof(*st));
+    queues Q;
+    if (queues_init(&Q, p, n)) { queues_free(&Q); layout_free(&L); return ORC_ENOMEM; }
+    uint64_t ctr = 0;
+    int64_t applied = 0;
+    if (max_updates > 0 && nnz > 0)
+        for (int64_t j = 0; j < n; ++j) q_push(&Q, orc_owner0(seed, j, p), (int32_t)j);
+    while (applied < max_updates && Q.nne > 0) {
+        int32_t q = Q.ne[orc_splitmix64(sched_seed + ctr++) % (uint64_t)Q.nne];
+        int32_t j = q_pop(&Q, q);
+        int64_t vi = find_visit(&L, j, q);
+        if (vi >= 0) {
+            int32_t *t = &visit_count[(int64_t)q * n + j];
+            apply_visit(&L, &L.visits[vi], k, W, H, lambda, orc_step(alpha, beta, gamma, (double)*t), 1, st);
+            applied += L.visits[vi].end - L.visits[vi].begin;
+            (*t)++;
+        }
+        int32_t dst = (int32_t)(orc_splitmix64(sched_seed + ctr++) % (uint64_t)p);
+        if (st) st->hops++;
+        q_push(&Q, dst, j);
+    }
+    queues_free(&Q);
+    layout_free(&L);
+    return ORC_OK;
+}
+
+/* Re-execute recorded visits.  Record x says: worker tq[x] applied its ratings of item
+ * tj[x] with step index tt[x], as the tseq[x]-th visit of that item.  Records of one
+ * worker are given in that worker's execution order.  A record runs once every earlier
+ * record of its worker has run and the item has completed tseq[x] visits. */
+int orc_replay(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+               const float *val, int32_t k, double lambda, double alpha, double beta,
+               double gamma, int32_t p, uint64_t seed, int64_t nrec, const int32_t *tq,
+               const int32_t *tj, const int32_t *tt, const int32_t *tseq, double *W, double *H,
+               orc_stats *st)
+{
+    int rc = check_common(k, p, 0);
+    if (rc) return rc;
+    layout L;
+    rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
+    if (rc) return rc;
+    if (st) memset(st, 0, sizeof(*st));
+    int64_t *wcount = (int64_t *)calloc((size_t)p + 1, sizeof(int64_t));
+    int64_t *wptr = (int64_t *)calloc((size_t)p + 1, sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc(sizeof(int64_t) * ((size_t)nrec + 1));
+    int64_t *fill = (int64_t *)calloc((size_t)p + 1, sizeof(int64_t));
+    int64_t *ndone = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (!wcount || !wptr || !order || !fill || !ndone) { rc = ORC_ENOMEM; goto out; }
+    for (int64_t x = 0; x < nrec; ++x) {
+        if (tq[x] < 0 || tq[x] >= p || tj[x] < 0 || tj[x] >= n) { rc = ORC_EINVAL; goto out; }
+        wcount[tq[x] + 1]++;
+    }
+    for (int32_t q = 0; q < p; ++q) wcount[q + 1] += wcount[q];
+    for (int64_t x = 0; x < nrec; ++x) order[wcount[tq[x]] + fill[tq[x]]++] = x;
+    for (int32_t q = 0; q < p; ++q) wptr[q] = wcount[q];
+    int64_t remaining = nrec;
+    while (remaining > 0) {
+        int64_t progressed = 0;
+        for (int32_t q = 0; q < p; ++q) {
+            while (wptr[q] < wcount[q + 1]) {
+                int64_t x = order[wptr[q]];
+                if (ndone[tj[x]] != tseq[x]) break;
+                int64_t vi = find_visit(&L, tj[x], q);
+                if (vi < 0) { rc = ORC_EINVAL; goto out; }
+                apply_visit(&L, &L.visits[vi], k, W, H, lambda, orc_step(alpha, beta, gamma, (double)tt[x]), 1, st);
+                ndone[tj[x]]++;
+                wptr[q]++;
+                progressed++;
+            }
+        }
+        if (!progressed) { rc = ORC_EDEADLOCK; goto out; }
+        remaining -= progressed;
+    }
+out:
+    free(wcount); free(wptr); free(order); free(fill); free(ndone);
+    layout_free(&L);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------- */
+/* Evaluation: FP64 dot products, Neumaier-compensated sums.                        */
+/* ------------------------------------------------------------------------------- */
+static void neumaier_add(double *sum, double *comp, double x)
+{
+    double t = *sum + x;
+    if (fabs(*sum) >= fabs(x)) *comp += (*sum - t) + x;
+    else *comp += (x - t) + *sum;
+    *sum = t;
+}
+
+static double dot(const double *a, const double *b, int32_t k)
+{
+    double d = 0.0;
+    for (int32_t l = 0; l < k; ++l) d += a[l] * b[l];
+    return d;
+}
+
+/* sqrt( sum over test ratings of (A_ij - <w_i, h_j>)^2 / |test| ); NaN for an empty set. */
+int orc_rmse(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+             const float *val, int32_t k, const double *W, const double *H, double *out)
+{
+    if (k <= 0) return ORC_EINVAL;
+    double sum = 0.0, comp = 0.0;
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (row[e] < 0 || row[e] >= m || col[e] < 0 || col[e] >= n) return ORC_EINVAL;
+        double err = (double)val[e] - dot(W + (int64_t)row[e] * k, H + (int64_t)col[e] * k, k);
+        neumaier_add(&sum, &comp, err * err);
+    }
+    *out = nnz > 0 ? sqrt((sum + comp) / (double)nnz) : NAN;
+    return ORC_OK;
+}
+
+/* J(W,H) = 1/2 sum over ratings of [ (A_ij - <w_i,h_j>)^2 + lambda (|w_i|^2 + |h_j|^2) ]. */
+int orc_objective(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                  const float *val, int32_t k, double lambda, const double *W, const double *H,
+                  double *out)
+{
+    if (k <= 0) return ORC_EINVAL;
+    double sum = 0.0, comp = 0.0;
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (row[e] < 0 || row[e] >= m || col[e] < 0 || col[e] >= n) return ORC_EINVAL;
+        const double *w = W + (int64_t)row[e] * k, *h = H + (int64_t)col[e] * k;
+        double err = (double)val[e] - dot(w, h, k);
+        neumaier_add(&sum, &comp, 0.5 * (err * err + lambda * (dot(w, w, k) + dot(h, h, k))));
+    }
+    *out = sum + comp;
+    return ORC_OK;
+}
