@@ -1,0 +1,146 @@
+"""NOMAD throughput benchmark on one MI355X.
+
+A step is one epoch of NOMAD SGD (every training rating updated once) over the
+Netflix-shaped medium workload: 480,189 x 17,770, 100M Zipf(1.1) cells (1.4M held out),
+integer 1..5 ratings from a planted rank-30 model, k = 100, lambda = 0.05, FP32 factors,
+fixed token-passing (ring) schedule.  Inputs are synthetic, generated on the GPU and
+resident in HBM before timing starts.
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E, bytes/s
+METRIC = "rating SGD updates/sec and % HBM roofline at matched test RMSE (FP32 vs BF16/batched)"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def bytes_per_update(k: int, s_w: int, s_h: int, n: int, nnz_train: int, p_ref: int = 256) -> float:
+    """Algorithmic HBM bytes per rating update: the 12-byte COO entry, w_i read and
+    written, and h_j read and written once per visit of a column to each of p_ref
+    workers, amortised over the column's ratings."""
+    return 12.0 + 2.0 * k * s_w + 2.0 * k * s_h * n * p_ref / nnz_train
+
+
+def cpu_baseline(prob, W0, H0, hp, P, seed, row_fraction=0.1):
+    """The FP64 oracle on a bounded sample: the ratings of the first row_fraction of the
+    rows (rows carry random Zipf weights, so this is a uniform row sample), one epoch of
+    the same ring schedule, one core."""
+    import numpy as np
+
+    import oracle
+
+    m_s = max(1, int(prob.m * row_fraction))
+    row = prob.row.cpu().numpy()
+    sel = row < m_s
+    r, c, v = row[sel], prob.col.cpu().numpy()[sel], prob.val.cpu().numpy()[sel]
+    W = W0[:m_s].cpu().numpy()
+    H = H0.cpu().numpy()
+    log(f"cpu baseline: oracle on rows [0,{m_s}) = {r.size} ratings")
+    t0 = time.perf_counter()
+    oracle.train_ring(m_s, prob.n, r, c, v, W, H, oracle.Hyper(hp["k"], hp["lam"], hp["alpha"], hp["beta"],
+                                                               hp["gamma"]), P, seed, 1)
+    dt = time.perf_counter() - t0
+    return {"value": r.size / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 epoch, ring order, {P} workers, FP64, rows [0,{m_s}) of the workload "
+                      f"({r.size} ratings), layout included, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workers", type=int, default=0)
+    ap.add_argument("--rows-per-chunk", type=int, default=0)
+    ap.add_argument("--items-per-chunk", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form is a "
+              f"design, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1312_0193_amd as nm
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    prob = synth.medium(device=dev)
+    hp = prob.hp
+    W0, H0 = synth.init_factors(prob.m, prob.n, hp["k"], 2, device=dev)
+    torch.cuda.synchronize()
+    log(f"generated m={prob.m} n={prob.n} train={prob.nnz} test={prob.test_row.numel()} "
+        f"in {time.perf_counter() - t:.1f} s")
+    seed = 2
+    model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp["k"], lam=hp["lam"],
+                     alpha=hp["alpha"], beta=hp["beta"], gamma=hp["gamma"], workers=args.workers, seed=seed,
+                     rows_per_chunk=args.rows_per_chunk, items_per_chunk=args.items_per_chunk)
+    P = model.workers
+    st0 = model.train(0)
+    log(f"layout {st0.layout_seconds:.3f} s, workers {P}")
+    for w in range(args.warmup):
+        s = model.train(1)
+        log(f"warmup epoch {w}: {s.seconds * 1e3:.2f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ksec = []
+    for step in range(args.steps):
+        s = model.train(1)
+        ksec.append(s.seconds)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log("epoch kernel ms: " + " ".join(f"{x * 1e3:.2f}" for x in ksec))
+    nnz = prob.nnz
+    value = args.steps * nnz / wall
+    rmse, obj = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
+    log(f"test RMSE after {args.warmup + args.steps} epochs: {rmse:.5f}")
+    B = bytes_per_update(hp["k"], 4, 4, prob.n, nnz)
+    avg_kernel = sum(ksec) / len(ksec)
+    achieved = B * nnz / avg_kernel
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "medium: 480189x17770, 100M Zipf(1.1) cells, 1.4M held out, int 1-5 ratings, "
+                               "k=100, lambda=0.05, ring schedule, FP32",
+                   "global_batch": nnz, "workers": P, "test_rmse": rmse,
+                   "rows_per_chunk": model.cfg.rows_per_chunk, "items_per_chunk": model.cfg.items_per_chunk},
+        "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "bytes_per_update": B, "kernel": "k_train", "avg_kernel_ms": avg_kernel * 1e3},
+    }
+    model.close()
+    if not args.no_cpu_baseline:
+        W0c, H0c = W0.cpu(), H0.cpu()
+        out["cpu_baseline"] = cpu_baseline(prob, W0c, H0c, hp, P, seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,137 @@
+/*
+ * nomad.h -- C ABI of the MI355X NOMAD library (libnomad.so).
+ *
+ * NOMAD (Yun, Yu, Hsieh, Vishwanathan, Dhillon) fits A ~ W H^T on the observed entries
+ * Omega of a sparse m x n rating matrix by stochastic gradient descent
+ * (section 2.3, eqs. w_update / h_update) on the objective J(W,H) of eq. (obj_fcn).
+ * The rows are split into p disjoint sets I_1..I_p with about the same number of
+ * ratings each (section 3.1 and its footnote); worker q owns and alone updates w_i for
+ * i in I_q.  Every item vector h_j is owned by exactly one worker at a time and moves
+ * between workers ("nomadic" variables, section 3.1, Algorithm 1), so no two concurrent
+ * updates touch the same parameter.  Here a worker is one wavefront of a persistent
+ * kernel on one GPU, and items move between workers in groups (the message batching
+ * of section 3.5).
+ *
+ * Conventions for every entry point
+ *   - Returns a nomad_status; nothing aborts or throws across the ABI.  On failure the
+ *     message is available from nomad_last_error(ctx) (or nomad_last_error(NULL) for
+ *     failures that leave no context, such as nomad_init).
+ *   - Pointers named d_* are device pointers (HIP global memory on the current device);
+ *     h_* pointers are host memory.  Arrays are dense, row-major, 0-based.
+ *   - Input arrays are read during the call only and stay owned by the caller.  The
+ *     context owns every allocation it makes; nomad_destroy frees them.
+ *   - All device work is ordered on the HIP stream given to nomad_init (NULL = the
+ *     default stream) and every entry point synchronises that stream before returning.
+ *   - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef NOMAD_H
+#define NOMAD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nomad_ctx nomad_ctx;
+
+typedef enum {
+    NOMAD_OK = 0,
+    NOMAD_EINVAL = 1,   /* bad argument: sizes, k, index out of range, duplicate (i,j) */
+    NOMAD_ENOMEM = 2,   /* device or host allocation failed */
+    NOMAD_EDEVICE = 3,  /* a HIP call failed, or the workers cannot all be resident */
+    NOMAD_ESTATE = 4,   /* call not valid in the context's state (e.g. NULL context) */
+    NOMAD_ENOTIMPL = 5  /* option combination not provided by this build */
+} nomad_status;
+
+/* Order in which items travel between workers.
+ *   RING: fixed token-passing order.  Item j starts at worker g(j) (its uniformly random
+ *     initial queue, Algorithm 1); in sub-step s of an epoch worker q holds the items
+ *     with g(j) = (q+s) mod p and processes them in ascending j; items then pass from q
+ *     to q-1.  Every rating is updated once per epoch and the result is one fixed serial
+ *     order of updates, independent of timing.
+ *   PERM: asynchronous.  Each group of items visits the workers holding its ratings in
+ *     an order drawn afresh every epoch (the random-permutation circulation of section
+ *     3.4); workers take groups in arrival order, so the serial order depends on timing. */
+typedef enum { NOMAD_SCHED_RING = 0, NOMAD_SCHED_PERM = 1 } nomad_sched;
+
+/* Storage type of W and H in device memory; arithmetic is always FP32. */
+typedef enum { NOMAD_FP32 = 0, NOMAD_BF16 = 1 } nomad_dtype;
+typedef enum { NOMAD_ROUND_RNE = 0, NOMAD_ROUND_STOCHASTIC = 1 } nomad_round;
+
+typedef struct {
+    int32_t k;          /* latent dimension, 1..256 */
+    float lambda;       /* regularisation of eq. (obj_fcn), >= 0 */
+    float alpha, beta, gamma; /* step size s_t = alpha / (1 + beta t^gamma), eq. (stepsize_method);
+                           t = number of earlier updates of the (i,j) pair = epochs done */
+    int32_t sched;      /* nomad_sched */
+    int32_t dtype;      /* nomad_dtype */
+    int32_t rounding;   /* nomad_round, used when dtype = NOMAD_BF16 */
+    int32_t workers;    /* p, number of workers (wavefronts); 0 = library default */
+    int32_t rows_per_chunk;  /* max distinct rows staged at once by a worker; 0 = default */
+    int32_t items_per_chunk; /* max distinct items staged at once by a worker; 0 = default */
+    int32_t record_trace;    /* 1 = record every (worker, group) visit for replay */
+    uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing */
+} nomad_config;
+
+typedef struct {
+    double seconds;        /* device time of the training kernel(s), HIP events */
+    uint64_t updates;      /* SGD updates applied by the call */
+    uint64_t epochs_done;  /* epochs completed since nomad_init */
+    double layout_seconds; /* device time spent by nomad_init building the layout */
+} nomad_stats;
+
+/* Default values of nomad_config (k = 0 means "caller must set"). */
+void nomad_config_default(nomad_config *cfg);
+
+/* Build a context for one problem: validates the training ratings, partitions the rows
+ * (section 3.1 footnote: equal numbers of ratings), lays the ratings out per worker in
+ * processing order, and copies W0/H0 into the context.
+ *   m, n      matrix size (m, n >= 1, each < 2^31); nnz >= 0 training ratings (< 2^32).
+ *   d_row, d_col, d_val  device COO, nnz entries each: int32 row in [0,m), int32 column in
+ *             [0,n), float rating.  Omega is a set: a repeated (i,j) is EINVAL.
+ *   d_W0      device m x k FP32 initial user factors, row-major (row stride k).
+ *   d_H0      device n x k FP32 initial item factors, row-major.
+ *   hip_stream  hipStream_t to order all work on (NULL = default stream).
+ * On success *out holds a new context; on failure *out is NULL. */
+nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int64_t n, int64_t nnz,
+                        const int32_t *d_row, const int32_t *d_col, const float *d_val,
+                        const float *d_W0, const float *d_H0, void *hip_stream);
+
+/* Run `epochs` >= 0 epochs of NOMAD SGD (every training rating updated once per epoch),
+ * continuing the step-size counter from earlier calls.  `out` may be NULL. */
+nomad_status nomad_train_epochs(nomad_ctx *ctx, int32_t epochs, nomad_stats *out);
+
+/* Test RMSE sqrt(sum (A_ij - <w_i,h_j>)^2 / nnz) (section 5.1) over the given device COO,
+ * with FP64 dot products and a deterministic compensated (Neumaier) sum.  If
+ * objective_out is not NULL it also receives
+ * J = 1/2 sum [ (A_ij - <w_i,h_j>)^2 + lambda (|w_i|^2 + |h_j|^2) ] over the same entries
+ * (eq. obj_fcn in its per-rating form).  nnz = 0 gives NaN.  Indices are checked. */
+nomad_status nomad_eval_rmse(nomad_ctx *ctx, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
+                             const float *d_val, double *rmse_out, double *objective_out);
+
+/* Copy the current factors out as FP32: d_W m x k, d_H n x k (device, row-major). */
+nomad_status nomad_get_factors(nomad_ctx *ctx, float *d_W, float *d_H);
+
+/* Row partition: h_row_start[0..p] (host, p+1 int64), worker q owns rows
+ * [h_row_start[q], h_row_start[q+1]).  *p_out receives p. */
+nomad_status nomad_get_partition(nomad_ctx *ctx, int32_t *p_out, int64_t *h_row_start, int64_t cap);
+
+/* Visit trace of the last nomad_train_epochs call with record_trace = 1.  Each record is
+ * four int32: (worker q, group g, step index t, visit sequence number of the group).
+ * Records of one worker appear in that worker's execution order.  With h_buf = NULL only
+ * *len is set; otherwise up to `cap` records are copied to h_buf (host). */
+nomad_status nomad_get_trace(nomad_ctx *ctx, int64_t *len, int32_t *h_buf, int64_t cap);
+
+/* Free every resource of the context.  NULL is ignored. */
+void nomad_destroy(nomad_ctx *ctx);
+
+/* Message of the last failure on ctx, or of the last failure of the calling thread
+ * when ctx is NULL.  Never NULL; the string stays valid until the next call. */
+const char *nomad_last_error(const nomad_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NOMAD_H */

@@ -1,0 +1,225 @@
+"""Python binding of libnomad.so, the MI355X NOMAD library (C ABI in include/nomad.h).
+
+This module only marshals arguments: every step of the computation runs in the HIP
+kernels of libnomad.so.  PyTorch provides device memory and the HIP stream.  There is
+no fallback: if the library is missing or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from dataclasses import dataclass
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+LIB_PATH = os.path.join(PKG, "libnomad.so")
+HEADER = os.path.join(ROOT, "include", "nomad.h")
+
+NOMAD_OK, NOMAD_EINVAL, NOMAD_ENOMEM, NOMAD_EDEVICE, NOMAD_ESTATE, NOMAD_ENOTIMPL = range(6)
+SCHED = {"ring": 0, "perm": 1}
+DTYPE = {"fp32": 0, "bf16": 1}
+ROUND = {"rne": 0, "stochastic": 1}
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENOTIMPL"}
+
+
+class NomadConfig(C.Structure):
+    _fields_ = [("k", C.c_int32), ("lambda_", C.c_float), ("alpha", C.c_float), ("beta", C.c_float),
+                ("gamma", C.c_float), ("sched", C.c_int32), ("dtype", C.c_int32), ("rounding", C.c_int32),
+                ("workers", C.c_int32), ("rows_per_chunk", C.c_int32), ("items_per_chunk", C.c_int32),
+                ("record_trace", C.c_int32), ("seed", C.c_uint64)]
+
+
+class NomadStats(C.Structure):
+    _fields_ = [("seconds", C.c_double), ("updates", C.c_uint64), ("epochs_done", C.c_uint64),
+                ("layout_seconds", C.c_double)]
+
+
+class NomadError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load() -> C.CDLL:
+    """Load libnomad.so (built by __graft_entry__.build() / paper_1312_0193_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1312_0193_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    P, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    lib.nomad_config_default.restype = None
+    lib.nomad_config_default.argtypes = [C.POINTER(NomadConfig)]
+    lib.nomad_init.restype = C.c_int
+    lib.nomad_init.argtypes = [C.POINTER(P), C.POINTER(NomadConfig), i64, i64, i64, P, P, P, P, P, P]
+    lib.nomad_train_epochs.restype = C.c_int
+    lib.nomad_train_epochs.argtypes = [P, i32, C.POINTER(NomadStats)]
+    lib.nomad_eval_rmse.restype = C.c_int
+    lib.nomad_eval_rmse.argtypes = [P, i64, P, P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.nomad_get_factors.restype = C.c_int
+    lib.nomad_get_factors.argtypes = [P, P, P]
+    lib.nomad_get_partition.restype = C.c_int
+    lib.nomad_get_partition.argtypes = [P, C.POINTER(i32), P, i64]
+    lib.nomad_get_trace.restype = C.c_int
+    lib.nomad_get_trace.argtypes = [P, C.POINTER(i64), P, i64]
+    lib.nomad_destroy.restype = None
+    lib.nomad_destroy.argtypes = [P]
+    lib.nomad_last_error.restype = C.c_char_p
+    lib.nomad_last_error.argtypes = [P]
+    _lib = lib
+    return lib
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions declared in include/nomad.h."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return re.findall(r"\b(nomad_[a-z_]+)\s*\(", src)
+
+
+def _check(rc: int, ctx=None):
+    if rc != NOMAD_OK:
+        msg = load().nomad_last_error(ctx).decode()
+        raise NomadError(rc, msg)
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream_handle():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev_i32(t):
+    import torch
+    return t.to(device="cuda", dtype=torch.int32).contiguous()
+
+
+def _dev_f32(t):
+    import torch
+    return t.to(device="cuda", dtype=torch.float32).contiguous()
+
+
+@dataclass
+class Stats:
+    seconds: float
+    updates: int
+    epochs_done: int
+    layout_seconds: float
+
+    @property
+    def updates_per_s(self) -> float:
+        return self.updates / self.seconds if self.seconds > 0 else float("nan")
+
+
+def make_config(k: int, lam: float, alpha: float, beta: float, gamma: float, *, sched="ring", dtype="fp32",
+                rounding="rne", workers=0, rows_per_chunk=0, items_per_chunk=0, record_trace=False,
+                seed=0) -> NomadConfig:
+    cfg = NomadConfig()
+    load().nomad_config_default(C.byref(cfg))
+    cfg.k, cfg.lambda_, cfg.alpha, cfg.beta, cfg.gamma = k, lam, alpha, beta, gamma
+    cfg.sched, cfg.dtype, cfg.rounding = SCHED[sched], DTYPE[dtype], ROUND[rounding]
+    cfg.workers, cfg.rows_per_chunk, cfg.items_per_chunk = workers, rows_per_chunk, items_per_chunk
+    cfg.record_trace = int(bool(record_trace))
+    cfg.seed = seed
+    return cfg
+
+
+class Nomad:
+    """One NOMAD problem resident on the GPU (wraps a nomad_ctx).
+
+    row, col, val: training ratings (int32, int32, float32; any device, copied to the GPU);
+    W0 (m x k), H0 (n x k): initial factors.
+    """
+
+    def __init__(self, m: int, n: int, row, col, val, W0, H0, *, k: int, lam: float, alpha: float,
+                 beta: float, gamma: float, **kw):
+        lib = load()
+        self.m, self.n, self.k = int(m), int(n), int(k)
+        self.cfg = make_config(k, lam, alpha, beta, gamma, **kw)
+        row, col, val = _dev_i32(row), _dev_i32(col), _dev_f32(val)
+        W0, H0 = _dev_f32(W0), _dev_f32(H0)
+        if tuple(W0.shape) != (self.m, k) or tuple(H0.shape) != (self.n, k):
+            raise ValueError("W0 must be m x k and H0 n x k")
+        self.nnz = int(row.numel())
+        ctx = C.c_void_p()
+        _check(lib.nomad_init(C.byref(ctx), C.byref(self.cfg), self.m, self.n, self.nnz, _ptr(row), _ptr(col),
+                              _ptr(val), _ptr(W0), _ptr(H0), _stream_handle()))
+        self.ctx = ctx
+
+    def _c(self):
+        if self.ctx is None:
+            raise NomadError(NOMAD_ESTATE, "context destroyed")
+        return self.ctx
+
+    def train(self, epochs: int) -> Stats:
+        st = NomadStats()
+        _check(load().nomad_train_epochs(self._c(), int(epochs), C.byref(st)), self.ctx)
+        return Stats(st.seconds, st.updates, st.epochs_done, st.layout_seconds)
+
+    def evaluate(self, row, col, val) -> tuple[float, float]:
+        """(RMSE, objective J) over the given ratings, FP64."""
+        row, col, val = _dev_i32(row), _dev_i32(col), _dev_f32(val)
+        r, j = C.c_double(), C.c_double()
+        _check(load().nomad_eval_rmse(self._c(), int(row.numel()), _ptr(row), _ptr(col), _ptr(val), C.byref(r),
+                                      C.byref(j)), self.ctx)
+        return r.value, j.value
+
+    def factors(self):
+        import torch
+        W = torch.empty(self.m, self.k, device="cuda", dtype=torch.float32)
+        H = torch.empty(self.n, self.k, device="cuda", dtype=torch.float32)
+        _check(load().nomad_get_factors(self._c(), _ptr(W), _ptr(H)), self.ctx)
+        return W, H
+
+    def partition(self):
+        import numpy as np
+        p = C.c_int32()
+        _check(load().nomad_get_partition(self._c(), C.byref(p), None, 0), self.ctx)
+        rs = np.zeros(p.value + 1, dtype=np.int64)
+        _check(load().nomad_get_partition(self._c(), C.byref(p), rs.ctypes.data_as(C.c_void_p), rs.size), self.ctx)
+        return rs
+
+    @property
+    def workers(self) -> int:
+        p = C.c_int32()
+        _check(load().nomad_get_partition(self._c(), C.byref(p), None, 0), self.ctx)
+        return p.value
+
+    def trace(self):
+        import numpy as np
+        n = C.c_int64()
+        _check(load().nomad_get_trace(self._c(), C.byref(n), None, 0), self.ctx)
+        buf = np.zeros((n.value, 4), dtype=np.int32)
+        if n.value:
+            _check(load().nomad_get_trace(self._c(), C.byref(n), buf.ctypes.data_as(C.c_void_p), n.value),
+                   self.ctx)
+        return buf
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            load().nomad_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

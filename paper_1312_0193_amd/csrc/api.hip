@@ -1,0 +1,363 @@
+// C ABI of libnomad.so (declared in include/nomad.h).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nomad.h"
+#include "nomad_internal.h"
+
+using nomad::Plan;
+
+struct nomad_ctx {
+    nomad_config cfg{};
+    int64_t m = 0, n = 0, nnz = 0;
+    int32_t k = 0, kp = 0, p = 0;
+    hipStream_t stream = nullptr;
+    Plan plan;
+    float *W = nullptr, *H = nullptr;  // m x kp, n x kp (row stride kp, padding kept at 0)
+    uint32_t *grp_done = nullptr;      // p tickets + 1 abort word
+    int64_t epochs_done = 0;
+    std::vector<int64_t> row_start;
+    int32_t *trace = nullptr;
+    int64_t *trace_len = nullptr;
+    int64_t trace_cap = 0;
+    int64_t trace_count = 0;
+    void *eval_scratch = nullptr;
+    size_t eval_scratch_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    double layout_seconds = 0.0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+nomad_status fail(nomad_ctx *ctx, nomad_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+nomad_status fail(nomad_ctx *ctx, nomad_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    if (ctx) ctx->err = buf;
+    return st;
+}
+
+nomad_status hip_fail(nomad_ctx *ctx, hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory)
+        return fail(ctx, NOMAD_ENOMEM, "%s: device allocation failed (%s)", what, hipGetErrorString(e));
+    return fail(ctx, NOMAD_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPTRY(ctx, expr, what)                             \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return hip_fail((ctx), _e, (what)); \
+    } while (0)
+
+int32_t round_up4(int32_t k) { return (k + 3) & ~3; }
+
+void release(nomad_ctx *c) {
+    if (!c) return;
+    nomad::free_plan(&c->plan);
+    (void)hipFree(c->W);
+    (void)hipFree(c->H);
+    (void)hipFree(c->grp_done);
+    (void)hipFree(c->trace);
+    (void)hipFree(c->trace_len);
+    (void)hipFree(c->eval_scratch);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+}
+
+}  // namespace
+
+extern "C" {
+
+void nomad_config_default(nomad_config *cfg) {
+    if (!cfg) return;
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->k = 0;
+    cfg->lambda = 0.05f;
+    cfg->alpha = 0.01f;
+    cfg->beta = 0.0f;
+    cfg->gamma = 1.5f;
+    cfg->sched = NOMAD_SCHED_RING;
+    cfg->dtype = NOMAD_FP32;
+    cfg->rounding = NOMAD_ROUND_RNE;
+    cfg->workers = 0;
+    cfg->rows_per_chunk = 0;
+    cfg->items_per_chunk = 0;
+    cfg->record_trace = 0;
+    cfg->seed = 0;
+}
+
+nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int64_t n, int64_t nnz,
+                        const int32_t *d_row, const int32_t *d_col, const float *d_val, const float *d_W0,
+                        const float *d_H0, void *hip_stream) {
+    if (!out) return fail(nullptr, NOMAD_EINVAL, "nomad_init: out is NULL");
+    *out = nullptr;
+    if (!cfg) return fail(nullptr, NOMAD_EINVAL, "nomad_init: cfg is NULL");
+    if (cfg->k < 1 || cfg->k > nomad::kMaxK)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: k=%d outside [1,%d]", cfg->k, nomad::kMaxK);
+    if (!(cfg->lambda >= 0.0f) || !std::isfinite(cfg->lambda))
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: lambda must be finite and >= 0");
+    if (!std::isfinite(cfg->alpha) || !std::isfinite(cfg->beta) || !std::isfinite(cfg->gamma) ||
+        cfg->alpha < 0.0f || cfg->beta < 0.0f || cfg->gamma < 0.0f)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: step-size parameters must be finite and >= 0");
+    if (m < 1 || n < 1 || m > INT32_MAX || n > INT32_MAX)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: m=%lld, n=%lld must be in [1, 2^31)", (long long)m,
+                    (long long)n);
+    if (nnz < 0 || nnz > (int64_t)UINT32_MAX)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: nnz=%lld outside [0, 2^32)", (long long)nnz);
+    if (nnz > 0 && (!d_row || !d_col || !d_val))
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: rating arrays are NULL");
+    if (!d_W0 || !d_H0) return fail(nullptr, NOMAD_EINVAL, "nomad_init: initial factors are NULL");
+    if (cfg->sched != NOMAD_SCHED_RING)
+        return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init: schedule %d is not provided by this build", cfg->sched);
+    if (cfg->dtype != NOMAD_FP32)
+        return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init: storage type %d is not provided by this build",
+                    cfg->dtype);
+
+    nomad_ctx *c = new (std::nothrow) nomad_ctx();
+    if (!c) return fail(nullptr, NOMAD_ENOMEM, "nomad_init: host allocation failed");
+    c->cfg = *cfg;
+    c->m = m;
+    c->n = n;
+    c->nnz = nnz;
+    c->k = cfg->k;
+    c->kp = round_up4(cfg->k);
+    c->stream = (hipStream_t)hip_stream;
+
+    auto bail = [&](nomad_status st) {
+        g_last_error = c->err;
+        release(c);
+        delete c;
+        return st;
+    };
+
+    // chunk capacity: rows + items <= 64 slots, LDS for two buffers within ~40 KB
+    int32_t rmax = cfg->rows_per_chunk, tmax = cfg->items_per_chunk;
+    if (rmax <= 0 || tmax <= 0) {
+        int32_t budget = (int32_t)(40960 / (2 * 4 * c->kp));
+        if (budget > 48) budget = 48;
+        if (budget < 3) budget = 3;
+        if (rmax <= 0) rmax = (2 * budget) / 3;
+        if (tmax <= 0) tmax = budget - (2 * budget) / 3;
+    }
+    if (rmax < 1 || tmax < 1 || rmax + tmax > nomad::kMaxSlots) {
+        nomad_status st = fail(c, NOMAD_EINVAL, "nomad_init: rows_per_chunk=%d items_per_chunk=%d must be >= 1 "
+                               "with sum <= %d", rmax, tmax, nomad::kMaxSlots);
+        return bail(st);
+    }
+    int dev = 0, max_lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        return bail(fail(c, NOMAD_EDEVICE, "nomad_init: no usable HIP device"));
+    const size_t lds = nomad::train_lds_bytes(c->kp, rmax, tmax);
+    if (lds > (size_t)max_lds)
+        return bail(fail(c, NOMAD_EINVAL, "nomad_init: chunk staging needs %zu bytes of LDS, device allows %d",
+                         lds, max_lds));
+    int32_t maxw = 0;
+    hipError_t he = nomad::train_max_workers(c->kp, rmax, tmax, &maxw);
+    if (he != hipSuccess) return bail(hip_fail(c, he, "nomad_init: occupancy query"));
+    int32_t p = cfg->workers;
+    if (p <= 0) p = maxw < 2048 ? maxw : 2048;
+    if (p < 1 || p > 4096)
+        return bail(fail(c, NOMAD_EINVAL, "nomad_init: workers=%d outside [1,4096]", p));
+    if (p > maxw)
+        return bail(fail(c, NOMAD_EDEVICE, "nomad_init: %d workers cannot all be resident (device holds %d "
+                         "with this chunk size)", p, maxw));
+    c->p = p;
+    c->cfg.workers = p;
+    c->cfg.rows_per_chunk = rmax;
+    c->cfg.items_per_chunk = tmax;
+
+    hipError_t e;
+    if ((e = hipMalloc(&c->W, sizeof(float) * (size_t)m * c->kp)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: W"));
+    if ((e = hipMalloc(&c->H, sizeof(float) * (size_t)n * c->kp)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: H"));
+    if ((e = hipMalloc(&c->grp_done, sizeof(uint32_t) * (size_t)(p + 1))) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: tickets"));
+    c->eval_scratch_bytes = nomad::eval_scratch_bytes();
+    if ((e = hipMalloc(&c->eval_scratch, c->eval_scratch_bytes)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: scratch"));
+    if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: events"));
+    hipStream_t st = c->stream;
+    if ((e = hipMemsetAsync(c->W, 0, sizeof(float) * (size_t)m * c->kp, st)) != hipSuccess ||
+        (e = hipMemsetAsync(c->H, 0, sizeof(float) * (size_t)n * c->kp, st)) != hipSuccess ||
+        (e = hipMemsetAsync(c->grp_done, 0, sizeof(uint32_t) * (size_t)(p + 1), st)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: clear"));
+    if ((e = hipMemcpy2DAsync(c->W, sizeof(float) * c->kp, d_W0, sizeof(float) * c->k, sizeof(float) * c->k, m,
+                              hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+        (e = hipMemcpy2DAsync(c->H, sizeof(float) * c->kp, d_H0, sizeof(float) * c->k, sizeof(float) * c->k, n,
+                              hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: copy initial factors"));
+
+    if ((e = hipEventRecord(c->ev0, st)) != hipSuccess) return bail(hip_fail(c, e, "nomad_init: event"));
+    int code = 0;
+    char msg[256] = {0};
+    e = nomad::build_plan(&c->plan, m, n, nnz, d_row, d_col, d_val, p, c->kp, rmax, tmax, cfg->seed, st, &code,
+                          msg, sizeof(msg));
+    if (e != hipSuccess) return bail(hip_fail(c, e, "nomad_init: layout"));
+    if (code != 0) return bail(fail(c, NOMAD_EINVAL, "nomad_init: %s", msg));
+    if ((e = hipEventRecord(c->ev1, st)) != hipSuccess || (e = hipEventSynchronize(c->ev1)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: event"));
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    c->layout_seconds = ms * 1e-3;
+    c->row_start.resize(p + 1);
+    if ((e = hipMemcpy(c->row_start.data(), c->plan.row_start, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost)) !=
+        hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: partition copy"));
+    *out = c;
+    return NOMAD_OK;
+}
+
+nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) {
+    if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_train_epochs: NULL context");
+    if (epochs < 0) return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epochs=%d < 0", epochs);
+    if (c->epochs_done + epochs > (int64_t)INT32_MAX / 2)
+        return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epoch counter would overflow");
+    if (out) memset(out, 0, sizeof(*out));
+    hipStream_t st = c->stream;
+    double seconds = 0.0;
+    if (epochs > 0) {
+        nomad::TrainArgs a{};
+        a.m = c->m;
+        a.n = c->n;
+        a.W = c->W;
+        a.H = c->H;
+        a.wck = c->plan.wck;
+        a.chunks = c->plan.chunks;
+        a.slots = c->plan.slots;
+        a.ratings = c->plan.ratings;
+        a.grp_done = c->grp_done;
+        a.kp = c->kp;
+        a.rmax = c->plan.rmax;
+        a.tmax = c->plan.tmax;
+        a.epoch0 = (int32_t)c->epochs_done;
+        a.epochs = epochs;
+        a.lambda = c->cfg.lambda;
+        a.alpha = c->cfg.alpha;
+        a.beta = c->cfg.beta;
+        a.gamma = c->cfg.gamma;
+        if (c->cfg.record_trace) {
+            const int64_t need = c->plan.nchunks * (int64_t)epochs;
+            if (need > c->trace_cap) {
+                (void)hipFree(c->trace);
+                c->trace = nullptr;
+                c->trace_cap = 0;
+                HIPTRY(c, hipMalloc(&c->trace, sizeof(int32_t) * 4 * (size_t)(need > 0 ? need : 1)), "trace");
+                c->trace_cap = need;
+            }
+            if (!c->trace_len) HIPTRY(c, hipMalloc(&c->trace_len, sizeof(int64_t)), "trace");
+            HIPTRY(c, hipMemsetAsync(c->trace_len, 0, sizeof(int64_t), st), "trace");
+            a.trace = c->trace;
+            a.trace_len = c->trace_len;
+            a.trace_cap = c->trace_cap;
+        }
+        HIPTRY(c, hipMemsetAsync(c->grp_done + c->p, 0, sizeof(uint32_t), st), "train: reset");
+        HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
+        HIPTRY(c, nomad::launch_train(a, c->p, st), "train: launch");
+        HIPTRY(c, hipEventRecord(c->ev1, st), "train: event");
+        HIPTRY(c, hipEventSynchronize(c->ev1), "train: kernel");
+        float ms = 0.0f;
+        HIPTRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1), "train: timing");
+        seconds = ms * 1e-3;
+        uint32_t aborted = 0;
+        HIPTRY(c, hipMemcpy(&aborted, c->grp_done + c->p, sizeof(uint32_t), hipMemcpyDeviceToHost), "train: flag");
+        if (aborted == 2)
+            return fail(c, NOMAD_EDEVICE, "nomad_train_epochs: malformed chunk plan detected; the factors are "
+                        "undefined");
+        if (aborted)
+            return fail(c, NOMAD_EDEVICE, "nomad_train_epochs: a worker waited beyond the time limit; the "
+                        "factors are undefined");
+        if (c->cfg.record_trace) {
+            HIPTRY(c, hipMemcpy(&c->trace_count, c->trace_len, sizeof(int64_t), hipMemcpyDeviceToHost), "trace");
+            if (c->trace_count > c->trace_cap) c->trace_count = c->trace_cap;
+        }
+        c->epochs_done += epochs;
+    }
+    if (out) {
+        out->seconds = seconds;
+        out->updates = (uint64_t)c->nnz * (uint64_t)epochs;
+        out->epochs_done = (uint64_t)c->epochs_done;
+        out->layout_seconds = c->layout_seconds;
+    }
+    return NOMAD_OK;
+}
+
+nomad_status nomad_eval_rmse(nomad_ctx *c, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
+                             const float *d_val, double *rmse_out, double *objective_out) {
+    if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_eval_rmse: NULL context");
+    if (!rmse_out) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: rmse_out is NULL");
+    if (nnz < 0) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: nnz < 0");
+    if (nnz > 0 && (!d_row || !d_col || !d_val)) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: NULL arrays");
+    double sq = 0.0, obj = 0.0;
+    int bad = 0;
+    if (nnz > 0) {
+        HIPTRY(c, nomad::eval_sums(c->W, c->H, c->k, c->kp, c->m, c->n, nnz, d_row, d_col, d_val, c->cfg.lambda, &sq,
+                                   &obj, &bad, c->eval_scratch, c->eval_scratch_bytes, c->stream),
+               "eval");
+        if (bad) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: rating index out of range");
+    }
+    *rmse_out = nnz > 0 ? std::sqrt(sq / (double)nnz) : NAN;
+    if (objective_out) *objective_out = nnz > 0 ? obj : 0.0;
+    return NOMAD_OK;
+}
+
+nomad_status nomad_get_factors(nomad_ctx *c, float *d_W, float *d_H) {
+    if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_factors: NULL context");
+    if (!d_W || !d_H) return fail(c, NOMAD_EINVAL, "nomad_get_factors: NULL output");
+    HIPTRY(c, hipMemcpy2DAsync(d_W, sizeof(float) * c->k, c->W, sizeof(float) * c->kp, sizeof(float) * c->k, c->m,
+                               hipMemcpyDeviceToDevice, c->stream),
+           "get_factors");
+    HIPTRY(c, hipMemcpy2DAsync(d_H, sizeof(float) * c->k, c->H, sizeof(float) * c->kp, sizeof(float) * c->k, c->n,
+                               hipMemcpyDeviceToDevice, c->stream),
+           "get_factors");
+    HIPTRY(c, hipStreamSynchronize(c->stream), "get_factors");
+    return NOMAD_OK;
+}
+
+nomad_status nomad_get_partition(nomad_ctx *c, int32_t *p_out, int64_t *h_row_start, int64_t cap) {
+    if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_partition: NULL context");
+    if (p_out) *p_out = c->p;
+    if (h_row_start) {
+        if (cap < c->p + 1) return fail(c, NOMAD_EINVAL, "nomad_get_partition: cap < p + 1");
+        memcpy(h_row_start, c->row_start.data(), sizeof(int64_t) * (c->p + 1));
+    }
+    return NOMAD_OK;
+}
+
+nomad_status nomad_get_trace(nomad_ctx *c, int64_t *len, int32_t *h_buf, int64_t cap) {
+    if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_trace: NULL context");
+    if (!len) return fail(c, NOMAD_EINVAL, "nomad_get_trace: len is NULL");
+    *len = c->trace_count;
+    if (h_buf && c->trace_count > 0) {
+        int64_t cnt = cap < c->trace_count ? cap : c->trace_count;
+        HIPTRY(c, hipMemcpy(h_buf, c->trace, sizeof(int32_t) * 4 * (size_t)cnt, hipMemcpyDeviceToHost), "trace");
+    }
+    return NOMAD_OK;
+}
+
+void nomad_destroy(nomad_ctx *c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    release(c);
+    delete c;
+}
+
+const char *nomad_last_error(const nomad_ctx *c) {
+    if (c) return c->err.c_str();
+    return g_last_error.c_str();
+}
+
+}  // extern "C"

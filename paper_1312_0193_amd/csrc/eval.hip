@@ -1,0 +1,125 @@
+// Test RMSE (section 5.1) and objective J(W,H) (eq. obj_fcn, per-rating form) with FP64
+// dot products and compensated (Neumaier) sums.  The entry-to-thread assignment and the
+// reduction tree are fixed, so the result does not depend on timing.
+#include "nomad_internal.h"
+
+namespace nomad {
+namespace {
+
+constexpr int kBlocks = 1024;
+constexpr int kThreads = 256;
+
+struct Comp {
+    double s, c;
+};
+
+__device__ __forceinline__ void neu_add(Comp &a, double x) {
+    double t = a.s + x;
+    if (fabs(a.s) >= fabs(x)) a.c += (a.s - t) + x;
+    else a.c += (x - t) + a.s;
+    a.s = t;
+}
+
+__device__ __forceinline__ Comp neu_merge(Comp a, Comp b) {
+    neu_add(a, b.s);
+    a.c += b.c;
+    return a;
+}
+
+__global__ __launch_bounds__(kThreads) void k_eval_partial(const float *W, const float *H, int32_t k,
+                                                          int32_t kp, int64_t m, int64_t n, int64_t nnz,
+                                                          const int32_t *row, const int32_t *col,
+                                                          const float *val, double lambda, Comp *part,
+                                                          int32_t *bad) {
+    __shared__ Comp sq[kThreads], ob[kThreads];
+    Comp a{0.0, 0.0}, b{0.0, 0.0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += stride) {
+        const int32_t i = row[e], j = col[e];
+        if (i < 0 || i >= m || j < 0 || j >= n) {
+            atomicOr(bad, 1);
+            continue;
+        }
+        const float *w = W + (int64_t)i * kp;
+        const float *h = H + (int64_t)j * kp;
+        double d = 0.0, ww = 0.0, hh = 0.0;
+        for (int32_t l = 0; l < k; ++l) {
+            const double wl = (double)w[l], hl = (double)h[l];
+            d += wl * hl;
+            ww += wl * wl;
+            hh += hl * hl;
+        }
+        const double err = (double)val[e] - d;
+        neu_add(a, err * err);
+        neu_add(b, 0.5 * (err * err + lambda * (ww + hh)));
+    }
+    sq[threadIdx.x] = a;
+    ob[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sq[threadIdx.x] = neu_merge(sq[threadIdx.x], sq[threadIdx.x + w]);
+            ob[threadIdx.x] = neu_merge(ob[threadIdx.x], ob[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sq[0];
+        part[2 * blockIdx.x + 1] = ob[0];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_eval_final(const Comp *part, int nparts, double *out) {
+    __shared__ Comp sq[kThreads], ob[kThreads];
+    Comp a{0.0, 0.0}, b{0.0, 0.0};
+    for (int x = threadIdx.x; x < nparts; x += blockDim.x) {
+        a = neu_merge(a, part[2 * x]);
+        b = neu_merge(b, part[2 * x + 1]);
+    }
+    sq[threadIdx.x] = a;
+    ob[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sq[threadIdx.x] = neu_merge(sq[threadIdx.x], sq[threadIdx.x + w]);
+            ob[threadIdx.x] = neu_merge(ob[threadIdx.x], ob[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sq[0].s + sq[0].c;
+        out[1] = ob[0].s + ob[0].c;
+    }
+}
+
+}  // namespace
+
+size_t eval_scratch_bytes() { return sizeof(Comp) * 2 * kBlocks + 2 * sizeof(double) + 64; }
+
+hipError_t eval_sums(const float *W, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,
+                     int64_t nnz, const int32_t *row, const int32_t *col, const float *val,
+                     double lambda, double *h_sq_err, double *h_obj, int *h_bad_index, void *scratch,
+                     size_t scratch_bytes, hipStream_t st) {
+    if (scratch_bytes < eval_scratch_bytes()) return hipErrorInvalidValue;
+    Comp *part = (Comp *)scratch;
+    double *out = (double *)(part + 2 * kBlocks);
+    int32_t *bad = (int32_t *)(out + 2);
+    hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_eval_partial, dim3(kBlocks), dim3(kThreads), 0, st, W, H, k, kp, m, n, nnz, row,
+                       col, val, lambda, part, bad);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_eval_final, dim3(1), dim3(kThreads), 0, st, part, kBlocks, out);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    double h_out[2];
+    int32_t h_bad = 0;
+    if ((e = hipMemcpyAsync(h_out, out, sizeof(h_out), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&h_bad, bad, sizeof(h_bad), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    *h_sq_err = h_out[0];
+    *h_obj = h_out[1];
+    *h_bad_index = h_bad;
+    return hipSuccess;
+}
+
+}  // namespace nomad

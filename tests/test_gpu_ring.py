@@ -1,0 +1,164 @@
+"""GPU parity of the fixed token-passing (ring) schedule: the HIP path, called through the
+C ABI, against the FP64 oracle on the same seeded inputs.
+
+Bar: after one epoch the factors agree to 1e-5 relative Frobenius error (FP32 arithmetic
+on the device vs FP64 in the oracle); RMSE / objective evaluation agrees to 1e-12.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1312_0193_amd as nm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_1EPOCH = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make(m, n, nnz, *, k, seed, degrees="uniform", lam=0.05, alpha=0.01, beta=1e-4, gamma=1.0):
+    prob = synth.small_case(m, n, nnz, seed=seed, degrees=degrees, k=k, lam=lam, alpha=alpha, beta=beta,
+                            gamma=gamma, test_frac=0.1)
+    W0, H0 = synth.init_factors(m, n, k, seed)
+    return prob, W0, H0, oracle.Hyper(k, lam, alpha, beta, gamma)
+
+
+def gpu_run(prob, W0, H0, hp, P, seed, calls, **kw):
+    print(f"[case] m={prob.m} n={prob.n} nnz={prob.nnz} k={hp.k} P={P} calls={calls} {kw}", flush=True)
+    model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
+                     beta=hp.beta, gamma=hp.gamma, workers=P, seed=seed, **kw)
+    for e in calls:
+        model.train(e)
+    W, H = model.factors()
+    return model, W.cpu().double().numpy(), H.cpu().double().numpy()
+
+
+def oracle_run(prob, W0, H0, hp, P, seed, epochs):
+    Wo, Ho, _ = oracle.train_ring(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(),
+                                  W0.numpy(), H0.numpy(), hp, P, seed, epochs)
+    return Wo, Ho
+
+
+CASES = [
+    # m, n, nnz, k, P, degrees, rows_per_chunk, items_per_chunk
+    (300, 200, 6_000, 3, 4, "uniform", 2, 1),        # tiny chunks: many carries and splits
+    (2_000, 1_000, 90_000, 16, 64, "uniform", 0, 0),  # the tiny workload's shape
+    (500, 80, 10_000, 100, 16, "uniform", 0, 0),      # k = 100 (two floats per lane)
+    (400, 300, 20_000, 130, 32, "uniform", 0, 0),     # four floats per lane
+    (200, 150, 9_000, 256, 8, "uniform", 0, 0),       # largest k
+    (50, 3_000, 8_000, 32, 7, "uniform", 4, 2),       # wide matrix, odd worker count
+    (3_000, 500, 60_000, 64, 24, "zipf", 5, 3),       # skewed degrees
+    (700, 90, 5_000, 16, 1, "uniform", 0, 0),         # a single worker
+    (257, 129, 3_001, 5, 3, "zipf", 3, 2),            # ragged sizes, odd k
+]
+
+
+@pytest.mark.parametrize("m,n,nnz,k,P,deg,rpc,ipc", CASES)
+def test_ring_one_epoch_matches_oracle(m, n, nnz, k, P, deg, rpc, ipc):
+    prob, W0, H0, hp = make(m, n, nnz, k=k, seed=m + n + k, degrees=deg)
+    seed = 1234 + P
+    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [1], rows_per_chunk=rpc, items_per_chunk=ipc)
+    Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 1)
+    assert rel(W, Wo) < TOL_1EPOCH and rel(H, Ho) < TOL_1EPOCH, (rel(W, Wo), rel(H, Ho))
+    # evaluation: same factors, FP64 on both sides
+    tr, tc, tv = prob.test_row.numpy(), prob.test_col.numpy(), prob.test_val.numpy()
+    r_gpu, j_gpu = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
+    assert r_gpu == pytest.approx(oracle.rmse(m, n, tr, tc, tv, W, H), rel=1e-12)
+    assert j_gpu == pytest.approx(oracle.objective(m, n, tr, tc, tv, W, H, hp.lam), rel=1e-12)
+    # partition is the ratings-balanced cut of the oracle
+    assert list(model.partition()) == list(oracle.partition(m, prob.row.numpy(), P))
+    model.close()
+
+
+def test_ring_multi_epoch_and_split_calls():
+    prob, W0, H0, hp = make(1_500, 700, 40_000, k=24, seed=5, beta=0.05, gamma=1.5)
+    P, seed = 12, 99
+    _, W1, H1 = gpu_run(prob, W0, H0, hp, P, seed, [3], rows_per_chunk=6, items_per_chunk=3)
+    m2, W2, H2 = gpu_run(prob, W0, H0, hp, P, seed, [1, 2], rows_per_chunk=6, items_per_chunk=3)
+    # the ring schedule is one fixed serial order: identical on every run and call split
+    assert np.array_equal(W1, W2) and np.array_equal(H1, H2)
+    Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 3)
+    assert rel(W1, Wo) < 3 * TOL_1EPOCH and rel(H1, Ho) < 3 * TOL_1EPOCH
+    st = m2.train(0)
+    assert st.epochs_done == 3 and st.updates == 0
+
+
+def test_ring_deterministic_across_contexts():
+    prob, W0, H0, hp = make(1_000, 400, 30_000, k=48, seed=8, degrees="zipf")
+    _, Wa, Ha = gpu_run(prob, W0, H0, hp, 20, 3, [2])
+    _, Wb, Hb = gpu_run(prob, W0, H0, hp, 20, 3, [2])
+    assert np.array_equal(Wa, Wb) and np.array_equal(Ha, Hb)
+
+
+def test_empty_and_single_rating():
+    k = 8
+    W0, H0 = synth.init_factors(10, 6, k, 1)
+    e = torch.zeros(0, dtype=torch.int32)
+    model = nm.Nomad(10, 6, e, e, e.float(), W0, H0, k=k, lam=0.1, alpha=0.1, beta=0.0, gamma=1.0, workers=4)
+    st = model.train(3)
+    W, H = model.factors()
+    assert st.updates == 0
+    assert torch.equal(W.cpu(), W0) and torch.equal(H.cpu(), H0)
+    r, _ = model.evaluate(e, e, e.float())
+    assert r != r  # NaN for an empty set
+    model.close()
+    row, col, val = torch.tensor([7], dtype=torch.int32), torch.tensor([2], dtype=torch.int32), torch.tensor([3.0])
+    model = nm.Nomad(10, 6, row, col, val, W0, H0, k=k, lam=0.1, alpha=0.1, beta=0.0, gamma=1.0, workers=4)
+    model.train(2)
+    W, H = model.factors()
+    Wo, Ho, _ = oracle.train_ring(10, 6, row.numpy(), col.numpy(), val.numpy(), W0.numpy(), H0.numpy(),
+                                  oracle.Hyper(k, 0.1, 0.1, 0.0, 1.0), 4, 0, 2)
+    assert rel(W.cpu().double().numpy(), Wo) < 1e-6 and rel(H.cpu().double().numpy(), Ho) < 1e-6
+    model.close()
+
+
+def test_invalid_inputs():
+    k = 4
+    W0, H0 = synth.init_factors(5, 5, k, 1)
+    row = torch.tensor([0, 5], dtype=torch.int32)
+    col = torch.tensor([0, 1], dtype=torch.int32)
+    val = torch.tensor([1.0, 2.0])
+    with pytest.raises(nm.NomadError) as ei:
+        nm.Nomad(5, 5, row, col, val, W0, H0, k=k, lam=0.1, alpha=0.1, beta=0.0, gamma=1.0, workers=2)
+    assert ei.value.status == nm.NOMAD_EINVAL
+    row = torch.tensor([1, 1], dtype=torch.int32)
+    col = torch.tensor([3, 3], dtype=torch.int32)
+    with pytest.raises(nm.NomadError) as ei:
+        nm.Nomad(5, 5, row, col, val, W0, H0, k=k, lam=0.1, alpha=0.1, beta=0.0, gamma=1.0, workers=2)
+    assert ei.value.status == nm.NOMAD_EINVAL and "repeated" in str(ei.value)
+    with pytest.raises(nm.NomadError) as ei:
+        nm.Nomad(5, 5, row[:1], col[:1], val[:1], W0, H0, k=k, lam=0.1, alpha=0.1, beta=0.0, gamma=1.0,
+                 workers=100_000)
+    assert ei.value.status in (nm.NOMAD_EINVAL, nm.NOMAD_EDEVICE)
+    model = nm.Nomad(5, 5, row[:1], col[:1], val[:1], W0, H0, k=k, lam=0.1, alpha=0.1, beta=0.0, gamma=1.0,
+                     workers=2)
+    with pytest.raises(nm.NomadError):
+        model.evaluate(torch.tensor([9], dtype=torch.int32), col[:1], val[:1])
+    with pytest.raises(nm.NomadError):
+        model.train(-1)
+    model.close()
+
+
+def test_trace_counts_every_block_visit():
+    prob, W0, H0, hp = make(600, 300, 12_000, k=16, seed=21)
+    P, seed, E = 6, 17, 2
+    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [E], record_trace=True)
+    tr = model.trace()
+    row, col = prob.row.numpy(), prob.col.numpy()
+    rs = oracle.partition(prob.m, row, P)
+    q_of = np.searchsorted(rs, row, "right") - 1
+    g_of = np.array([oracle.owner0(seed, j, P) for j in range(prob.n)])[col]
+    blocks = {(int(q), int(g)) for q, g in zip(q_of, g_of)}
+    assert len(tr) == E * len(blocks)
+    got = {(int(a), int(b)) for a, b in tr[:, :2]}
+    assert got == blocks
+    # every group's visits carry consecutive tickets, each epoch's t equal to the epoch
+    for g in range(P):
+        t = np.sort(tr[tr[:, 1] == g, 3])
+        assert np.array_equal(t, np.arange(len(t)))
+    model.close()
