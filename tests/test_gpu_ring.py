@@ -25,7 +25,14 @@ def make(m, n, nnz, *, k, seed, degrees="uniform", lam=0.05, alpha=0.01, beta=1e
     prob = synth.small_case(m, n, nnz, seed=seed, degrees=degrees, k=k, lam=lam, alpha=alpha, beta=beta,
                             gamma=gamma, test_frac=0.1)
     W0, H0 = synth.init_factors(m, n, k, seed)
-    return prob, W0, H0, oracle.Hyper(k, lam, alpha, beta, gamma)
+    return prob, W0, H0, f32_hyper(k, lam, alpha, beta, gamma)
+
+
+def f32_hyper(k, lam, alpha, beta, gamma):
+    """The C ABI carries lambda and the step-size parameters as float: hand the oracle
+    the same float32-rounded values."""
+    f = lambda x: float(np.float32(x))  # noqa: E731
+    return oracle.Hyper(k, f(lam), f(alpha), f(beta), f(gamma))
 
 
 def gpu_run(prob, W0, H0, hp, P, seed, calls, **kw):
@@ -112,7 +119,7 @@ def test_empty_and_single_rating():
     model.train(2)
     W, H = model.factors()
     Wo, Ho, _ = oracle.train_ring(10, 6, row.numpy(), col.numpy(), val.numpy(), W0.numpy(), H0.numpy(),
-                                  oracle.Hyper(k, 0.1, 0.1, 0.0, 1.0), 4, 0, 2)
+                                  f32_hyper(k, 0.1, 0.1, 0.0, 1.0), 4, 0, 2)
     assert rel(W.cpu().double().numpy(), Wo) < 1e-6 and rel(H.cpu().double().numpy(), Ho) < 1e-6
     model.close()
 
