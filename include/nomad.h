@@ -9,8 +9,8 @@
  * i in I_q.  Every item vector h_j is owned by exactly one worker at a time and moves
  * between workers ("nomadic" variables, section 3.1, Algorithm 1), so no two concurrent
  * updates touch the same parameter.  Here a worker is one wavefront of a persistent
- * kernel on one GPU, and items move between workers in groups (the message batching
- * of section 3.5).
+ * kernel on one GPU; it stages a few rows and items at a time in LDS and hands each
+ * item on as soon as it is done with it.
  *
  * Conventions for every entry point
  *   - Returns a nomad_status; nothing aborts or throws across the ABI.  On failure the
@@ -46,10 +46,10 @@ typedef enum {
 
 /* Order in which items travel between workers.
  *   RING: fixed token-passing order.  Item j starts at worker g(j) (its uniformly random
- *     initial queue, Algorithm 1); in sub-step s of an epoch worker q holds the items
- *     with g(j) = (q+s) mod p and processes them in ascending j; items then pass from q
- *     to q-1.  Every rating is updated once per epoch and the result is one fixed serial
- *     order of updates, independent of timing.
+ *     initial queue, Algorithm 1); in sub-step s of an epoch worker q processes the items
+ *     with g(j) = (q+s) mod p in ascending j; items then pass from q to q-1.  Every
+ *     rating is updated once per epoch and the result is one fixed serial order of
+ *     updates, independent of timing.
  *   PERM: asynchronous.  Each group of items visits the workers holding its ratings in
  *     an order drawn afresh every epoch (the random-permutation circulation of section
  *     3.4); workers take groups in arrival order, so the serial order depends on timing. */
@@ -70,7 +70,7 @@ typedef struct {
     int32_t workers;    /* p, number of workers (wavefronts); 0 = library default */
     int32_t rows_per_chunk;  /* max distinct rows staged at once by a worker; 0 = default */
     int32_t items_per_chunk; /* max distinct items staged at once by a worker; 0 = default */
-    int32_t record_trace;    /* 1 = record every (worker, group) visit for replay */
+    int32_t record_trace;    /* 1 = record every (worker, item) visit for replay */
     uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing */
 } nomad_config;
 
@@ -118,10 +118,19 @@ nomad_status nomad_get_factors(nomad_ctx *ctx, float *d_W, float *d_H);
 nomad_status nomad_get_partition(nomad_ctx *ctx, int32_t *p_out, int64_t *h_row_start, int64_t cap);
 
 /* Visit trace of the last nomad_train_epochs call with record_trace = 1.  Each record is
- * four int32: (worker q, group g, step index t, visit sequence number of the group).
- * Records of one worker appear in that worker's execution order.  With h_buf = NULL only
- * *len is set; otherwise up to `cap` records are copied to h_buf (host). */
+ * four int32: (worker q, item j, step index t, visit sequence number of item j since
+ * nomad_init), one per visit of an item at a worker, written when the worker takes the
+ * item over.  Records of one worker appear in that worker's execution order.  With
+ * h_buf = NULL only *len is set; otherwise up to `cap` records are copied to h_buf
+ * (host). */
 nomad_status nomad_get_trace(nomad_ctx *ctx, int64_t *len, int32_t *h_buf, int64_t cap);
+
+/* Per-worker counters of the last nomad_train_epochs call: p rows of eight int64 in
+ * h_stats (host, cap >= 8p): time in the kernel, time blocked acquiring an item group,
+ * time waiting for the previous chunk's memory traffic, chunks processed, time in the
+ * SGD updates, time issuing write-backs and prefetches, ratings processed, time staging
+ * vectors into LDS.  Times are ticks of the device's 100 MHz constant clock. */
+nomad_status nomad_get_worker_stats(nomad_ctx *ctx, int64_t *h_stats, int64_t cap);
 
 /* Free every resource of the context.  NULL is ignored. */
 void nomad_destroy(nomad_ctx *ctx);

@@ -71,6 +71,8 @@ def load() -> C.CDLL:
     lib.nomad_get_partition.argtypes = [P, C.POINTER(i32), P, i64]
     lib.nomad_get_trace.restype = C.c_int
     lib.nomad_get_trace.argtypes = [P, C.POINTER(i64), P, i64]
+    lib.nomad_get_worker_stats.restype = C.c_int
+    lib.nomad_get_worker_stats.argtypes = [P, P, i64]
     lib.nomad_destroy.restype = None
     lib.nomad_destroy.argtypes = [P]
     lib.nomad_last_error.restype = C.c_char_p
@@ -205,6 +207,16 @@ class Nomad:
         if n.value:
             _check(load().nomad_get_trace(self._c(), C.byref(n), buf.ctypes.data_as(C.c_void_p), n.value),
                    self.ctx)
+        return buf
+
+    def worker_stats(self):
+        """(p, 8) int64 per worker for the last train() call, 100 MHz ticks unless a count:
+        kernel, blocked on groups, waiting on memory, chunks, updates, issuing memory
+        traffic, ratings, staging into LDS."""
+        import numpy as np
+        p = self.workers
+        buf = np.zeros((p, 8), dtype=np.int64)
+        _check(load().nomad_get_worker_stats(self._c(), buf.ctypes.data_as(C.c_void_p), buf.size), self.ctx)
         return buf
 
     def close(self):

@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -18,9 +19,10 @@ struct nomad_ctx {
     hipStream_t stream = nullptr;
     Plan plan;
     float *W = nullptr, *H = nullptr;  // m x kp, n x kp (row stride kp, padding kept at 0)
-    uint32_t *grp_done = nullptr;      // p tickets + 1 abort word
+    uint32_t *tok_done = nullptr;      // n item counters + 1 abort word
     int64_t epochs_done = 0;
     std::vector<int64_t> row_start;
+    int64_t *wstats = nullptr;         // p x 4 per-worker counters of the last call
     int32_t *trace = nullptr;
     int64_t *trace_len = nullptr;
     int64_t trace_cap = 0;
@@ -67,9 +69,10 @@ void release(nomad_ctx *c) {
     nomad::free_plan(&c->plan);
     (void)hipFree(c->W);
     (void)hipFree(c->H);
-    (void)hipFree(c->grp_done);
+    (void)hipFree(c->tok_done);
     (void)hipFree(c->trace);
     (void)hipFree(c->trace_len);
+    (void)hipFree(c->wstats);
     (void)hipFree(c->eval_scratch);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
@@ -142,17 +145,17 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     };
 
     // chunk capacity: rows + items <= 64 slots, LDS for two buffers within ~40 KB
+    // Chunk capacity: rows + items <= 64 slots and within the register staging of the
+    // worker kernel; by default 32 rows and 16 items, fewer for large k.
     int32_t rmax = cfg->rows_per_chunk, tmax = cfg->items_per_chunk;
-    if (rmax <= 0 || tmax <= 0) {
-        int32_t budget = (int32_t)(40960 / (2 * 4 * c->kp));
-        if (budget > 48) budget = 48;
-        if (budget < 3) budget = 3;
-        if (rmax <= 0) rmax = (2 * budget) / 3;
-        if (tmax <= 0) tmax = budget - (2 * budget) / 3;
-    }
-    if (rmax < 1 || tmax < 1 || rmax + tmax > nomad::kMaxSlots) {
-        nomad_status st = fail(c, NOMAD_EINVAL, "nomad_init: rows_per_chunk=%d items_per_chunk=%d must be >= 1 "
-                               "with sum <= %d", rmax, tmax, nomad::kMaxSlots);
+    const int32_t vec_per_step = 64 / (c->kp / 4);  // vectors one staging step moves
+    if (rmax <= 0) rmax = std::min(32, vec_per_step * nomad::kRowPiecesPerLane);
+    if (tmax <= 0) tmax = std::min(16, vec_per_step * nomad::kItemPiecesPerLane);
+    if (rmax < 1 || tmax < 1 || !nomad::train_chunk_fits(c->kp, rmax, tmax)) {
+        nomad_status st = fail(c, NOMAD_EINVAL, "nomad_init: rows_per_chunk=%d items_per_chunk=%d: need >= 1 each, "
+                               "sum <= %d, rows <= %d and items <= %d for k=%d", rmax, tmax, nomad::kMaxSlots,
+                               vec_per_step * nomad::kRowPiecesPerLane, vec_per_step * nomad::kItemPiecesPerLane,
+                               c->k);
         return bail(st);
     }
     int dev = 0, max_lds = 0;
@@ -183,8 +186,10 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
         return bail(hip_fail(c, e, "nomad_init: W"));
     if ((e = hipMalloc(&c->H, sizeof(float) * (size_t)n * c->kp)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: H"));
-    if ((e = hipMalloc(&c->grp_done, sizeof(uint32_t) * (size_t)(p + 1))) != hipSuccess)
-        return bail(hip_fail(c, e, "nomad_init: tickets"));
+    if ((e = hipMalloc(&c->tok_done, sizeof(uint32_t) * (size_t)(n + 1))) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: item counters"));
+    if ((e = hipMalloc(&c->wstats, sizeof(int64_t) * nomad::kWStatCount * (size_t)p)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: worker counters"));
     c->eval_scratch_bytes = nomad::eval_scratch_bytes();
     if ((e = hipMalloc(&c->eval_scratch, c->eval_scratch_bytes)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: scratch"));
@@ -193,7 +198,7 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     hipStream_t st = c->stream;
     if ((e = hipMemsetAsync(c->W, 0, sizeof(float) * (size_t)m * c->kp, st)) != hipSuccess ||
         (e = hipMemsetAsync(c->H, 0, sizeof(float) * (size_t)n * c->kp, st)) != hipSuccess ||
-        (e = hipMemsetAsync(c->grp_done, 0, sizeof(uint32_t) * (size_t)(p + 1), st)) != hipSuccess)
+        (e = hipMemsetAsync(c->tok_done, 0, sizeof(uint32_t) * (size_t)(n + 1), st)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: clear"));
     if ((e = hipMemcpy2DAsync(c->W, sizeof(float) * c->kp, d_W0, sizeof(float) * c->k, sizeof(float) * c->k, m,
                               hipMemcpyDeviceToDevice, st)) != hipSuccess ||
@@ -239,7 +244,7 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         a.chunks = c->plan.chunks;
         a.slots = c->plan.slots;
         a.ratings = c->plan.ratings;
-        a.grp_done = c->grp_done;
+        a.tok_done = c->tok_done;
         a.kp = c->kp;
         a.rmax = c->plan.rmax;
         a.tmax = c->plan.tmax;
@@ -250,7 +255,7 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         a.beta = c->cfg.beta;
         a.gamma = c->cfg.gamma;
         if (c->cfg.record_trace) {
-            const int64_t need = c->plan.nchunks * (int64_t)epochs;
+            const int64_t need = c->plan.nslots * (int64_t)epochs;
             if (need > c->trace_cap) {
                 (void)hipFree(c->trace);
                 c->trace = nullptr;
@@ -264,16 +269,18 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
             a.trace_len = c->trace_len;
             a.trace_cap = c->trace_cap;
         }
-        HIPTRY(c, hipMemsetAsync(c->grp_done + c->p, 0, sizeof(uint32_t), st), "train: reset");
+        HIPTRY(c, hipMemsetAsync(c->tok_done + c->n, 0, sizeof(uint32_t), st), "train: reset");
+        HIPTRY(c, hipMemsetAsync(c->wstats, 0, sizeof(int64_t) * nomad::kWStatCount * (size_t)c->p, st), "train: reset");
+        a.wstats = c->wstats;
         HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
-        HIPTRY(c, nomad::launch_train(a, c->p, st), "train: launch");
+        HIPTRY(c, nomad::launch_train(a, c->p, c->tok_done + c->n, st), "train: launch");
         HIPTRY(c, hipEventRecord(c->ev1, st), "train: event");
         HIPTRY(c, hipEventSynchronize(c->ev1), "train: kernel");
         float ms = 0.0f;
         HIPTRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1), "train: timing");
         seconds = ms * 1e-3;
         uint32_t aborted = 0;
-        HIPTRY(c, hipMemcpy(&aborted, c->grp_done + c->p, sizeof(uint32_t), hipMemcpyDeviceToHost), "train: flag");
+        HIPTRY(c, hipMemcpy(&aborted, c->tok_done + c->n, sizeof(uint32_t), hipMemcpyDeviceToHost), "train: flag");
         if (aborted == 2)
             return fail(c, NOMAD_EDEVICE, "nomad_train_epochs: malformed chunk plan detected; the factors are "
                         "undefined");
@@ -345,6 +352,15 @@ nomad_status nomad_get_trace(nomad_ctx *c, int64_t *len, int32_t *h_buf, int64_t
         int64_t cnt = cap < c->trace_count ? cap : c->trace_count;
         HIPTRY(c, hipMemcpy(h_buf, c->trace, sizeof(int32_t) * 4 * (size_t)cnt, hipMemcpyDeviceToHost), "trace");
     }
+    return NOMAD_OK;
+}
+
+nomad_status nomad_get_worker_stats(nomad_ctx *c, int64_t *h_stats, int64_t cap) {
+    if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_worker_stats: NULL context");
+    if (!h_stats || cap < (int64_t)nomad::kWStatCount * c->p)
+        return fail(c, NOMAD_EINVAL, "nomad_get_worker_stats: need room for %d values", nomad::kWStatCount * c->p);
+    HIPTRY(c, hipMemcpy(h_stats, c->wstats, sizeof(int64_t) * nomad::kWStatCount * (size_t)c->p, hipMemcpyDeviceToHost),
+           "worker stats");
     return NOMAD_OK;
 }
 

@@ -7,8 +7,8 @@
 //   4. order the ratings by (worker q, ring sub-step s = (g(j) - q) mod p, item j, row i)
 //      with two stable radix sorts (first by (j, i), then by (q, s)); a repeated (i, j)
 //      is rejected (Omega is a set);
-//   5. per group g, number the non-empty blocks (q, g) in ring order (the order in which
-//      group g meets the workers in one epoch of the fixed token-passing schedule);
+//   5. number the visits of every item (its runs of ratings at one worker) in ring order,
+//      i.e. by sub-step s, and count each item's visits per epoch;
 //   6. cut each worker's ratings into chunks (see nomad_internal.h) in two passes: count,
 //      then fill; finally link the last chunk of an epoch with the first one of the next.
 #include <hipcub/hipcub.hpp>
@@ -117,25 +117,47 @@ __global__ void k_block_bounds(const uint32_t *key, int64_t nnz, int64_t *bfirst
     }
 }
 
-// For every group, the non-empty blocks in ring order (sub-step s ascending).
-__global__ void k_tickets(const int64_t *bfirst, const int64_t *bend, int32_t p, int32_t *bvis,
-                          int32_t *nblk) {
-    int32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= p) return;
-    int32_t cnt = 0;
-    for (int32_t s = 0; s < p; ++s) {
-        int32_t q = (g - s + p) % p;
-        int64_t b = (int64_t)q * p + s;
-        if (bend[b] > bfirst[b]) bvis[b] = cnt++;
+// Visits: maximal runs of one (worker, item) in the (q, s, j, i) order.
+__global__ void k_visit_start(const uint32_t *key2, const int32_t *scol, int64_t nnz, uint32_t *is_start) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        is_start[e] = (e == 0 || key2[e] != key2[e - 1] || scol[e] != scol[e - 1]) ? 1u : 0u;
+}
+
+// For each visit (at its first rating e): sort key (item, sub-step) and the visit id.
+__global__ void k_visit_keys(const uint32_t *is_start, const uint32_t *vid, const uint32_t *key2,
+                             const int32_t *scol, int64_t nnz, int32_t p, uint64_t *vkey, uint32_t *vidx,
+                             uint32_t *nvis) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        if (!is_start[e]) continue;
+        const uint32_t v = vid[e];
+        const uint32_t s = key2[e] % (uint32_t)p;
+        vkey[v] = (uint64_t)scol[e] * (uint64_t)p + s;
+        vidx[v] = v;
+        atomicAdd(&nvis[scol[e]], 1u);
     }
-    nblk[g] = cnt;
+}
+
+// Visit ordinal within its item: position in the (item, sub-step) order minus the
+// item's first position.
+__global__ void k_visit_ordinal(const uint64_t *vkey_sorted, const uint32_t *vidx_sorted, const uint32_t *seg,
+                                int64_t nv, int32_t p, uint32_t *vord) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nv;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t j = vkey_sorted[t] / (uint64_t)p;
+        vord[vidx_sorted[t]] = (uint32_t)(t - seg[j]);
+    }
 }
 
 struct ChunkerArgs {
     const int32_t *srow, *scol;
     const float *sval;
     const int64_t *bfirst, *bend;
-    const int32_t *bvis, *nblk;
+    const uint32_t *vid;   // exclusive count of visit starts before each rating
+    const uint32_t *is_start;
+    const uint32_t *vord;  // visit ordinal within its item, per visit id
+    const uint32_t *nvis;  // visits per epoch of each item
     int32_t p, rmax, tmax;
     int32_t *rowmap;       // m entries, -1 initially: (chunk << 8) | slot of the row's last chunk
     int64_t *ck_count;     // pass 1 output: chunks per worker
@@ -147,64 +169,97 @@ struct ChunkerArgs {
     RatingRec *ratings;
 };
 
-// One thread per worker walks its ratings in processing order and cuts chunks.
+// One thread per worker walks its ratings in processing order and cuts chunks.  A row
+// (item) that the next chunk uses again stays in LDS at the same physical slot; the
+// other rows and items of a chunk take free physical slots, so a worker needs a single
+// staging buffer and never copies within LDS.  Chunks do not carry anything across an
+// epoch boundary.
 template <bool kFill>
 __global__ void k_chunker(ChunkerArgs a) {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.p) return;
     const int32_t p = a.p;
-    int32_t rid[kMaxSlots], rsrc[kMaxSlots];
-    int32_t tid[kMaxSlots], tsrc[kMaxSlots];
+    int32_t rid[kMaxSlots], rphys[kMaxSlots], prev_rphys[kMaxSlots];
+    int32_t tid[kMaxSlots], tphys[kMaxSlots], tv[kMaxSlots];
+    uint8_t rcar[kMaxSlots], tcar[kMaxSlots];
+    uint8_t lrs[kMaxRatingsPerChunk], lts[kMaxRatingsPerChunk];
     int64_t c = 0;                   // local index of the open chunk
-    int64_t ck_base = kFill ? a.ck_off[q] : 0;
+    const int64_t ck_base = kFill ? a.ck_off[q] : 0;
     int64_t sl_pos = kFill ? a.sl_off[q] : 0;  // next free slot record (global)
     int64_t nslots_local = 0;
     int64_t prev_slot_base = -1;     // slot records of the previous chunk (global index)
     int32_t prev_nr = 0;
-    int32_t prev_last_tok = -1, prev_last_tok_slot = -1;  // last item of the previous chunk
+    int32_t prev_last_tok = -1, prev_last_tok_slot = -1, prev_last_tok_phys = -1;
     bool prev_same_block = false;
     int32_t nr = 0, nt = 0, nrat = 0;
     int64_t rat0 = 0;
     uint32_t flags = 0;
-    int32_t g = 0, vb = 0, nb = 0;
-    bool open = false;
+    int32_t g = 0;
     int32_t cur_tok = -1;
 
+    auto assign = [](int32_t *phys, const uint8_t *car, int32_t count) {
+        uint64_t used = 0;
+        for (int32_t x = 0; x < count; ++x)
+            if (car[x]) used |= 1ull << phys[x];
+        for (int32_t x = 0; x < count; ++x) {
+            if (car[x]) continue;
+            const int32_t slot = __builtin_ctzll(~used);
+            phys[x] = slot;
+            used |= 1ull << slot;
+        }
+    };
     auto close_chunk = [&](bool last_of_block) {
-        uint32_t f = flags | (last_of_block ? kLastOfBlock : 0u);
+        const uint32_t f = flags | (last_of_block ? kLastOfBlock : 0u);
+        assign(rphys, rcar, nr);
+        assign(tphys, tcar, nt);
         if (kFill) {
             ChunkRec r;
             r.rat = rat0;
             r.slot = sl_pos;
             r.info = (uint32_t)nrat | ((uint32_t)nr << 8) | ((uint32_t)nt << 16) | (f << 24);
             r.group = g;
-            r.vblk = vb;
-            r.nblk = nb;
+            r.pad0 = r.pad1 = 0;
             a.chunks[ck_base + c] = r;
             for (int32_t x = 0; x < nr; ++x) {
-                SlotRec s; s.id = rid[x]; s.src = (int16_t)rsrc[x]; s.keep = 0;
+                SlotRec s;
+                s.id = rid[x];
+                s.phys = (int16_t)rphys[x];
+                s.flags = rcar[x] ? 0 : kSlotNew;
+                s.v = 0;
+                s.nvis = 0;
                 a.slots[sl_pos + x] = s;
             }
             for (int32_t x = 0; x < nt; ++x) {
-                SlotRec s; s.id = tid[x]; s.src = (int16_t)tsrc[x]; s.keep = 0;
+                SlotRec s;
+                s.id = tid[x];
+                s.phys = (int16_t)tphys[x];
+                s.flags = tcar[x] ? 0 : kSlotNew;
+                s.v = tv[x];
+                s.nvis = (int32_t)a.nvis[tid[x]];
                 a.slots[sl_pos + nr + x] = s;
             }
+            for (int32_t x = 0; x < nrat; ++x) {
+                RatingRec rr;
+                rr.slots = (uint32_t)rphys[lrs[x]] | ((uint32_t)tphys[lts[x]] << 8);
+                rr.r = a.sval[rat0 + x];
+                a.ratings[rat0 + x] = rr;
+            }
         }
+        for (int32_t x = 0; x < nr; ++x) prev_rphys[x] = rphys[x];
         prev_slot_base = sl_pos;
         prev_nr = nr;
         prev_last_tok = nt > 0 ? tid[nt - 1] : -1;
         prev_last_tok_slot = nt - 1;
+        prev_last_tok_phys = nt > 0 ? tphys[nt - 1] : -1;
         prev_same_block = !last_of_block;
         sl_pos += nr + nt;
         nslots_local += nr + nt;
         ++c;
-        open = false;
     };
     auto open_chunk = [&](int64_t first_rating, uint32_t f) {
         nr = nt = nrat = 0;
         rat0 = first_rating;
         flags = f;
-        open = true;
         cur_tok = -1;
     };
 
@@ -213,8 +268,6 @@ __global__ void k_chunker(ChunkerArgs a) {
         const int64_t f0 = a.bfirst[b], f1 = a.bend[b];
         if (f1 <= f0) continue;
         g = (q + s) % p;
-        vb = a.bvis[b];
-        nb = a.nblk[g];
         prev_same_block = false;  // a new block never carries items
         open_chunk(f0, kFirstOfBlock);
         for (int64_t e = f0; e < f1; ++e) {
@@ -232,10 +285,13 @@ __global__ void k_chunker(ChunkerArgs a) {
             if (tok_new) {
                 ts = nt++;
                 tid[ts] = j;
-                tsrc[ts] = -1;
+                tcar[ts] = 0;
+                tphys[ts] = -1;
+                tv[ts] = kFill ? (int32_t)a.vord[a.vid[e] + a.is_start[e] - 1u] : 0;
                 if (prev_same_block && nrat == 0 && j == prev_last_tok) {
-                    tsrc[ts] = prev_last_tok_slot;
-                    if (kFill) a.slots[prev_slot_base + prev_nr + prev_last_tok_slot].keep = 1;
+                    tcar[ts] = 1;
+                    tphys[ts] = prev_last_tok_phys;
+                    if (kFill) a.slots[prev_slot_base + prev_nr + prev_last_tok_slot].flags |= kSlotKeep;
                 }
                 cur_tok = j;
             } else {
@@ -245,21 +301,19 @@ __global__ void k_chunker(ChunkerArgs a) {
             if (!row_in) {
                 rs = nr++;
                 rid[rs] = i;
-                rsrc[rs] = -1;
+                rcar[rs] = 0;
+                rphys[rs] = -1;
                 if (v >= 0 && c > 0 && (int64_t)(v >> 8) == c - 1) {
-                    rsrc[rs] = v & 255;
-                    if (kFill) a.slots[prev_slot_base + (v & 255)].keep = 1;
+                    rcar[rs] = 1;
+                    rphys[rs] = prev_rphys[v & 255];
+                    if (kFill) a.slots[prev_slot_base + (v & 255)].flags |= kSlotKeep;
                 }
                 a.rowmap[i] = (int32_t)((c << 8) | rs);
             } else {
                 rs = v & 255;
             }
-            if (kFill) {
-                RatingRec r;
-                r.slots = (uint32_t)rs | ((uint32_t)ts << 8);
-                r.r = a.sval[e];
-                a.ratings[e] = r;
-            }
+            lrs[nrat] = (uint8_t)rs;
+            lts[nrat] = (uint8_t)ts;
             ++nrat;
         }
         close_chunk(true);
@@ -267,22 +321,6 @@ __global__ void k_chunker(ChunkerArgs a) {
     if (!kFill) {
         a.ck_count[q] = c;
         a.sl_count[q] = nslots_local;
-        return;
-    }
-    // Link the last chunk of an epoch with the first chunk of the next epoch: rows of the
-    // first chunk whose latest appearance is the last chunk are carried across.
-    if (c > 0) {
-        const int64_t last = c - 1;
-        const ChunkRec first = a.chunks[ck_base];
-        const int32_t nr0 = (first.info >> 8) & 255;
-        for (int32_t x = 0; x < nr0; ++x) {
-            SlotRec s = a.slots[first.slot + x];
-            int32_t v = a.rowmap[s.id];
-            if (v >= 0 && (int64_t)(v >> 8) == last) {
-                a.slots[first.slot + x].src = (int16_t)(v & 255);
-                a.slots[prev_slot_base + (v & 255)].keep = 1;
-            }
-        }
     }
 }
 
@@ -313,7 +351,7 @@ void free_plan(Plan *pl) {
     (void)hipFree(pl->chunks);
     (void)hipFree(pl->slots);
     (void)hipFree(pl->ratings);
-    (void)hipFree(pl->nblk);
+    (void)hipFree(pl->nvis);
     *pl = Plan();
 }
 
@@ -335,7 +373,11 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
     unsigned long long *deg = nullptr;
     int64_t *rowptr = nullptr, *bfirst = nullptr, *bend = nullptr;
     int64_t *ck_count = nullptr, *sl_count = nullptr, *ck_off = nullptr, *sl_off = nullptr;
-    int32_t *err = nullptr, *bvis = nullptr, *rowmap = nullptr;
+    int32_t *err = nullptr, *rowmap = nullptr;
+    uint32_t *is_start = nullptr, *vid = nullptr, *vidx = nullptr, *vidx_s = nullptr, *nvis = nullptr,
+             *seg = nullptr, *vord = nullptr;
+    uint64_t *vkey = nullptr, *vkey_s = nullptr;
+    int64_t nvisits = 0;
     uint64_t *key1 = nullptr, *key1s = nullptr;
     uint32_t *idx1 = nullptr, *idx1s = nullptr, *key2 = nullptr, *key2s = nullptr;
     int32_t *srow = nullptr, *scol = nullptr;
@@ -349,7 +391,6 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
 
     CK(dalloc(&pl->row_start, p + 1));
     CK(dalloc(&pl->wck, p + 1));
-    CK(dalloc(&pl->nblk, p));
     CK(dalloc(&err, 1));
     CK(hipMemsetAsync(err, 0, sizeof(int32_t), st));
     CK(dalloc(&deg, m + 1));
@@ -426,18 +467,52 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
     (void)hipFree(idx1); idx1 = nullptr;
     (void)hipFree(idx1s); idx1s = nullptr;
 
-    // 5: blocks and their visit ordinals
-    CK(dalloc(&bfirst, nb2)); CK(dalloc(&bend, nb2)); CK(dalloc(&bvis, nb2));
+    // 5: blocks; visits of every item numbered in ring order
+    CK(dalloc(&bfirst, nb2)); CK(dalloc(&bend, nb2));
     CK(hipMemsetAsync(bfirst, 0, sizeof(int64_t) * nb2, st));
     CK(hipMemsetAsync(bend, 0, sizeof(int64_t) * nb2, st));
-    CK(hipMemsetAsync(bvis, 0, sizeof(int32_t) * nb2, st));
+    CK(dalloc(&nvis, n + 1));
+    CK(dalloc(&seg, n + 1));
+    CK(hipMemsetAsync(nvis, 0, sizeof(uint32_t) * (n + 1), st));
+    CK(dalloc(&is_start, nnz)); CK(dalloc(&vid, nnz));
     if (nnz > 0) {
         hipLaunchKernelGGL(k_block_bounds, dim3(grid_for(nnz)), dim3(kThreads), 0, st, key2s, nnz, bfirst,
                            bend);
         CK(hipGetLastError());
+        hipLaunchKernelGGL(k_visit_start, dim3(grid_for(nnz)), dim3(kThreads), 0, st, key2s, scol, nnz, is_start);
+        CK(hipGetLastError());
+        size_t need = 0;
+        CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, is_start, vid, nnz, st));
+        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, is_start, vid, nnz, st));
+        uint32_t h_last[2] = {0, 0};
+        CK(hipMemcpyAsync(&h_last[0], vid + nnz - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        CK(hipMemcpyAsync(&h_last[1], is_start + nnz - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        nvisits = (int64_t)h_last[0] + h_last[1];
     }
-    hipLaunchKernelGGL(k_tickets, dim3((p + 63) / 64), dim3(64), 0, st, bfirst, bend, p, bvis, pl->nblk);
-    CK(hipGetLastError());
+    CK(dalloc(&vkey, nvisits)); CK(dalloc(&vkey_s, nvisits));
+    CK(dalloc(&vidx, nvisits)); CK(dalloc(&vidx_s, nvisits)); CK(dalloc(&vord, nvisits));
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_visit_keys, dim3(grid_for(nnz)), dim3(kThreads), 0, st, is_start, vid, key2s, scol, nnz,
+                           p, vkey, vidx, nvis);
+        CK(hipGetLastError());
+        int eb = bits_for((uint64_t)n * (uint64_t)p);
+        size_t need = 0;
+        CK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, vkey, vkey_s, vidx, vidx_s, nvisits, 0, eb, st));
+        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
+        CK(hipcub::DeviceRadixSort::SortPairs(tmp, need, vkey, vkey_s, vidx, vidx_s, nvisits, 0, eb, st));
+        need = 0;
+        CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, nvis, seg, n + 1, st));
+        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, nvis, seg, n + 1, st));
+        hipLaunchKernelGGL(k_visit_ordinal, dim3(grid_for(nvisits)), dim3(kThreads), 0, st, vkey_s, vidx_s, seg,
+                           nvisits, p, vord);
+        CK(hipGetLastError());
+    }
+    pl->nvisits = nvisits;
+    CK(dalloc(&pl->nvis, n));
+    CK(hipMemcpyAsync(pl->nvis, nvis, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
 
     // 6: chunks, two passes
     CK(dalloc(&rowmap, m));
@@ -447,7 +522,7 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
     CK(hipMemsetAsync(sl_count, 0, sizeof(int64_t) * (p + 1), st));
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(m)), dim3(kThreads), 0, st, rowmap, m, -1);
     ca.srow = srow; ca.scol = scol; ca.sval = sval;
-    ca.bfirst = bfirst; ca.bend = bend; ca.bvis = bvis; ca.nblk = pl->nblk;
+    ca.bfirst = bfirst; ca.bend = bend; ca.vid = vid; ca.is_start = is_start; ca.vord = vord; ca.nvis = nvis;
     ca.p = p; ca.rmax = rmax; ca.tmax = tmax; ca.rowmap = rowmap;
     ca.ck_count = ck_count; ca.sl_count = sl_count;
     hipLaunchKernelGGL(k_chunker<false>, dim3((p + 63) / 64), dim3(64), 0, st, ca);
@@ -476,7 +551,9 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
     CK(hipStreamSynchronize(st));
 
 done:
-    (void)hipFree(deg); (void)hipFree(rowptr); (void)hipFree(bfirst); (void)hipFree(bend); (void)hipFree(bvis);
+    (void)hipFree(deg); (void)hipFree(rowptr); (void)hipFree(bfirst); (void)hipFree(bend);
+    (void)hipFree(is_start); (void)hipFree(vid); (void)hipFree(vidx); (void)hipFree(vidx_s); (void)hipFree(nvis);
+    (void)hipFree(seg); (void)hipFree(vord); (void)hipFree(vkey); (void)hipFree(vkey_s);
     (void)hipFree(ck_count); (void)hipFree(sl_count); (void)hipFree(ck_off); (void)hipFree(sl_off);
     (void)hipFree(err); (void)hipFree(rowmap); (void)hipFree(key1); (void)hipFree(key1s); (void)hipFree(idx1); (void)hipFree(idx1s);
     (void)hipFree(key2); (void)hipFree(key2s); (void)hipFree(srow); (void)hipFree(scol); (void)hipFree(sval); (void)hipFree(tmp);

@@ -151,21 +151,27 @@ def test_invalid_inputs():
     model.close()
 
 
-def test_trace_counts_every_block_visit():
+def test_trace_records_every_item_visit_and_replays():
+    """The visit trace lists every (worker, item) visit once per epoch with consecutive
+    per-item visit numbers; replaying it in the oracle reproduces the GPU factors."""
     prob, W0, H0, hp = make(600, 300, 12_000, k=16, seed=21)
     P, seed, E = 6, 17, 2
-    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [E], record_trace=True)
+    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [E], record_trace=True, rows_per_chunk=5,
+                          items_per_chunk=3)
     tr = model.trace()
     row, col = prob.row.numpy(), prob.col.numpy()
     rs = oracle.partition(prob.m, row, P)
     q_of = np.searchsorted(rs, row, "right") - 1
-    g_of = np.array([oracle.owner0(seed, j, P) for j in range(prob.n)])[col]
-    blocks = {(int(q), int(g)) for q, g in zip(q_of, g_of)}
-    assert len(tr) == E * len(blocks)
-    got = {(int(a), int(b)) for a, b in tr[:, :2]}
-    assert got == blocks
-    # every group's visits carry consecutive tickets, each epoch's t equal to the epoch
-    for g in range(P):
-        t = np.sort(tr[tr[:, 1] == g, 3])
+    visits = {(int(q), int(j)) for q, j in zip(q_of, col)}
+    assert len(tr) == E * len(visits)
+    assert {(int(a), int(b)) for a, b in tr[:, :2]} == visits
+    for j in np.unique(tr[:, 1]):
+        t = np.sort(tr[tr[:, 1] == j, 3])
         assert np.array_equal(t, np.arange(len(t)))
+    # replay: records of one worker in that worker's order (trace order within a worker)
+    order = np.argsort(tr[:, 0], kind="stable")
+    t2 = tr[order]
+    Wr, Hr, _ = oracle.replay(prob.m, prob.n, row, col, prob.val.numpy(), W0.numpy(), H0.numpy(), hp, P, seed,
+                              t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
+    assert rel(W, Wr) < 2 * TOL_1EPOCH and rel(H, Hr) < 2 * TOL_1EPOCH
     model.close()
