@@ -35,6 +35,50 @@ def bytes_per_update(k: int, s_w: int, s_h: int, n: int, nnz_train: int, p_ref: 
     return 12.0 + 2.0 * k * s_w + 2.0 * k * s_h * n * p_ref / nnz_train
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1312_0193_amd", "csrc", "train.hip")
+COUNTERS = os.path.join(ROOT, "profiles", "k_train_medium_counters.txt")
+COPY_BYTES = 2 << 30  # calibration copy: 2 GiB read + 2 GiB written per dispatch
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per training launch from the committed rocprofv3 counter summary, each
+    counter scaled by what it reads for a plain copy of known size; None when the
+    summary is missing or was taken on a different kernel source."""
+    if not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    for line in open(COUNTERS):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        fetch = float(kv["FETCH_SIZE_kib_per_dispatch"]) * float(kv["fetch_scale"])
+        write = float(kv["WRITE_SIZE_kib_per_dispatch"]) * float(kv["write_scale"])
+    except (KeyError, ValueError):
+        return None
+    return (fetch + write) * 1024.0
+
+
+def copy_calibrate(reps=3):
+    """A plain device copy of COPY_BYTES (the counter calibration kernel)."""
+    import torch
+
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "reps": reps}), flush=True)
+
+
 def cpu_baseline(prob, W0, H0, hp, P, seed, row_fraction=0.1):
     """The FP64 oracle on a bounded sample: the ratings of the first row_fraction of the
     rows (rows carry random Zipf weights, so this is a uniform row sample), one epoch of
@@ -68,7 +112,12 @@ def main():
     ap.add_argument("--rows-per-chunk", type=int, default=0)
     ap.add_argument("--items-per-chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibrate", action="store_true",
+                    help="run only the plain copy used to calibrate the HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calibrate:
+        copy_calibrate()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form is a "
               f"design, not a build", file=sys.stderr)
@@ -114,6 +163,7 @@ def main():
     B = bytes_per_update(hp["k"], 4, 4, prob.n, nnz)
     avg_kernel = sum(ksec) / len(ksec)
     achieved = B * nnz / avg_kernel
+    traffic = measured_traffic()
     out = {
         "metric": METRIC,
         "value": value,
@@ -130,9 +180,9 @@ def main():
         "config": {"workload": "medium: 480189x17770, 100M Zipf(1.1) cells, 1.4M held out, int 1-5 ratings, "
                                "k=100, lambda=0.05, ring schedule, FP32",
                    "global_batch": nnz, "workers": P, "test_rmse": rmse,
-                   "rows_per_chunk": model.cfg.rows_per_chunk, "items_per_chunk": model.cfg.items_per_chunk},
+                   "epochs_trained": args.warmup + args.steps, "kernel_source": kernel_source_hash()},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK, "traffic": None,
+                     "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "bytes_per_update": B, "kernel": "k_train", "avg_kernel_ms": avg_kernel * 1e3},
     }
     model.close()
