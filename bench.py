@@ -36,6 +36,7 @@ def bytes_per_update(k: int, s_w: int, s_h: int, n: int, nnz_train: int, p_ref: 
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1312_0193_amd", "csrc", "train.hip")
+KERNEL_NAME = "k_worker"
 COUNTERS = os.path.join(ROOT, "profiles", "k_train_medium_counters.txt")
 COPY_BYTES = 2 << 30  # calibration copy: 2 GiB read + 2 GiB written per dispatch
 
@@ -109,8 +110,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workers", type=int, default=0)
-    ap.add_argument("--rows-per-chunk", type=int, default=0)
-    ap.add_argument("--items-per-chunk", type=int, default=0)
+    ap.add_argument("--lds-slots", type=int, default=0)
+    ap.add_argument("--loads-per-chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="run only the plain copy used to calibrate the HBM byte counters")
@@ -140,7 +141,7 @@ def main():
     seed = 2
     model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp["k"], lam=hp["lam"],
                      alpha=hp["alpha"], beta=hp["beta"], gamma=hp["gamma"], workers=args.workers, seed=seed,
-                     rows_per_chunk=args.rows_per_chunk, items_per_chunk=args.items_per_chunk)
+                     lds_slots=args.lds_slots, loads_per_chunk=args.loads_per_chunk)
     P = model.workers
     st0 = model.train(0)
     log(f"layout {st0.layout_seconds:.3f} s, workers {P}")
@@ -183,7 +184,7 @@ def main():
                    "epochs_trained": args.warmup + args.steps, "kernel_source": kernel_source_hash()},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
-                     "bytes_per_update": B, "kernel": "k_train", "avg_kernel_ms": avg_kernel * 1e3},
+                     "bytes_per_update": B, "kernel": KERNEL_NAME, "avg_kernel_ms": avg_kernel * 1e3},
     }
     model.close()
     if not args.no_cpu_baseline:

@@ -8,9 +8,10 @@
  * ratings each (section 3.1 and its footnote); worker q owns and alone updates w_i for
  * i in I_q.  Every item vector h_j is owned by exactly one worker at a time and moves
  * between workers ("nomadic" variables, section 3.1, Algorithm 1), so no two concurrent
- * updates touch the same parameter.  Here a worker is one wavefront of a persistent
- * kernel on one GPU; it stages a few rows and items at a time in LDS and hands each
- * item on as soon as it is done with it.
+ * updates touch the same parameter.  Here a worker is one workgroup of a persistent
+ * kernel on one GPU: a compute wavefront runs the updates on rows and items held in
+ * LDS while a memory wavefront stages the next ones and hands each item on as soon as
+ * its visit ends.
  *
  * Conventions for every entry point
  *   - Returns a nomad_status; nothing aborts or throws across the ABI.  On failure the
@@ -68,8 +69,10 @@ typedef struct {
     int32_t dtype;      /* nomad_dtype */
     int32_t rounding;   /* nomad_round, used when dtype = NOMAD_BF16 */
     int32_t workers;    /* p, number of workers (wavefronts); 0 = library default */
-    int32_t rows_per_chunk;  /* max distinct rows staged at once by a worker; 0 = default */
-    int32_t items_per_chunk; /* max distinct items staged at once by a worker; 0 = default */
+    int32_t lds_slots;       /* rows and items a worker keeps in LDS (2..256); 0 = default */
+    int32_t loads_per_chunk; /* max vectors a worker loads for one chunk of <= 64 ratings
+                                (2..64, and at most what one staging round holds for k);
+                                0 = default */
     int32_t record_trace;    /* 1 = record every (worker, item) visit for replay */
     uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing */
 } nomad_config;
@@ -125,11 +128,16 @@ nomad_status nomad_get_partition(nomad_ctx *ctx, int32_t *p_out, int64_t *h_row_
  * (host). */
 nomad_status nomad_get_trace(nomad_ctx *ctx, int64_t *len, int32_t *h_buf, int64_t cap);
 
-/* Per-worker counters of the last nomad_train_epochs call: p rows of eight int64 in
- * h_stats (host, cap >= 8p): time in the kernel, time blocked acquiring an item group,
- * time waiting for the previous chunk's memory traffic, chunks processed, time in the
- * SGD updates, time issuing write-backs and prefetches, ratings processed, time staging
- * vectors into LDS.  Times are ticks of the device's 100 MHz constant clock. */
+/* Per-worker counters of the last nomad_train_epochs call: p rows of sixteen int64 in
+ * h_stats (host, cap >= 16p).  Times are ticks of the device's 100 MHz constant clock.
+ *   0 compute wave: time in the kernel          8 memory wave: time in the kernel
+ *   1 memory wave: waiting for items            9 memory wave: write-backs of evicted rows
+ *   2 memory wave: waiting for loads/stores       and LDS stores of staged chunks
+ *   3 chunks processed                         10 memory wave: passing on items
+ *   4 compute wave: SGD updates                11 memory wave: issuing prefetches and polls
+ *   5 memory wave: waiting for free LDS slots  12 vectors loaded
+ *   6 ratings processed                        13 vectors loaded without prefetch
+ *   7 compute wave: waiting for staged chunks  14, 15 zero */
 nomad_status nomad_get_worker_stats(nomad_ctx *ctx, int64_t *h_stats, int64_t cap);
 
 /* Free every resource of the context.  NULL is ignored. */

@@ -26,7 +26,7 @@ _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENOTIMPL"}
 class NomadConfig(C.Structure):
     _fields_ = [("k", C.c_int32), ("lambda_", C.c_float), ("alpha", C.c_float), ("beta", C.c_float),
                 ("gamma", C.c_float), ("sched", C.c_int32), ("dtype", C.c_int32), ("rounding", C.c_int32),
-                ("workers", C.c_int32), ("rows_per_chunk", C.c_int32), ("items_per_chunk", C.c_int32),
+                ("workers", C.c_int32), ("lds_slots", C.c_int32), ("loads_per_chunk", C.c_int32),
                 ("record_trace", C.c_int32), ("seed", C.c_uint64)]
 
 
@@ -126,13 +126,13 @@ class Stats:
 
 
 def make_config(k: int, lam: float, alpha: float, beta: float, gamma: float, *, sched="ring", dtype="fp32",
-                rounding="rne", workers=0, rows_per_chunk=0, items_per_chunk=0, record_trace=False,
+                rounding="rne", workers=0, lds_slots=0, loads_per_chunk=0, record_trace=False,
                 seed=0) -> NomadConfig:
     cfg = NomadConfig()
     load().nomad_config_default(C.byref(cfg))
     cfg.k, cfg.lambda_, cfg.alpha, cfg.beta, cfg.gamma = k, lam, alpha, beta, gamma
     cfg.sched, cfg.dtype, cfg.rounding = SCHED[sched], DTYPE[dtype], ROUND[rounding]
-    cfg.workers, cfg.rows_per_chunk, cfg.items_per_chunk = workers, rows_per_chunk, items_per_chunk
+    cfg.workers, cfg.lds_slots, cfg.loads_per_chunk = workers, lds_slots, loads_per_chunk
     cfg.record_trace = int(bool(record_trace))
     cfg.seed = seed
     return cfg
@@ -210,12 +210,11 @@ class Nomad:
         return buf
 
     def worker_stats(self):
-        """(p, 8) int64 per worker for the last train() call, 100 MHz ticks unless a count:
-        kernel, blocked on groups, waiting on memory, chunks, updates, issuing memory
-        traffic, ratings, staging into LDS."""
+        """(p, 16) int64 per worker for the last train() call, 100 MHz ticks unless a count
+        (columns as listed in include/nomad.h)."""
         import numpy as np
         p = self.workers
-        buf = np.zeros((p, 8), dtype=np.int64)
+        buf = np.zeros((p, 16), dtype=np.int64)
         _check(load().nomad_get_worker_stats(self._c(), buf.ctypes.data_as(C.c_void_p), buf.size), self.ctx)
         return buf
 

@@ -22,7 +22,8 @@ struct nomad_ctx {
     uint32_t *tok_done = nullptr;      // n item counters + 1 abort word
     int64_t epochs_done = 0;
     std::vector<int64_t> row_start;
-    int64_t *wstats = nullptr;         // p x 4 per-worker counters of the last call
+    int64_t max_worker_chunks = 0;
+    int64_t *wstats = nullptr;         // p x kWStatCount per-worker counters of the last call
     int32_t *trace = nullptr;
     int64_t *trace_len = nullptr;
     int64_t trace_cap = 0;
@@ -94,8 +95,8 @@ void nomad_config_default(nomad_config *cfg) {
     cfg->dtype = NOMAD_FP32;
     cfg->rounding = NOMAD_ROUND_RNE;
     cfg->workers = 0;
-    cfg->rows_per_chunk = 0;
-    cfg->items_per_chunk = 0;
+    cfg->lds_slots = 0;
+    cfg->loads_per_chunk = 0;
     cfg->record_trace = 0;
     cfg->seed = 0;
 }
@@ -144,42 +145,40 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
         return st;
     };
 
-    // chunk capacity: rows + items <= 64 slots, LDS for two buffers within ~40 KB
-    // Chunk capacity: rows + items <= 64 slots and within the register staging of the
-    // worker kernel; by default 32 rows and 16 items, fewer for large k.
-    int32_t rmax = cfg->rows_per_chunk, tmax = cfg->items_per_chunk;
-    const int32_t vec_per_step = 64 / (c->kp / 4);  // vectors one staging step moves
-    if (rmax <= 0) rmax = std::min(32, vec_per_step * nomad::kRowPiecesPerLane);
-    if (tmax <= 0) tmax = std::min(16, vec_per_step * nomad::kItemPiecesPerLane);
-    if (rmax < 1 || tmax < 1 || !nomad::train_chunk_fits(c->kp, rmax, tmax)) {
-        nomad_status st = fail(c, NOMAD_EINVAL, "nomad_init: rows_per_chunk=%d items_per_chunk=%d: need >= 1 each, "
-                               "sum <= %d, rows <= %d and items <= %d for k=%d", rmax, tmax, nomad::kMaxSlots,
-                               vec_per_step * nomad::kRowPiecesPerLane, vec_per_step * nomad::kItemPiecesPerLane,
-                               c->k);
+    // LDS slots per worker and loads per chunk.  By default a worker's vectors take about
+    // 32 KB of LDS (four workers per CU) and a chunk loads as much as one staging round of
+    // the memory wave holds.
+    const int32_t cap = nomad::max_loads_per_chunk(c->kp);
+    int32_t slots = cfg->lds_slots, loads = cfg->loads_per_chunk;
+    if (slots <= 0) slots = std::min(nomad::kMaxSlots, std::max(8, (int32_t)(32768 / (c->kp * 4))));
+    if (loads <= 0) loads = std::min(cap, std::max(2, slots / 3));
+    if (slots < 2 || slots > nomad::kMaxSlots || loads < 2 || loads > cap || loads > slots) {
+        nomad_status st = fail(c, NOMAD_EINVAL, "nomad_init: lds_slots=%d loads_per_chunk=%d: need 2 <= slots <= %d "
+                               "and 2 <= loads <= min(slots, %d) for k=%d", slots, loads, nomad::kMaxSlots, cap, c->k);
         return bail(st);
     }
     int dev = 0, max_lds = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
         return bail(fail(c, NOMAD_EDEVICE, "nomad_init: no usable HIP device"));
-    const size_t lds = nomad::train_lds_bytes(c->kp, rmax, tmax);
+    const size_t lds = nomad::train_lds_bytes(c->kp, slots);
     if (lds > (size_t)max_lds)
-        return bail(fail(c, NOMAD_EINVAL, "nomad_init: chunk staging needs %zu bytes of LDS, device allows %d",
-                         lds, max_lds));
+        return bail(fail(c, NOMAD_EINVAL, "nomad_init: %d LDS slots need %zu bytes of LDS, device allows %d",
+                         slots, lds, max_lds));
     int32_t maxw = 0;
-    hipError_t he = nomad::train_max_workers(c->kp, rmax, tmax, &maxw);
+    hipError_t he = nomad::train_max_workers(c->kp, slots, &maxw);
     if (he != hipSuccess) return bail(hip_fail(c, he, "nomad_init: occupancy query"));
     int32_t p = cfg->workers;
-    if (p <= 0) p = maxw < 2048 ? maxw : 2048;
+    if (p <= 0) p = maxw < 1024 ? maxw : 1024;
     if (p < 1 || p > 4096)
         return bail(fail(c, NOMAD_EINVAL, "nomad_init: workers=%d outside [1,4096]", p));
     if (p > maxw)
         return bail(fail(c, NOMAD_EDEVICE, "nomad_init: %d workers cannot all be resident (device holds %d "
-                         "with this chunk size)", p, maxw));
+                         "with %d LDS slots)", p, maxw, slots));
     c->p = p;
     c->cfg.workers = p;
-    c->cfg.rows_per_chunk = rmax;
-    c->cfg.items_per_chunk = tmax;
+    c->cfg.lds_slots = slots;
+    c->cfg.loads_per_chunk = loads;
 
     hipError_t e;
     if ((e = hipMalloc(&c->W, sizeof(float) * (size_t)m * c->kp)) != hipSuccess)
@@ -209,7 +208,7 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     if ((e = hipEventRecord(c->ev0, st)) != hipSuccess) return bail(hip_fail(c, e, "nomad_init: event"));
     int code = 0;
     char msg[256] = {0};
-    e = nomad::build_plan(&c->plan, m, n, nnz, d_row, d_col, d_val, p, c->kp, rmax, tmax, cfg->seed, st, &code,
+    e = nomad::build_plan(&c->plan, m, n, nnz, d_row, d_col, d_val, p, c->kp, slots, loads, cfg->seed, st, &code,
                           msg, sizeof(msg));
     if (e != hipSuccess) return bail(hip_fail(c, e, "nomad_init: layout"));
     if (code != 0) return bail(fail(c, NOMAD_EINVAL, "nomad_init: %s", msg));
@@ -222,6 +221,12 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     if ((e = hipMemcpy(c->row_start.data(), c->plan.row_start, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost)) !=
         hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: partition copy"));
+    {
+        std::vector<int64_t> wck(p + 1);
+        if ((e = hipMemcpy(wck.data(), c->plan.wck, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost)) != hipSuccess)
+            return bail(hip_fail(c, e, "nomad_init: plan copy"));
+        for (int32_t q = 0; q < p; ++q) c->max_worker_chunks = std::max(c->max_worker_chunks, wck[q + 1] - wck[q]);
+    }
     *out = c;
     return NOMAD_OK;
 }
@@ -231,6 +236,9 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
     if (epochs < 0) return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epochs=%d < 0", epochs);
     if (c->epochs_done + epochs > (int64_t)INT32_MAX / 2)
         return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epoch counter would overflow");
+    if ((int64_t)epochs * c->max_worker_chunks >= (int64_t)INT32_MAX)
+        return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epochs=%d too many for one call (%lld chunks per epoch "
+                    "on the busiest worker)", epochs, (long long)c->max_worker_chunks);
     if (out) memset(out, 0, sizeof(*out));
     hipStream_t st = c->stream;
     double seconds = 0.0;
@@ -242,12 +250,11 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         a.H = c->H;
         a.wck = c->plan.wck;
         a.chunks = c->plan.chunks;
-        a.slots = c->plan.slots;
+        a.events = c->plan.events;
         a.ratings = c->plan.ratings;
         a.tok_done = c->tok_done;
         a.kp = c->kp;
-        a.rmax = c->plan.rmax;
-        a.tmax = c->plan.tmax;
+        a.slots = c->plan.slots;
         a.epoch0 = (int32_t)c->epochs_done;
         a.epochs = epochs;
         a.lambda = c->cfg.lambda;
@@ -255,7 +262,7 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         a.beta = c->cfg.beta;
         a.gamma = c->cfg.gamma;
         if (c->cfg.record_trace) {
-            const int64_t need = c->plan.nslots * (int64_t)epochs;
+            const int64_t need = c->plan.nvisits * (int64_t)epochs;
             if (need > c->trace_cap) {
                 (void)hipFree(c->trace);
                 c->trace = nullptr;

@@ -9,8 +9,8 @@
 //      is rejected (Omega is a set);
 //   5. number the visits of every item (its runs of ratings at one worker) in ring order,
 //      i.e. by sub-step s, and count each item's visits per epoch;
-//   6. cut each worker's ratings into chunks (see nomad_internal.h) in two passes: count,
-//      then fill; finally link the last chunk of an epoch with the first one of the next.
+//   6. plan each worker's chunks and LDS slots (planner.h) in two passes: count, then
+//      fill.
 #include <hipcub/hipcub.hpp>
 
 #include <cstdio>
@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "nomad_internal.h"
+#include "planner.h"
 
 namespace nomad {
 namespace {
@@ -107,16 +108,6 @@ __global__ void k_gather(const uint32_t *idx, const int32_t *row, const int32_t 
     }
 }
 
-// Block boundaries from the sorted (q, s) keys: blocks are [bfirst[b], bend[b]).
-__global__ void k_block_bounds(const uint32_t *key, int64_t nnz, int64_t *bfirst, int64_t *bend) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t b = key[e];
-        if (e == 0 || key[e - 1] != b) bfirst[b] = e;
-        if (e == nnz - 1 || key[e + 1] != b) bend[b] = e + 1;
-    }
-}
-
 // Visits: maximal runs of one (worker, item) in the (q, s, j, i) order.
 __global__ void k_visit_start(const uint32_t *key2, const int32_t *scol, int64_t nnz, uint32_t *is_start) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
@@ -150,177 +141,39 @@ __global__ void k_visit_ordinal(const uint64_t *vkey_sorted, const uint32_t *vid
     }
 }
 
-struct ChunkerArgs {
-    const int32_t *srow, *scol;
-    const float *sval;
-    const int64_t *bfirst, *bend;
-    const uint32_t *vid;   // exclusive count of visit starts before each rating
-    const uint32_t *is_start;
-    const uint32_t *vord;  // visit ordinal within its item, per visit id
-    const uint32_t *nvis;  // visits per epoch of each item
-    int32_t p, rmax, tmax;
-    int32_t *rowmap;       // m entries, -1 initially: (chunk << 8) | slot of the row's last chunk
-    int64_t *ck_count;     // pass 1 output: chunks per worker
-    int64_t *sl_count;     // pass 1 output: slots per worker
-    const int64_t *ck_off; // pass 2 input: first chunk of each worker
-    const int64_t *sl_off; // pass 2 input: first slot of each worker
-    ChunkRec *chunks;      // pass 2 output
-    SlotRec *slots;
-    RatingRec *ratings;
-};
+// Per-rating visit information for the planner: v | nvis << 16 (the visit's ordinal
+// among the item's visits in one epoch of the ring order, and the item's visits per epoch).
+__global__ void k_vinfo(const uint32_t *vid, const uint32_t *is_start, const uint32_t *vord, const uint32_t *nvis,
+                        const int32_t *scol, int64_t nnz, uint32_t *vinfo) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        vinfo[e] = vord[vid[e] + is_start[e] - 1u] | (nvis[scol[e]] << 16);
+}
 
-// One thread per worker walks its ratings in processing order and cuts chunks.  A row
-// (item) that the next chunk uses again stays in LDS at the same physical slot; the
-// other rows and items of a chunk take free physical slots, so a worker needs a single
-// staging buffer and never copies within LDS.  Chunks do not carry anything across an
-// epoch boundary.
-template <bool kFill>
-__global__ void k_chunker(ChunkerArgs a) {
+// First rating of each worker in the (q, s, j, i) order: rowptr at its first row.
+__global__ void k_worker_first(const int64_t *rowptr, const int64_t *row_start, int32_t p, int64_t *wfirst) {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.p) return;
-    const int32_t p = a.p;
-    int32_t rid[kMaxSlots], rphys[kMaxSlots], prev_rphys[kMaxSlots];
-    int32_t tid[kMaxSlots], tphys[kMaxSlots], tv[kMaxSlots];
-    uint8_t rcar[kMaxSlots], tcar[kMaxSlots];
-    uint8_t lrs[kMaxRatingsPerChunk], lts[kMaxRatingsPerChunk];
-    int64_t c = 0;                   // local index of the open chunk
-    const int64_t ck_base = kFill ? a.ck_off[q] : 0;
-    int64_t sl_pos = kFill ? a.sl_off[q] : 0;  // next free slot record (global)
-    int64_t nslots_local = 0;
-    int64_t prev_slot_base = -1;     // slot records of the previous chunk (global index)
-    int32_t prev_nr = 0;
-    int32_t prev_last_tok = -1, prev_last_tok_slot = -1, prev_last_tok_phys = -1;
-    bool prev_same_block = false;
-    int32_t nr = 0, nt = 0, nrat = 0;
-    int64_t rat0 = 0;
-    uint32_t flags = 0;
-    int32_t g = 0;
-    int32_t cur_tok = -1;
+    if (q <= p) wfirst[q] = rowptr[row_start[q]];
+}
 
-    auto assign = [](int32_t *phys, const uint8_t *car, int32_t count) {
-        uint64_t used = 0;
-        for (int32_t x = 0; x < count; ++x)
-            if (car[x]) used |= 1ull << phys[x];
-        for (int32_t x = 0; x < count; ++x) {
-            if (car[x]) continue;
-            const int32_t slot = __builtin_ctzll(~used);
-            phys[x] = slot;
-            used |= 1ull << slot;
-        }
-    };
-    auto close_chunk = [&](bool last_of_block) {
-        const uint32_t f = flags | (last_of_block ? kLastOfBlock : 0u);
-        assign(rphys, rcar, nr);
-        assign(tphys, tcar, nt);
-        if (kFill) {
-            ChunkRec r;
-            r.rat = rat0;
-            r.slot = sl_pos;
-            r.info = (uint32_t)nrat | ((uint32_t)nr << 8) | ((uint32_t)nt << 16) | (f << 24);
-            r.group = g;
-            r.pad0 = r.pad1 = 0;
-            a.chunks[ck_base + c] = r;
-            for (int32_t x = 0; x < nr; ++x) {
-                SlotRec s;
-                s.id = rid[x];
-                s.phys = (int16_t)rphys[x];
-                s.flags = rcar[x] ? 0 : kSlotNew;
-                s.v = 0;
-                s.nvis = 0;
-                a.slots[sl_pos + x] = s;
-            }
-            for (int32_t x = 0; x < nt; ++x) {
-                SlotRec s;
-                s.id = tid[x];
-                s.phys = (int16_t)tphys[x];
-                s.flags = tcar[x] ? 0 : kSlotNew;
-                s.v = tv[x];
-                s.nvis = (int32_t)a.nvis[tid[x]];
-                a.slots[sl_pos + nr + x] = s;
-            }
-            for (int32_t x = 0; x < nrat; ++x) {
-                RatingRec rr;
-                rr.slots = (uint32_t)rphys[lrs[x]] | ((uint32_t)tphys[lts[x]] << 8);
-                rr.r = a.sval[rat0 + x];
-                a.ratings[rat0 + x] = rr;
-            }
-        }
-        for (int32_t x = 0; x < nr; ++x) prev_rphys[x] = rphys[x];
-        prev_slot_base = sl_pos;
-        prev_nr = nr;
-        prev_last_tok = nt > 0 ? tid[nt - 1] : -1;
-        prev_last_tok_slot = nt - 1;
-        prev_last_tok_phys = nt > 0 ? tphys[nt - 1] : -1;
-        prev_same_block = !last_of_block;
-        sl_pos += nr + nt;
-        nslots_local += nr + nt;
-        ++c;
-    };
-    auto open_chunk = [&](int64_t first_rating, uint32_t f) {
-        nr = nt = nrat = 0;
-        rat0 = first_rating;
-        flags = f;
-        cur_tok = -1;
-    };
-
-    for (int32_t s = 0; s < p; ++s) {
-        const int64_t b = (int64_t)q * p + s;
-        const int64_t f0 = a.bfirst[b], f1 = a.bend[b];
-        if (f1 <= f0) continue;
-        g = (q + s) % p;
-        prev_same_block = false;  // a new block never carries items
-        open_chunk(f0, kFirstOfBlock);
-        for (int64_t e = f0; e < f1; ++e) {
-            const int32_t i = a.srow[e], j = a.scol[e];
-            int32_t v = a.rowmap[i];
-            bool row_in = v >= 0 && (int64_t)(v >> 8) == c;
-            bool tok_new = nt == 0 || j != cur_tok;
-            if (nrat == kMaxRatingsPerChunk || (tok_new && nt == a.tmax) || (!row_in && nr == a.rmax)) {
-                close_chunk(false);
-                open_chunk(e, 0u);
-                row_in = false;
-                tok_new = true;
-            }
-            int32_t ts;
-            if (tok_new) {
-                ts = nt++;
-                tid[ts] = j;
-                tcar[ts] = 0;
-                tphys[ts] = -1;
-                tv[ts] = kFill ? (int32_t)a.vord[a.vid[e] + a.is_start[e] - 1u] : 0;
-                if (prev_same_block && nrat == 0 && j == prev_last_tok) {
-                    tcar[ts] = 1;
-                    tphys[ts] = prev_last_tok_phys;
-                    if (kFill) a.slots[prev_slot_base + prev_nr + prev_last_tok_slot].flags |= kSlotKeep;
-                }
-                cur_tok = j;
-            } else {
-                ts = nt - 1;
-            }
-            int32_t rs;
-            if (!row_in) {
-                rs = nr++;
-                rid[rs] = i;
-                rcar[rs] = 0;
-                rphys[rs] = -1;
-                if (v >= 0 && c > 0 && (int64_t)(v >> 8) == c - 1) {
-                    rcar[rs] = 1;
-                    rphys[rs] = prev_rphys[v & 255];
-                    if (kFill) a.slots[prev_slot_base + (v & 255)].flags |= kSlotKeep;
-                }
-                a.rowmap[i] = (int32_t)((c << 8) | rs);
-            } else {
-                rs = v & 255;
-            }
-            lrs[nrat] = (uint8_t)rs;
-            lts[nrat] = (uint8_t)ts;
-            ++nrat;
-        }
-        close_chunk(true);
+// One thread per worker runs the planner (planner.h): count pass, then fill pass.
+template <bool kFill>
+__global__ void k_planner(PlanIn in, const int64_t *wfirst, PlanOut base, const int64_t *ck_off,
+                          const int64_t *ev_off, int64_t *ck_count, int64_t *ev_count, int64_t *ld_count,
+                          int32_t *err, int32_t p) {
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= p) return;
+    PlanOut o = base;
+    if (kFill) {
+        o.ck0 = ck_off[q];
+        o.ev0 = ev_off[q];
     }
+    const PlanCount r = plan_worker<kFill>(in, wfirst[q], wfirst[q + 1], o);
+    if (r.status) atomicOr(err, 4);
     if (!kFill) {
-        a.ck_count[q] = c;
-        a.sl_count[q] = nslots_local;
+        ck_count[q] = r.chunks;
+        ev_count[q] = r.events;
+        ld_count[q] = r.loads;
     }
 }
 
@@ -349,9 +202,8 @@ void free_plan(Plan *pl) {
     (void)hipFree(pl->row_start);
     (void)hipFree(pl->wck);
     (void)hipFree(pl->chunks);
-    (void)hipFree(pl->slots);
+    (void)hipFree(pl->events);
     (void)hipFree(pl->ratings);
-    (void)hipFree(pl->nvis);
     *pl = Plan();
 }
 
@@ -362,18 +214,20 @@ void free_plan(Plan *pl) {
     } while (0)
 
 hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t *d_row,
-                      const int32_t *d_col, const float *d_val, int32_t p, int32_t kp, int32_t rmax,
-                      int32_t tmax, uint64_t seed, hipStream_t st, int *err_code, char *msg,
+                      const int32_t *d_col, const float *d_val, int32_t p, int32_t kp, int32_t slots,
+                      int32_t loads, uint64_t seed, hipStream_t st, int *err_code, char *msg,
                       size_t msg_len) {
     hipError_t rc = hipSuccess;
     *err_code = 0;
     *pl = Plan();
-    pl->m = m; pl->n = n; pl->nnz = nnz; pl->p = p; pl->kp = kp; pl->rmax = rmax; pl->tmax = tmax;
+    pl->m = m; pl->n = n; pl->nnz = nnz; pl->p = p; pl->kp = kp; pl->slots = slots; pl->loads = loads;
 
     unsigned long long *deg = nullptr;
-    int64_t *rowptr = nullptr, *bfirst = nullptr, *bend = nullptr;
-    int64_t *ck_count = nullptr, *sl_count = nullptr, *ck_off = nullptr, *sl_off = nullptr;
-    int32_t *err = nullptr, *rowmap = nullptr;
+    int64_t *rowptr = nullptr;
+    int64_t *ck_count = nullptr, *ev_count = nullptr, *ld_count = nullptr, *ck_off = nullptr, *ev_off = nullptr;
+    int64_t *wfirst = nullptr;
+    int32_t *err = nullptr, *rowmap = nullptr, *nxt = nullptr;
+    uint32_t *vinfo = nullptr;
     uint32_t *is_start = nullptr, *vid = nullptr, *vidx = nullptr, *vidx_s = nullptr, *nvis = nullptr,
              *seg = nullptr, *vord = nullptr;
     uint64_t *vkey = nullptr, *vkey_s = nullptr;
@@ -386,8 +240,9 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
     size_t tmp_bytes = 0;
     int32_t h_err = 0;
     const int64_t nb2 = (int64_t)p * p;
-    ChunkerArgs ca{};
-    int64_t h_tot[2] = {0, 0};
+    PlanIn pin{};
+    PlanOut pout{};
+    int64_t h_tot[3] = {0, 0, 0};
 
     CK(dalloc(&pl->row_start, p + 1));
     CK(dalloc(&pl->wck, p + 1));
@@ -467,18 +322,12 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
     (void)hipFree(idx1); idx1 = nullptr;
     (void)hipFree(idx1s); idx1s = nullptr;
 
-    // 5: blocks; visits of every item numbered in ring order
-    CK(dalloc(&bfirst, nb2)); CK(dalloc(&bend, nb2));
-    CK(hipMemsetAsync(bfirst, 0, sizeof(int64_t) * nb2, st));
-    CK(hipMemsetAsync(bend, 0, sizeof(int64_t) * nb2, st));
+    // 5: visits of every item numbered in ring order
     CK(dalloc(&nvis, n + 1));
     CK(dalloc(&seg, n + 1));
     CK(hipMemsetAsync(nvis, 0, sizeof(uint32_t) * (n + 1), st));
     CK(dalloc(&is_start, nnz)); CK(dalloc(&vid, nnz));
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_block_bounds, dim3(grid_for(nnz)), dim3(kThreads), 0, st, key2s, nnz, bfirst,
-                           bend);
-        CK(hipGetLastError());
         hipLaunchKernelGGL(k_visit_start, dim3(grid_for(nnz)), dim3(kThreads), 0, st, key2s, scol, nnz, is_start);
         CK(hipGetLastError());
         size_t need = 0;
@@ -511,50 +360,71 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
         CK(hipGetLastError());
     }
     pl->nvisits = nvisits;
-    CK(dalloc(&pl->nvis, n));
-    CK(hipMemcpyAsync(pl->nvis, nvis, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, st));
 
-    // 6: chunks, two passes
+    // 6: per-worker plans, two passes
+    CK(dalloc(&vinfo, nnz));
+    CK(dalloc(&nxt, nnz));
     CK(dalloc(&rowmap, m));
-    CK(dalloc(&ck_count, p + 1)); CK(dalloc(&sl_count, p + 1));
-    CK(dalloc(&ck_off, p + 1)); CK(dalloc(&sl_off, p + 1));
+    CK(dalloc(&wfirst, p + 1));
+    CK(dalloc(&ck_count, p + 1)); CK(dalloc(&ev_count, p + 1)); CK(dalloc(&ld_count, p + 1));
+    CK(dalloc(&ck_off, p + 1)); CK(dalloc(&ev_off, p + 1));
     CK(hipMemsetAsync(ck_count, 0, sizeof(int64_t) * (p + 1), st));
-    CK(hipMemsetAsync(sl_count, 0, sizeof(int64_t) * (p + 1), st));
+    CK(hipMemsetAsync(ev_count, 0, sizeof(int64_t) * (p + 1), st));
+    CK(hipMemsetAsync(ld_count, 0, sizeof(int64_t) * (p + 1), st));
     hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(m)), dim3(kThreads), 0, st, rowmap, m, -1);
-    ca.srow = srow; ca.scol = scol; ca.sval = sval;
-    ca.bfirst = bfirst; ca.bend = bend; ca.vid = vid; ca.is_start = is_start; ca.vord = vord; ca.nvis = nvis;
-    ca.p = p; ca.rmax = rmax; ca.tmax = tmax; ca.rowmap = rowmap;
-    ca.ck_count = ck_count; ca.sl_count = sl_count;
-    hipLaunchKernelGGL(k_chunker<false>, dim3((p + 63) / 64), dim3(64), 0, st, ca);
+    hipLaunchKernelGGL(k_worker_first, dim3((p + 1 + 63) / 64), dim3(64), 0, st, rowptr, pl->row_start, p, wfirst);
+    CK(hipGetLastError());
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_vinfo, dim3(grid_for(nnz)), dim3(kThreads), 0, st, vid, is_start, vord, nvis, scol, nnz,
+                           vinfo);
+        CK(hipGetLastError());
+    }
+    pin.srow = srow; pin.scol = scol; pin.sval = sval; pin.blk = key2s; pin.vinfo = vinfo;
+    pin.slots = slots; pin.cap = loads; pin.look = kLookahead; pin.nxt = nxt; pin.rowmap = rowmap;
+    hipLaunchKernelGGL(k_planner<false>, dim3((p + 63) / 64), dim3(64), 0, st, pin, wfirst, pout, ck_off, ev_off,
+                       ck_count, ev_count, ld_count, err, p);
     CK(hipGetLastError());
     {
         size_t need = 0;
         CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, ck_count, ck_off, p + 1, st));
         if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
         CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, ck_count, ck_off, p + 1, st));
-        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, sl_count, sl_off, p + 1, st));
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, ev_count, ev_off, p + 1, st));
     }
     CK(hipMemcpyAsync(&h_tot[0], ck_off + p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    CK(hipMemcpyAsync(&h_tot[1], sl_off + p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&h_tot[1], ev_off + p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
+    if (h_err & 4) {
+        *err_code = 1;
+        snprintf(msg, msg_len, "%d LDS slots per worker are too few", slots);
+        goto done;
+    }
+    {
+        std::vector<int64_t> lc(p + 1);
+        CK(hipMemcpy(lc.data(), ld_count, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost));
+        int64_t t = 0;
+        for (int32_t q = 0; q < p; ++q) t += lc[q];
+        pl->nloads = t;
+    }
     pl->nchunks = h_tot[0];
-    pl->nslots = h_tot[1];
+    pl->nevents = h_tot[1];
     CK(dalloc(&pl->chunks, pl->nchunks));
-    CK(dalloc(&pl->slots, pl->nslots));
+    CK(dalloc(&pl->events, pl->nevents));
     CK(dalloc(&pl->ratings, nnz));
     CK(hipMemcpyAsync(pl->wck, ck_off, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToDevice, st));
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(m)), dim3(kThreads), 0, st, rowmap, m, -1);
-    ca.ck_off = ck_off; ca.sl_off = sl_off;
-    ca.chunks = pl->chunks; ca.slots = pl->slots; ca.ratings = pl->ratings;
-    hipLaunchKernelGGL(k_chunker<true>, dim3((p + 63) / 64), dim3(64), 0, st, ca);
+    pout.chunks = pl->chunks; pout.events = pl->events; pout.ratings = pl->ratings;
+    hipLaunchKernelGGL(k_planner<true>, dim3((p + 63) / 64), dim3(64), 0, st, pin, wfirst, pout, ck_off, ev_off,
+                       ck_count, ev_count, ld_count, err, p);
     CK(hipGetLastError());
     CK(hipStreamSynchronize(st));
 
 done:
-    (void)hipFree(deg); (void)hipFree(rowptr); (void)hipFree(bfirst); (void)hipFree(bend);
+    (void)hipFree(deg); (void)hipFree(rowptr);
     (void)hipFree(is_start); (void)hipFree(vid); (void)hipFree(vidx); (void)hipFree(vidx_s); (void)hipFree(nvis);
     (void)hipFree(seg); (void)hipFree(vord); (void)hipFree(vkey); (void)hipFree(vkey_s);
-    (void)hipFree(ck_count); (void)hipFree(sl_count); (void)hipFree(ck_off); (void)hipFree(sl_off);
+    (void)hipFree(ck_count); (void)hipFree(ev_count); (void)hipFree(ld_count); (void)hipFree(ck_off);
+    (void)hipFree(ev_off); (void)hipFree(wfirst); (void)hipFree(vinfo); (void)hipFree(nxt);
     (void)hipFree(err); (void)hipFree(rowmap); (void)hipFree(key1); (void)hipFree(key1s); (void)hipFree(idx1); (void)hipFree(idx1s);
     (void)hipFree(key2); (void)hipFree(key2s); (void)hipFree(srow); (void)hipFree(scol); (void)hipFree(sval); (void)hipFree(tmp);
     if (rc != hipSuccess || *err_code != 0) free_plan(pl);

@@ -1,37 +1,39 @@
-// NOMAD worker kernel: one wavefront = one worker (Algorithm 1), persistent for a whole
-// nomad_train_epochs call.
+// NOMAD worker kernel: one workgroup = one worker (Algorithm 1), persistent for a whole
+// nomad_train_epochs call.  The workgroup has two wavefronts:
 //
-// Worker q walks its chunks in plan order, epoch after epoch.  Before a chunk uses an
-// item h_j that it does not carry over from the previous chunk, it waits until item j
-// has finished every earlier visit in the ring order (a per-item counter of finished
-// visits reaches this visit's ticket), which makes worker q the sole owner of h_j
-// (owner-computes rule, section 3.1).  The chunk's rows w_i and items h_j are staged in
-// LDS, the SGD updates of section 2.3 run over the chunk's ratings in plan order on LDS,
-// and an item leaving LDS is written back and passed on by advancing its counter.
+//   compute wave   runs the SGD updates of section 2.3 over each chunk's ratings in plan
+//                  order, on vectors held in LDS, and counts finished chunks ("done");
+//   memory wave    stages chunks ahead of it ("staged"): once the compute wave has freed a
+//                  chunk's slots it writes back the rows the chunk evicts and loads rows
+//                  w_i and items h_j straight into their LDS slots (LDS-DMA loads), copies
+//                  the chunk's rating records into a small LDS ring, and after the compute
+//                  wave has finished a chunk passes on the items whose visit ended there.
 //
-// Software pipeline (per iteration x, one chunk; one LDS staging area per worker):
-//   top    wait for the memory traffic issued in iteration x-1; pass on the items chunk
-//          x-1 finished with (written back right after its updates); write back chunk
-//          x-1's rows that chunk x does not keep in their LDS slots; write chunk x's
-//          prefetched vectors (registers) into their LDS slots.  If some of chunk x was
-//          not prefetched (an item not yet free when polled, or the first chunk of an
-//          epoch), wait for its items and load what is missing;
-//   issue  prefetch chunk x+1 into registers (rows; its new items too when they were
-//          seen free), records of chunk x+3, ratings of chunk x+2, and poll the counters
-//          of the items chunk x+2 takes over;
-//   sgd    the updates of chunk x on LDS, no global memory access; then the items the
-//          next chunk does not keep are written back (device-coherent) so that the next
-//          top can pass them on.
-// A worker that blocks has already passed on every item it finished with, which keeps
-// the ring order free of waiting cycles.
+// Owner-computes rule (section 3.1): before the memory wave loads an item for a visit it
+// waits until the item has finished every earlier visit in the ring order (a per-item
+// counter of finished visits reaches the visit's ticket), so worker q is the sole owner
+// of h_j while the visit lasts.  When the visit ends the item is written back and the
+// counter advanced.  Rows w_i are owned by the worker for good.
+//
+// Memory-wave pipeline, iteration x (chunk x):
+//   wait for the loads and stores of iteration x-1; pass on items whose write-back
+//   completed; load what was not loaded ahead (items that were not yet free when polled,
+//   or the first chunk of an epoch); publish chunk x to the compute wave; retire the
+//   chunks the compute wave has finished; wait until the compute wave has finished every
+//   chunk that used the slots chunk x+1 overwrites, write back the rows chunk x+1 evicts
+//   and issue its loads; poll the items of chunk x+2, read the events of chunk x+3 and
+//   the record of chunk x+4.
+// Every wait of the memory wave keeps passing on finished items, so a worker never holds
+// an item that another worker waits for while it waits itself (no cycles in the ring
+// order), and every wait is bounded in time.
 //
 // Memory ordering of a hand-off: item vectors are written with device-coherent stores
-// (agent scope, sc1) and the counter is advanced with a device-coherent store only after
+// (agent scope) and the counter is advanced with a device-coherent store only after
 // "s_waitcnt vmcnt(0)" has seen those stores complete; the next owner polls the counter
-// with device-coherent loads and reads the item with device-coherent loads.  Rows w_i
-// are private to their worker (always the same wavefront, hence the same CU and XCD) and
-// use ordinary cached loads and stores; a wavefront's own accesses to one address are
-// performed in program order.
+// with device-coherent loads and reads the item with device-coherent loads.  Rows use
+// ordinary loads and stores from the same wavefront, whose accesses to one address are
+// performed in program order.  The two wavefronts of a worker synchronise through LDS
+// words written after "s_waitcnt lgkmcnt(0)".
 #include <cmath>
 #include <utility>
 
@@ -76,62 +78,9 @@ __device__ __forceinline__ void lds_write(float *p, const float (&v)[VEC]) {
     if constexpr (VEC == 4) { *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]); }
 }
 
-
-
 // Seconds-scale bound on any single wait, so that a broken schedule ends the kernel
 // instead of hanging the device (100 MHz constant clock).
 constexpr uint64_t kWaitLimitTicks = 20ull * 100000000ull;
-
-// Slot records of one chunk, one per lane (rows first, then items): global id,
-// phys | flags << 16, and for items the visit ordinal and visits per epoch.
-struct Recs {
-    int id, pf, v, nvis;
-};
-__device__ __forceinline__ int rec_phys(int pf) { return (int)(int16_t)(pf & 0xffff); }
-__device__ __forceinline__ bool rec_new(int pf) { return ((pf >> 16) & kSlotNew) != 0; }
-__device__ __forceinline__ bool rec_keep(int pf) { return ((pf >> 16) & kSlotKeep) != 0; }
-
-__device__ __forceinline__ Recs load_recs(const SlotRec *g, int count, int lane) {
-    Recs r{0, 0, 0, 0};
-    if (lane < count) {
-        const int4 v = *(const int4 *)(g + lane);
-        r.id = v.x;
-        r.pf = v.y;
-        r.v = v.z;
-        r.nvis = v.w;
-    }
-    return r;
-}
-
-// Staging geometry: a vector of kp floats is lpr = kp / 4 lanes of 16 bytes; one step
-// moves rpi = 64 / lpr vectors, lane l handling piece l % lpr of vector l / lpr.
-struct Geo {
-    int kp, lpr, rpi, vb, piece;
-    bool act;
-};
-__device__ __forceinline__ Geo make_geo(int kp, int lane) {
-    Geo g;
-    g.kp = kp;
-    g.lpr = kp >> 2;
-    g.rpi = 64 / g.lpr;
-    g.vb = lane / g.lpr;
-    g.piece = lane - g.vb * g.lpr;
-    g.act = g.vb < g.rpi;
-    return g;
-}
-
-// This lane's value of a per-slot record field for vector vb of the step at `base`.
-__device__ __forceinline__ int slot_val(int field, int base, const Geo &g) {
-    if (g.rpi <= 4) {
-        int out = __builtin_amdgcn_readlane(field, base);
-        for (int b = 1; b < g.rpi; ++b) {
-            const int v = __builtin_amdgcn_readlane(field, base + b);
-            out = g.vb == b ? v : out;
-        }
-        return out;
-    }
-    return __shfl(field, (base + g.vb) & 63);
-}
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2_t __attribute__((ext_vector_type(2)));
@@ -148,224 +97,81 @@ __device__ __forceinline__ void coherent_store4(float *p, f32x4_t v) {
     __hip_atomic_store((uint64_t *)p + 1, u.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void wait_all() { asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_lgkm() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
-// Register staging of one chunk: step i of the rows holds vectors [rpi i, rpi i + rpi).
-struct Staging {
-    f32x4_t row[kRowPiecesPerLane];
-    f32x4_t item[kItemPiecesPerLane];
+// Clock read only when per-worker counters are requested.
+__device__ __forceinline__ uint64_t tick(bool on) { return on ? wall_clock64() : 0; }
+
+// ---------------------------------------------------------------------------------------
+// LDS of one worker: S vector slots, a ring of kRing staged chunks (rating records and
+// the items each chunk releases), and the synchronisation words.
+enum SyncWord { kStaged = 0, kDone = 1, kStop = 2 };
+
+struct Lds {
+    float *vec;         // S x kp
+    RatingRec *rat;     // kRing x 64
+    int32_t *rel_id;    // kRing x 64
+    uint32_t *rel_tk;   // kRing x 64
+    int32_t *rel_slot;  // kRing x 64
+    int32_t *cnt;       // kRing x 2: ratings, releases
+    int32_t *sync;      // staged, done, stop, unused
+    float *dump;        // 64 x 4: writes of lanes beyond the vector width
 };
 
-struct ChunkMeta {
-    int64_t rat, slot;
-    int nrat, nr, nt;
-    int group;
-    int epoch;
-    bool epoch_start;
-};
+constexpr size_t kRingBytes = (size_t)kRing * 64 * (sizeof(RatingRec) + 3 * sizeof(int32_t)) + kRing * 2 * 4 + 4 * 4;
 
-// Position of a chunk in the worker's cyclic walk: chunk index and epoch.
-struct Cursor {
-    int64_t c;
-    int epoch;
-};
-__device__ __forceinline__ Cursor advance(Cursor u, int64_t nck) {
-    if (++u.c == nck) {
-        u.c = 0;
-        ++u.epoch;
-    }
-    return u;
-}
-__device__ __forceinline__ ChunkMeta chunk_meta(const TrainArgs &a, int64_t c0, Cursor u) {
-    const ChunkRec r = a.chunks[c0 + u.c];
-    ChunkMeta m;
-    m.rat = r.rat;
-    m.slot = r.slot;
-    m.nrat = r.info & 255;
-    m.nr = (r.info >> 8) & 255;
-    m.nt = (r.info >> 16) & 255;
-    m.group = r.group;
-    m.epoch = u.epoch;
-    m.epoch_start = u.c == 0;
-    return m;
+__device__ __forceinline__ Lds lds_layout(void *base, int S, int kp) {
+    char *p = (char *)base;
+    Lds L;
+    L.vec = (float *)p;
+    p += (size_t)S * kp * sizeof(float);
+    L.rat = (RatingRec *)p;
+    p += kRing * 64 * sizeof(RatingRec);
+    L.rel_id = (int32_t *)p;
+    p += kRing * 64 * 4;
+    L.rel_tk = (uint32_t *)p;
+    p += kRing * 64 * 4;
+    L.rel_slot = (int32_t *)p;
+    p += kRing * 64 * 4;
+    L.cnt = (int32_t *)p;
+    p += kRing * 2 * 4;
+    L.sync = (int32_t *)p;
+    p += 4 * 4;
+    L.dump = (float *)p;
+    return L;
 }
 
-__device__ __forceinline__ int item_lane_field(int field, int nr, int lane) { return __shfl(field, (lane + nr) & 63); }
-
-// Counter value at which this chunk's visit of an item may start.
-__device__ __forceinline__ uint32_t item_ticket(const ChunkMeta &m, int v, int nvis) {
-    return (uint32_t)((int64_t)m.epoch * nvis + v);
+__device__ __forceinline__ int sync_load(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void sync_store(int32_t *p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Plan validation: a malformed plan (ids or slots out of range) ends the kernel instead
-// of letting a load or a store touch memory outside the factors or the staging area.
-__device__ __forceinline__ bool recs_ok(const TrainArgs &a, const ChunkMeta &m, const Recs &r, int lane) {
-    bool bad = m.nr > a.rmax || m.nt > a.tmax || m.nrat > kMaxRatingsPerChunk || m.nrat < 1;
-    if (lane < m.nr + m.nt) {
-        const bool is_row = lane < m.nr;
-        const int ph = rec_phys(r.pf);
-        bad |= r.id < 0 || r.id >= (is_row ? a.m : a.n) || ph < 0 || ph >= (is_row ? a.rmax : a.tmax);
-    }
-    return __builtin_amdgcn_ballot_w64(bad) == 0;
-}
-__device__ __forceinline__ bool ratings_ok(const TrainArgs &a, const ChunkMeta &m, const RatingRec &rr, int lane) {
-    bool bad = false;
-    if (lane < m.nrat) bad = (int)(rr.slots & 255) >= a.rmax || (int)(rr.slots >> 8) >= a.tmax;
-    return __builtin_amdgcn_ballot_w64(bad) == 0;
-}
+// ---------------------------------------------------------------------------------------
+// Compute wave.
 
-// Load into registers the new rows / items of chunk m (rows with plain loads, items with
-// device-coherent loads).  Steps use literal indices so the staging stays in registers.
-template <int I>
-__device__ __forceinline__ void prefetch_row_step(const TrainArgs &a, const ChunkMeta &m, const Recs &r,
-                                                  Staging &st, const Geo &g) {
-    const int base = g.rpi * I;
-    if (base < m.nr) {
-        const int id = slot_val(r.id, base, g), pf = slot_val(r.pf, base, g);
-        if (g.act && base + g.vb < m.nr && rec_new(pf))
-            st.row[I] = *(const f32x4_t *)(a.W + (int64_t)id * g.kp + g.piece * 4);
-    }
-}
-template <int I>
-__device__ __forceinline__ void prefetch_item_step(const TrainArgs &a, const ChunkMeta &m, const Recs &r,
-                                                   Staging &st, const Geo &g) {
-    const int base = g.rpi * I;
-    if (base < m.nt) {
-        const int id = slot_val(r.id, m.nr + base, g), pf = slot_val(r.pf, m.nr + base, g);
-        if (g.act && base + g.vb < m.nt && rec_new(pf))
-            st.item[I] = coherent_load4(a.H + (int64_t)id * g.kp + g.piece * 4);
-    }
-}
-template <int... I, int... J>
-__device__ __forceinline__ void prefetch_steps(const TrainArgs &a, const ChunkMeta &m, const Recs &r, Staging &st,
-                                               const Geo &g, bool rows, bool items,
-                                               std::integer_sequence<int, I...>, std::integer_sequence<int, J...>) {
-    if (rows) (prefetch_row_step<I>(a, m, r, st, g), ...);
-    if (items) (prefetch_item_step<J>(a, m, r, st, g), ...);
-}
-__device__ __forceinline__ void prefetch(const TrainArgs &a, const ChunkMeta &m, const Recs &r, Staging &st,
-                                         const Geo &g, bool rows, bool items) {
-    prefetch_steps(a, m, r, st, g, rows, items, std::make_integer_sequence<int, kRowPiecesPerLane>(),
-                   std::make_integer_sequence<int, kItemPiecesPerLane>());
-}
-
-// Write staged vectors into their LDS slots (same predicate as prefetch).
-template <int I>
-__device__ __forceinline__ void commit_row_step(const ChunkMeta &m, const Recs &r, const Staging &st, float *lds,
-                                                const Geo &g) {
-    const int base = g.rpi * I;
-    if (base < m.nr) {
-        const int pf = slot_val(r.pf, base, g);
-        if (g.act && base + g.vb < m.nr && rec_new(pf))
-            *(f32x4_t *)(lds + rec_phys(pf) * g.kp + g.piece * 4) = st.row[I];
-    }
-}
-template <int I>
-__device__ __forceinline__ void commit_item_step(const ChunkMeta &m, const Recs &r, const Staging &st, float *lds,
-                                                 int rmax, const Geo &g) {
-    const int base = g.rpi * I;
-    if (base < m.nt) {
-        const int pf = slot_val(r.pf, m.nr + base, g);
-        if (g.act && base + g.vb < m.nt && rec_new(pf))
-            *(f32x4_t *)(lds + (rmax + rec_phys(pf)) * g.kp + g.piece * 4) = st.item[I];
-    }
-}
-template <int... I, int... J>
-__device__ __forceinline__ void commit_steps(const ChunkMeta &m, const Recs &r, const Staging &st, float *lds, int rmax,
-                                             const Geo &g, bool rows, bool items, std::integer_sequence<int, I...>,
-                                             std::integer_sequence<int, J...>) {
-    if (rows) (commit_row_step<I>(m, r, st, lds, g), ...);
-    if (items) (commit_item_step<J>(m, r, st, lds, rmax, g), ...);
-}
-__device__ __forceinline__ void commit(const ChunkMeta &m, const Recs &r, const Staging &st, float *lds, int rmax,
-                                       const Geo &g, bool rows, bool items) {
-    commit_steps(m, r, st, lds, rmax, g, rows, items, std::make_integer_sequence<int, kRowPiecesPerLane>(),
-                 std::make_integer_sequence<int, kItemPiecesPerLane>());
-}
-
-// Store chunk m's rows that the next chunk does not keep (or all of them).
-__device__ __forceinline__ void write_back_rows(const TrainArgs &a, const ChunkMeta &m, const Recs &r,
-                                                const float *lds, const Geo &g, bool all) {
-    for (int base = 0; base < m.nr; base += g.rpi) {
-        const int id = slot_val(r.id, base, g), pf = slot_val(r.pf, base, g);
-        if (g.act && base + g.vb < m.nr && (all || !rec_keep(pf)))
-            *(f32x4_t *)(a.W + (int64_t)id * g.kp + g.piece * 4) =
-                *(const f32x4_t *)(lds + rec_phys(pf) * g.kp + g.piece * 4);
-    }
-}
-
-// Store chunk m's items that the next chunk does not keep (or all), device-coherent.
-__device__ __forceinline__ void write_back_items(const TrainArgs &a, const ChunkMeta &m, const Recs &r,
-                                                 const float *lds, const Geo &g, bool all) {
-    for (int base = 0; base < m.nt; base += g.rpi) {
-        const int id = slot_val(r.id, m.nr + base, g), pf = slot_val(r.pf, m.nr + base, g);
-        if (g.act && base + g.vb < m.nt && (all || !rec_keep(pf)))
-            coherent_store4(a.H + (int64_t)id * g.kp + g.piece * 4,
-                            *(const f32x4_t *)(lds + (a.rmax + rec_phys(pf)) * g.kp + g.piece * 4));
-    }
-}
-
-// Items of chunk m passed on after its write back (lane t = item slot t): id in those
-// lanes, -1 elsewhere; *tk = the counter value to publish.
-__device__ __forceinline__ int leaving_items(const ChunkMeta &m, const Recs &r, bool all, int lane, uint32_t *tk) {
-    const int id = item_lane_field(r.id, m.nr, lane), pf = item_lane_field(r.pf, m.nr, lane);
-    const int v = item_lane_field(r.v, m.nr, lane), nv = item_lane_field(r.nvis, m.nr, lane);
-    *tk = item_ticket(m, v, nv) + 1u;
-    return (lane < m.nt && (all || !rec_keep(pf))) ? id : -1;
-}
-
-// Items chunk m takes over (not kept by its predecessor): id in those lanes, -1 elsewhere;
-// *tk = the counter value to wait for.
-__device__ __forceinline__ int new_items(const ChunkMeta &m, const Recs &r, int lane, uint32_t *tk) {
-    const int id = item_lane_field(r.id, m.nr, lane), pf = item_lane_field(r.pf, m.nr, lane);
-    const int v = item_lane_field(r.v, m.nr, lane), nv = item_lane_field(r.nvis, m.nr, lane);
-    *tk = item_ticket(m, v, nv);
-    return (lane < m.nt && rec_new(pf)) ? id : -1;
-}
-
-__device__ __forceinline__ void publish(uint32_t *tok, int id, uint32_t tk) {
-    if (id >= 0) __hip_atomic_store(tok + id, tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint32_t poll_items(const uint32_t *tok, int id) {
-    return id >= 0 ? __hip_atomic_load(tok + id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
-}
-
-// Block until every lane's item counter equals its ticket; false if the kernel must end.
-__device__ __forceinline__ bool acquire_items(uint32_t *tok, int id, uint32_t tk, uint32_t *abort_flag) {
-    bool pending = id >= 0 && __hip_atomic_load(tok + id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tk;
-    if (__builtin_amdgcn_ballot_w64(pending) == 0) return true;
-    const uint64_t t0 = wall_clock64();
-    while (true) {
-        __builtin_amdgcn_s_sleep(2);
-        if (pending) pending = __hip_atomic_load(tok + id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tk;
-        if (__builtin_amdgcn_ballot_w64(pending) == 0) return true;
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
-        if (wall_clock64() - t0 > kWaitLimitTicks) {
-            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return false;
-        }
-    }
-}
-
-// SGD over the chunk's ratings in plan order, on LDS.  The next rating's row (and item,
+// SGD over one chunk's ratings in plan order, on LDS.  The next rating's row (and item,
 // when it changes) is read ahead; a read-ahead row equal to the current one takes the
 // freshly updated value.  Lanes beyond the vector width compute on zeros and write to a
 // scratch line of LDS.
 template <int VEC, int NR16>
-__device__ __forceinline__ void sgd_chunk(float *buf, float *dump, int kp, int rmax, const RatingRec &rr, int nrat,
-                                          float s, float shrink, int lane) {
+__device__ __forceinline__ void sgd_chunk(float *vec, float *dump, int kp, const RatingRec &rr, int nrat, float s,
+                                          float shrink, int lane) {
+    if (nrat <= 0) return;
     const bool on = lane * VEC < kp;
     const int roff = on ? lane * VEC : 0;
-    float *const wbase = on ? buf + lane * VEC : dump + lane * VEC;  // write address base
+    float *const wbase = on ? vec + lane * VEC : dump + lane * VEC;  // write address base
     const int r_sl = (int)rr.slots;
     const float r_val = rr.r;
     int sl = rl_i(r_sl, 0);
     float r = rl_f(r_val, 0);
-    int rs = sl & 255, ts = sl >> 8;
+    int rs = sl & 255, ts = (sl >> 8) & 255;
     float w[VEC], h[VEC];
-    lds_read<VEC>(buf + rs * kp + roff, w);
-    lds_read<VEC>(buf + (rmax + ts) * kp + roff, h);
+    lds_read<VEC>(vec + rs * kp + roff, w);
+    lds_read<VEC>(vec + ts * kp + roff, h);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
         w[v] = on ? w[v] : 0.0f;
@@ -375,11 +181,11 @@ __device__ __forceinline__ void sgd_chunk(float *buf, float *dump, int kp, int r
         const int xn = x + 1 < nrat ? x + 1 : x;
         const int sln = rl_i(r_sl, xn);
         const float rn = rl_f(r_val, xn);
-        const int rsn = sln & 255, tsn = sln >> 8;
+        const int rsn = sln & 255, tsn = (sln >> 8) & 255;
         const bool switch_item = tsn != ts;
         float wn[VEC], hn[VEC];
-        lds_read<VEC>(buf + rsn * kp + roff, wn);
-        if (switch_item) lds_read<VEC>(buf + (rmax + tsn) * kp + roff, hn);
+        lds_read<VEC>(vec + rsn * kp + roff, wn);
+        if (switch_item) lds_read<VEC>(vec + tsn * kp + roff, hn);
         float d = 0.0f;
 #pragma unroll
         for (int v = 0; v < VEC; ++v) d = fmaf(w[v], h[v], d);
@@ -393,11 +199,11 @@ __device__ __forceinline__ void sgd_chunk(float *buf, float *dump, int kp, int r
         }
         lds_write<VEC>(wbase + rs * kp, w);
         if (x + 1 == nrat) {
-            lds_write<VEC>(wbase + (rmax + ts) * kp, h);
+            lds_write<VEC>(wbase + ts * kp, h);
             break;
         }
         if (switch_item) {
-            lds_write<VEC>(wbase + (rmax + ts) * kp, h);
+            lds_write<VEC>(wbase + ts * kp, h);
 #pragma unroll
             for (int v = 0; v < VEC; ++v) h[v] = on ? hn[v] : 0.0f;
         }
@@ -411,201 +217,568 @@ __device__ __forceinline__ void sgd_chunk(float *buf, float *dump, int kp, int r
     }
 }
 
-__device__ __forceinline__ void raise_abort(uint32_t *abort_flag, uint32_t code, int lane) {
-    wait_all();
-    if (lane == 0) __hip_atomic_store(abort_flag, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ void record_visits(const TrainArgs &a, int q, const ChunkMeta &m, int id, uint32_t tk) {
-    if (id < 0) return;
-    const int64_t slot = (int64_t)atomicAdd((unsigned long long *)a.trace_len, 1ull);
-    if (slot < a.trace_cap) {
-        a.trace[4 * slot + 0] = q;
-        a.trace[4 * slot + 1] = id;
-        a.trace[4 * slot + 2] = m.epoch;
-        a.trace[4 * slot + 3] = (int32_t)tk;
-    }
-}
-
-// Clock read only when per-worker counters are requested.
-__device__ __forceinline__ uint64_t tick(bool on) { return on ? wall_clock64() : 0; }
-
 template <int VEC, int NR16>
-__global__ __launch_bounds__(64) void k_train(TrainArgs a, uint32_t *abort_flag) {
-    extern __shared__ float4 lds4[];
-    const int q = blockIdx.x;
-    const int lane = threadIdx.x;
-    const int64_t c0 = a.wck[q], c1 = a.wck[q + 1];
-    const int64_t nck = c1 - c0;
-    if (nck <= 0 || a.epochs <= 0) return;
-    const int kp = a.kp, rmax = a.rmax;
-    const Geo geo = make_geo(kp, lane);
-    float *const lds = reinterpret_cast<float *>(lds4);
-    float *const dump = lds + (a.rmax + a.tmax) * kp;
-    const int64_t total = nck * (int64_t)a.epochs;
+__device__ __forceinline__ void compute_wave(const TrainArgs &a, const Lds &L, int64_t nck, int q, int lane) {
     const bool prof = a.wstats != nullptr;
     const uint64_t t_start = tick(prof);
-    uint64_t t_acq = 0, t_mem = 0, t_sgd = 0, t_issue = 0, t_stage = 0, n_rat = 0;
-    uint32_t *const tok = a.tok_done;
-
-    // Prologue: metadata of chunks 0..3, records of chunks 0..2, ratings of chunks 0, 1.
-    Cursor u0{0, a.epoch0};
-    const Cursor u1 = advance(u0, nck), u2 = advance(u1, nck), u3 = advance(u2, nck);
-    ChunkMeta m0 = chunk_meta(a, c0, u0);
-    ChunkMeta m1 = chunk_meta(a, c0, u1);
-    ChunkMeta m2 = chunk_meta(a, c0, u2);
-    ChunkMeta m3 = chunk_meta(a, c0, u3);
-    Cursor u4 = advance(u3, nck);
-    Recs r0 = load_recs(a.slots + m0.slot, m0.nr + m0.nt, lane);
-    Recs r1 = load_recs(a.slots + m1.slot, m1.nr + m1.nt, lane);
-    Recs r2 = load_recs(a.slots + m2.slot, m2.nr + m2.nt, lane);
-    RatingRec rr0{0, 0.0f}, rr1{0, 0.0f};
-    if (lane < m0.nrat) rr0 = a.ratings[m0.rat + lane];
-    if (lane < m1.nrat) rr1 = a.ratings[m1.rat + lane];
-    wait_all();
-    if (!recs_ok(a, m0, r0, lane) || !ratings_ok(a, m0, rr0, lane) || !recs_ok(a, m1, r1, lane) ||
-        !recs_ok(a, m2, r2, lane)) {
-        raise_abort(abort_flag, 2u, lane);
-        return;
-    }
-    Staging st;
-    bool staged_rows = false, staged_items = false;  // chunk m0's new vectors are in `st`
-    uint32_t poll = 0;                                // lane t: counter of chunk m1's new item t
-    bool polled = false;
-    {
-        uint32_t tk;
-        const int id = new_items(m1, r1, lane, &tk);
-        poll = poll_items(tok, id);
-        polled = true;
-    }
-    int pend_id = -1;  // items written back in the previous iteration, to be passed on
-    uint32_t pend_tk = 0;
-    ChunkMeta mp = m0;  // chunk it-1
-    Recs rp = r0;
-    int s_epoch = -1;
+    uint64_t t_sgd = 0, t_starve = 0;
+    int64_t n_rat = 0;
+    const int64_t total = nck * a.epochs;
+    int epoch = -1, ex = a.epoch0;
+    int64_t lx = 0;
     float s_step = 0.0f, s_shrink = 1.0f;
-
-    for (int64_t it = 0; it < total; ++it) {
-        const bool has_next = it + 1 < total, has_next2 = it + 2 < total, has_next3 = it + 3 < total;
-        const ChunkMeta m4 = chunk_meta(a, c0, u4);  // used from the next iteration on
-
-        // ---- top
-        const uint64_t t_top = tick(prof);
-        wait_all();
-        const uint64_t t_s0 = tick(prof);
-        t_mem += t_s0 - t_top;
-        publish(tok, pend_id, pend_tk);
-        pend_id = -1;
-        if (it > 0 && (!ratings_ok(a, m0, rr0, lane) || (has_next2 && !recs_ok(a, m2, r2, lane)))) {
-            raise_abort(abort_flag, 2u, lane);
-            return;
-        }
-        if (it > 0) write_back_rows(a, mp, rp, lds, geo, false);
-        if (!staged_rows || !staged_items) {
-            // Everything this worker could pass on was passed on above; wait for the
-            // items and load what was not prefetched.
-            uint32_t tk;
-            const int id = new_items(m0, r0, lane, &tk);
-            const uint64_t t_a = tick(prof);
-            if (!staged_items && !acquire_items(tok, id, tk, abort_flag)) {
-                wait_all();
-                return;
+    for (int64_t x = 0; x < total; ++x) {
+        if (sync_load(&L.sync[kStaged]) <= x) {
+            const uint64_t t0 = tick(prof);
+            while (sync_load(&L.sync[kStaged]) <= x) {
+                if (sync_load(&L.sync[kStop])) return;
+                __builtin_amdgcn_s_sleep(1);
             }
-            prefetch(a, m0, r0, st, geo, !staged_rows, !staged_items);
-            wait_all();
-            t_acq += tick(prof) - t_a;
-            if (a.trace && !staged_items) record_visits(a, q, m0, id, tk);
+            t_starve += tick(prof) - t0;
         }
-        commit(m0, r0, st, lds, rmax, geo, true, true);
-        if (a.trace && staged_items) {
-            uint32_t tk;
-            const int id = new_items(m0, r0, lane, &tk);
-            record_visits(a, q, m0, id, tk);
-        }
-        const uint64_t t_i0 = tick(prof);
-        t_stage += t_i0 - t_s0;
-
-        // ---- issue: prefetch chunk it+1 (not across an epoch boundary), records it+3,
-        //      ratings it+2, poll the counters of chunk it+2's new items
-        bool staged_rows1 = false, staged_items1 = false;
-        if (has_next && !m1.epoch_start) {
-            uint32_t tk;
-            const int id = new_items(m1, r1, lane, &tk);
-            staged_rows1 = true;
-            staged_items1 = __builtin_amdgcn_ballot_w64(id >= 0 && !(polled && poll == tk)) == 0;
-            prefetch(a, m1, r1, st, geo, true, staged_items1);
-        }
-        Recs r3 = r2;
-        if (has_next3) r3 = load_recs(a.slots + m3.slot, m3.nr + m3.nt, lane);
-        RatingRec rr2 = rr1;
-        if (has_next2 && lane < m2.nrat) rr2 = a.ratings[m2.rat + lane];
-        bool polled2 = false;
-        uint32_t poll2 = 0;
-        if (has_next2) {
-            uint32_t tk;
-            const int id = new_items(m2, r2, lane, &tk);
-            poll2 = poll_items(tok, id);
-            polled2 = true;
-        }
-
-        // ---- sgd on chunk it
-        const uint64_t t_g0 = tick(prof);
-        t_issue += t_g0 - t_i0;
-        if (m0.epoch != s_epoch) {
-            s_epoch = m0.epoch;
-            s_step = (float)(a.alpha / (1.0 + a.beta * pow((double)s_epoch, a.gamma)));
+        compiler_fence();
+        const int ent = (int)(x & (kRing - 1));
+        const int nrat = L.cnt[2 * ent];
+        RatingRec rr{0u, 0.0f};
+        if (lane < nrat) rr = L.rat[ent * 64 + lane];
+        if (ex != epoch) {
+            // s_t = alpha / (1 + beta t^gamma), t = epochs done (every rating is updated
+            // once per epoch), eq. (stepsize_method).
+            epoch = ex;
+            const double t = (double)ex;
+            const double sd = a.alpha / (1.0 + a.beta * (t > 0.0 ? pow(t, a.gamma) : 0.0));
+            s_step = (float)sd;
             s_shrink = 1.0f - s_step * a.lambda;
         }
-        sgd_chunk<VEC, NR16>(lds, dump, kp, rmax, rr0, m0.nrat, s_step, s_shrink, lane);
-        t_sgd += tick(prof) - t_g0;
-        n_rat += m0.nrat;
-        // Items chunk it is done with leave now; they are passed on at the next top.
-        write_back_items(a, m0, r0, lds, geo, !has_next);
-        pend_id = leaving_items(m0, r0, !has_next, lane, &pend_tk);
-
-        mp = m0;
-        rp = r0;
-        m0 = m1;
-        r0 = r1;
-        rr0 = rr1;
-        m1 = m2;
-        r1 = r2;
-        rr1 = rr2;
-        m2 = m3;
-        r2 = r3;
-        m3 = m4;
-        u4 = advance(u4, nck);
-        poll = poll2;
-        polled = polled2;
-        staged_rows = staged_rows1;
-        staged_items = staged_items1;
+        const uint64_t t0 = tick(prof);
+        sgd_chunk<VEC, NR16>(L.vec, L.dump, a.kp, rr, nrat, s_step, s_shrink, lane);
+        wait_lgkm();
+        t_sgd += tick(prof) - t0;
+        n_rat += nrat;
+        if (lane == 0) sync_store(&L.sync[kDone], (int)(x + 1));
+        if (++lx == nck) {
+            lx = 0;
+            ++ex;
+        }
     }
-    // The last chunk (now mp): everything back to global memory, then pass on its items
-    // and those written back in the last iteration.
-    write_back_rows(a, mp, rp, lds, geo, true);
-    wait_all();
-    publish(tok, pend_id, pend_tk);
-    if (lane == 0 && prof) {
+    if (prof && lane == 0) {
         int64_t *w = a.wstats + (int64_t)q * kWStatCount;
         w[kWStatTotal] = (int64_t)(wall_clock64() - t_start);
-        w[kWStatAcquire] = (int64_t)t_acq;
-        w[kWStatMemWait] = (int64_t)t_mem;
         w[kWStatChunks] = total;
         w[kWStatSgd] = (int64_t)t_sgd;
-        w[kWStatIssue] = (int64_t)t_issue;
-        w[kWStatRatings] = (int64_t)n_rat;
-        w[kWStatStage] = (int64_t)t_stage;
+        w[kWStatRatings] = n_rat;
+        w[kWStatStarve] = (int64_t)t_starve;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Memory wave.
+
+struct Meta {
+    int64_t rat, ev;
+    int nrat, nload, nrel, nflush, need;
+};
+
+// Record of the chunk at local index lc of the worker's plan (chunk x = lc + epoch * nck
+// of the call); an empty record when x is past the end of the call.
+__device__ __forceinline__ Meta load_meta(const TrainArgs &a, int64_t c0, int64_t lc, bool valid) {
+    Meta m{0, 0, 0, 0, 0, 0, 0};
+    if (!valid) return m;
+    const ChunkRec r = a.chunks[c0 + lc];
+    m.rat = r.rat;
+    m.ev = r.ev;
+    m.nrat = r.nrat;
+    m.nload = r.nload;
+    m.nrel = r.nrel;
+    m.nflush = r.nflush;
+    m.need = r.need_done;
+    return m;
+}
+
+// Event records of one chunk, one per lane (loads, then releases).
+struct Ev {
+    int id;
+    int sk;
+    int evict;
+    int vis;
+};
+__device__ __forceinline__ Ev load_ev(const EvRec *g, int count, int lane) {
+    Ev e{0, 0, -1, 0};
+    if (lane < count) {
+        const int4 v = *(const int4 *)(g + lane);
+        e.id = v.x;
+        e.sk = v.y;
+        e.evict = v.z;
+        e.vis = v.w;
+    }
+    return e;
+}
+__device__ __forceinline__ int ev_slot(int sk) { return sk & 255; }
+__device__ __forceinline__ int ev_kind(int sk) { return (sk >> 8) & 255; }
+// Counter value at which the visit may start in epoch `epoch`.
+__device__ __forceinline__ uint32_t ev_ticket(int vis, int epoch) {
+    return (uint32_t)((int64_t)epoch * (int64_t)((uint32_t)vis >> 16) + (int64_t)(vis & 0xffff));
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__device__ __forceinline__ uint32_t lds_addr(const float *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)p;
+}
+
+// LDS reads of the memory wave, waited for inside the asm block.  Written as asm so that
+// the compiler does not put "s_waitcnt vmcnt(0)" in front of them (it cannot tell these
+// slots from those the wave's LDS-DMA loads write, and would make every read wait for
+// all outstanding stores).  The slots read here are never the target of a load in
+// flight: a slot is read before any load into it is issued.
+__device__ __forceinline__ void lds_read4x4_now(const float *p0, const float *p1, const float *p2, const float *p3,
+                                                f32x4_t &v0, f32x4_t &v1, f32x4_t &v2, f32x4_t &v3) {
+    asm volatile(
+        "ds_read_b128 %0, %4\n\t"
+        "ds_read_b128 %1, %5\n\t"
+        "ds_read_b128 %2, %6\n\t"
+        "ds_read_b128 %3, %7\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3)
+        : "v"(lds_addr(p0)), "v"(lds_addr(p1)), "v"(lds_addr(p2)), "v"(lds_addr(p3))
+        : "memory");
+}
+
+struct MemoryWave {
+    const TrainArgs &a;
+    const Lds &L;
+    const int64_t c0, nck, total;
+    const int q, lane, kp;
+    uint32_t *const abort_flag;
+    const bool prof;
+    int64_t retired = 0;  // chunks whose releases have been issued
+    int64_t retired_lc = 0;  // its local index in the plan
+    int pub_id = -1;      // items written back, counter value to publish (one per lane)
+    uint32_t pub_tk = 0;
+    int pub_n = 0;
+    uint64_t t_acq = 0, t_mem = 0, t_slot = 0, t_commit = 0, t_retire = 0, t_issue = 0, t_evict = 0, t_poll = 0;
+    int64_t n_loads = 0, n_late = 0;
+
+    __device__ MemoryWave(const TrainArgs &a_, const Lds &L_, int64_t c0_, int64_t nck_, int q_, int lane_,
+                          uint32_t *abort_)
+        : a(a_), L(L_), c0(c0_), nck(nck_), total(nck_ * a_.epochs), q(q_), lane(lane_), kp(a_.kp),
+          abort_flag(abort_), prof(a_.wstats != nullptr) {}
+
+    __device__ __forceinline__ void publish() {
+        if (lane < pub_n) __hip_atomic_store(a.tok_done + pub_id, pub_tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pub_n = 0;
+    }
+
+    // Copy `count` vectors from LDS slots to global memory (W, or H with device-coherent
+    // stores): lane t < count of `id` / `sk` gives the vector's id (< 0: skip) and slot.
+    // A vector is kp / 4 lanes of 16 bytes, so one instruction moves rpi = 64 / (kp / 4)
+    // vectors.  All reads of a batch of 16 instructions land in distinct registers before
+    // the first store, so no read waits for an earlier store.
+    __device__ __forceinline__ void slots_to_global(float *dst, bool coherent, int id, int sk, int count) {
+        const int lpr = kp >> 2, rpi = 64 / lpr, vb = lane / lpr, piece = lane - vb * lpr;
+        const bool act = vb < rpi;
+        for (int b0 = 0; b0 < count; b0 += 16 * rpi) {
+            int gid[16];
+            const float *src[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                gid[r] = -1;
+                src[r] = L.vec;
+                if (b0 + r * rpi < count) {
+                    const int t = b0 + r * rpi + vb;
+                    const int g = __shfl(id, t & 63), s = ev_slot(__shfl(sk, t & 63));
+                    gid[r] = (act && t < count) ? g : -1;
+                    src[r] = L.vec + (gid[r] >= 0 ? s : 0) * kp + piece * 4;
+                }
+            }
+            f32x4_t v[16];
+#pragma unroll
+            for (int r = 0; r < 16; r += 4)
+                if (b0 + r * rpi < count)
+                    lds_read4x4_now(src[r], src[r + 1], src[r + 2], src[r + 3], v[r], v[r + 1], v[r + 2], v[r + 3]);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if (b0 + r * rpi >= count || gid[r] < 0) continue;
+                float *p = dst + (int64_t)gid[r] * kp + piece * 4;
+                if (coherent)
+                    coherent_store4(p, v[r]);
+                else
+                    *(f32x4_t *)p = v[r];
+            }
+        }
+    }
+
+    // Write back the rows left in LDS at the end of an epoch (after its last chunk y).
+    __device__ __forceinline__ void flush() {
+        const Meta m = load_meta(a, c0, nck - 1, true);
+        const int64_t f0 = m.ev + m.nload + m.nrel;
+        for (int b0 = 0; b0 < m.nflush; b0 += 64) {
+            const int cnt = m.nflush - b0 < 64 ? m.nflush - b0 : 64;
+            const Ev f = load_ev(a.events + f0 + b0, cnt, lane);
+            wait_vm();
+            const bool ok = lane >= cnt || (f.id >= 0 && f.id < a.m && ev_slot(f.sk) < a.slots);
+            if (__builtin_amdgcn_ballot_w64(!ok) != 0) continue;  // malformed: skip (validated elsewhere)
+            slots_to_global(a.W, false, f.id, f.sk, cnt);
+        }
+    }
+
+    // Pass on the items of every chunk the compute wave has finished: device-coherent
+    // write-back now, counter published once the stores have completed.
+    __device__ __forceinline__ void retire() {
+        const int64_t d = sync_load(&L.sync[kDone]);
+        compiler_fence();
+        while (retired < d) {
+            const int64_t y = retired;
+            const int ent = (int)(y & (kRing - 1));
+            const int nrel = L.cnt[2 * ent + 1];
+            if (nrel > 0) {
+                if (pub_n + nrel > 64) {
+                    wait_vm();
+                    publish();
+                }
+                const int rid = lane < nrel ? L.rel_id[ent * 64 + lane] : -1;
+                const int rsl = lane < nrel ? L.rel_slot[ent * 64 + lane] : 0;
+                slots_to_global(a.H, true, rid, rsl, nrel);
+                const int r = lane - pub_n;
+                if (r >= 0 && r < nrel) {
+                    pub_id = L.rel_id[ent * 64 + r];
+                    pub_tk = L.rel_tk[ent * 64 + r];
+                }
+                pub_n += nrel;
+            }
+            if (retired_lc == nck - 1) {
+                flush();
+                retired_lc = 0;
+            } else {
+                ++retired_lc;
+            }
+            ++retired;
+        }
+    }
+
+    // Retire and publish while waiting.
+    __device__ __forceinline__ void service() {
+        retire();
+        if (pub_n > 0) {
+            wait_vm();
+            publish();
+        }
+    }
+
+    __device__ __forceinline__ bool give_up(uint64_t t0) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
+        if (wall_clock64() - t0 > kWaitLimitTicks) {
+            if (lane == 0) __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return true;
+        }
+        return false;
+    }
+
+    // End the worker early: tell the compute wave, and record `code` (if non-zero).
+    __device__ __forceinline__ void stop(uint32_t code) {
+        wait_vm();
+        if (code && lane == 0) __hip_atomic_store(abort_flag, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) sync_store(&L.sync[kStop], 1);
+    }
+
+    // Wait until the compute wave has finished `need` chunks.
+    __device__ __forceinline__ bool wait_done(int64_t need) {
+        if (sync_load(&L.sync[kDone]) >= need) return true;
+        const uint64_t t0 = wall_clock64();
+        while (sync_load(&L.sync[kDone]) < need) {
+            service();
+            if (give_up(t0)) return false;
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (prof) t_slot += wall_clock64() - t0;
+        return true;
+    }
+
+    // Wait until every item event of `e` flagged in `mask` may start (epoch `epoch`).
+    __device__ __forceinline__ bool acquire(const Ev &e, uint64_t mask, int epoch) {
+        const bool mine = ((mask >> lane) & 1ull) != 0;
+        const uint32_t tk = ev_ticket(e.vis, epoch);
+        bool pending = mine && __hip_atomic_load(a.tok_done + e.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tk;
+        if (__builtin_amdgcn_ballot_w64(pending) == 0) return true;
+        const uint64_t t0 = wall_clock64();
+        while (true) {
+            service();
+            __builtin_amdgcn_s_sleep(2);
+            if (pending)
+                pending = __hip_atomic_load(a.tok_done + e.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tk;
+            if (__builtin_amdgcn_ballot_w64(pending) == 0) break;
+            if (give_up(t0)) return false;
+        }
+        if (prof) t_acq += wall_clock64() - t0;
+        return true;
+    }
+
+    // Plan validation: a malformed plan (ids or slots out of range) ends the kernel
+    // instead of letting a load or a store touch memory outside its arrays.
+    __device__ __forceinline__ bool events_ok(const Meta &m, const Ev &e) {
+        bool bad = m.nrat > kMaxRatingsPerChunk || m.nload + m.nrel > kMaxEventsPerChunk || m.nrat < 0;
+        if (lane < m.nload) {
+            const int k = ev_kind(e.sk);
+            bad |= ev_slot(e.sk) >= a.slots || (k != kEvLoadRow && k != kEvLoadItem) || e.id < 0 ||
+                   e.id >= (k == kEvLoadRow ? a.m : a.n) || e.evict >= a.m;
+        } else if (lane < m.nload + m.nrel) {
+            bad |= ev_kind(e.sk) != kEvRelease || ev_slot(e.sk) >= a.slots || e.id < 0 || e.id >= a.n;
+        }
+        return __builtin_amdgcn_ballot_w64(bad) == 0;
+    }
+    __device__ __forceinline__ bool ratings_ok(const Meta &m, const RatingRec &rr) {
+        bool bad = false;
+        if (lane < m.nrat) bad = (int)(rr.slots & 255) >= a.slots || (int)((rr.slots >> 8) & 255) >= a.slots;
+        return __builtin_amdgcn_ballot_w64(bad) == 0;
+    }
+
+    __device__ __forceinline__ uint64_t kind_mask(const Ev &e, int nload, int kind) {
+        return __builtin_amdgcn_ballot_w64(lane < nload && ev_kind(e.sk) == kind);
+    }
+
+    // Write back the rows a chunk's loads evict (their slots must be free).
+    __device__ __forceinline__ void evict(const Ev &e, int nload) {
+        slots_to_global(a.W, false, e.evict, e.sk, nload);
+    }
+
+    // Load the vectors of the events flagged in `mask` into their slots: each event lane
+    // computes its source address and LDS slot address once, then one LDS-DMA
+    // instruction per vector (rows plain, items device-coherent).
+    __device__ __forceinline__ void load_vectors(const Ev &e, int nload, uint64_t mask) {
+        const bool item = ev_kind(e.sk) == kEvLoadItem;
+        const uint64_t src = (uint64_t)(uintptr_t)((item ? a.H : a.W) + (int64_t)e.id * kp);
+        const uint32_t s_lo = (uint32_t)src, s_hi = (uint32_t)(src >> 32);
+        const int dst = ev_slot(e.sk) * kp;
+        const uint64_t items = mask & kind_mask(e, nload, kEvLoadItem), rows = mask & ~items;
+        const bool on = lane < (kp >> 2);
+        for (uint64_t mk = rows; mk; mk &= mk - 1) {
+            const int t = __builtin_ctzll(mk);
+            const uint64_t p = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(s_lo, t) |
+                               ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(s_hi, t) << 32);
+            float *d = L.vec + __builtin_amdgcn_readlane(dst, t);
+            if (on)
+                __builtin_amdgcn_global_load_lds((const void *)((const float *)(uintptr_t)p + lane * 4),
+                                                 (lds_void_t *)d, 16, 0, 0);
+        }
+        for (uint64_t mk = items; mk; mk &= mk - 1) {
+            const int t = __builtin_ctzll(mk);
+            const uint64_t p = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(s_lo, t) |
+                               ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(s_hi, t) << 32);
+            float *d = L.vec + __builtin_amdgcn_readlane(dst, t);
+            if (on)
+                __builtin_amdgcn_global_load_lds((const void *)((const float *)(uintptr_t)p + lane * 4),
+                                                 (lds_void_t *)d, 16, 0, 16);
+        }
+    }
+
+    __device__ __forceinline__ void run() {
+        if (total <= 0) return;
+        // Local plan index of chunk x+4 (advanced with wrap-around, no division).
+        int64_t lc4 = 0;
+        auto next_lc = [&](int64_t lc) { return lc + 1 == nck ? 0 : lc + 1; };
+        Meta m0 = load_meta(a, c0, lc4, 0 < total);
+        lc4 = next_lc(lc4);
+        Meta m1 = load_meta(a, c0, lc4, 1 < total);
+        lc4 = next_lc(lc4);
+        Meta m2 = load_meta(a, c0, lc4, 2 < total);
+        lc4 = next_lc(lc4);
+        Meta m3 = load_meta(a, c0, lc4, 3 < total);
+        lc4 = next_lc(lc4);
+        Ev e0 = load_ev(a.events + m0.ev, m0.nload + m0.nrel, lane);
+        Ev e1 = load_ev(a.events + m1.ev, m1.nload + m1.nrel, lane);
+        Ev e2 = load_ev(a.events + m2.ev, m2.nload + m2.nrel, lane);
+        RatingRec rr0{0u, 0.0f}, rr1{0u, 0.0f};
+        if (lane < m0.nrat) rr0 = a.ratings[m0.rat + lane];
+        wait_vm();
+        if (!events_ok(m0, e0) || !events_ok(m1, e1) || !events_ok(m2, e2)) {
+            stop(2u);
+            return;
+        }
+        uint32_t pr1 = 0, pr2 = 0;
+        if (lane < m1.nload && ev_kind(e1.sk) == kEvLoadItem)
+            pr1 = __hip_atomic_load(a.tok_done + e1.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t fm0 = 0, fm1 = 0;  // loads of chunk x / x+1 already issued
+        int64_t lx = 0;
+        int ex = a.epoch0;
+        for (int64_t x = 0; x < total; ++x) {
+            // Loads of this chunk issued in iteration x-1 and write-backs are complete.
+            uint64_t t0 = tick(prof);
+            wait_vm();
+            t_mem += tick(prof) - t0;
+            if (pub_n > 0) publish();
+            if (!events_ok(m2, e2)) {
+                stop(2u);
+                return;
+            }
+            const int64_t xbase = x - lx;  // first chunk of this epoch
+            // A new epoch starts once the previous one has been written back entirely.
+            if (x > 0 && lx == 0) {
+                if (!wait_done(x)) { stop(0u); return; }
+                retire();
+            }
+            if (!ratings_ok(m0, rr0)) {
+                stop(2u);
+                return;
+            }
+            const uint64_t loads = m0.nload >= 64 ? ~0ull : ((1ull << m0.nload) - 1ull);
+            const uint64_t rem = loads & ~fm0;
+            n_loads += m0.nload;
+            if (rem) {
+                // Not prefetched: the first chunk of an epoch, or items that were not free
+                // when polled.
+                n_late += __builtin_popcountll(rem);
+                if (fm0 == 0) {
+                    int64_t need = xbase + m0.need;
+                    if (x - kRing + 1 > need) need = x - kRing + 1;
+                    if (!wait_done(need)) { stop(0u); return; }
+                    retire();
+                    evict(e0, m0.nload);
+                }
+                const uint64_t items = kind_mask(e0, m0.nload, kEvLoadItem) & rem;
+                if (items && !acquire(e0, items, ex)) { stop(0u); return; }
+                load_vectors(e0, m0.nload, rem);
+                t0 = tick(prof);
+                wait_vm();
+                t_mem += tick(prof) - t0;
+            }
+            uint64_t tc = tick(prof);
+            // Ring entry for the compute wave: ratings, and the items released after it.
+            const int ent = (int)(x & (kRing - 1));
+            if (lane < m0.nrat) L.rat[ent * 64 + lane] = rr0;
+            {
+                const int src = (m0.nload + lane) & 63;
+                const int rid = __shfl(e0.id, src), rsk = __shfl(e0.sk, src), rvis = __shfl(e0.vis, src);
+                if (lane < m0.nrel) {
+                    L.rel_id[ent * 64 + lane] = rid;
+                    L.rel_slot[ent * 64 + lane] = ev_slot(rsk);
+                    L.rel_tk[ent * 64 + lane] = ev_ticket(rvis, ex) + 1u;
+                }
+            }
+            if (lane == 0) {
+                L.cnt[2 * ent] = m0.nrat;
+                L.cnt[2 * ent + 1] = m0.nrel;
+            }
+            wait_lgkm();
+            if (lane == 0) sync_store(&L.sync[kStaged], (int)(x + 1));
+            t_commit += tick(prof) - tc;
+            if (a.trace) {
+                // One record per item taken over, in event order (the order of the visits).
+                const uint64_t im = kind_mask(e0, m0.nload, kEvLoadItem);
+                int64_t base = 0;
+                if (lane == 0 && im) base = (int64_t)atomicAdd((unsigned long long *)a.trace_len,
+                                                               (unsigned long long)__builtin_popcountll(im));
+                base = __shfl(base, 0);
+                const int64_t slot = base + __builtin_popcountll(im & ((1ull << lane) - 1ull));
+                if (((im >> lane) & 1ull) && slot < a.trace_cap) {
+                    a.trace[4 * slot + 0] = q;
+                    a.trace[4 * slot + 1] = e0.id;
+                    a.trace[4 * slot + 2] = ex;
+                    a.trace[4 * slot + 3] = (int32_t)ev_ticket(e0.vis, ex);
+                }
+            }
+            tc = tick(prof);
+            retire();
+            t_retire += tick(prof) - tc;
+
+            // Chunk x+1 (not across an epoch boundary: the epoch's rows are written back
+            // first): once its slots are free, write back the rows it evicts and load its
+            // rows and the items seen free.  Then poll chunk x+2, read events x+3 and the
+            // record of x+4.
+            const int64_t lx1 = lx + 1 == nck ? 0 : lx + 1;
+            const int ex1 = lx + 1 == nck ? ex + 1 : ex;
+            fm1 = 0;
+            if (x + 1 < total) {
+                if (lane < m1.nrat) rr1 = a.ratings[m1.rat + lane];
+                if (lx1 != 0) {
+                    int64_t need = xbase + m1.need;
+                    if (x + 1 - kRing + 1 > need) need = x + 1 - kRing + 1;
+                    if (!wait_done(need)) { stop(0u); return; }
+                    tc = tick(prof);
+                    retire();
+                    t_retire += tick(prof) - tc;
+                    tc = tick(prof);
+                    evict(e1, m1.nload);
+                    t_evict += tick(prof) - tc;
+                    tc = tick(prof);
+                    const uint64_t rows = kind_mask(e1, m1.nload, kEvLoadRow);
+                    const bool ready =
+                        lane < m1.nload && ev_kind(e1.sk) == kEvLoadItem && pr1 == ev_ticket(e1.vis, ex1);
+                    fm1 = rows | __builtin_amdgcn_ballot_w64(ready);
+                    load_vectors(e1, m1.nload, fm1);
+                    t_issue += tick(prof) - tc;
+                }
+            }
+            tc = tick(prof);
+            pr2 = 0;
+            if (x + 2 < total && lane < m2.nload && ev_kind(e2.sk) == kEvLoadItem)
+                pr2 = __hip_atomic_load(a.tok_done + e2.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const Ev e3 = load_ev(a.events + m3.ev, m3.nload + m3.nrel, lane);
+            const Meta m4 = load_meta(a, c0, lc4, x + 4 < total);
+            lc4 = next_lc(lc4);
+            t_poll += tick(prof) - tc;
+
+            m0 = m1;
+            m1 = m2;
+            m2 = m3;
+            m3 = m4;
+            e0 = e1;
+            e1 = e2;
+            e2 = e3;
+            pr1 = pr2;
+            rr0 = rr1;
+            fm0 = fm1;
+            lx = lx1;
+            ex = ex1;
+        }
+        // Everything computed: pass on the last items, write back the last rows.
+        if (!wait_done(total)) { stop(0u); return; }
+        retire();
+        wait_vm();
+        publish();
+    }
+};
+
+template <int VEC, int NR16>
+__global__ __launch_bounds__(128) void k_worker(TrainArgs a, uint32_t *abort_flag) {
+    extern __shared__ float4 lds4[];
+    const int q = blockIdx.x;
+    const int64_t c0 = a.wck[q], nck = a.wck[q + 1] - c0;
+    if (nck <= 0 || a.epochs <= 0) return;
+    const Lds L = lds_layout(lds4, a.slots, a.kp);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (threadIdx.x < 4) L.sync[threadIdx.x] = 0;
+    __syncthreads();
+    if (wave == 0) {
+        compute_wave<VEC, NR16>(a, L, nck, q, lane);
+    } else {
+        const uint64_t t_start = tick(a.wstats != nullptr);
+        MemoryWave mw(a, L, c0, nck, q, lane, abort_flag);
+        mw.run();
+        if (a.wstats && lane == 0) {
+            int64_t *w = a.wstats + (int64_t)q * kWStatCount;
+            w[kWStatAcquire] = (int64_t)mw.t_acq;
+            w[kWStatMemWait] = (int64_t)mw.t_mem;
+            w[kWStatSlotWait] = (int64_t)mw.t_slot;
+            w[kWStatMemTotal] = (int64_t)(wall_clock64() - t_start);
+            w[kWStatCommit] = (int64_t)mw.t_commit;
+            w[kWStatRetire] = (int64_t)mw.t_retire;
+            w[kWStatIssue] = (int64_t)mw.t_issue;
+            w[kWStatLoads] = mw.n_loads;
+            w[kWStatLate] = mw.n_late;
+            w[14] = (int64_t)mw.t_evict;
+            w[15] = (int64_t)mw.t_poll;
+        }
     }
 }
 
 template <int VEC, int NR16>
 hipError_t launch_t(const TrainArgs &a, int32_t p, size_t lds, uint32_t *abort_flag, hipStream_t st) {
-    hipLaunchKernelGGL((k_train<VEC, NR16>), dim3(p), dim3(64), lds, st, a, abort_flag);
+    hipLaunchKernelGGL((k_worker<VEC, NR16>), dim3(p), dim3(128), lds, st, a, abort_flag);
     return hipGetLastError();
 }
 
 template <int VEC, int NR16>
-const void *kernel_ptr() { return (const void *)&k_train<VEC, NR16>; }
+const void *kernel_ptr() { return (const void *)&k_worker<VEC, NR16>; }
 
 const void *pick_kernel(int kp) {
     if (kp <= 16) return kernel_ptr<1, 1>();
@@ -617,31 +790,25 @@ const void *pick_kernel(int kp) {
 
 }  // namespace
 
-size_t train_lds_bytes(int32_t kp, int32_t rmax, int32_t tmax) {
-    // one staging area and one scratch line for lanes beyond the vector width
-    return (size_t)(rmax + tmax) * (size_t)kp * sizeof(float) + 64 * 4 * sizeof(float);
+size_t train_lds_bytes(int32_t kp, int32_t slots) {
+    return (size_t)slots * (size_t)kp * sizeof(float) + kRingBytes + 64 * 4 * sizeof(float);
 }
 
-bool train_chunk_fits(int32_t kp, int32_t rmax, int32_t tmax) {
-    const int lpr = kp / 4, rpi = 64 / lpr;
-    return rmax <= rpi * kRowPiecesPerLane && tmax <= rpi * kItemPiecesPerLane && rmax + tmax <= kMaxSlots;
-}
-
-hipError_t train_max_workers(int32_t kp, int32_t rmax, int32_t tmax, int32_t *max_workers) {
+hipError_t train_max_workers(int32_t kp, int32_t slots, int32_t *max_workers) {
     int dev = 0, cus = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const size_t lds = train_lds_bytes(kp, rmax, tmax);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(kp), 64, lds);
+    const size_t lds = train_lds_bytes(kp, slots);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(kp), 128, lds);
     if (e != hipSuccess) return e;
     *max_workers = nb * cus;
     return hipSuccess;
 }
 
 hipError_t launch_train(const TrainArgs &a, int32_t p, uint32_t *abort_flag, hipStream_t st) {
-    const size_t lds = train_lds_bytes(a.kp, a.rmax, a.tmax);
+    const size_t lds = train_lds_bytes(a.kp, a.slots);
     if (a.kp <= 16) return launch_t<1, 1>(a, p, lds, abort_flag, st);
     if (a.kp <= 32) return launch_t<1, 2>(a, p, lds, abort_flag, st);
     if (a.kp <= 64) return launch_t<1, 4>(a, p, lds, abort_flag, st);

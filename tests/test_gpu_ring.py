@@ -52,24 +52,25 @@ def oracle_run(prob, W0, H0, hp, P, seed, epochs):
 
 
 CASES = [
-    # m, n, nnz, k, P, degrees, rows_per_chunk, items_per_chunk
-    (300, 200, 6_000, 3, 4, "uniform", 2, 1),        # tiny chunks: many carries and splits
+    # m, n, nnz, k, P, degrees, LDS slots, loads per chunk (0 = library default)
+    (300, 200, 6_000, 3, 4, "uniform", 4, 2),         # tiny slot budget: constant eviction
     (2_000, 1_000, 90_000, 16, 64, "uniform", 0, 0),  # the tiny workload's shape
     (500, 80, 10_000, 100, 16, "uniform", 0, 0),      # k = 100 (two floats per lane)
     (400, 300, 20_000, 130, 32, "uniform", 0, 0),     # four floats per lane
     (200, 150, 9_000, 256, 8, "uniform", 0, 0),       # largest k
-    (50, 3_000, 8_000, 32, 7, "uniform", 4, 2),       # wide matrix, odd worker count
-    (3_000, 500, 60_000, 64, 24, "zipf", 5, 3),       # skewed degrees
+    (50, 3_000, 8_000, 32, 7, "uniform", 6, 3),       # wide matrix, odd worker count
+    (3_000, 500, 60_000, 64, 24, "zipf", 8, 4),       # skewed degrees
     (700, 90, 5_000, 16, 1, "uniform", 0, 0),         # a single worker
-    (257, 129, 3_001, 5, 3, "zipf", 3, 2),            # ragged sizes, odd k
+    (257, 129, 3_001, 5, 3, "zipf", 2, 2),            # ragged sizes, odd k, two slots
+    (1_200, 900, 50_000, 100, 40, "zipf", 96, 32),    # roomy slots: rows cached across items
 ]
 
 
-@pytest.mark.parametrize("m,n,nnz,k,P,deg,rpc,ipc", CASES)
-def test_ring_one_epoch_matches_oracle(m, n, nnz, k, P, deg, rpc, ipc):
+@pytest.mark.parametrize("m,n,nnz,k,P,deg,slots,loads", CASES)
+def test_ring_one_epoch_matches_oracle(m, n, nnz, k, P, deg, slots, loads):
     prob, W0, H0, hp = make(m, n, nnz, k=k, seed=m + n + k, degrees=deg)
     seed = 1234 + P
-    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [1], rows_per_chunk=rpc, items_per_chunk=ipc)
+    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [1], lds_slots=slots, loads_per_chunk=loads)
     Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 1)
     assert rel(W, Wo) < TOL_1EPOCH and rel(H, Ho) < TOL_1EPOCH, (rel(W, Wo), rel(H, Ho))
     # evaluation: same factors, FP64 on both sides
@@ -85,8 +86,8 @@ def test_ring_one_epoch_matches_oracle(m, n, nnz, k, P, deg, rpc, ipc):
 def test_ring_multi_epoch_and_split_calls():
     prob, W0, H0, hp = make(1_500, 700, 40_000, k=24, seed=5, beta=0.05, gamma=1.5)
     P, seed = 12, 99
-    _, W1, H1 = gpu_run(prob, W0, H0, hp, P, seed, [3], rows_per_chunk=6, items_per_chunk=3)
-    m2, W2, H2 = gpu_run(prob, W0, H0, hp, P, seed, [1, 2], rows_per_chunk=6, items_per_chunk=3)
+    _, W1, H1 = gpu_run(prob, W0, H0, hp, P, seed, [3], lds_slots=6, loads_per_chunk=3)
+    m2, W2, H2 = gpu_run(prob, W0, H0, hp, P, seed, [1, 2], lds_slots=6, loads_per_chunk=3)
     # the ring schedule is one fixed serial order: identical on every run and call split
     assert np.array_equal(W1, W2) and np.array_equal(H1, H2)
     Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 3)
@@ -156,8 +157,7 @@ def test_trace_records_every_item_visit_and_replays():
     per-item visit numbers; replaying it in the oracle reproduces the GPU factors."""
     prob, W0, H0, hp = make(600, 300, 12_000, k=16, seed=21)
     P, seed, E = 6, 17, 2
-    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [E], record_trace=True, rows_per_chunk=5,
-                          items_per_chunk=3)
+    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [E], record_trace=True, lds_slots=5, loads_per_chunk=3)
     tr = model.trace()
     row, col = prob.row.numpy(), prob.col.numpy()
     rs = oracle.partition(prob.m, row, P)
