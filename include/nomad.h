@@ -74,6 +74,8 @@ typedef struct {
                                 (2..64, and at most what one staging round holds for k);
                                 0 = default */
     int32_t record_trace;    /* 1 = record every (worker, item) visit for replay */
+    int32_t collect_stats;   /* 1 = time the phases of every worker (nomad_get_worker_stats);
+                                counts are always collected */
     uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing */
 } nomad_config;
 

@@ -16,6 +16,7 @@ struct nomad_ctx {
     nomad_config cfg{};
     int64_t m = 0, n = 0, nnz = 0;
     int32_t k = 0, kp = 0, p = 0;
+    int32_t group = 1;                 // workers per workgroup of the training kernel
     hipStream_t stream = nullptr;
     Plan plan;
     float *W = nullptr, *H = nullptr;  // m x kp, n x kp (row stride kp, padding kept at 0)
@@ -98,6 +99,7 @@ void nomad_config_default(nomad_config *cfg) {
     cfg->lds_slots = 0;
     cfg->loads_per_chunk = 0;
     cfg->record_trace = 0;
+    cfg->collect_stats = 0;
     cfg->seed = 0;
 }
 
@@ -166,7 +168,8 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
         return bail(fail(c, NOMAD_EINVAL, "nomad_init: %d LDS slots need %zu bytes of LDS, device allows %d",
                          slots, lds, max_lds));
     int32_t maxw = 0;
-    hipError_t he = nomad::train_max_workers(c->kp, slots, &maxw);
+    c->group = nomad::train_group(c->kp, slots, (size_t)max_lds);
+    hipError_t he = nomad::train_max_workers(c->kp, slots, c->group, &maxw);
     if (he != hipSuccess) return bail(hip_fail(c, he, "nomad_init: occupancy query"));
     int32_t p = cfg->workers;
     if (p <= 0) p = maxw < 1024 ? maxw : 1024;
@@ -255,6 +258,8 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         a.tok_done = c->tok_done;
         a.kp = c->kp;
         a.slots = c->plan.slots;
+        a.p = c->p;
+        a.group = c->group;
         a.epoch0 = (int32_t)c->epochs_done;
         a.epochs = epochs;
         a.lambda = c->cfg.lambda;
@@ -279,6 +284,7 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         HIPTRY(c, hipMemsetAsync(c->tok_done + c->n, 0, sizeof(uint32_t), st), "train: reset");
         HIPTRY(c, hipMemsetAsync(c->wstats, 0, sizeof(int64_t) * nomad::kWStatCount * (size_t)c->p, st), "train: reset");
         a.wstats = c->wstats;
+        a.timing = c->cfg.collect_stats != 0;
         HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
         HIPTRY(c, nomad::launch_train(a, c->p, c->tok_done + c->n, st), "train: launch");
         HIPTRY(c, hipEventRecord(c->ev1, st), "train: event");

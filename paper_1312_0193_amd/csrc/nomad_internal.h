@@ -132,10 +132,13 @@ struct TrainArgs {
     uint32_t *tok_done;       // n: completed visits of each item (across calls)
     int32_t kp;
     int32_t slots;            // S
+    int32_t p;                // workers
+    int32_t group;            // workers per workgroup (1, 2 or 4)
     int32_t epoch0, epochs;
     float lambda;
     double alpha, beta, gamma;
-    int64_t *wstats;          // optional: per worker kWStatCount counters
+    int64_t *wstats;          // per worker kWStatCount counters
+    bool timing;              // also time the phases (costs clock reads)
     int32_t *trace;           // optional: 4 ints per visit
     int64_t *trace_len;       // optional counter
     int64_t trace_cap;
@@ -151,9 +154,10 @@ hipError_t build_plan(Plan *plan, int64_t m, int64_t n, int64_t nnz, const int32
 void free_plan(Plan *plan);
 
 // train.hip
-size_t train_lds_bytes(int32_t kp, int32_t slots);
+size_t train_lds_bytes(int32_t kp, int32_t slots);  // per worker
+int32_t train_group(int32_t kp, int32_t slots, size_t max_lds_per_block);
 hipError_t launch_train(const TrainArgs &a, int32_t p, uint32_t *abort_flag, hipStream_t stream);
-hipError_t train_max_workers(int32_t kp, int32_t slots, int32_t *max_workers);
+hipError_t train_max_workers(int32_t kp, int32_t slots, int32_t group, int32_t *max_workers);
 
 // eval.hip: FP64 RMSE / objective with a deterministic compensated sum.
 hipError_t eval_sums(const float *W, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,

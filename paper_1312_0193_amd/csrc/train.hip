@@ -50,19 +50,34 @@ __device__ __forceinline__ float rl_f(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
-// Sum over the wavefront of x; lanes beyond the active 16-lane rows must hold 0.
-// Row-wise butterfly with DPP, then row broadcasts toward lane 63 (or 31 / 15).
+// Cross-row steps of a wavefront sum, on gfx950's lane swaps.  With the same value in
+// both operands, v_permlane16_swap leaves rows (0,0,2,2) in one register and (1,1,3,3)
+// in the other; v_permlane32_swap leaves the lower half in both halves of one register
+// and the upper half in the other.  Written as asm: the compiler's own form of these
+// swaps returns the first result in place of the second.  The s_nop pairs cover the
+// VALU-to-swap and swap-to-VALU hazards.
+__device__ __forceinline__ float swap_add16(float x) {
+    float y = x;
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
+    return x + y;
+}
+__device__ __forceinline__ float swap_add32(float x) {
+    float y = x;
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
+    return x + y;
+}
+
+// Sum over the first NR16 16-lane rows of x, returned in every lane (lanes beyond the
+// active rows must hold 0): butterfly within each row with DPP, then the row swaps.
 template <int NR16>
 __device__ __forceinline__ float wave_sum(float x) {
     x += DPP_F(x, 0xB1, 0xF, true);   // quad_perm [1,0,3,2]
     x += DPP_F(x, 0x4E, 0xF, true);   // quad_perm [2,3,0,1]
     x += DPP_F(x, 0x124, 0xF, true);  // row_ror 4
     x += DPP_F(x, 0x128, 0xF, true);  // row_ror 8
-    if constexpr (NR16 == 1) return rl_f(x, 15);
-    x += DPP_F(x, 0x142, 0xA, false); // row_bcast 15 into rows 1 and 3
-    if constexpr (NR16 == 2) return rl_f(x, 31);
-    x += DPP_F(x, 0x143, 0xC, false); // row_bcast 31 into rows 2 and 3
-    return rl_f(x, 63);
+    if constexpr (NR16 >= 2) x = swap_add16(x);
+    if constexpr (NR16 >= 4) x = swap_add32(x);
+    return x;
 }
 
 template <int VEC>
@@ -117,10 +132,15 @@ struct Lds {
     int32_t *rel_slot;  // kRing x 64
     int32_t *cnt;       // kRing x 2: ratings, releases
     int32_t *sync;      // staged, done, stop, unused
-    float *dump;        // 64 x 4: writes of lanes beyond the vector width
+    float *zero;        // 64 x 4 zeros: read and written by lanes beyond the vector width
 };
 
 constexpr size_t kRingBytes = (size_t)kRing * 64 * (sizeof(RatingRec) + 3 * sizeof(int32_t)) + kRing * 2 * 4 + 4 * 4;
+
+// LDS of one worker (a multiple of 16 bytes): slots, ring, synchronisation, zero line.
+__host__ __device__ inline size_t worker_lds_bytes(int kp, int slots) {
+    return (size_t)slots * (size_t)kp * sizeof(float) + kRingBytes + 64 * 4 * sizeof(float);
+}
 
 __device__ __forceinline__ Lds lds_layout(void *base, int S, int kp) {
     char *p = (char *)base;
@@ -139,7 +159,7 @@ __device__ __forceinline__ Lds lds_layout(void *base, int S, int kp) {
     p += kRing * 2 * 4;
     L.sync = (int32_t *)p;
     p += 4 * 4;
-    L.dump = (float *)p;
+    L.zero = (float *)p;
     return L;
 }
 
@@ -153,73 +173,98 @@ __device__ __forceinline__ void sync_store(int32_t *p, int v) {
 // ---------------------------------------------------------------------------------------
 // Compute wave.
 
-// SGD over one chunk's ratings in plan order, on LDS.  The next rating's row (and item,
-// when it changes) is read ahead; a read-ahead row equal to the current one takes the
-// freshly updated value.  Lanes beyond the vector width compute on zeros and write to a
-// scratch line of LDS.
+// SGD over one chunk's ratings in plan order, on LDS.
+//
+// Lane l holds elements [VEC l, VEC l + VEC) of a vector; lanes beyond the vector width
+// read and write a line of zeros (their terms add nothing to the dot products).  Every
+// rating issues the same LDS operations: write its row and item, then read the row and
+// item of the rating two ahead into one of two alternating register sets.  A read-ahead
+// row is stale only if it is the row of the rating just before it, which then takes the
+// freshly updated registers instead; likewise for an item continuing its run (an item
+// has a single run of ratings per chunk, so the first read of a run is never stale).
+template <int VEC>
+struct SgdLane {
+    float *base;  // this lane's elements of slot 0 (or the zero line)
+    int stride;   // floats per slot (kp), 0 for lanes beyond the vector width
+};
+
+template <int VEC>
+__device__ __forceinline__ void read_vec(const SgdLane<VEC> &ln, int slot, float (&v)[VEC]) {
+    lds_read<VEC>(ln.base + __umul24(slot, ln.stride), v);
+}
+template <int VEC>
+__device__ __forceinline__ void write_vec(const SgdLane<VEC> &ln, int slot, const float (&v)[VEC]) {
+    lds_write<VEC>(ln.base + __umul24(slot, ln.stride), v);
+}
+
+template <int VEC>
+struct SgdState {
+    float w[VEC], h[VEC];  // rating x-1's updated row and item
+    int rs_p, ts_p;        // their slots (-1: none yet)
+};
+
 template <int VEC, int NR16>
-__device__ __forceinline__ void sgd_chunk(float *vec, float *dump, int kp, const RatingRec &rr, int nrat, float s,
-                                          float shrink, int lane) {
-    if (nrat <= 0) return;
-    const bool on = lane * VEC < kp;
-    const int roff = on ? lane * VEC : 0;
-    float *const wbase = on ? vec + lane * VEC : dump + lane * VEC;  // write address base
-    const int r_sl = (int)rr.slots;
-    const float r_val = rr.r;
-    int sl = rl_i(r_sl, 0);
-    float r = rl_f(r_val, 0);
-    int rs = sl & 255, ts = (sl >> 8) & 255;
+__device__ __forceinline__ void sgd_step(const SgdLane<VEC> &ln, SgdState<VEC> &S, float (&wb)[VEC],
+                                         float (&hb)[VEC], int r_sl, float r_val, int x, int nrat, float s,
+                                         float shrink) {
+    const int sl = rl_i(r_sl, x);
+    const int rs = sl & 255, ts = (sl >> 8) & 255;
+    const float r = rl_f(r_val, x);
+    const bool same_row = rs == S.rs_p, same_item = ts == S.ts_p;
     float w[VEC], h[VEC];
-    lds_read<VEC>(vec + rs * kp + roff, w);
-    lds_read<VEC>(vec + ts * kp + roff, h);
 #pragma unroll
     for (int v = 0; v < VEC; ++v) {
-        w[v] = on ? w[v] : 0.0f;
-        h[v] = on ? h[v] : 0.0f;
+        w[v] = same_row ? S.w[v] : wb[v];
+        h[v] = same_item ? S.h[v] : hb[v];
     }
-    for (int x = 0; x < nrat; ++x) {
-        const int xn = x + 1 < nrat ? x + 1 : x;
-        const int sln = rl_i(r_sl, xn);
-        const float rn = rl_f(r_val, xn);
-        const int rsn = sln & 255, tsn = (sln >> 8) & 255;
-        const bool switch_item = tsn != ts;
-        float wn[VEC], hn[VEC];
-        lds_read<VEC>(vec + rsn * kp + roff, wn);
-        if (switch_item) lds_read<VEC>(vec + tsn * kp + roff, hn);
-        float d = 0.0f;
+    float d = 0.0f;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) d = fmaf(w[v], h[v], d);
-        d = wave_sum<NR16>(d);
-        const float se = s * (r - d);
+    for (int v = 0; v < VEC; ++v) d = fmaf(w[v], h[v], d);
+    d = wave_sum<NR16>(d);
+    const float se = s * (r - d);
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            const float wv = w[v], hv = h[v];
-            w[v] = fmaf(se, hv, shrink * wv);
-            h[v] = fmaf(se, wv, shrink * hv);
-        }
-        lds_write<VEC>(wbase + rs * kp, w);
-        if (x + 1 == nrat) {
-            lds_write<VEC>(wbase + ts * kp, h);
-            break;
-        }
-        if (switch_item) {
-            lds_write<VEC>(wbase + ts * kp, h);
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) h[v] = on ? hn[v] : 0.0f;
-        }
-        if (rsn != rs) {
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) w[v] = on ? wn[v] : 0.0f;
-        }
-        rs = rsn;
-        ts = tsn;
-        r = rn;
+    for (int v = 0; v < VEC; ++v) {
+        S.w[v] = fmaf(se, h[v], shrink * w[v]);
+        S.h[v] = fmaf(se, w[v], shrink * h[v]);
     }
+    write_vec<VEC>(ln, rs, S.w);
+    write_vec<VEC>(ln, ts, S.h);
+    S.rs_p = rs;
+    S.ts_p = ts;
+    const int x2 = x + 2 < nrat ? x + 2 : nrat - 1;
+    const int sl2 = rl_i(r_sl, x2);
+    read_vec<VEC>(ln, sl2 & 255, wb);
+    read_vec<VEC>(ln, (sl2 >> 8) & 255, hb);
+}
+
+template <int VEC, int NR16>
+__device__ __forceinline__ void sgd_chunk(const SgdLane<VEC> &ln, const RatingRec &rr, int nrat, float s,
+                                          float shrink) {
+    if (nrat <= 0) return;
+    const int r_sl = (int)rr.slots;
+    const float r_val = rr.r;
+    float wb0[VEC], hb0[VEC], wb1[VEC], hb1[VEC];
+    const int sl0 = rl_i(r_sl, 0), sl1 = rl_i(r_sl, nrat > 1 ? 1 : 0);
+    read_vec<VEC>(ln, sl0 & 255, wb0);
+    read_vec<VEC>(ln, (sl0 >> 8) & 255, hb0);
+    read_vec<VEC>(ln, sl1 & 255, wb1);
+    read_vec<VEC>(ln, (sl1 >> 8) & 255, hb1);
+    SgdState<VEC> S;
+    S.rs_p = -1;
+    S.ts_p = -1;
+#pragma unroll
+    for (int v = 0; v < VEC; ++v) S.w[v] = S.h[v] = 0.0f;
+    int x = 0;
+    for (; x + 1 < nrat; x += 2) {
+        sgd_step<VEC, NR16>(ln, S, wb0, hb0, r_sl, r_val, x, nrat, s, shrink);
+        sgd_step<VEC, NR16>(ln, S, wb1, hb1, r_sl, r_val, x + 1, nrat, s, shrink);
+    }
+    if (x < nrat) sgd_step<VEC, NR16>(ln, S, wb0, hb0, r_sl, r_val, x, nrat, s, shrink);
 }
 
 template <int VEC, int NR16>
 __device__ __forceinline__ void compute_wave(const TrainArgs &a, const Lds &L, int64_t nck, int q, int lane) {
-    const bool prof = a.wstats != nullptr;
+    const bool prof = a.timing;
     const uint64_t t_start = tick(prof);
     uint64_t t_sgd = 0, t_starve = 0;
     int64_t n_rat = 0;
@@ -227,6 +272,10 @@ __device__ __forceinline__ void compute_wave(const TrainArgs &a, const Lds &L, i
     int epoch = -1, ex = a.epoch0;
     int64_t lx = 0;
     float s_step = 0.0f, s_shrink = 1.0f;
+    const bool on = lane * VEC < a.kp;
+    SgdLane<VEC> ln;
+    ln.base = on ? L.vec + lane * VEC : L.zero + lane * VEC;
+    ln.stride = on ? a.kp : 0;
     for (int64_t x = 0; x < total; ++x) {
         if (sync_load(&L.sync[kStaged]) <= x) {
             const uint64_t t0 = tick(prof);
@@ -251,7 +300,7 @@ __device__ __forceinline__ void compute_wave(const TrainArgs &a, const Lds &L, i
             s_shrink = 1.0f - s_step * a.lambda;
         }
         const uint64_t t0 = tick(prof);
-        sgd_chunk<VEC, NR16>(L.vec, L.dump, a.kp, rr, nrat, s_step, s_shrink, lane);
+        sgd_chunk<VEC, NR16>(ln, rr, nrat, s_step, s_shrink);
         wait_lgkm();
         t_sgd += tick(prof) - t0;
         n_rat += nrat;
@@ -261,9 +310,9 @@ __device__ __forceinline__ void compute_wave(const TrainArgs &a, const Lds &L, i
             ++ex;
         }
     }
-    if (prof && lane == 0) {
+    if (a.wstats && lane == 0) {
         int64_t *w = a.wstats + (int64_t)q * kWStatCount;
-        w[kWStatTotal] = (int64_t)(wall_clock64() - t_start);
+        w[kWStatTotal] = (int64_t)(tick(prof) - t_start);
         w[kWStatChunks] = total;
         w[kWStatSgd] = (int64_t)t_sgd;
         w[kWStatRatings] = n_rat;
@@ -331,8 +380,8 @@ __device__ __forceinline__ uint32_t lds_addr(const float *p) {
 // slots from those the wave's LDS-DMA loads write, and would make every read wait for
 // all outstanding stores).  The slots read here are never the target of a load in
 // flight: a slot is read before any load into it is issued.
-__device__ __forceinline__ void lds_read4x4_now(const float *p0, const float *p1, const float *p2, const float *p3,
-                                                f32x4_t &v0, f32x4_t &v1, f32x4_t &v2, f32x4_t &v3) {
+__device__ __forceinline__ void lds_read4x4_now(uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3, f32x4_t &v0,
+                                                f32x4_t &v1, f32x4_t &v2, f32x4_t &v3) {
     asm volatile(
         "ds_read_b128 %0, %4\n\t"
         "ds_read_b128 %1, %5\n\t"
@@ -340,7 +389,7 @@ __device__ __forceinline__ void lds_read4x4_now(const float *p0, const float *p1
         "ds_read_b128 %3, %7\n\t"
         "s_waitcnt lgkmcnt(0)"
         : "=&v"(v0), "=&v"(v1), "=&v"(v2), "=&v"(v3)
-        : "v"(lds_addr(p0)), "v"(lds_addr(p1)), "v"(lds_addr(p2)), "v"(lds_addr(p3))
+        : "v"(p0), "v"(p1), "v"(p2), "v"(p3)
         : "memory");
 }
 
@@ -362,7 +411,7 @@ struct MemoryWave {
     __device__ MemoryWave(const TrainArgs &a_, const Lds &L_, int64_t c0_, int64_t nck_, int q_, int lane_,
                           uint32_t *abort_)
         : a(a_), L(L_), c0(c0_), nck(nck_), total(nck_ * a_.epochs), q(q_), lane(lane_), kp(a_.kp),
-          abort_flag(abort_), prof(a_.wstats != nullptr) {}
+          abort_flag(abort_), prof(a_.timing) {}
 
     __device__ __forceinline__ void publish() {
         if (lane < pub_n) __hip_atomic_store(a.tok_done + pub_id, pub_tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -372,32 +421,34 @@ struct MemoryWave {
     // Copy `count` vectors from LDS slots to global memory (W, or H with device-coherent
     // stores): lane t < count of `id` / `sk` gives the vector's id (< 0: skip) and slot.
     // A vector is kp / 4 lanes of 16 bytes, so one instruction moves rpi = 64 / (kp / 4)
-    // vectors.  All reads of a batch of 16 instructions land in distinct registers before
-    // the first store, so no read waits for an earlier store.
+    // vectors.  All reads of a batch of 8 instructions land in distinct registers before
+    // the first store, so no read of a batch waits for a store of the same batch.
     __device__ __forceinline__ void slots_to_global(float *dst, bool coherent, int id, int sk, int count) {
+        constexpr int kRounds = 8;
         const int lpr = kp >> 2, rpi = 64 / lpr, vb = lane / lpr, piece = lane - vb * lpr;
         const bool act = vb < rpi;
-        for (int b0 = 0; b0 < count; b0 += 16 * rpi) {
-            int gid[16];
-            const float *src[16];
+        const uint32_t base = lds_addr(L.vec) + (uint32_t)piece * 16u;
+        for (int b0 = 0; b0 < count; b0 += kRounds * rpi) {
+            int gid[kRounds];
+            uint32_t src[kRounds];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < kRounds; ++r) {
                 gid[r] = -1;
-                src[r] = L.vec;
+                src[r] = base;
                 if (b0 + r * rpi < count) {
                     const int t = b0 + r * rpi + vb;
                     const int g = __shfl(id, t & 63), s = ev_slot(__shfl(sk, t & 63));
                     gid[r] = (act && t < count) ? g : -1;
-                    src[r] = L.vec + (gid[r] >= 0 ? s : 0) * kp + piece * 4;
+                    src[r] = base + (uint32_t)((gid[r] >= 0 ? s : 0) * kp) * 4u;
                 }
             }
-            f32x4_t v[16];
+            f32x4_t v[kRounds];
 #pragma unroll
-            for (int r = 0; r < 16; r += 4)
+            for (int r = 0; r < kRounds; r += 4)
                 if (b0 + r * rpi < count)
                     lds_read4x4_now(src[r], src[r + 1], src[r + 2], src[r + 3], v[r], v[r + 1], v[r + 2], v[r + 3]);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
+            for (int r = 0; r < kRounds; ++r) {
                 if (b0 + r * rpi >= count || gid[r] < 0) continue;
                 float *p = dst + (int64_t)gid[r] * kp + piece * 4;
                 if (coherent)
@@ -738,20 +789,31 @@ struct MemoryWave {
     }
 };
 
+// A workgroup holds `group` workers: waves [0, group) are their compute waves and waves
+// [group, 2 group) their memory waves, each worker with its own part of the LDS.  With
+// waves dealt to the SIMDs in turn, a SIMD then runs one compute and one memory wave
+// instead of two compute waves.
 template <int VEC, int NR16>
-__global__ __launch_bounds__(128) void k_worker(TrainArgs a, uint32_t *abort_flag) {
+__global__ __launch_bounds__(512) void k_worker(TrainArgs a, uint32_t *abort_flag) {
     extern __shared__ float4 lds4[];
-    const int q = blockIdx.x;
+    const int G = a.group;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sub = wave % G;
+    const bool compute = wave < G;
+    const int q = blockIdx.x * G + sub;
+    const Lds L = lds_layout((char *)lds4 + (size_t)sub * worker_lds_bytes(a.kp, a.slots), a.slots, a.kp);
+    if (compute) {
+        if (lane < 4) L.sync[lane] = 0;
+        for (int i = lane; i < 64 * 4; i += 64) L.zero[i] = 0.0f;
+    }
+    __syncthreads();
+    if (q >= a.p) return;
     const int64_t c0 = a.wck[q], nck = a.wck[q + 1] - c0;
     if (nck <= 0 || a.epochs <= 0) return;
-    const Lds L = lds_layout(lds4, a.slots, a.kp);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (threadIdx.x < 4) L.sync[threadIdx.x] = 0;
-    __syncthreads();
-    if (wave == 0) {
+    if (compute) {
         compute_wave<VEC, NR16>(a, L, nck, q, lane);
     } else {
-        const uint64_t t_start = tick(a.wstats != nullptr);
+        const uint64_t t_start = tick(a.timing);
         MemoryWave mw(a, L, c0, nck, q, lane, abort_flag);
         mw.run();
         if (a.wstats && lane == 0) {
@@ -759,7 +821,7 @@ __global__ __launch_bounds__(128) void k_worker(TrainArgs a, uint32_t *abort_fla
             w[kWStatAcquire] = (int64_t)mw.t_acq;
             w[kWStatMemWait] = (int64_t)mw.t_mem;
             w[kWStatSlotWait] = (int64_t)mw.t_slot;
-            w[kWStatMemTotal] = (int64_t)(wall_clock64() - t_start);
+            w[kWStatMemTotal] = (int64_t)(tick(a.timing) - t_start);
             w[kWStatCommit] = (int64_t)mw.t_commit;
             w[kWStatRetire] = (int64_t)mw.t_retire;
             w[kWStatIssue] = (int64_t)mw.t_issue;
@@ -772,8 +834,8 @@ __global__ __launch_bounds__(128) void k_worker(TrainArgs a, uint32_t *abort_fla
 }
 
 template <int VEC, int NR16>
-hipError_t launch_t(const TrainArgs &a, int32_t p, size_t lds, uint32_t *abort_flag, hipStream_t st) {
-    hipLaunchKernelGGL((k_worker<VEC, NR16>), dim3(p), dim3(128), lds, st, a, abort_flag);
+hipError_t launch_t(const TrainArgs &a, int32_t blocks, size_t lds, uint32_t *abort_flag, hipStream_t st) {
+    hipLaunchKernelGGL((k_worker<VEC, NR16>), dim3(blocks), dim3(128 * a.group), lds, st, a, abort_flag);
     return hipGetLastError();
 }
 
@@ -790,30 +852,36 @@ const void *pick_kernel(int kp) {
 
 }  // namespace
 
-size_t train_lds_bytes(int32_t kp, int32_t slots) {
-    return (size_t)slots * (size_t)kp * sizeof(float) + kRingBytes + 64 * 4 * sizeof(float);
+size_t train_lds_bytes(int32_t kp, int32_t slots) { return worker_lds_bytes(kp, slots); }
+
+int32_t train_group(int32_t kp, int32_t slots, size_t max_lds_per_block) {
+    const size_t per = worker_lds_bytes(kp, slots);
+    for (int32_t g = 4; g > 1; g >>= 1)
+        if ((size_t)g * per <= max_lds_per_block) return g;
+    return 1;
 }
 
-hipError_t train_max_workers(int32_t kp, int32_t slots, int32_t *max_workers) {
+hipError_t train_max_workers(int32_t kp, int32_t slots, int32_t group, int32_t *max_workers) {
     int dev = 0, cus = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const size_t lds = train_lds_bytes(kp, slots);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(kp), 128, lds);
+    const size_t lds = (size_t)group * worker_lds_bytes(kp, slots);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(kp), 128 * group, lds);
     if (e != hipSuccess) return e;
-    *max_workers = nb * cus;
+    *max_workers = nb * cus * group;
     return hipSuccess;
 }
 
 hipError_t launch_train(const TrainArgs &a, int32_t p, uint32_t *abort_flag, hipStream_t st) {
-    const size_t lds = train_lds_bytes(a.kp, a.slots);
-    if (a.kp <= 16) return launch_t<1, 1>(a, p, lds, abort_flag, st);
-    if (a.kp <= 32) return launch_t<1, 2>(a, p, lds, abort_flag, st);
-    if (a.kp <= 64) return launch_t<1, 4>(a, p, lds, abort_flag, st);
-    if (a.kp <= 128) return launch_t<2, 4>(a, p, lds, abort_flag, st);
-    return launch_t<4, 4>(a, p, lds, abort_flag, st);
+    const size_t lds = (size_t)a.group * worker_lds_bytes(a.kp, a.slots);
+    const int32_t blocks = (p + a.group - 1) / a.group;
+    if (a.kp <= 16) return launch_t<1, 1>(a, blocks, lds, abort_flag, st);
+    if (a.kp <= 32) return launch_t<1, 2>(a, blocks, lds, abort_flag, st);
+    if (a.kp <= 64) return launch_t<1, 4>(a, blocks, lds, abort_flag, st);
+    if (a.kp <= 128) return launch_t<2, 4>(a, blocks, lds, abort_flag, st);
+    return launch_t<4, 4>(a, blocks, lds, abort_flag, st);
 }
 
 }  // namespace nomad

@@ -30,7 +30,39 @@ def test_config_struct_matches_header_defaults():
     cfg = nm.NomadConfig()
     nm.load().nomad_config_default(C.byref(cfg))
     assert cfg.sched == 0 and cfg.dtype == 0 and cfg.workers == 0 and cfg.k == 0
-    assert C.sizeof(nm.NomadConfig) == 56
+    assert cfg.collect_stats == 0 and cfg.record_trace == 0
+
+
+def test_binding_structs_match_the_c_header(tmp_path):
+    """Field offsets and sizes of the ctypes structs equal those a C compiler gives for
+    include/nomad.h."""
+    import shutil
+    import subprocess
+
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    fields = {"nomad_config": nm.NomadConfig, "nomad_stats": nm.NomadStats}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "nomad.h"', "int main(void) {"]
+    for cname, cls in fields.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            cf = "lambda" if fname == "lambda_" else fname
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {cf}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([gcc, "-I", os.path.dirname(nm.HEADER), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    seen = {}
+    for line in filter(None, out):
+        cname, what, val = line.split()
+        seen[(cname, what)] = int(val)
+    for cname, cls in fields.items():
+        assert seen[(cname, "size")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert seen[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
 
 
 def test_null_arguments_are_rejected_without_a_device():
