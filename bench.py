@@ -110,8 +110,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workers", type=int, default=0)
-    ap.add_argument("--lds-slots", type=int, default=0)
-    ap.add_argument("--loads-per-chunk", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0, help="compute waves per worker (0 = library default)")
+    ap.add_argument("--item-slots", type=int, default=0, help="item slots per worker (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="run only the plain copy used to calibrate the HBM byte counters")
@@ -141,7 +141,7 @@ def main():
     seed = 2
     model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp["k"], lam=hp["lam"],
                      alpha=hp["alpha"], beta=hp["beta"], gamma=hp["gamma"], workers=args.workers, seed=seed,
-                     lds_slots=args.lds_slots, loads_per_chunk=args.loads_per_chunk)
+                     waves_per_worker=args.waves, item_slots=args.item_slots)
     P = model.workers
     st0 = model.train(0)
     log(f"layout {st0.layout_seconds:.3f} s, workers {P}")

@@ -9,9 +9,10 @@
  * i in I_q.  Every item vector h_j is owned by exactly one worker at a time and moves
  * between workers ("nomadic" variables, section 3.1, Algorithm 1), so no two concurrent
  * updates touch the same parameter.  Here a worker is one workgroup of a persistent
- * kernel on one GPU: a compute wavefront runs the updates on rows and items held in
- * LDS while a memory wavefront stages the next ones and hands each item on as soon as
- * its visit ends.
+ * kernel on one GPU (normally one per CU), the hybrid layout of section 3.4: its rows are
+ * split again among its compute wavefronts, each item visits them in ascending order
+ * through LDS, and a memory wavefront takes items over from other workers and hands
+ * them on.
  *
  * Conventions for every entry point
  *   - Returns a nomad_status; nothing aborts or throws across the ABI.  On failure the
@@ -68,11 +69,11 @@ typedef struct {
     int32_t sched;      /* nomad_sched */
     int32_t dtype;      /* nomad_dtype */
     int32_t rounding;   /* nomad_round, used when dtype = NOMAD_BF16 */
-    int32_t workers;    /* p, number of workers (wavefronts); 0 = library default */
-    int32_t lds_slots;       /* rows and items a worker keeps in LDS (2..256); 0 = default */
-    int32_t loads_per_chunk; /* max vectors a worker loads for one chunk of <= 64 ratings
-                                (2..64, and at most what one staging round holds for k);
-                                0 = default */
+    int32_t workers;    /* p, number of workers (workgroups, all resident at once);
+                           0 = one per compute unit */
+    int32_t waves_per_worker; /* compute wavefronts of a worker, 1..15; 0 = 8 */
+    int32_t item_slots;  /* items a worker holds in LDS at once: a power of two, 1..64;
+                            0 = as many as LDS allows, up to 64 */
     int32_t record_trace;    /* 1 = record every (worker, item) visit for replay */
     int32_t collect_stats;   /* 1 = time the phases of every worker (nomad_get_worker_stats);
                                 counts are always collected */
@@ -131,15 +132,16 @@ nomad_status nomad_get_partition(nomad_ctx *ctx, int32_t *p_out, int64_t *h_row_
 nomad_status nomad_get_trace(nomad_ctx *ctx, int64_t *len, int32_t *h_buf, int64_t cap);
 
 /* Per-worker counters of the last nomad_train_epochs call: p rows of sixteen int64 in
- * h_stats (host, cap >= 16p).  Times are ticks of the device's 100 MHz constant clock.
- *   0 compute wave: time in the kernel          8 memory wave: time in the kernel
- *   1 memory wave: waiting for items            9 memory wave: write-backs of evicted rows
- *   2 memory wave: waiting for loads/stores       and LDS stores of staged chunks
- *   3 chunks processed                         10 memory wave: passing on items
- *   4 compute wave: SGD updates                11 memory wave: issuing prefetches and polls
- *   5 memory wave: waiting for free LDS slots  12 vectors loaded
- *   6 ratings processed                        13 vectors loaded without prefetch
- *   7 compute wave: waiting for staged chunks  14, 15 zero */
+ * h_stats (host, cap >= 16p).  Times are ticks of the device's 100 MHz constant clock and
+ * are only collected with collect_stats = 1; counts are always collected.
+ *   0 memory wave: time in the kernel            5 compute waves: time waiting for items
+ *   1 memory wave: rounds of its loop              (sum over the waves)
+ *   2 visits taken over                          6 ratings updated
+ *   3 polls of an item not yet free              7 row reads served from an update still in
+ *   4 compute waves: time in the kernel            a wave's prefetch window
+ *     (sum over the waves)                       8 compute waves: longest time in the kernel
+ *                                                9 memory wave: waiting for its loads/stores
+ *   10..15 zero */
 nomad_status nomad_get_worker_stats(nomad_ctx *ctx, int64_t *h_stats, int64_t cap);
 
 /* Free every resource of the context.  NULL is ignored. */

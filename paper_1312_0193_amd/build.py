@@ -13,7 +13,7 @@ LIB = os.path.join(PKG, "libnomad.so")
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
-    "-std=c++17",
+    "-std=c++20",
     "-fPIC",
     "-shared",
     # keep the compiler from forming packed-FP32 instructions (v_pk_*_f32)

@@ -16,14 +16,16 @@ struct nomad_ctx {
     nomad_config cfg{};
     int64_t m = 0, n = 0, nnz = 0;
     int32_t k = 0, kp = 0, p = 0;
-    int32_t group = 1;                 // workers per workgroup of the training kernel
+    int32_t nw = 0, slots = 0;         // compute waves and item slots per worker
+    int32_t cus = 0, max_lds = 0;
     hipStream_t stream = nullptr;
     Plan plan;
     float *W = nullptr, *H = nullptr;  // m x kp, n x kp (row stride kp, padding kept at 0)
     uint32_t *tok_done = nullptr;      // n item counters + 1 abort word
+    float *dummy = nullptr;            // target of the workers' placeholder stores
+    int32_t *diag = nullptr;           // 8 words describing a wait that ran out of time
     int64_t epochs_done = 0;
     std::vector<int64_t> row_start;
-    int64_t max_worker_chunks = 0;
     int64_t *wstats = nullptr;         // p x kWStatCount per-worker counters of the last call
     int32_t *trace = nullptr;
     int64_t *trace_len = nullptr;
@@ -72,6 +74,8 @@ void release(nomad_ctx *c) {
     (void)hipFree(c->W);
     (void)hipFree(c->H);
     (void)hipFree(c->tok_done);
+    (void)hipFree(c->dummy);
+    (void)hipFree(c->diag);
     (void)hipFree(c->trace);
     (void)hipFree(c->trace_len);
     (void)hipFree(c->wstats);
@@ -96,8 +100,8 @@ void nomad_config_default(nomad_config *cfg) {
     cfg->dtype = NOMAD_FP32;
     cfg->rounding = NOMAD_ROUND_RNE;
     cfg->workers = 0;
-    cfg->lds_slots = 0;
-    cfg->loads_per_chunk = 0;
+    cfg->waves_per_worker = 0;
+    cfg->item_slots = 0;
     cfg->record_trace = 0;
     cfg->collect_stats = 0;
     cfg->seed = 0;
@@ -147,41 +151,46 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
         return st;
     };
 
-    // LDS slots per worker and loads per chunk.  By default a worker's vectors take about
-    // 32 KB of LDS (four workers per CU) and a chunk loads as much as one staging round of
-    // the memory wave holds.
-    const int32_t cap = nomad::max_loads_per_chunk(c->kp);
-    int32_t slots = cfg->lds_slots, loads = cfg->loads_per_chunk;
-    if (slots <= 0) slots = std::min(nomad::kMaxSlots, std::max(8, (int32_t)(32768 / (c->kp * 4))));
-    if (loads <= 0) loads = std::min(cap, std::max(2, slots / 3));
-    if (slots < 2 || slots > nomad::kMaxSlots || loads < 2 || loads > cap || loads > slots) {
-        nomad_status st = fail(c, NOMAD_EINVAL, "nomad_init: lds_slots=%d loads_per_chunk=%d: need 2 <= slots <= %d "
-                               "and 2 <= loads <= min(slots, %d) for k=%d", slots, loads, nomad::kMaxSlots, cap, c->k);
-        return bail(st);
-    }
-    int dev = 0, max_lds = 0;
+    // Workers, compute waves per worker and item slots.  By default one worker runs on
+    // every CU with eight compute waves, and holds up to 64 items (fewer if LDS is short).
+    int dev = 0, max_lds = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return bail(fail(c, NOMAD_EDEVICE, "nomad_init: no usable HIP device"));
-    const size_t lds = nomad::train_lds_bytes(c->kp, slots);
+    const int32_t nw = cfg->waves_per_worker > 0 ? cfg->waves_per_worker : nomad::kDefaultWaves;
+    if (nw < 1 || nw > nomad::kMaxWaves)
+        return bail(fail(c, NOMAD_EINVAL, "nomad_init: waves_per_worker=%d outside [1,%d]", nw, nomad::kMaxWaves));
+    int32_t slots = cfg->item_slots;
+    if (slots <= 0) {
+        slots = nomad::kMaxItemSlots;
+        while (slots > 8 && nomad::train_lds_bytes(c->kp, nw, slots) > (size_t)max_lds) slots >>= 1;
+    }
+    if (slots < 1 || slots > nomad::kMaxItemSlots || (slots & (slots - 1)) != 0)
+        return bail(fail(c, NOMAD_EINVAL, "nomad_init: item_slots=%d must be a power of two in [1,%d]", slots,
+                         nomad::kMaxItemSlots));
+    const size_t lds = nomad::train_lds_bytes(c->kp, nw, slots);
     if (lds > (size_t)max_lds)
-        return bail(fail(c, NOMAD_EINVAL, "nomad_init: %d LDS slots need %zu bytes of LDS, device allows %d",
-                         slots, lds, max_lds));
+        return bail(fail(c, NOMAD_EINVAL, "nomad_init: %d compute waves and %d item slots need %zu bytes of LDS for "
+                         "k=%d, device allows %d", nw, slots, lds, c->k, max_lds));
     int32_t maxw = 0;
-    c->group = nomad::train_group(c->kp, slots, (size_t)max_lds);
-    hipError_t he = nomad::train_max_workers(c->kp, slots, c->group, &maxw);
+    hipError_t he = nomad::train_max_workers(c->kp, nw, slots, &maxw);
     if (he != hipSuccess) return bail(hip_fail(c, he, "nomad_init: occupancy query"));
     int32_t p = cfg->workers;
-    if (p <= 0) p = maxw < 1024 ? maxw : 1024;
-    if (p < 1 || p > 4096)
-        return bail(fail(c, NOMAD_EINVAL, "nomad_init: workers=%d outside [1,4096]", p));
+    if (p <= 0) p = maxw < cus ? maxw : cus;
+    if (p < 1 || p > nomad::kMaxWorkers)
+        return bail(fail(c, NOMAD_EINVAL, "nomad_init: workers=%d outside [1,%d]", p, nomad::kMaxWorkers));
     if (p > maxw)
         return bail(fail(c, NOMAD_EDEVICE, "nomad_init: %d workers cannot all be resident (device holds %d "
-                         "with %d LDS slots)", p, maxw, slots));
+                         "with %d compute waves and %d item slots)", p, maxw, nw, slots));
     c->p = p;
+    c->nw = nw;
+    c->slots = slots;
+    c->cus = cus;
+    c->max_lds = max_lds;
     c->cfg.workers = p;
-    c->cfg.lds_slots = slots;
-    c->cfg.loads_per_chunk = loads;
+    c->cfg.waves_per_worker = nw;
+    c->cfg.item_slots = slots;
 
     hipError_t e;
     if ((e = hipMalloc(&c->W, sizeof(float) * (size_t)m * c->kp)) != hipSuccess)
@@ -190,6 +199,10 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
         return bail(hip_fail(c, e, "nomad_init: H"));
     if ((e = hipMalloc(&c->tok_done, sizeof(uint32_t) * (size_t)(n + 1))) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: item counters"));
+    if ((e = hipMalloc(&c->dummy, sizeof(float) * nomad::kMaxWaves * (size_t)p)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: scratch words"));
+    if ((e = hipMalloc(&c->diag, sizeof(int32_t) * 8)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: diagnostics"));
     if ((e = hipMalloc(&c->wstats, sizeof(int64_t) * nomad::kWStatCount * (size_t)p)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: worker counters"));
     c->eval_scratch_bytes = nomad::eval_scratch_bytes();
@@ -211,10 +224,10 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     if ((e = hipEventRecord(c->ev0, st)) != hipSuccess) return bail(hip_fail(c, e, "nomad_init: event"));
     int code = 0;
     char msg[256] = {0};
-    e = nomad::build_plan(&c->plan, m, n, nnz, d_row, d_col, d_val, p, c->kp, slots, loads, cfg->seed, st, &code,
-                          msg, sizeof(msg));
+    e = nomad::build_plan(&c->plan, m, n, nnz, d_row, d_col, d_val, p, nw, cfg->seed, st, &code, msg,
+                          sizeof(msg));
     if (e != hipSuccess) return bail(hip_fail(c, e, "nomad_init: layout"));
-    if (code != 0) return bail(fail(c, NOMAD_EINVAL, "nomad_init: %s", msg));
+    if (code != 0) return bail(fail(c, (nomad_status)code, "nomad_init: %s", msg));
     if ((e = hipEventRecord(c->ev1, st)) != hipSuccess || (e = hipEventSynchronize(c->ev1)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: event"));
     float ms = 0.0f;
@@ -224,12 +237,6 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     if ((e = hipMemcpy(c->row_start.data(), c->plan.row_start, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost)) !=
         hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: partition copy"));
-    {
-        std::vector<int64_t> wck(p + 1);
-        if ((e = hipMemcpy(wck.data(), c->plan.wck, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost)) != hipSuccess)
-            return bail(hip_fail(c, e, "nomad_init: plan copy"));
-        for (int32_t q = 0; q < p; ++q) c->max_worker_chunks = std::max(c->max_worker_chunks, wck[q + 1] - wck[q]);
-    }
     *out = c;
     return NOMAD_OK;
 }
@@ -239,9 +246,9 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
     if (epochs < 0) return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epochs=%d < 0", epochs);
     if (c->epochs_done + epochs > (int64_t)INT32_MAX / 2)
         return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epoch counter would overflow");
-    if ((int64_t)epochs * c->max_worker_chunks >= (int64_t)INT32_MAX)
-        return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epochs=%d too many for one call (%lld chunks per epoch "
-                    "on the busiest worker)", epochs, (long long)c->max_worker_chunks);
+    if ((int64_t)nomad::kMaxEpochsPerLaunch * c->plan.max_worker_visits >= (int64_t)INT32_MAX)
+        return fail(c, NOMAD_EINVAL, "nomad_train_epochs: %lld visits per epoch on the busiest worker are too many",
+                    (long long)c->plan.max_worker_visits);
     if (out) memset(out, 0, sizeof(*out));
     hipStream_t st = c->stream;
     double seconds = 0.0;
@@ -251,21 +258,19 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         a.n = c->n;
         a.W = c->W;
         a.H = c->H;
-        a.wck = c->plan.wck;
-        a.chunks = c->plan.chunks;
-        a.events = c->plan.events;
-        a.ratings = c->plan.ratings;
+        a.recs = c->plan.recs;
+        a.rbase = c->plan.rbase;
+        a.visits = c->plan.visits;
+        a.vbase = c->plan.vbase;
         a.tok_done = c->tok_done;
+        a.abort_flag = c->tok_done + c->n;
+        a.dummy = c->dummy;
+        a.diag = c->diag;
         a.kp = c->kp;
-        a.slots = c->plan.slots;
         a.p = c->p;
-        a.group = c->group;
-        a.epoch0 = (int32_t)c->epochs_done;
-        a.epochs = epochs;
+        a.nw = c->nw;
+        a.slots = c->slots;
         a.lambda = c->cfg.lambda;
-        a.alpha = c->cfg.alpha;
-        a.beta = c->cfg.beta;
-        a.gamma = c->cfg.gamma;
         if (c->cfg.record_trace) {
             const int64_t need = c->plan.nvisits * (int64_t)epochs;
             if (need > c->trace_cap) {
@@ -282,11 +287,28 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
             a.trace_cap = c->trace_cap;
         }
         HIPTRY(c, hipMemsetAsync(c->tok_done + c->n, 0, sizeof(uint32_t), st), "train: reset");
+        HIPTRY(c, hipMemsetAsync(c->diag, 0, sizeof(int32_t) * 8, st), "train: reset");
         HIPTRY(c, hipMemsetAsync(c->wstats, 0, sizeof(int64_t) * nomad::kWStatCount * (size_t)c->p, st), "train: reset");
         a.wstats = c->wstats;
         a.timing = c->cfg.collect_stats != 0;
         HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
-        HIPTRY(c, nomad::launch_train(a, c->p, c->tok_done + c->n, st), "train: launch");
+        // Launches of at most kMaxEpochsPerLaunch epochs, each with its step sizes
+        // s_t = alpha / (1 + beta t^gamma), t = epochs done (every rating is updated once
+        // per epoch), eq. (stepsize_method).
+        for (int32_t done = 0; done < epochs;) {
+            const int32_t ne = std::min(epochs - done, (int32_t)nomad::kMaxEpochsPerLaunch);
+            a.epoch0 = (int32_t)(c->epochs_done + done);
+            a.epochs = ne;
+            for (int32_t e = 0; e < ne; ++e) {
+                const double t = (double)(a.epoch0 + e);
+                const float s = (float)((double)c->cfg.alpha /
+                                        (1.0 + (double)c->cfg.beta * (t > 0.0 ? std::pow(t, (double)c->cfg.gamma) : 0.0)));
+                a.step_s[e] = s;
+                a.step_c[e] = 1.0f - s * c->cfg.lambda;
+            }
+            HIPTRY(c, nomad::launch_train(a, st), "train: launch");
+            done += ne;
+        }
         HIPTRY(c, hipEventRecord(c->ev1, st), "train: event");
         HIPTRY(c, hipEventSynchronize(c->ev1), "train: kernel");
         float ms = 0.0f;
@@ -295,11 +317,15 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         uint32_t aborted = 0;
         HIPTRY(c, hipMemcpy(&aborted, c->tok_done + c->n, sizeof(uint32_t), hipMemcpyDeviceToHost), "train: flag");
         if (aborted == 2)
-            return fail(c, NOMAD_EDEVICE, "nomad_train_epochs: malformed chunk plan detected; the factors are "
+            return fail(c, NOMAD_EDEVICE, "nomad_train_epochs: malformed layout detected; the factors are "
                         "undefined");
-        if (aborted)
-            return fail(c, NOMAD_EDEVICE, "nomad_train_epochs: a worker waited beyond the time limit; the "
-                        "factors are undefined");
+        if (aborted) {
+            int32_t d[8] = {0};
+            (void)hipMemcpy(d, c->diag, sizeof(d), hipMemcpyDeviceToHost);
+            return fail(c, NOMAD_EDEVICE, "nomad_train_epochs: a worker waited beyond the time limit (worker %d, "
+                        "wave %d, %d %d %d %d %d %d); the factors are undefined", d[0] - 1, d[1], d[2], d[3], d[4],
+                        d[5], d[6], d[7]);
+        }
         if (c->cfg.record_trace) {
             HIPTRY(c, hipMemcpy(&c->trace_count, c->trace_len, sizeof(int64_t), hipMemcpyDeviceToHost), "trace");
             if (c->trace_count > c->trace_cap) c->trace_count = c->trace_cap;

@@ -3,14 +3,18 @@
 //   1. check indices, count ratings per row;
 //   2. exclusive scan -> rowptr;
 //   3. row partition: row_start[q] = min{ i : rowptr[i] >= ceil(q * nnz / p) } (the
-//      "same number of ratings" split of section 3.1, footnote);
+//      "same number of ratings" split of section 3.1, footnote), then the same rule
+//      inside each worker's block for its compute waves;
 //   4. order the ratings by (worker q, ring sub-step s = (g(j) - q) mod p, item j, row i)
 //      with two stable radix sorts (first by (j, i), then by (q, s)); a repeated (i, j)
 //      is rejected (Omega is a set);
-//   5. number the visits of every item (its runs of ratings at one worker) in ring order,
-//      i.e. by sub-step s, and count each item's visits per epoch;
-//   6. plan each worker's chunks and LDS slots (planner.h) in two passes: count, then
-//      fill.
+//   5. visits (maximal runs of one (worker, item)) numbered in ring order per item, and
+//      per worker in processing order;
+//   6. per rating: the visit information its wave needs (visit index, first / last rating
+//      of the wave in the visit, the wave before it in the visit); per visit: item,
+//      ordinal, visits of the item per epoch, last wave;
+//   7. the ratings of each wave gathered into one stream, in processing order (a stable
+//      sort by (worker, wave)).
 #include <hipcub/hipcub.hpp>
 
 #include <cstdio>
@@ -18,7 +22,6 @@
 #include <vector>
 
 #include "nomad_internal.h"
-#include "planner.h"
 
 namespace nomad {
 namespace {
@@ -32,10 +35,12 @@ inline int grid_for(int64_t n, int threads = kThreads, int cap = 65536) {
     return (int)b;
 }
 
+#define GRID_LOOP(e, n) \
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (n); e += (int64_t)gridDim.x * blockDim.x)
+
 __global__ void k_check_degree(const int32_t *row, const int32_t *col, int64_t nnz, int64_t m,
                                int64_t n, unsigned long long *deg, int32_t *err) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(e, nnz) {
         int32_t i = row[e], j = col[e];
         if (i < 0 || i >= m || j < 0 || j >= n) {
             atomicOr(err, 1);
@@ -45,34 +50,52 @@ __global__ void k_check_degree(const int32_t *row, const int32_t *col, int64_t n
     }
 }
 
+// Smallest i in [lo, hi] with rowptr[i] >= target (rowptr is non-decreasing).
+__device__ inline int64_t lower_row(const int64_t *rowptr, int64_t lo, int64_t hi, int64_t target) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if (rowptr[mid] >= target) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
 __global__ void k_partition(const int64_t *rowptr, int64_t m, int64_t nnz, int32_t p,
                             int64_t *row_start) {
     int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q > p) return;
     if (q == 0) { row_start[0] = 0; return; }
     if (q == p) { row_start[p] = m; return; }
-    int64_t target = ((int64_t)q * nnz + p - 1) / p;
-    int64_t lo = 0, hi = m;  // smallest i in [0, m] with rowptr[i] >= target
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (rowptr[mid] >= target) hi = mid; else lo = mid + 1;
-    }
-    row_start[q] = lo;
+    const int64_t target = ((int64_t)q * nnz + p - 1) / p;
+    row_start[q] = lower_row(rowptr, 0, m, target);
 }
 
-__device__ inline int32_t worker_of_row(const int64_t *row_start, int32_t p, int64_t i) {
-    int32_t lo = 0, hi = p - 1;  // largest q with row_start[q] <= i
+// Wave w of worker q starts at the smallest row i of the block with
+// #ratings in [row_start[q], i) >= ceil(w * nnz_q / nw).
+__global__ void k_wave_partition(const int64_t *rowptr, const int64_t *row_start, int64_t m, int32_t p,
+                                 int32_t nw, int64_t *wave_start) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t > (int64_t)p * nw) return;
+    if (t == (int64_t)p * nw) { wave_start[t] = m; return; }
+    const int32_t q = (int32_t)(t / nw), w = (int32_t)(t % nw);
+    const int64_t r0 = row_start[q], r1 = row_start[q + 1];
+    const int64_t base = rowptr[r0], nq = rowptr[r1] - base;
+    const int64_t target = base + ((int64_t)w * nq + nw - 1) / nw;
+    wave_start[t] = lower_row(rowptr, r0, r1, target);
+}
+
+// Largest index t in [0, cnt) with bounds[t] <= i.
+__device__ inline int32_t find_block(const int64_t *bounds, int32_t cnt, int64_t i) {
+    int32_t lo = 0, hi = cnt - 1;
     while (lo < hi) {
         int32_t mid = (lo + hi + 1) >> 1;
-        if (row_start[mid] <= i) lo = mid; else hi = mid - 1;
+        if (bounds[mid] <= i) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
 __global__ void k_key_ji(const int32_t *row, const int32_t *col, int64_t nnz, int64_t m,
                          uint64_t *key, uint32_t *idx) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(e, nnz) {
         key[e] = (uint64_t)col[e] * (uint64_t)m + (uint64_t)row[e];
         idx[e] = (uint32_t)e;
     }
@@ -87,10 +110,9 @@ __global__ void k_check_dup(const uint64_t *key, int64_t nnz, int32_t *err) {
 
 __global__ void k_key_qs(const uint32_t *idx, const int32_t *row, const int32_t *col, int64_t nnz,
                          const int64_t *row_start, int32_t p, uint64_t seed, uint32_t *key) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(e, nnz) {
         uint32_t x = idx[e];
-        int32_t q = worker_of_row(row_start, p, row[x]);
+        int32_t q = find_block(row_start, p, row[x]);
         int32_t g = item_group(seed, col[x], p);
         int32_t s = (g - q + p) % p;
         key[e] = (uint32_t)q * (uint32_t)p + (uint32_t)s;
@@ -99,8 +121,7 @@ __global__ void k_key_qs(const uint32_t *idx, const int32_t *row, const int32_t 
 
 __global__ void k_gather(const uint32_t *idx, const int32_t *row, const int32_t *col,
                          const float *val, int64_t nnz, int32_t *srow, int32_t *scol, float *sval) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(e, nnz) {
         uint32_t x = idx[e];
         srow[e] = row[x];
         scol[e] = col[x];
@@ -110,8 +131,7 @@ __global__ void k_gather(const uint32_t *idx, const int32_t *row, const int32_t 
 
 // Visits: maximal runs of one (worker, item) in the (q, s, j, i) order.
 __global__ void k_visit_start(const uint32_t *key2, const int32_t *scol, int64_t nnz, uint32_t *is_start) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x)
+    GRID_LOOP(e, nnz)
         is_start[e] = (e == 0 || key2[e] != key2[e - 1] || scol[e] != scol[e - 1]) ? 1u : 0u;
 }
 
@@ -119,8 +139,7 @@ __global__ void k_visit_start(const uint32_t *key2, const int32_t *scol, int64_t
 __global__ void k_visit_keys(const uint32_t *is_start, const uint32_t *vid, const uint32_t *key2,
                              const int32_t *scol, int64_t nnz, int32_t p, uint64_t *vkey, uint32_t *vidx,
                              uint32_t *nvis) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(e, nnz) {
         if (!is_start[e]) continue;
         const uint32_t v = vid[e];
         const uint32_t s = key2[e] % (uint32_t)p;
@@ -134,53 +153,62 @@ __global__ void k_visit_keys(const uint32_t *is_start, const uint32_t *vid, cons
 // item's first position.
 __global__ void k_visit_ordinal(const uint64_t *vkey_sorted, const uint32_t *vidx_sorted, const uint32_t *seg,
                                 int64_t nv, int32_t p, uint32_t *vord) {
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nv;
-         t += (int64_t)gridDim.x * blockDim.x) {
+    GRID_LOOP(t, nv) {
         const uint64_t j = vkey_sorted[t] / (uint64_t)p;
         vord[vidx_sorted[t]] = (uint32_t)(t - seg[j]);
     }
 }
 
-// Per-rating visit information for the planner: v | nvis << 16 (the visit's ordinal
-// among the item's visits in one epoch of the ring order, and the item's visits per epoch).
-__global__ void k_vinfo(const uint32_t *vid, const uint32_t *is_start, const uint32_t *vord, const uint32_t *nvis,
-                        const int32_t *scol, int64_t nnz, uint32_t *vinfo) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
-         e += (int64_t)gridDim.x * blockDim.x)
-        vinfo[e] = vord[vid[e] + is_start[e] - 1u] | (nvis[scol[e]] << 16);
-}
-
-// First rating of each worker in the (q, s, j, i) order: rowptr at its first row.
-__global__ void k_worker_first(const int64_t *rowptr, const int64_t *row_start, int32_t p, int64_t *wfirst) {
+// First visit of each worker: the visit of its first rating in the sorted order (the
+// next worker's first visit if it has no ratings).
+__global__ void k_visit_base(const int64_t *rowptr, const int64_t *row_start, const uint32_t *vid, int64_t nnz,
+                             int64_t nvisits, int32_t p, int64_t *vbase) {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q <= p) wfirst[q] = rowptr[row_start[q]];
+    if (q > p) return;
+    const int64_t e = rowptr[row_start[q]];
+    vbase[q] = (q < p && e < nnz) ? (int64_t)vid[e] : nvisits;
 }
 
-// One thread per worker runs the planner (planner.h): count pass, then fill pass.
-template <bool kFill>
-__global__ void k_planner(PlanIn in, const int64_t *wfirst, PlanOut base, const int64_t *ck_off,
-                          const int64_t *ev_off, int64_t *ck_count, int64_t *ev_count, int64_t *ld_count,
-                          int32_t *err, int32_t p) {
-    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= p) return;
-    PlanOut o = base;
-    if (kFill) {
-        o.ck0 = ck_off[q];
-        o.ev0 = ev_off[q];
-    }
-    const PlanCount r = plan_worker<kFill>(in, wfirst[q], wfirst[q + 1], o);
-    if (r.status) atomicOr(err, 4);
-    if (!kFill) {
-        ck_count[q] = r.chunks;
-        ev_count[q] = r.events;
-        ld_count[q] = r.loads;
+// Rating records and visit records.
+__global__ void k_records(const int32_t *srow, const int32_t *scol, const float *sval, const uint32_t *key2,
+                          const uint32_t *is_start, const uint32_t *vid, const uint32_t *vord, const uint32_t *nvis,
+                          const int64_t *vbase, const int64_t *wave_start, int64_t nnz, int32_t p, int32_t nw,
+                          RatingRec *rec, VisitRec *visits, uint32_t *key3) {
+    GRID_LOOP(e, nnz) {
+        const int32_t q = (int32_t)(key2[e] / (uint32_t)p);
+        const int64_t *ws = wave_start + (int64_t)q * nw;
+        const int32_t w = find_block(ws, nw, srow[e]);
+        const uint32_t v = vid[e] + is_start[e] - 1u;  // global visit id
+        const bool next_start = e + 1 == nnz || is_start[e + 1];
+        const bool first = is_start[e] || find_block(ws, nw, srow[e - 1]) != w;
+        const bool last = next_start || find_block(ws, nw, srow[e + 1]) != w;
+        const uint32_t prev = (first && !is_start[e]) ? (uint32_t)find_block(ws, nw, srow[e - 1]) + 1u : 0u;
+        const uint32_t x = (uint32_t)((int64_t)v - vbase[q]);
+        RatingRec r;
+        r.row = srow[e];
+        r.r = sval[e];
+        r.info = x | (first ? kInfoFirst : 0u) | (last ? kInfoLast : 0u) | (prev << kInfoPrevShift);
+        rec[e] = r;
+        key3[e] = (uint32_t)q * (uint32_t)nw + (uint32_t)w;
+        if (is_start[e]) {
+            visits[v].j = scol[e];
+            visits[v].v = vord[v];
+            visits[v].nvis = nvis[scol[e]];
+        }
+        if (next_start) visits[v].lastw = w;
     }
 }
 
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * blockDim.x)
-        p[e] = v;
+__global__ void k_count_keys(const uint32_t *key, int64_t nnz, unsigned long long *cnt) {
+    GRID_LOOP(e, nnz) atomicAdd(&cnt[key[e]], 1ull);
+}
+
+__global__ void k_permute_recs(const uint32_t *idx, const RatingRec *in, int64_t nnz, RatingRec *out) {
+    GRID_LOOP(e, nnz) out[e] = in[idx[e]];
+}
+
+__global__ void k_iota(uint32_t *p, int64_t n) {
+    GRID_LOOP(e, n) p[e] = (uint32_t)e;
 }
 
 int bits_for(uint64_t maxval) {
@@ -196,14 +224,31 @@ hipError_t dalloc(T **p, size_t count) {
     return hipMalloc((void **)p, count * sizeof(T));
 }
 
+// Temporary storage of the hipCUB calls, grown on demand.
+struct Tmp {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t need(size_t b) {
+        if (b <= bytes) return hipSuccess;
+        (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, b);
+        if (e == hipSuccess) bytes = b;
+        return e;
+    }
+    ~Tmp() { (void)hipFree(p); }
+};
+
 }  // namespace
 
 void free_plan(Plan *pl) {
     (void)hipFree(pl->row_start);
-    (void)hipFree(pl->wck);
-    (void)hipFree(pl->chunks);
-    (void)hipFree(pl->events);
-    (void)hipFree(pl->ratings);
+    (void)hipFree(pl->wave_start);
+    (void)hipFree(pl->rbase);
+    (void)hipFree(pl->recs);
+    (void)hipFree(pl->vbase);
+    (void)hipFree(pl->visits);
     *pl = Plan();
 }
 
@@ -213,46 +258,43 @@ void free_plan(Plan *pl) {
         if (_e != hipSuccess) { rc = _e; goto done; } \
     } while (0)
 
-hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t *d_row,
-                      const int32_t *d_col, const float *d_val, int32_t p, int32_t kp, int32_t slots,
-                      int32_t loads, uint64_t seed, hipStream_t st, int *err_code, char *msg,
-                      size_t msg_len) {
+hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
+                      const float *d_val, int32_t p, int32_t nw, uint64_t seed, hipStream_t st, int *err_code,
+                      char *msg, size_t msg_len) {
     hipError_t rc = hipSuccess;
     *err_code = 0;
     *pl = Plan();
-    pl->m = m; pl->n = n; pl->nnz = nnz; pl->p = p; pl->kp = kp; pl->slots = slots; pl->loads = loads;
+    pl->m = m; pl->n = n; pl->nnz = nnz; pl->p = p; pl->nw = nw;
 
-    unsigned long long *deg = nullptr;
+    Tmp tmp;
+    unsigned long long *deg = nullptr, *kcount = nullptr;
     int64_t *rowptr = nullptr;
-    int64_t *ck_count = nullptr, *ev_count = nullptr, *ld_count = nullptr, *ck_off = nullptr, *ev_off = nullptr;
-    int64_t *wfirst = nullptr;
-    int32_t *err = nullptr, *rowmap = nullptr, *nxt = nullptr;
-    uint32_t *vinfo = nullptr;
+    int32_t *err = nullptr;
     uint32_t *is_start = nullptr, *vid = nullptr, *vidx = nullptr, *vidx_s = nullptr, *nvis = nullptr,
              *seg = nullptr, *vord = nullptr;
     uint64_t *vkey = nullptr, *vkey_s = nullptr;
     int64_t nvisits = 0;
     uint64_t *key1 = nullptr, *key1s = nullptr;
-    uint32_t *idx1 = nullptr, *idx1s = nullptr, *key2 = nullptr, *key2s = nullptr;
+    uint32_t *idx1 = nullptr, *idx1s = nullptr, *key2 = nullptr, *key2s = nullptr, *key3 = nullptr,
+             *key3s = nullptr, *idx3 = nullptr, *idx3s = nullptr;
     int32_t *srow = nullptr, *scol = nullptr;
     float *sval = nullptr;
-    void *tmp = nullptr;
-    size_t tmp_bytes = 0;
+    RatingRec *rec0 = nullptr;
     int32_t h_err = 0;
     const int64_t nb2 = (int64_t)p * p;
-    PlanIn pin{};
-    PlanOut pout{};
-    int64_t h_tot[3] = {0, 0, 0};
+    const int64_t nwt = (int64_t)p * nw;
 
     CK(dalloc(&pl->row_start, p + 1));
-    CK(dalloc(&pl->wck, p + 1));
+    CK(dalloc(&pl->wave_start, nwt + 1));
+    CK(dalloc(&pl->rbase, nwt + 1));
+    CK(dalloc(&pl->vbase, p + 1));
     CK(dalloc(&err, 1));
     CK(hipMemsetAsync(err, 0, sizeof(int32_t), st));
     CK(dalloc(&deg, m + 1));
     CK(dalloc(&rowptr, m + 1));
     CK(hipMemsetAsync(deg, 0, sizeof(unsigned long long) * (m + 1), st));
 
-    // 1-3: degrees, scan, partition
+    // 1-3: degrees, scan, partitions
     if (nnz > 0)
         hipLaunchKernelGGL(k_check_degree, dim3(grid_for(nnz)), dim3(kThreads), 0, st, d_row, d_col, nnz,
                            m, n, deg, err);
@@ -260,11 +302,13 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
     {
         size_t need = 0;
         CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, (const int64_t *)deg, rowptr, m + 1, st));
-        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
-        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, (const int64_t *)deg, rowptr, m + 1, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp.p, need, (const int64_t *)deg, rowptr, m + 1, st));
     }
-    hipLaunchKernelGGL(k_partition, dim3((p + 1 + 63) / 64), dim3(64), 0, st, rowptr, m, nnz, p,
-                       pl->row_start);
+    hipLaunchKernelGGL(k_partition, dim3((p + 1 + 63) / 64), dim3(64), 0, st, rowptr, m, nnz, p, pl->row_start);
+    CK(hipGetLastError());
+    hipLaunchKernelGGL(k_wave_partition, dim3(grid_for(nwt + 1)), dim3(kThreads), 0, st, rowptr, pl->row_start, m,
+                       p, nw, pl->wave_start);
     CK(hipGetLastError());
     CK(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
@@ -279,14 +323,13 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
     CK(dalloc(&key1, nnz)); CK(dalloc(&key1s, nnz));
     CK(dalloc(&idx1, nnz)); CK(dalloc(&idx1s, nnz));
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_key_ji, dim3(grid_for(nnz)), dim3(kThreads), 0, st, d_row, d_col, nnz, m,
-                           key1, idx1);
+        hipLaunchKernelGGL(k_key_ji, dim3(grid_for(nnz)), dim3(kThreads), 0, st, d_row, d_col, nnz, m, key1, idx1);
         CK(hipGetLastError());
-        int eb = bits_for((uint64_t)n * (uint64_t)m);
+        const int eb = bits_for((uint64_t)n * (uint64_t)m);
         size_t need = 0;
         CK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, key1, key1s, idx1, idx1s, nnz, 0, eb, st));
-        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
-        CK(hipcub::DeviceRadixSort::SortPairs(tmp, need, key1, key1s, idx1, idx1s, nnz, 0, eb, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceRadixSort::SortPairs(tmp.p, need, key1, key1s, idx1, idx1s, nnz, 0, eb, st));
         hipLaunchKernelGGL(k_check_dup, dim3(grid_for(nnz)), dim3(kThreads), 0, st, key1s, nnz, err);
         CK(hipGetLastError());
         CK(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -305,18 +348,18 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
         hipLaunchKernelGGL(k_key_qs, dim3(grid_for(nnz)), dim3(kThreads), 0, st, idx1s, d_row, d_col, nnz,
                            pl->row_start, p, seed, key2);
         CK(hipGetLastError());
-        CK(dalloc(&idx1, nnz));  // reuse as output indices
-        int eb = bits_for((uint64_t)nb2 - 1);
+        CK(dalloc(&idx1, nnz));  // output indices
+        const int eb = bits_for((uint64_t)nb2 - 1);
         size_t need = 0;
         CK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, key2, key2s, idx1s, idx1, nnz, 0, eb, st));
-        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
-        CK(hipcub::DeviceRadixSort::SortPairs(tmp, need, key2, key2s, idx1s, idx1, nnz, 0, eb, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceRadixSort::SortPairs(tmp.p, need, key2, key2s, idx1s, idx1, nnz, 0, eb, st));
     }
     (void)hipFree(key2); key2 = nullptr;
     CK(dalloc(&srow, nnz)); CK(dalloc(&scol, nnz)); CK(dalloc(&sval, nnz));
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_gather, dim3(grid_for(nnz)), dim3(kThreads), 0, st, idx1, d_row, d_col, d_val,
-                           nnz, srow, scol, sval);
+        hipLaunchKernelGGL(k_gather, dim3(grid_for(nnz)), dim3(kThreads), 0, st, idx1, d_row, d_col, d_val, nnz,
+                           srow, scol, sval);
         CK(hipGetLastError());
     }
     (void)hipFree(idx1); idx1 = nullptr;
@@ -332,8 +375,8 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
         CK(hipGetLastError());
         size_t need = 0;
         CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, is_start, vid, nnz, st));
-        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
-        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, is_start, vid, nnz, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp.p, need, is_start, vid, nnz, st));
         uint32_t h_last[2] = {0, 0};
         CK(hipMemcpyAsync(&h_last[0], vid + nnz - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
         CK(hipMemcpyAsync(&h_last[1], is_start + nnz - 1, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
@@ -346,87 +389,90 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
         hipLaunchKernelGGL(k_visit_keys, dim3(grid_for(nnz)), dim3(kThreads), 0, st, is_start, vid, key2s, scol, nnz,
                            p, vkey, vidx, nvis);
         CK(hipGetLastError());
-        int eb = bits_for((uint64_t)n * (uint64_t)p);
+        const int eb = bits_for((uint64_t)n * (uint64_t)p);
         size_t need = 0;
         CK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, vkey, vkey_s, vidx, vidx_s, nvisits, 0, eb, st));
-        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
-        CK(hipcub::DeviceRadixSort::SortPairs(tmp, need, vkey, vkey_s, vidx, vidx_s, nvisits, 0, eb, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceRadixSort::SortPairs(tmp.p, need, vkey, vkey_s, vidx, vidx_s, nvisits, 0, eb, st));
         need = 0;
         CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, nvis, seg, n + 1, st));
-        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
-        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, nvis, seg, n + 1, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp.p, need, nvis, seg, n + 1, st));
         hipLaunchKernelGGL(k_visit_ordinal, dim3(grid_for(nvisits)), dim3(kThreads), 0, st, vkey_s, vidx_s, seg,
                            nvisits, p, vord);
         CK(hipGetLastError());
     }
+    (void)hipFree(vkey); vkey = nullptr;
+    (void)hipFree(vkey_s); vkey_s = nullptr;
+    (void)hipFree(vidx); vidx = nullptr;
+    (void)hipFree(vidx_s); vidx_s = nullptr;
     pl->nvisits = nvisits;
-
-    // 6: per-worker plans, two passes
-    CK(dalloc(&vinfo, nnz));
-    CK(dalloc(&nxt, nnz));
-    CK(dalloc(&rowmap, m));
-    CK(dalloc(&wfirst, p + 1));
-    CK(dalloc(&ck_count, p + 1)); CK(dalloc(&ev_count, p + 1)); CK(dalloc(&ld_count, p + 1));
-    CK(dalloc(&ck_off, p + 1)); CK(dalloc(&ev_off, p + 1));
-    CK(hipMemsetAsync(ck_count, 0, sizeof(int64_t) * (p + 1), st));
-    CK(hipMemsetAsync(ev_count, 0, sizeof(int64_t) * (p + 1), st));
-    CK(hipMemsetAsync(ld_count, 0, sizeof(int64_t) * (p + 1), st));
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(m)), dim3(kThreads), 0, st, rowmap, m, -1);
-    hipLaunchKernelGGL(k_worker_first, dim3((p + 1 + 63) / 64), dim3(64), 0, st, rowptr, pl->row_start, p, wfirst);
+    hipLaunchKernelGGL(k_visit_base, dim3((p + 1 + 63) / 64), dim3(64), 0, st, rowptr, pl->row_start, vid, nnz,
+                       nvisits, p, pl->vbase);
     CK(hipGetLastError());
+
+    // 6: records
+    CK(dalloc(&pl->visits, nvisits));
+    CK(dalloc(&rec0, nnz));
+    CK(dalloc(&key3, nnz));
     if (nnz > 0) {
-        hipLaunchKernelGGL(k_vinfo, dim3(grid_for(nnz)), dim3(kThreads), 0, st, vid, is_start, vord, nvis, scol, nnz,
-                           vinfo);
+        hipLaunchKernelGGL(k_records, dim3(grid_for(nnz)), dim3(kThreads), 0, st, srow, scol, sval, key2s, is_start,
+                           vid, vord, nvis, pl->vbase, pl->wave_start, nnz, p, nw, rec0, pl->visits, key3);
         CK(hipGetLastError());
     }
-    pin.srow = srow; pin.scol = scol; pin.sval = sval; pin.blk = key2s; pin.vinfo = vinfo;
-    pin.slots = slots; pin.cap = loads; pin.look = kLookahead; pin.nxt = nxt; pin.rowmap = rowmap;
-    hipLaunchKernelGGL(k_planner<false>, dim3((p + 63) / 64), dim3(64), 0, st, pin, wfirst, pout, ck_off, ev_off,
-                       ck_count, ev_count, ld_count, err, p);
-    CK(hipGetLastError());
+    (void)hipFree(srow); srow = nullptr;
+    (void)hipFree(scol); scol = nullptr;
+    (void)hipFree(sval); sval = nullptr;
+    (void)hipFree(key2s); key2s = nullptr;
+    (void)hipFree(is_start); is_start = nullptr;
+    (void)hipFree(vid); vid = nullptr;
+
+    // 7: one stream per wave
+    CK(dalloc(&kcount, nwt + 1));
+    CK(hipMemsetAsync(kcount, 0, sizeof(unsigned long long) * (nwt + 1), st));
+    CK(dalloc(&pl->recs, nnz));
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_count_keys, dim3(grid_for(nnz)), dim3(kThreads), 0, st, key3, nnz, kcount);
+        CK(hipGetLastError());
+        CK(dalloc(&key3s, nnz)); CK(dalloc(&idx3, nnz)); CK(dalloc(&idx3s, nnz));
+        hipLaunchKernelGGL(k_iota, dim3(grid_for(nnz)), dim3(kThreads), 0, st, idx3, nnz);
+        CK(hipGetLastError());
+        const int eb = bits_for((uint64_t)(nwt > 1 ? nwt - 1 : 1));
+        size_t need = 0;
+        CK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, key3, key3s, idx3, idx3s, nnz, 0, eb, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceRadixSort::SortPairs(tmp.p, need, key3, key3s, idx3, idx3s, nnz, 0, eb, st));
+        hipLaunchKernelGGL(k_permute_recs, dim3(grid_for(nnz)), dim3(kThreads), 0, st, idx3s, rec0, nnz, pl->recs);
+        CK(hipGetLastError());
+    }
     {
         size_t need = 0;
-        CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, ck_count, ck_off, p + 1, st));
-        if (need > tmp_bytes) { (void)hipFree(tmp); tmp = nullptr; CK(hipMalloc(&tmp, need)); tmp_bytes = need; }
-        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, ck_count, ck_off, p + 1, st));
-        CK(hipcub::DeviceScan::ExclusiveSum(tmp, need, ev_count, ev_off, p + 1, st));
-    }
-    CK(hipMemcpyAsync(&h_tot[0], ck_off + p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    CK(hipMemcpyAsync(&h_tot[1], ev_off + p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    CK(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    CK(hipStreamSynchronize(st));
-    if (h_err & 4) {
-        *err_code = 1;
-        snprintf(msg, msg_len, "%d LDS slots per worker are too few", slots);
-        goto done;
+        CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, (const int64_t *)kcount, pl->rbase, nwt + 1, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp.p, need, (const int64_t *)kcount, pl->rbase, nwt + 1, st));
     }
     {
-        std::vector<int64_t> lc(p + 1);
-        CK(hipMemcpy(lc.data(), ld_count, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost));
-        int64_t t = 0;
-        for (int32_t q = 0; q < p; ++q) t += lc[q];
-        pl->nloads = t;
+        std::vector<int64_t> vb(p + 1);
+        CK(hipMemcpyAsync(vb.data(), pl->vbase, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        int64_t mx = 0;
+        for (int32_t q = 0; q < p; ++q) mx = vb[q + 1] - vb[q] > mx ? vb[q + 1] - vb[q] : mx;
+        pl->max_worker_visits = mx;
+        if (mx > (int64_t)kInfoXMask) {
+            *err_code = 5;
+            snprintf(msg, msg_len, "a worker has %lld visits per epoch; at most %u are supported", (long long)mx,
+                     kInfoXMask);
+            goto done;
+        }
     }
-    pl->nchunks = h_tot[0];
-    pl->nevents = h_tot[1];
-    CK(dalloc(&pl->chunks, pl->nchunks));
-    CK(dalloc(&pl->events, pl->nevents));
-    CK(dalloc(&pl->ratings, nnz));
-    CK(hipMemcpyAsync(pl->wck, ck_off, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToDevice, st));
-    pout.chunks = pl->chunks; pout.events = pl->events; pout.ratings = pl->ratings;
-    hipLaunchKernelGGL(k_planner<true>, dim3((p + 63) / 64), dim3(64), 0, st, pin, wfirst, pout, ck_off, ev_off,
-                       ck_count, ev_count, ld_count, err, p);
-    CK(hipGetLastError());
-    CK(hipStreamSynchronize(st));
 
 done:
-    (void)hipFree(deg); (void)hipFree(rowptr);
+    (void)hipFree(deg); (void)hipFree(kcount); (void)hipFree(rowptr); (void)hipFree(err);
     (void)hipFree(is_start); (void)hipFree(vid); (void)hipFree(vidx); (void)hipFree(vidx_s); (void)hipFree(nvis);
     (void)hipFree(seg); (void)hipFree(vord); (void)hipFree(vkey); (void)hipFree(vkey_s);
-    (void)hipFree(ck_count); (void)hipFree(ev_count); (void)hipFree(ld_count); (void)hipFree(ck_off);
-    (void)hipFree(ev_off); (void)hipFree(wfirst); (void)hipFree(vinfo); (void)hipFree(nxt);
-    (void)hipFree(err); (void)hipFree(rowmap); (void)hipFree(key1); (void)hipFree(key1s); (void)hipFree(idx1); (void)hipFree(idx1s);
-    (void)hipFree(key2); (void)hipFree(key2s); (void)hipFree(srow); (void)hipFree(scol); (void)hipFree(sval); (void)hipFree(tmp);
+    (void)hipFree(key1); (void)hipFree(key1s); (void)hipFree(idx1); (void)hipFree(idx1s);
+    (void)hipFree(key2); (void)hipFree(key2s); (void)hipFree(key3); (void)hipFree(key3s); (void)hipFree(idx3);
+    (void)hipFree(idx3s); (void)hipFree(srow); (void)hipFree(scol); (void)hipFree(sval); (void)hipFree(rec0);
     if (rc != hipSuccess || *err_code != 0) free_plan(pl);
     return rc;
 }

@@ -1,38 +1,33 @@
-// NOMAD worker kernel: one workgroup = one worker (Algorithm 1), persistent for a whole
-// nomad_train_epochs call.  The workgroup has two wavefronts:
+// NOMAD worker kernel (Algorithm 1, in the hybrid form of section 3.4): one workgroup is
+// one worker and stays resident for a whole nomad_train_epochs call.  A workgroup has
+// nw compute wavefronts and one memory wavefront.
 //
-//   compute wave   runs the SGD updates of section 2.3 over each chunk's ratings in plan
-//                  order, on vectors held in LDS, and counts finished chunks ("done");
-//   memory wave    stages chunks ahead of it ("staged"): once the compute wave has freed a
-//                  chunk's slots it writes back the rows the chunk evicts and loads rows
-//                  w_i and items h_j straight into their LDS slots (LDS-DMA loads), copies
-//                  the chunk's rating records into a small LDS ring, and after the compute
-//                  wave has finished a chunk passes on the items whose visit ended there.
+//   compute wave w   owns a contiguous sub-block of the worker's rows.  It reads its
+//                    ratings as one stream in processing order and runs the SGD updates
+//                    of section 2.3 on them.  Rows w_i stream through registers: the row
+//                    of the rating D places ahead is loaded while the current one is
+//                    updated, and a row used again inside that window is handed on
+//                    through LDS instead of being re-read.  The item h_j of a visit comes
+//                    from an LDS slot and goes back there at the end of the wave's part
+//                    of the visit; the waves of the worker take the item in ascending
+//                    order (rows ascending).
+//   memory wave      takes items over (a visit may start once the item's counter of
+//                    finished visits equals the visit's ticket), loads them into LDS
+//                    slots, and passes each item on once the last wave holding ratings of
+//                    it is done: device-coherent write-back of h_j, then the counter
+//                    advanced.
 //
-// Owner-computes rule (section 3.1): before the memory wave loads an item for a visit it
-// waits until the item has finished every earlier visit in the ring order (a per-item
-// counter of finished visits reaches the visit's ticket), so worker q is the sole owner
-// of h_j while the visit lasts.  When the visit ends the item is written back and the
-// counter advanced.  Rows w_i are owned by the worker for good.
+// The serial order this realises is the fixed ring order: worker q, sub-step s, items of
+// group (q + s) mod p ascending, rows ascending.  Every row and every item sees its
+// updates in that order, so the result does not depend on timing, on nw or on the number
+// of item slots.
 //
-// Memory-wave pipeline, iteration x (chunk x):
-//   wait for the loads and stores of iteration x-1; pass on items whose write-back
-//   completed; load what was not loaded ahead (items that were not yet free when polled,
-//   or the first chunk of an epoch); publish chunk x to the compute wave; retire the
-//   chunks the compute wave has finished; wait until the compute wave has finished every
-//   chunk that used the slots chunk x+1 overwrites, write back the rows chunk x+1 evicts
-//   and issue its loads; poll the items of chunk x+2, read the events of chunk x+3 and
-//   the record of chunk x+4.
-// Every wait of the memory wave keeps passing on finished items, so a worker never holds
-// an item that another worker waits for while it waits itself (no cycles in the ring
-// order), and every wait is bounded in time.
-//
-// Memory ordering of a hand-off: item vectors are written with device-coherent stores
-// (agent scope) and the counter is advanced with a device-coherent store only after
-// "s_waitcnt vmcnt(0)" has seen those stores complete; the next owner polls the counter
-// with device-coherent loads and reads the item with device-coherent loads.  Rows use
-// ordinary loads and stores from the same wavefront, whose accesses to one address are
-// performed in program order.  The two wavefronts of a worker synchronise through LDS
+// Memory ordering of a hand-off between workers: the item is written with
+// device-coherent stores, "s_waitcnt vmcnt(0)" sees them complete, and only then is the
+// counter advanced with a device-coherent store; the next owner polls the counter with
+// device-coherent loads and loads the item with device-coherent LDS-DMA loads.  Rows use
+// ordinary loads and stores of the one wavefront that owns them, whose accesses to one
+// address are performed in program order.  Waves of a worker synchronise through LDS
 // words written after "s_waitcnt lgkmcnt(0)".
 #include <cmath>
 #include <utility>
@@ -80,17 +75,38 @@ __device__ __forceinline__ float wave_sum(float x) {
     return x;
 }
 
+typedef __attribute__((address_space(3))) float lds_float;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
+// VEC consecutive floats of global memory or LDS.
 template <int VEC>
-__device__ __forceinline__ void lds_read(const float *p, float (&v)[VEC]) {
+__device__ __forceinline__ void vload(const float *p, float (&v)[VEC]) {
     if constexpr (VEC == 1) { v[0] = p[0]; }
-    if constexpr (VEC == 2) { float2 t = *(const float2 *)p; v[0] = t.x; v[1] = t.y; }
-    if constexpr (VEC == 4) { float4 t = *(const float4 *)p; v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w; }
+    if constexpr (VEC == 2) { const float2 t = *(const float2 *)p; v[0] = t.x; v[1] = t.y; }
+    if constexpr (VEC == 4) { const float4 t = *(const float4 *)p; v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w; }
 }
 template <int VEC>
-__device__ __forceinline__ void lds_write(float *p, const float (&v)[VEC]) {
+__device__ __forceinline__ void vstore(float *p, const float (&v)[VEC]) {
     if constexpr (VEC == 1) { p[0] = v[0]; }
     if constexpr (VEC == 2) { *(float2 *)p = make_float2(v[0], v[1]); }
     if constexpr (VEC == 4) { *(float4 *)p = make_float4(v[0], v[1], v[2], v[3]); }
+}
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) f32x2v lds_f32x2;
+typedef __attribute__((address_space(3))) f32x4v lds_f32x4;
+
+template <int VEC>
+__device__ __forceinline__ void lload(const lds_float *p, float (&v)[VEC]) {
+    if constexpr (VEC == 1) { v[0] = p[0]; }
+    if constexpr (VEC == 2) { const f32x2v t = *(const lds_f32x2 *)p; v[0] = t.x; v[1] = t.y; }
+    if constexpr (VEC == 4) { const f32x4v t = *(const lds_f32x4 *)p; v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w; }
+}
+template <int VEC>
+__device__ __forceinline__ void lstore(lds_float *p, const float (&v)[VEC]) {
+    if constexpr (VEC == 1) { p[0] = v[0]; }
+    if constexpr (VEC == 2) { *(lds_f32x2 *)p = f32x2v{v[0], v[1]}; }
+    if constexpr (VEC == 4) { *(lds_f32x4 *)p = f32x4v{v[0], v[1], v[2], v[3]}; }
 }
 
 // Seconds-scale bound on any single wait, so that a broken schedule ends the kernel
@@ -100,68 +116,22 @@ constexpr uint64_t kWaitLimitTicks = 20ull * 100000000ull;
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef uint64_t u64x2_t __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ f32x4_t coherent_load4(const float *p) {
-    u64x2_t v;
-    v.x = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    v.y = __hip_atomic_load((const uint64_t *)p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __builtin_bit_cast(f32x4_t, v);
-}
 __device__ __forceinline__ void coherent_store4(float *p, f32x4_t v) {
     const u64x2_t u = __builtin_bit_cast(u64x2_t, v);
     __hip_atomic_store((uint64_t *)p, u.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store((uint64_t *)p + 1, u.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Number of consecutive set bits of m from bit 0 (64 when all are set; the count-trailing-
+// zeros instruction gives -1 for a zero input).
+__device__ __forceinline__ int leading_run(uint64_t m) { return ~m == 0 ? 64 : (int)__builtin_ctzll(~m); }
+
 __device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ void wait_lgkm() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
-// Clock read only when per-worker counters are requested.
+// Clock read only when phase timing is requested.
 __device__ __forceinline__ uint64_t tick(bool on) { return on ? wall_clock64() : 0; }
-
-// ---------------------------------------------------------------------------------------
-// LDS of one worker: S vector slots, a ring of kRing staged chunks (rating records and
-// the items each chunk releases), and the synchronisation words.
-enum SyncWord { kStaged = 0, kDone = 1, kStop = 2 };
-
-struct Lds {
-    float *vec;         // S x kp
-    RatingRec *rat;     // kRing x 64
-    int32_t *rel_id;    // kRing x 64
-    uint32_t *rel_tk;   // kRing x 64
-    int32_t *rel_slot;  // kRing x 64
-    int32_t *cnt;       // kRing x 2: ratings, releases
-    int32_t *sync;      // staged, done, stop, unused
-    float *zero;        // 64 x 4 zeros: read and written by lanes beyond the vector width
-};
-
-constexpr size_t kRingBytes = (size_t)kRing * 64 * (sizeof(RatingRec) + 3 * sizeof(int32_t)) + kRing * 2 * 4 + 4 * 4;
-
-// LDS of one worker (a multiple of 16 bytes): slots, ring, synchronisation, zero line.
-__host__ __device__ inline size_t worker_lds_bytes(int kp, int slots) {
-    return (size_t)slots * (size_t)kp * sizeof(float) + kRingBytes + 64 * 4 * sizeof(float);
-}
-
-__device__ __forceinline__ Lds lds_layout(void *base, int S, int kp) {
-    char *p = (char *)base;
-    Lds L;
-    L.vec = (float *)p;
-    p += (size_t)S * kp * sizeof(float);
-    L.rat = (RatingRec *)p;
-    p += kRing * 64 * sizeof(RatingRec);
-    L.rel_id = (int32_t *)p;
-    p += kRing * 64 * 4;
-    L.rel_tk = (uint32_t *)p;
-    p += kRing * 64 * 4;
-    L.rel_slot = (int32_t *)p;
-    p += kRing * 64 * 4;
-    L.cnt = (int32_t *)p;
-    p += kRing * 2 * 4;
-    L.sync = (int32_t *)p;
-    p += 4 * 4;
-    L.zero = (float *)p;
-    return L;
-}
 
 __device__ __forceinline__ int sync_load(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -170,216 +140,328 @@ __device__ __forceinline__ void sync_store(int32_t *p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Prefetch window (ratings in flight) of a compute wave for VEC floats per lane.
+template <int VEC>
+constexpr int window() { return VEC == 4 ? 8 : 16; }
+
+__host__ __device__ inline int window_for_kp(int kp) { return kp > 128 ? 8 : 16; }
+
+// ---------------------------------------------------------------------------------------
+// LDS of a worker: item slots, forwarding slots of every compute wave, and the words the
+// waves synchronise on.
+struct Lds {
+    float *items;     // slots x kp
+    float *rows;      // nw x (D + 1) x kp: row slots of every compute wave
+    uint32_t *recs;   // nw x 3 x 192: record batches of every compute wave
+    int32_t *flag;    // nw: 1 + the last visit each compute wave finished
+    int32_t *ctl;     // [0] visits loaded, [1] stop
+};
+
+__host__ __device__ inline size_t lds_bytes(int kp, int nw, int slots) {
+    return ((size_t)slots * kp + (size_t)nw * (window_for_kp(kp) + 1) * kp) * sizeof(float) +
+           (size_t)nw * 3 * 192 * 4 + (kMaxWaves + 1 + 4) * 4;
+}
+
+__device__ __forceinline__ Lds lds_layout(void *base, int kp, int nw, int slots) {
+    char *p = (char *)base;
+    Lds L;
+    L.items = (float *)p;
+    p += (size_t)slots * kp * sizeof(float);
+    L.rows = (float *)p;
+    p += (size_t)nw * (window_for_kp(kp) + 1) * kp * sizeof(float);
+    L.recs = (uint32_t *)p;
+    p += (size_t)nw * 3 * 192 * 4;
+    L.flag = (int32_t *)p;
+    p += (kMaxWaves + 1) * 4;
+    L.ctl = (int32_t *)p;
+    return L;
+}
+
+__device__ __forceinline__ lds_float *to_lds(float *p) { return (lds_float *)(p); }
+
+// Record the end of the worker: every wave stops waiting.
+__device__ __forceinline__ void raise_abort(uint32_t *abort_flag, const Lds &L, uint32_t code) {
+    __hip_atomic_store(abort_flag, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    sync_store(&L.ctl[1], 1);
+}
+
+// First wait that ran out of time: diag[0] = 1 + worker, then wave (-1: memory wave) and
+// what it waited for.
+__device__ __forceinline__ void note_timeout(int32_t *diag, int q, int w, int a0, int a1, int a2, int a3) {
+    if (atomicCAS(diag, 0, q + 1) == 0) {
+        diag[1] = w;
+        diag[2] = a0;
+        diag[3] = a1;
+        diag[4] = a2;
+        diag[5] = a3;
+    }
+}
+
+// Wait until the LDS word *p exceeds x.  False if the worker is stopping.
+__device__ __forceinline__ bool wait_above(const int32_t *p, int x, const Lds &L, uint32_t *abort_flag,
+                                           int lane, int32_t *diag, int q, int w, int which) {
+    if (sync_load(p) > x) return true;
+    const uint64_t t0 = wall_clock64();
+    while (sync_load(p) <= x) {
+        if (sync_load(&L.ctl[1])) return false;
+        if (wall_clock64() - t0 > kWaitLimitTicks) {
+            if (lane == 0) {
+                note_timeout(diag, q, w, x, sync_load(p), which, sync_load(&L.ctl[0]));
+                raise_abort(abort_flag, L, 1u);
+            }
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// LDS-DMA loads, written as asm so that the compiler neither sees them as LDS writes (it
+// would then wait for every outstanding memory operation before each LDS read) nor counts
+// them; the waits for them are explicit.  m0 holds the LDS address of lane 0's data; lane
+// l writes at m0 + l * (bytes per lane).  Lanes outside `mask` do nothing.
+
+__device__ __forceinline__ uint32_t lds_off(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
+}
+
+#define NOMAD_DMA16(cpol)                                   \
+    uint64_t saved;                                         \
+    uint32_t m0s;                                           \
+    asm volatile(                                           \
+        "s_mov_b32 %1, m0\n\t"                              \
+        "s_mov_b64 %0, exec\n\t"                            \
+        "s_and_b64 exec, exec, %4\n\t"                      \
+        "s_mov_b32 m0, %3\n\t"                              \
+        "s_nop 0\n\t"                                       \
+        "global_load_lds_dwordx4 %2, off" cpol "\n\t"        \
+        "s_mov_b64 exec, %0\n\t"                            \
+        "s_mov_b32 m0, %1"                                  \
+        : "=&s"(saved), "=&s"(m0s)                          \
+        : "v"(src), "s"(lds), "s"(mask)                     \
+        : "memory")
+
+__device__ __forceinline__ void dma16(const void *src, uint32_t lds, uint64_t mask) { NOMAD_DMA16(""); }
+// Device-coherent form (sc1), for items handed over by other workers.
+__device__ __forceinline__ void dma16_coherent(const void *src, uint32_t lds, uint64_t mask) { NOMAD_DMA16(" sc1"); }
+
+__device__ __forceinline__ void dma4(const void *src, uint32_t lds) {
+    uint32_t m0s;
+    asm volatile(
+        "s_mov_b32 %0, m0\n\t"
+        "s_mov_b32 m0, %2\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dword %1, off\n\t"
+        "s_mov_b32 m0, %0"
+        : "=&s"(m0s)
+        : "v"(src), "s"(lds)
+        : "memory");
+}
+
 // ---------------------------------------------------------------------------------------
 // Compute wave.
-
-// SGD over one chunk's ratings in plan order, on LDS.
 //
-// Lane l holds elements [VEC l, VEC l + VEC) of a vector; lanes beyond the vector width
-// read and write a line of zeros (their terms add nothing to the dot products).  Every
-// rating issues the same LDS operations: write its row and item, then read the row and
-// item of the rating two ahead into one of two alternating register sets.  A read-ahead
-// row is stale only if it is the row of the rating just before it, which then takes the
-// freshly updated registers instead; likewise for an item continuing its run (an item
-// has a single run of ratings per chunk, so the first read of a run is never stale).
-template <int VEC>
-struct SgdLane {
-    float *base;  // this lane's elements of slot 0 (or the zero line)
-    int stride;   // floats per slot (kp), 0 for lanes beyond the vector width
-};
+// The rows of the next D ratings are in flight into D LDS slots.  Step y updates rating y
+// (slot y mod D) and then starts the load of rating y + D into the same slot.  Every step
+// issues exactly one row load (into the wave's spare slot when the row is handed on
+// instead) and one store (a 4-byte placeholder when the row is handed on), so when step y
+// begins at least 2(D-1) memory operations were issued after the load of its row, and
+// "s_waitcnt vmcnt(2D-2)" is enough to see that load complete.  Record batches (64
+// ratings) are loaded one batch ahead into a ring of three; they only add operations.
 
-template <int VEC>
-__device__ __forceinline__ void read_vec(const SgdLane<VEC> &ln, int slot, float (&v)[VEC]) {
-    lds_read<VEC>(ln.base + __umul24(slot, ln.stride), v);
-}
-template <int VEC>
-__device__ __forceinline__ void write_vec(const SgdLane<VEC> &ln, int slot, const float (&v)[VEC]) {
-    lds_write<VEC>(ln.base + __umul24(slot, ln.stride), v);
-}
+template <int VEC, int NR16, int D>
+struct ComputeWave {
+    static_assert(2 * (D - 1) <= 63, "vmcnt range");
+    const TrainArgs &a;
+    const Lds &L;
+    const int q, w, lane, kp;
+    const bool on;            // lane holds elements of the vectors
+    const int loff;           // first element of the lane (0 for lanes beyond the width)
+    const RatingRec *rs;      // the wave's stream
+    const int64_t cnt;        // ratings per epoch
+    const int64_t total;      // ratings of the launch
+    lds_float *const rows;    // D + 1 row slots (the last one takes loads that are not used)
+    const uint32_t rows_lds;
+    const lds_u32 *const recs;  // 3 x 64 records (as dwords)
+    const uint32_t recs_lds;
+    lds_float *const items;
+    const uint64_t row_mask;  // lanes that load a row (16 bytes each)
+    int64_t bstart = 0;       // stream position of the next record batch to load
+    int win = -1;             // lane u: row of the rating in window slot u (-1: none)
+    uint64_t forwarded = 0, t_wait = 0;
 
-template <int VEC>
-struct SgdState {
-    float w[VEC], h[VEC];  // rating x-1's updated row and item
-    int rs_p, ts_p;        // their slots (-1: none yet)
-};
+    __device__ ComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0, int64_t cnt_)
+        : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), on(lane_ * VEC < a_.kp), loff(on ? lane_ * VEC : 0),
+          rs(a_.recs + r0), cnt(cnt_), total(cnt_ * a_.epochs),
+          rows(to_lds(L_.rows) + (size_t)w_ * (D + 1) * a_.kp),
+          rows_lds(lds_off(L_.rows) + (uint32_t)(w_ * (D + 1) * a_.kp * 4)),
+          recs((const lds_u32 *)(L_.recs + (size_t)w_ * 3 * 192)), recs_lds(lds_off(L_.recs) + (uint32_t)(w_ * 3 * 192 * 4)),
+          items(to_lds(L_.items) + (on ? lane_ * VEC : 0)),
+          row_mask((a_.kp >> 2) >= 64 ? ~0ull : ((1ull << (a_.kp >> 2)) - 1ull)) {}
 
-template <int VEC, int NR16>
-__device__ __forceinline__ void sgd_step(const SgdLane<VEC> &ln, SgdState<VEC> &S, float (&wb)[VEC],
-                                         float (&hb)[VEC], int r_sl, float r_val, int x, int nrat, float s,
-                                         float shrink) {
-    const int sl = rl_i(r_sl, x);
-    const int rs = sl & 255, ts = (sl >> 8) & 255;
-    const float r = rl_f(r_val, x);
-    const bool same_row = rs == S.rs_p, same_item = ts == S.ts_p;
-    float w[VEC], h[VEC];
+    // Load the records of batch b (64 ratings from stream position bstart) into ring
+    // entry b mod 3: three dword loads of 64 lanes.
+    __device__ __forceinline__ void load_batch(int64_t b) {
+        const uint32_t *src = (const uint32_t *)rs;
+        const uint32_t dst = recs_lds + (uint32_t)b % 3u * 192u * 4u;
 #pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-        w[v] = same_row ? S.w[v] : wb[v];
-        h[v] = same_item ? S.h[v] : hb[v];
+        for (int t = 0; t < 3; ++t) {
+            const int dwi = 64 * t + lane;  // dword of the batch
+            int64_t rec = bstart + dwi / 3;
+            while (rec >= cnt) rec -= cnt;
+            dma4(src + rec * 3 + dwi % 3, dst + (uint32_t)(t * 256));
+        }
+        bstart += 64;
+        while (bstart >= cnt) bstart -= cnt;
     }
-    float d = 0.0f;
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) d = fmaf(w[v], h[v], d);
-    d = wave_sum<NR16>(d);
-    const float se = s * (r - d);
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) {
-        S.w[v] = fmaf(se, h[v], shrink * w[v]);
-        S.h[v] = fmaf(se, w[v], shrink * h[v]);
-    }
-    write_vec<VEC>(ln, rs, S.w);
-    write_vec<VEC>(ln, ts, S.h);
-    S.rs_p = rs;
-    S.ts_p = ts;
-    const int x2 = x + 2 < nrat ? x + 2 : nrat - 1;
-    const int sl2 = rl_i(r_sl, x2);
-    read_vec<VEC>(ln, sl2 & 255, wb);
-    read_vec<VEC>(ln, (sl2 >> 8) & 255, hb);
-}
 
-template <int VEC, int NR16>
-__device__ __forceinline__ void sgd_chunk(const SgdLane<VEC> &ln, const RatingRec &rr, int nrat, float s,
-                                          float shrink) {
-    if (nrat <= 0) return;
-    const int r_sl = (int)rr.slots;
-    const float r_val = rr.r;
-    float wb0[VEC], hb0[VEC], wb1[VEC], hb1[VEC];
-    const int sl0 = rl_i(r_sl, 0), sl1 = rl_i(r_sl, nrat > 1 ? 1 : 0);
-    read_vec<VEC>(ln, sl0 & 255, wb0);
-    read_vec<VEC>(ln, (sl0 >> 8) & 255, hb0);
-    read_vec<VEC>(ln, sl1 & 255, wb1);
-    read_vec<VEC>(ln, (sl1 >> 8) & 255, hb1);
-    SgdState<VEC> S;
-    S.rs_p = -1;
-    S.ts_p = -1;
-#pragma unroll
-    for (int v = 0; v < VEC; ++v) S.w[v] = S.h[v] = 0.0f;
-    int x = 0;
-    for (; x + 1 < nrat; x += 2) {
-        sgd_step<VEC, NR16>(ln, S, wb0, hb0, r_sl, r_val, x, nrat, s, shrink);
-        sgd_step<VEC, NR16>(ln, S, wb1, hb1, r_sl, r_val, x + 1, nrat, s, shrink);
+    __device__ __forceinline__ RatingRec record(int64_t y) {
+        const lds_u32 *p = recs + ((uint32_t)(y >> 6) % 3u * 64u + (uint32_t)(y & 63)) * 3u;
+        RatingRec r;
+        r.row = __builtin_amdgcn_readfirstlane((int)p[0]);
+        r.r = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane((int)p[1]));
+        r.info = (uint32_t)__builtin_amdgcn_readfirstlane((int)p[2]);
+        return r;
     }
-    if (x < nrat) sgd_step<VEC, NR16>(ln, S, wb0, hb0, r_sl, r_val, x, nrat, s, shrink);
-}
 
-template <int VEC, int NR16>
-__device__ __forceinline__ void compute_wave(const TrainArgs &a, const Lds &L, int64_t nck, int q, int lane) {
-    const bool prof = a.timing;
-    const uint64_t t_start = tick(prof);
-    uint64_t t_sgd = 0, t_starve = 0;
-    int64_t n_rat = 0;
-    const int64_t total = nck * a.epochs;
-    int epoch = -1, ex = a.epoch0;
-    int64_t lx = 0;
-    float s_step = 0.0f, s_shrink = 1.0f;
-    const bool on = lane * VEC < a.kp;
-    SgdLane<VEC> ln;
-    ln.base = on ? L.vec + lane * VEC : L.zero + lane * VEC;
-    ln.stride = on ? a.kp : 0;
-    for (int64_t x = 0; x < total; ++x) {
-        if (sync_load(&L.sync[kStaged]) <= x) {
-            const uint64_t t0 = tick(prof);
-            while (sync_load(&L.sync[kStaged]) <= x) {
-                if (sync_load(&L.sync[kStop])) return;
-                __builtin_amdgcn_s_sleep(1);
+    __device__ __forceinline__ void placeholder_store() {
+        if (lane == 0) a.dummy[(int64_t)q * kMaxWaves + w] = 0.0f;
+    }
+
+    // Start loading the row of rating y into slot u (or into the spare slot if a rating
+    // still in the window updates the same row: that one hands its result on).
+    __device__ __forceinline__ void issue(int64_t y, int u) {
+        if (y < total) {
+            if ((y & 63) == 0 && y > 0) load_batch((y >> 6) + 1);
+            const int row = record(y).row;
+            const uint64_t same = __builtin_amdgcn_ballot_w64(win == row) & ~(1ull << u);
+            win = lane == u ? row : win;
+            const float *src = a.W + (int64_t)row * kp + (lane & 63) * 4;
+            const uint32_t dst = rows_lds + (uint32_t)((same ? D : u) * kp * 4);
+            dma16(src, dst, row_mask);
+        } else {
+            win = lane == u ? -1 : win;
+            dma16(a.W + (lane & 63) * 4, rows_lds + (uint32_t)(D * kp * 4), row_mask);
+        }
+    }
+
+    // Update rating y in window slot u (section 2.3: one residual, both vectors from
+    // their values before the update).
+    __device__ __forceinline__ bool step(int64_t y, int u, float (&h)[VEC], int xbase, float s, float c) {
+        const RatingRec rec = record(y);
+        const int X = xbase + (int)(rec.info & kInfoXMask);
+        const int slot = X & (a.slots - 1);
+        if (rec.info & kInfoFirst) {
+            // This wave's part of visit X starts: wait for the item, from the memory wave
+            // (first wave of the visit) or from the wave before.
+            const uint32_t pw = (rec.info >> kInfoPrevShift) & kInfoPrevMask;
+            const int32_t *word = pw ? &L.flag[pw - 1] : &L.ctl[0];
+            const uint64_t t0 = tick(a.timing);
+            if (!wait_above(word, X, L, a.abort_flag, lane, a.diag, q, w, (int)pw)) return false;
+            compiler_fence();
+            t_wait += tick(a.timing) - t0;
+            lload<VEC>(items + (size_t)slot * kp, h);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) h[v] = on ? h[v] : 0.0f;
+        }
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (D - 1)) : "memory");
+        float wv[VEC];
+        lload<VEC>(rows + u * kp + loff, wv);
+        // Lanes beyond the vector width hold h = 0 and copies of finite elements in wv, so
+        // they add nothing to the dot product; their se is 0, so their h stays 0.
+        float d = 0.0f;
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) d = fmaf(wv[v], h[v], d);
+        d = wave_sum<NR16>(d);
+        const float se0 = s * (rec.r - d);
+        const float se = on ? se0 : 0.0f;
+        float nw[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+            nw[v] = fmaf(se, h[v], c * wv[v]);
+            h[v] = fmaf(se, wv[v], c * h[v]);
+        }
+        // Hand the row on to the next rating of the window that uses it, or store it.
+        const uint64_t same = __builtin_amdgcn_ballot_w64(win == rec.row) & ~(1ull << u);
+        if (same) {
+            ++forwarded;
+            const uint64_t full = (1ull << D) - 1ull;
+            const uint64_t rot = ((same >> (u + 1)) | (same << (D - u - 1))) & full;
+            int t = u + 1 + (int)__builtin_ctzll(rot);
+            if (t >= D) t -= D;
+            if (on) lstore<VEC>(rows + t * kp + loff, nw);
+            placeholder_store();
+        } else {
+            if (on) vstore<VEC>(a.W + (int64_t)rec.row * kp + loff, nw);
+        }
+        if (rec.info & kInfoLast) {
+            if (on) lstore<VEC>(items + (size_t)slot * kp, h);
+            wait_lgkm();
+            if (lane == 0) sync_store(&L.flag[w], X + 1);
+        }
+        return true;
+    }
+
+    __device__ void run() {
+        if (total <= 0) return;
+        const uint64_t t_start = tick(a.timing);
+        load_batch(0);
+        load_batch(1);
+        wait_vm();
+        for (int u = 0; u < D; ++u) {
+            issue(u, u);
+            placeholder_store();
+        }
+        float h[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) h[v] = 0.0f;
+        const int nv = (int)(a.vbase[q + 1] - a.vbase[q]);
+        int e = 0, xbase = 0;
+        int64_t left = cnt;
+        float s = a.step_s[0];
+        float c = a.step_c[0];
+        int64_t y = 0;
+        int u = 0;
+        for (; y < total; ++y) {
+            if (!step(y, u, h, xbase, s, c)) break;
+            issue(y + D, u);
+            if (++u == D) u = 0;
+            if (--left == 0) {
+                left = cnt;
+                ++e;
+                xbase += nv;
+                if (e < a.epochs) {
+                    s = a.step_s[e];
+                    c = a.step_c[e];
+                }
             }
-            t_starve += tick(prof) - t0;
         }
-        compiler_fence();
-        const int ent = (int)(x & (kRing - 1));
-        const int nrat = L.cnt[2 * ent];
-        RatingRec rr{0u, 0.0f};
-        if (lane < nrat) rr = L.rat[ent * 64 + lane];
-        if (ex != epoch) {
-            // s_t = alpha / (1 + beta t^gamma), t = epochs done (every rating is updated
-            // once per epoch), eq. (stepsize_method).
-            epoch = ex;
-            const double t = (double)ex;
-            const double sd = a.alpha / (1.0 + a.beta * (t > 0.0 ? pow(t, a.gamma) : 0.0));
-            s_step = (float)sd;
-            s_shrink = 1.0f - s_step * a.lambda;
-        }
-        const uint64_t t0 = tick(prof);
-        sgd_chunk<VEC, NR16>(ln, rr, nrat, s_step, s_shrink);
-        wait_lgkm();
-        t_sgd += tick(prof) - t0;
-        n_rat += nrat;
-        if (lane == 0) sync_store(&L.sync[kDone], (int)(x + 1));
-        if (++lx == nck) {
-            lx = 0;
-            ++ex;
+        wait_vm();
+        if (a.wstats && lane == 0) {
+            unsigned long long *ws = (unsigned long long *)(a.wstats + (int64_t)q * kWStatCount);
+            const uint64_t tot = tick(a.timing) - t_start;
+            atomicAdd(&ws[kWStatCompTotal], (unsigned long long)tot);
+            atomicMax(&ws[kWStatCompMax], (unsigned long long)tot);
+            atomicAdd(&ws[kWStatItemWait], (unsigned long long)t_wait);
+            atomicAdd(&ws[kWStatRatings], (unsigned long long)y);
+            atomicAdd(&ws[kWStatForwarded], (unsigned long long)forwarded);
         }
     }
-    if (a.wstats && lane == 0) {
-        int64_t *w = a.wstats + (int64_t)q * kWStatCount;
-        w[kWStatTotal] = (int64_t)(tick(prof) - t_start);
-        w[kWStatChunks] = total;
-        w[kWStatSgd] = (int64_t)t_sgd;
-        w[kWStatRatings] = n_rat;
-        w[kWStatStarve] = (int64_t)t_starve;
-    }
-}
+};
 
 // ---------------------------------------------------------------------------------------
 // Memory wave.
 
-struct Meta {
-    int64_t rat, ev;
-    int nrat, nload, nrel, nflush, need;
-};
-
-// Record of the chunk at local index lc of the worker's plan (chunk x = lc + epoch * nck
-// of the call); an empty record when x is past the end of the call.
-__device__ __forceinline__ Meta load_meta(const TrainArgs &a, int64_t c0, int64_t lc, bool valid) {
-    Meta m{0, 0, 0, 0, 0, 0, 0};
-    if (!valid) return m;
-    const ChunkRec r = a.chunks[c0 + lc];
-    m.rat = r.rat;
-    m.ev = r.ev;
-    m.nrat = r.nrat;
-    m.nload = r.nload;
-    m.nrel = r.nrel;
-    m.nflush = r.nflush;
-    m.need = r.need_done;
-    return m;
-}
-
-// Event records of one chunk, one per lane (loads, then releases).
-struct Ev {
-    int id;
-    int sk;
-    int evict;
-    int vis;
-};
-__device__ __forceinline__ Ev load_ev(const EvRec *g, int count, int lane) {
-    Ev e{0, 0, -1, 0};
-    if (lane < count) {
-        const int4 v = *(const int4 *)(g + lane);
-        e.id = v.x;
-        e.sk = v.y;
-        e.evict = v.z;
-        e.vis = v.w;
-    }
-    return e;
-}
-__device__ __forceinline__ int ev_slot(int sk) { return sk & 255; }
-__device__ __forceinline__ int ev_kind(int sk) { return (sk >> 8) & 255; }
-// Counter value at which the visit may start in epoch `epoch`.
-__device__ __forceinline__ uint32_t ev_ticket(int vis, int epoch) {
-    return (uint32_t)((int64_t)epoch * (int64_t)((uint32_t)vis >> 16) + (int64_t)(vis & 0xffff));
-}
-
-typedef __attribute__((address_space(3))) void lds_void_t;
-
 __device__ __forceinline__ uint32_t lds_addr(const float *p) {
     return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float *)p;
 }
+typedef __attribute__((address_space(3))) void lds_void_t;
 
 // LDS reads of the memory wave, waited for inside the asm block.  Written as asm so that
 // the compiler does not put "s_waitcnt vmcnt(0)" in front of them (it cannot tell these
-// slots from those the wave's LDS-DMA loads write, and would make every read wait for
-// all outstanding stores).  The slots read here are never the target of a load in
-// flight: a slot is read before any load into it is issued.
+// slots from those the wave's LDS-DMA loads write).  The slots read here are never the
+// target of a load in flight: a slot is read before any load into it is issued.
 __device__ __forceinline__ void lds_read4x4_now(uint32_t p0, uint32_t p1, uint32_t p2, uint32_t p3, f32x4_t &v0,
                                                 f32x4_t &v1, f32x4_t &v2, f32x4_t &v3) {
     asm volatile(
@@ -392,42 +474,51 @@ __device__ __forceinline__ void lds_read4x4_now(uint32_t p0, uint32_t p1, uint32
         : "v"(p0), "v"(p1), "v"(p2), "v"(p3)
         : "memory");
 }
+__device__ __forceinline__ int lds_read_i32_now(const int32_t *p) {
+    int v;
+    asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)"
+                 : "=v"(v)
+                 : "v"((uint32_t)(uintptr_t)(const __attribute__((address_space(3))) int32_t *)p)
+                 : "memory");
+    return v;
+}
 
 struct MemoryWave {
     const TrainArgs &a;
     const Lds &L;
-    const int64_t c0, nck, total;
-    const int q, lane, kp;
+    const int q, lane, kp, S;
+    const int64_t vb;   // first visit record of the worker
+    const int nv;       // visits per epoch
+    const int V;        // visits of the call
     uint32_t *const abort_flag;
-    const bool prof;
-    int64_t retired = 0;  // chunks whose releases have been issued
-    int64_t retired_lc = 0;  // its local index in the plan
-    int pub_id = -1;      // items written back, counter value to publish (one per lane)
+    int Xl = 0, Xr = 0; // visits taken over / passed on
+    // visits held (loaded, not yet passed on): lane (X mod S)
+    int f_j = 0, f_lw = 0;
+    uint32_t f_tk = 0;
+    // candidates: lane l = visit Xl + l
+    int c_j = 0, c_lw = 0;
+    uint32_t c_tk = 0, c_pv = 0, c_v = 0, c_nvis = 0;
+    int c_state = 0;    // 0 none, 1 record requested, 2 record known, 3 polled
+    // items passed on this round: published once their stores are complete
+    int pub_j = 0;
     uint32_t pub_tk = 0;
-    int pub_n = 0;
-    uint64_t t_acq = 0, t_mem = 0, t_slot = 0, t_commit = 0, t_retire = 0, t_issue = 0, t_evict = 0, t_poll = 0;
-    int64_t n_loads = 0, n_late = 0;
+    int npub = 0;
+    uint64_t iters = 0, misses = 0, t_mem = 0;
+    const uint64_t row_mask;  // lanes that load a vector (16 bytes each)
 
-    __device__ MemoryWave(const TrainArgs &a_, const Lds &L_, int64_t c0_, int64_t nck_, int q_, int lane_,
-                          uint32_t *abort_)
-        : a(a_), L(L_), c0(c0_), nck(nck_), total(nck_ * a_.epochs), q(q_), lane(lane_), kp(a_.kp),
-          abort_flag(abort_), prof(a_.timing) {}
+    __device__ MemoryWave(const TrainArgs &a_, const Lds &L_, int q_, int lane_)
+        : a(a_), L(L_), q(q_), lane(lane_), kp(a_.kp), S(a_.slots), vb(a_.vbase[q_]),
+          nv((int)(a_.vbase[q_ + 1] - a_.vbase[q_])), V((int)(a_.vbase[q_ + 1] - a_.vbase[q_]) * a_.epochs),
+          abort_flag(a_.abort_flag), row_mask((a_.kp >> 2) >= 64 ? ~0ull : ((1ull << (a_.kp >> 2)) - 1ull)) {}
 
-    __device__ __forceinline__ void publish() {
-        if (lane < pub_n) __hip_atomic_store(a.tok_done + pub_id, pub_tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        pub_n = 0;
-    }
-
-    // Copy `count` vectors from LDS slots to global memory (W, or H with device-coherent
-    // stores): lane t < count of `id` / `sk` gives the vector's id (< 0: skip) and slot.
-    // A vector is kp / 4 lanes of 16 bytes, so one instruction moves rpi = 64 / (kp / 4)
-    // vectors.  All reads of a batch of 8 instructions land in distinct registers before
-    // the first store, so no read of a batch waits for a store of the same batch.
-    __device__ __forceinline__ void slots_to_global(float *dst, bool coherent, int id, int sk, int count) {
+    // Write items back from LDS slots with device-coherent stores: lane t < count gives
+    // the item (id) and its slot.  A vector is kp / 4 lanes of 16 bytes, so one
+    // instruction moves rpi = 64 / (kp / 4) vectors.
+    __device__ __forceinline__ void write_back(int id, int sl, int count) {
         constexpr int kRounds = 8;
-        const int lpr = kp >> 2, rpi = 64 / lpr, vb = lane / lpr, piece = lane - vb * lpr;
-        const bool act = vb < rpi;
-        const uint32_t base = lds_addr(L.vec) + (uint32_t)piece * 16u;
+        const int lpr = kp >> 2, rpi = 64 / lpr, vbk = lane / lpr, piece = lane - vbk * lpr;
+        const bool act = vbk < rpi;
+        const uint32_t base = lds_addr(L.items) + (uint32_t)piece * 16u;
         for (int b0 = 0; b0 < count; b0 += kRounds * rpi) {
             int gid[kRounds];
             uint32_t src[kRounds];
@@ -436,8 +527,8 @@ struct MemoryWave {
                 gid[r] = -1;
                 src[r] = base;
                 if (b0 + r * rpi < count) {
-                    const int t = b0 + r * rpi + vb;
-                    const int g = __shfl(id, t & 63), s = ev_slot(__shfl(sk, t & 63));
+                    const int t = b0 + r * rpi + vbk;
+                    const int g = __shfl(id, t & 63), s = __shfl(sl, t & 63);
                     gid[r] = (act && t < count) ? g : -1;
                     src[r] = base + (uint32_t)((gid[r] >= 0 ? s : 0) * kp) * 4u;
                 }
@@ -450,438 +541,238 @@ struct MemoryWave {
 #pragma unroll
             for (int r = 0; r < kRounds; ++r) {
                 if (b0 + r * rpi >= count || gid[r] < 0) continue;
-                float *p = dst + (int64_t)gid[r] * kp + piece * 4;
-                if (coherent)
-                    coherent_store4(p, v[r]);
-                else
-                    *(f32x4_t *)p = v[r];
+                coherent_store4(a.H + (int64_t)gid[r] * kp + piece * 4, v[r]);
             }
         }
     }
 
-    // Write back the rows left in LDS at the end of an epoch (after its last chunk y).
-    __device__ __forceinline__ void flush() {
-        const Meta m = load_meta(a, c0, nck - 1, true);
-        const int64_t f0 = m.ev + m.nload + m.nrel;
-        for (int b0 = 0; b0 < m.nflush; b0 += 64) {
-            const int cnt = m.nflush - b0 < 64 ? m.nflush - b0 : 64;
-            const Ev f = load_ev(a.events + f0 + b0, cnt, lane);
-            wait_vm();
-            const bool ok = lane >= cnt || (f.id >= 0 && f.id < a.m && ev_slot(f.sk) < a.slots);
-            if (__builtin_amdgcn_ballot_w64(!ok) != 0) continue;  // malformed: skip (validated elsewhere)
-            slots_to_global(a.W, false, f.id, f.sk, cnt);
-        }
+    // Load item `j` into LDS slot `sl` (device-coherent LDS-DMA, 16 bytes per lane).
+    __device__ __forceinline__ void load_item(int j, int sl) {
+        const float *src = a.H + (int64_t)j * kp + (lane & 63) * 4;
+        const uint32_t dst = lds_off(L.items) + (uint32_t)(sl * kp * 4);
+        dma16_coherent(src, dst, row_mask);
     }
 
-    // Pass on the items of every chunk the compute wave has finished: device-coherent
-    // write-back now, counter published once the stores have completed.
-    __device__ __forceinline__ void retire() {
-        const int64_t d = sync_load(&L.sync[kDone]);
-        compiler_fence();
-        while (retired < d) {
-            const int64_t y = retired;
-            const int ent = (int)(y & (kRing - 1));
-            const int nrel = L.cnt[2 * ent + 1];
-            if (nrel > 0) {
-                if (pub_n + nrel > 64) {
-                    wait_vm();
-                    publish();
-                }
-                const int rid = lane < nrel ? L.rel_id[ent * 64 + lane] : -1;
-                const int rsl = lane < nrel ? L.rel_slot[ent * 64 + lane] : 0;
-                slots_to_global(a.H, true, rid, rsl, nrel);
-                const int r = lane - pub_n;
-                if (r >= 0 && r < nrel) {
-                    pub_id = L.rel_id[ent * 64 + r];
-                    pub_tk = L.rel_tk[ent * 64 + r];
-                }
-                pub_n += nrel;
-            }
-            if (retired_lc == nck - 1) {
-                flush();
-                retired_lc = 0;
-            } else {
-                ++retired_lc;
-            }
-            ++retired;
-        }
+    __device__ __forceinline__ bool stopping() {
+        return sync_load(&L.ctl[1]) != 0 ||
+               __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
     }
 
-    // Retire and publish while waiting.
-    __device__ __forceinline__ void service() {
-        retire();
-        if (pub_n > 0) {
-            wait_vm();
-            publish();
-        }
-    }
-
-    __device__ __forceinline__ bool give_up(uint64_t t0) {
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return true;
-        if (wall_clock64() - t0 > kWaitLimitTicks) {
-            if (lane == 0) __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return true;
-        }
-        return false;
-    }
-
-    // End the worker early: tell the compute wave, and record `code` (if non-zero).
-    __device__ __forceinline__ void stop(uint32_t code) {
-        wait_vm();
-        if (code && lane == 0) __hip_atomic_store(abort_flag, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (lane == 0) sync_store(&L.sync[kStop], 1);
-    }
-
-    // Wait until the compute wave has finished `need` chunks.
-    __device__ __forceinline__ bool wait_done(int64_t need) {
-        if (sync_load(&L.sync[kDone]) >= need) return true;
-        const uint64_t t0 = wall_clock64();
-        while (sync_load(&L.sync[kDone]) < need) {
-            service();
-            if (give_up(t0)) return false;
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (prof) t_slot += wall_clock64() - t0;
-        return true;
-    }
-
-    // Wait until every item event of `e` flagged in `mask` may start (epoch `epoch`).
-    __device__ __forceinline__ bool acquire(const Ev &e, uint64_t mask, int epoch) {
-        const bool mine = ((mask >> lane) & 1ull) != 0;
-        const uint32_t tk = ev_ticket(e.vis, epoch);
-        bool pending = mine && __hip_atomic_load(a.tok_done + e.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tk;
-        if (__builtin_amdgcn_ballot_w64(pending) == 0) return true;
-        const uint64_t t0 = wall_clock64();
-        while (true) {
-            service();
-            __builtin_amdgcn_s_sleep(2);
-            if (pending)
-                pending = __hip_atomic_load(a.tok_done + e.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tk;
-            if (__builtin_amdgcn_ballot_w64(pending) == 0) break;
-            if (give_up(t0)) return false;
-        }
-        if (prof) t_acq += wall_clock64() - t0;
-        return true;
-    }
-
-    // Plan validation: a malformed plan (ids or slots out of range) ends the kernel
-    // instead of letting a load or a store touch memory outside its arrays.
-    __device__ __forceinline__ bool events_ok(const Meta &m, const Ev &e) {
-        bool bad = m.nrat > kMaxRatingsPerChunk || m.nload + m.nrel > kMaxEventsPerChunk || m.nrat < 0;
-        if (lane < m.nload) {
-            const int k = ev_kind(e.sk);
-            bad |= ev_slot(e.sk) >= a.slots || (k != kEvLoadRow && k != kEvLoadItem) || e.id < 0 ||
-                   e.id >= (k == kEvLoadRow ? a.m : a.n) || e.evict >= a.m;
-        } else if (lane < m.nload + m.nrel) {
-            bad |= ev_kind(e.sk) != kEvRelease || ev_slot(e.sk) >= a.slots || e.id < 0 || e.id >= a.n;
-        }
-        return __builtin_amdgcn_ballot_w64(bad) == 0;
-    }
-    __device__ __forceinline__ bool ratings_ok(const Meta &m, const RatingRec &rr) {
-        bool bad = false;
-        if (lane < m.nrat) bad = (int)(rr.slots & 255) >= a.slots || (int)((rr.slots >> 8) & 255) >= a.slots;
-        return __builtin_amdgcn_ballot_w64(bad) == 0;
-    }
-
-    __device__ __forceinline__ uint64_t kind_mask(const Ev &e, int nload, int kind) {
-        return __builtin_amdgcn_ballot_w64(lane < nload && ev_kind(e.sk) == kind);
-    }
-
-    // Write back the rows a chunk's loads evict (their slots must be free).
-    __device__ __forceinline__ void evict(const Ev &e, int nload) {
-        slots_to_global(a.W, false, e.evict, e.sk, nload);
-    }
-
-    // Load the vectors of the events flagged in `mask` into their slots: each event lane
-    // computes its source address and LDS slot address once, then one LDS-DMA
-    // instruction per vector (rows plain, items device-coherent).
-    __device__ __forceinline__ void load_vectors(const Ev &e, int nload, uint64_t mask) {
-        const bool item = ev_kind(e.sk) == kEvLoadItem;
-        const uint64_t src = (uint64_t)(uintptr_t)((item ? a.H : a.W) + (int64_t)e.id * kp);
-        const uint32_t s_lo = (uint32_t)src, s_hi = (uint32_t)(src >> 32);
-        const int dst = ev_slot(e.sk) * kp;
-        const uint64_t items = mask & kind_mask(e, nload, kEvLoadItem), rows = mask & ~items;
-        const bool on = lane < (kp >> 2);
-        for (uint64_t mk = rows; mk; mk &= mk - 1) {
-            const int t = __builtin_ctzll(mk);
-            const uint64_t p = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(s_lo, t) |
-                               ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(s_hi, t) << 32);
-            float *d = L.vec + __builtin_amdgcn_readlane(dst, t);
-            if (on)
-                __builtin_amdgcn_global_load_lds((const void *)((const float *)(uintptr_t)p + lane * 4),
-                                                 (lds_void_t *)d, 16, 0, 0);
-        }
-        for (uint64_t mk = items; mk; mk &= mk - 1) {
-            const int t = __builtin_ctzll(mk);
-            const uint64_t p = (uint64_t)(uint32_t)__builtin_amdgcn_readlane(s_lo, t) |
-                               ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(s_hi, t) << 32);
-            float *d = L.vec + __builtin_amdgcn_readlane(dst, t);
-            if (on)
-                __builtin_amdgcn_global_load_lds((const void *)((const float *)(uintptr_t)p + lane * 4),
-                                                 (lds_void_t *)d, 16, 0, 16);
-        }
-    }
-
-    __device__ __forceinline__ void run() {
-        if (total <= 0) return;
-        // Local plan index of chunk x+4 (advanced with wrap-around, no division).
-        int64_t lc4 = 0;
-        auto next_lc = [&](int64_t lc) { return lc + 1 == nck ? 0 : lc + 1; };
-        Meta m0 = load_meta(a, c0, lc4, 0 < total);
-        lc4 = next_lc(lc4);
-        Meta m1 = load_meta(a, c0, lc4, 1 < total);
-        lc4 = next_lc(lc4);
-        Meta m2 = load_meta(a, c0, lc4, 2 < total);
-        lc4 = next_lc(lc4);
-        Meta m3 = load_meta(a, c0, lc4, 3 < total);
-        lc4 = next_lc(lc4);
-        Ev e0 = load_ev(a.events + m0.ev, m0.nload + m0.nrel, lane);
-        Ev e1 = load_ev(a.events + m1.ev, m1.nload + m1.nrel, lane);
-        Ev e2 = load_ev(a.events + m2.ev, m2.nload + m2.nrel, lane);
-        RatingRec rr0{0u, 0.0f}, rr1{0u, 0.0f};
-        if (lane < m0.nrat) rr0 = a.ratings[m0.rat + lane];
-        wait_vm();
-        if (!events_ok(m0, e0) || !events_ok(m1, e1) || !events_ok(m2, e2)) {
-            stop(2u);
-            return;
-        }
-        uint32_t pr1 = 0, pr2 = 0;
-        if (lane < m1.nload && ev_kind(e1.sk) == kEvLoadItem)
-            pr1 = __hip_atomic_load(a.tok_done + e1.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t fm0 = 0, fm1 = 0;  // loads of chunk x / x+1 already issued
-        int64_t lx = 0;
-        int ex = a.epoch0;
-        for (int64_t x = 0; x < total; ++x) {
-            // Loads of this chunk issued in iteration x-1 and write-backs are complete.
-            uint64_t t0 = tick(prof);
-            wait_vm();
-            t_mem += tick(prof) - t0;
-            if (pub_n > 0) publish();
-            if (!events_ok(m2, e2)) {
-                stop(2u);
-                return;
-            }
-            const int64_t xbase = x - lx;  // first chunk of this epoch
-            // A new epoch starts once the previous one has been written back entirely.
-            if (x > 0 && lx == 0) {
-                if (!wait_done(x)) { stop(0u); return; }
-                retire();
-            }
-            if (!ratings_ok(m0, rr0)) {
-                stop(2u);
-                return;
-            }
-            const uint64_t loads = m0.nload >= 64 ? ~0ull : ((1ull << m0.nload) - 1ull);
-            const uint64_t rem = loads & ~fm0;
-            n_loads += m0.nload;
-            if (rem) {
-                // Not prefetched: the first chunk of an epoch, or items that were not free
-                // when polled.
-                n_late += __builtin_popcountll(rem);
-                if (fm0 == 0) {
-                    int64_t need = xbase + m0.need;
-                    if (x - kRing + 1 > need) need = x - kRing + 1;
-                    if (!wait_done(need)) { stop(0u); return; }
-                    retire();
-                    evict(e0, m0.nload);
-                }
-                const uint64_t items = kind_mask(e0, m0.nload, kEvLoadItem) & rem;
-                if (items && !acquire(e0, items, ex)) { stop(0u); return; }
-                load_vectors(e0, m0.nload, rem);
-                t0 = tick(prof);
-                wait_vm();
-                t_mem += tick(prof) - t0;
-            }
-            uint64_t tc = tick(prof);
-            // Ring entry for the compute wave: ratings, and the items released after it.
-            const int ent = (int)(x & (kRing - 1));
-            if (lane < m0.nrat) L.rat[ent * 64 + lane] = rr0;
+    __device__ void run() {
+        if (V <= 0) return;
+        const uint64_t t_start = tick(a.timing);
+        const int Smask = S - 1;
+        uint64_t t_prog = wall_clock64();
+        while (Xr < V) {
+            ++iters;
+            bool progress = false;
+            // 1. Pass on the visits every wave of which is done (in order).
             {
-                const int src = (m0.nload + lane) & 63;
-                const int rid = __shfl(e0.id, src), rsk = __shfl(e0.sk, src), rvis = __shfl(e0.vis, src);
-                if (lane < m0.nrel) {
-                    L.rel_id[ent * 64 + lane] = rid;
-                    L.rel_slot[ent * 64 + lane] = ev_slot(rsk);
-                    L.rel_tk[ent * 64 + lane] = ev_ticket(rvis, ex) + 1u;
+                const int inflight = Xl - Xr;
+                const int X = Xr + lane;
+                const int sl = X & Smask;
+                const int j = __shfl(f_j, sl), lw = __shfl(f_lw, sl);
+                const uint32_t tk = (uint32_t)__shfl((int)f_tk, sl);
+                bool done = false;
+                if (lane < inflight) done = lds_read_i32_now(&L.flag[lw]) > X;
+                const uint64_t dm = __builtin_amdgcn_ballot_w64(done);
+                const int nr = leading_run(dm);
+                if (nr > 0) {
+                    write_back(j, sl, nr);
+                    pub_j = j;
+                    pub_tk = tk + 1u;
+                    npub = nr;
+                    Xr += nr;
+                    progress = true;
                 }
             }
-            if (lane == 0) {
-                L.cnt[2 * ent] = m0.nrat;
-                L.cnt[2 * ent + 1] = m0.nrel;
-            }
-            wait_lgkm();
-            if (lane == 0) sync_store(&L.sync[kStaged], (int)(x + 1));
-            t_commit += tick(prof) - tc;
-            if (a.trace) {
-                // One record per item taken over, in event order (the order of the visits).
-                const uint64_t im = kind_mask(e0, m0.nload, kEvLoadItem);
-                int64_t base = 0;
-                if (lane == 0 && im) base = (int64_t)atomicAdd((unsigned long long *)a.trace_len,
-                                                               (unsigned long long)__builtin_popcountll(im));
-                base = __shfl(base, 0);
-                const int64_t slot = base + __builtin_popcountll(im & ((1ull << lane) - 1ull));
-                if (((im >> lane) & 1ull) && slot < a.trace_cap) {
-                    a.trace[4 * slot + 0] = q;
-                    a.trace[4 * slot + 1] = e0.id;
-                    a.trace[4 * slot + 2] = ex;
-                    a.trace[4 * slot + 3] = (int32_t)ev_ticket(e0.vis, ex);
+            // 2. Take over the candidates found free, in order, as far as slots allow.
+            int nl = 0;
+            {
+                const bool ready = c_state == 3 && c_pv == c_tk;
+                nl = leading_run(__builtin_amdgcn_ballot_w64(ready));
+                const int room = Xr + S - Xl;
+                if (nl > room) nl = room;
+                if (nl > V - Xl) nl = V - Xl;
+                if (nl < room && nl < V - Xl) {  // the next visit's item is still held elsewhere
+                    const int cs = __shfl(c_state, nl & 63);
+                    if (cs == 3) ++misses;
+                }
+                for (int t = 0; t < nl; ++t) {
+                    const int j = __shfl(c_j, t);
+                    load_item(j, (Xl + t) & Smask);
+                }
+                if (nl > 0) {
+                    // holder lanes: slot s takes candidate t = (s - Xl) mod S when t < nl
+                    const int t = (lane - Xl) & Smask;
+                    const int j = __shfl(c_j, t), lw = __shfl(c_lw, t);
+                    const uint32_t tk = (uint32_t)__shfl((int)c_tk, t);
+                    if (lane < S && t < nl) {
+                        f_j = j;
+                        f_lw = lw;
+                        f_tk = tk;
+                    }
+                    if (a.trace) {
+                        int64_t base = 0;
+                        if (lane == 0) base = (int64_t)atomicAdd((unsigned long long *)a.trace_len,
+                                                                 (unsigned long long)nl);
+                        base = __shfl(base, 0);
+                        if (lane < nl && base + lane < a.trace_cap) {
+                            const int X = Xl + lane;
+                            int32_t *tr = a.trace + 4 * (base + lane);
+                            tr[0] = q;
+                            tr[1] = c_j;
+                            tr[2] = a.epoch0 + X / nv;
+                            tr[3] = (int32_t)c_tk;
+                        }
+                    }
+                    Xl += nl;
+                    // shift the candidate window down
+                    const int src = lane + nl;
+                    const int sj = __shfl(c_j, src & 63), slw = __shfl(c_lw, src & 63),
+                              sst = __shfl(c_state, src & 63);
+                    const uint32_t stk = (uint32_t)__shfl((int)c_tk, src & 63),
+                                   spv = (uint32_t)__shfl((int)c_pv, src & 63);
+                    const bool in = src < 64;
+                    c_j = sj;
+                    c_lw = slw;
+                    c_tk = stk;
+                    c_pv = spv;
+                    c_state = in ? sst : 0;
+                    progress = true;
                 }
             }
-            tc = tick(prof);
-            retire();
-            t_retire += tick(prof) - tc;
-
-            // Chunk x+1 (not across an epoch boundary: the epoch's rows are written back
-            // first): once its slots are free, write back the rows it evicts and load its
-            // rows and the items seen free.  Then poll chunk x+2, read events x+3 and the
-            // record of x+4.
-            const int64_t lx1 = lx + 1 == nck ? 0 : lx + 1;
-            const int ex1 = lx + 1 == nck ? ex + 1 : ex;
-            fm1 = 0;
-            if (x + 1 < total) {
-                if (lane < m1.nrat) rr1 = a.ratings[m1.rat + lane];
-                if (lx1 != 0) {
-                    int64_t need = xbase + m1.need;
-                    if (x + 1 - kRing + 1 > need) need = x + 1 - kRing + 1;
-                    if (!wait_done(need)) { stop(0u); return; }
-                    tc = tick(prof);
-                    retire();
-                    t_retire += tick(prof) - tc;
-                    tc = tick(prof);
-                    evict(e1, m1.nload);
-                    t_evict += tick(prof) - tc;
-                    tc = tick(prof);
-                    const uint64_t rows = kind_mask(e1, m1.nload, kEvLoadRow);
-                    const bool ready =
-                        lane < m1.nload && ev_kind(e1.sk) == kEvLoadItem && pr1 == ev_ticket(e1.vis, ex1);
-                    fm1 = rows | __builtin_amdgcn_ballot_w64(ready);
-                    load_vectors(e1, m1.nload, fm1);
-                    t_issue += tick(prof) - tc;
+            // 3. Poll the candidates whose record is known; request the missing records.
+            const int X = Xl + lane;
+            bool req = false;
+            uint32_t e_rel = 0;
+            if (X < V) {
+                if (c_state >= 2) {
+                    c_pv = __hip_atomic_load(a.tok_done + c_j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    c_state = 3;
+                } else {
+                    e_rel = (uint32_t)X / (uint32_t)nv;
+                    const int x = X - (int)e_rel * nv;
+                    const int4 r = *(const int4 *)(a.visits + vb + x);
+                    c_j = r.x;
+                    c_v = (uint32_t)r.y;
+                    c_nvis = (uint32_t)r.z;
+                    c_lw = r.w;
+                    req = true;
                 }
             }
-            tc = tick(prof);
-            pr2 = 0;
-            if (x + 2 < total && lane < m2.nload && ev_kind(e2.sk) == kEvLoadItem)
-                pr2 = __hip_atomic_load(a.tok_done + e2.id, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const Ev e3 = load_ev(a.events + m3.ev, m3.nload + m3.nrel, lane);
-            const Meta m4 = load_meta(a, c0, lc4, x + 4 < total);
-            lc4 = next_lc(lc4);
-            t_poll += tick(prof) - tc;
-
-            m0 = m1;
-            m1 = m2;
-            m2 = m3;
-            m3 = m4;
-            e0 = e1;
-            e1 = e2;
-            e2 = e3;
-            pr1 = pr2;
-            rr0 = rr1;
-            fm0 = fm1;
-            lx = lx1;
-            ex = ex1;
+            // 4. Wait for every load and store of the round, then publish.
+            {
+                const uint64_t t0 = tick(a.timing);
+                wait_vm();
+                t_mem += tick(a.timing) - t0;
+            }
+            if (req) {
+                bool bad = c_j < 0 || c_j >= a.n || c_lw < 0 || c_lw >= a.nw;
+                if (__builtin_amdgcn_ballot_w64(bad)) {
+                    if (lane == 0) raise_abort(abort_flag, L, 2u);
+                    return;
+                }
+                c_tk = ((uint32_t)a.epoch0 + e_rel) * c_nvis + c_v;
+                c_state = 2;
+            }
+            if (npub > 0) {
+                if (lane < npub)
+                    __hip_atomic_store(a.tok_done + pub_j, pub_tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                npub = 0;
+            }
+            if (nl > 0 && lane == 0) sync_store(&L.ctl[0], Xl);
+            if (progress) {
+                t_prog = wall_clock64();
+            } else {
+                if (stopping()) break;
+                if (wall_clock64() - t_prog > kWaitLimitTicks) {
+                    const int st0 = __shfl(c_state, 0), j0 = __shfl(c_j, 0);
+                    const uint32_t tk0 = (uint32_t)__shfl((int)c_tk, 0), pv0 = (uint32_t)__shfl((int)c_pv, 0);
+                    if (lane == 0) {
+                        note_timeout(a.diag, q, -1, Xr, Xl, V, st0 * 1000000 + j0);
+                        a.diag[6] = (int32_t)tk0;
+                        a.diag[7] = (int32_t)pv0;
+                        raise_abort(abort_flag, L, 1u);
+                    }
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
         }
-        // Everything computed: pass on the last items, write back the last rows.
-        if (!wait_done(total)) { stop(0u); return; }
-        retire();
         wait_vm();
-        publish();
+        if (a.wstats && lane == 0) {
+            unsigned long long *ws = (unsigned long long *)(a.wstats + (int64_t)q * kWStatCount);
+            atomicAdd(&ws[kWStatMemTotal], (unsigned long long)(tick(a.timing) - t_start));
+            atomicAdd(&ws[kWStatMemIters], (unsigned long long)iters);
+            atomicAdd(&ws[kWStatVisits], (unsigned long long)Xl);
+            atomicAdd(&ws[kWStatPollMiss], (unsigned long long)misses);
+            atomicAdd(&ws[kWStatMemWait], (unsigned long long)t_mem);
+        }
     }
 };
 
-// A workgroup holds `group` workers: waves [0, group) are their compute waves and waves
-// [group, 2 group) their memory waves, each worker with its own part of the LDS.  With
-// waves dealt to the SIMDs in turn, a SIMD then runs one compute and one memory wave
-// instead of two compute waves.
 template <int VEC, int NR16>
-__global__ __launch_bounds__(512) void k_worker(TrainArgs a, uint32_t *abort_flag) {
+__global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
     extern __shared__ float4 lds4[];
-    const int G = a.group;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int sub = wave % G;
-    const bool compute = wave < G;
-    const int q = blockIdx.x * G + sub;
-    const Lds L = lds_layout((char *)lds4 + (size_t)sub * worker_lds_bytes(a.kp, a.slots), a.slots, a.kp);
-    if (compute) {
-        if (lane < 4) L.sync[lane] = 0;
-        for (int i = lane; i < 64 * 4; i += 64) L.zero[i] = 0.0f;
-    }
+    constexpr int D = window<VEC>();
+    // The wave index is the same in every lane: say so, so that everything derived from it
+    // lives in scalar registers.
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x;
+    const Lds L = lds_layout(lds4, a.kp, a.nw, a.slots);
+    if (threadIdx.x < kMaxWaves + 1) L.flag[threadIdx.x] = 0;
+    if (threadIdx.x < 2) L.ctl[threadIdx.x] = 0;
     __syncthreads();
-    if (q >= a.p) return;
-    const int64_t c0 = a.wck[q], nck = a.wck[q + 1] - c0;
-    if (nck <= 0 || a.epochs <= 0) return;
-    if (compute) {
-        compute_wave<VEC, NR16>(a, L, nck, q, lane);
-    } else {
-        const uint64_t t_start = tick(a.timing);
-        MemoryWave mw(a, L, c0, nck, q, lane, abort_flag);
+    if (q >= a.p || a.epochs <= 0) return;
+    if (wave < a.nw) {
+        const int64_t i0 = a.rbase[(int64_t)q * a.nw + wave], i1 = a.rbase[(int64_t)q * a.nw + wave + 1];
+        ComputeWave<VEC, NR16, D> cw(a, L, q, wave, lane, i0, i1 - i0);
+        cw.run();
+    } else if (wave == a.nw) {
+        MemoryWave mw(a, L, q, lane);
         mw.run();
-        if (a.wstats && lane == 0) {
-            int64_t *w = a.wstats + (int64_t)q * kWStatCount;
-            w[kWStatAcquire] = (int64_t)mw.t_acq;
-            w[kWStatMemWait] = (int64_t)mw.t_mem;
-            w[kWStatSlotWait] = (int64_t)mw.t_slot;
-            w[kWStatMemTotal] = (int64_t)(tick(a.timing) - t_start);
-            w[kWStatCommit] = (int64_t)mw.t_commit;
-            w[kWStatRetire] = (int64_t)mw.t_retire;
-            w[kWStatIssue] = (int64_t)mw.t_issue;
-            w[kWStatLoads] = mw.n_loads;
-            w[kWStatLate] = mw.n_late;
-            w[14] = (int64_t)mw.t_evict;
-            w[15] = (int64_t)mw.t_poll;
-        }
     }
 }
 
 template <int VEC, int NR16>
-hipError_t launch_t(const TrainArgs &a, int32_t blocks, size_t lds, uint32_t *abort_flag, hipStream_t st) {
-    hipLaunchKernelGGL((k_worker<VEC, NR16>), dim3(blocks), dim3(128 * a.group), lds, st, a, abort_flag);
+hipError_t launch_t(const TrainArgs &a, hipStream_t st) {
+    const size_t lds = lds_bytes(a.kp, a.nw, a.slots);
+    hipLaunchKernelGGL((k_worker<VEC, NR16>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
     return hipGetLastError();
 }
 
-template <int VEC, int NR16>
-const void *kernel_ptr() { return (const void *)&k_worker<VEC, NR16>; }
-
 const void *pick_kernel(int kp) {
-    if (kp <= 16) return kernel_ptr<1, 1>();
-    if (kp <= 32) return kernel_ptr<1, 2>();
-    if (kp <= 64) return kernel_ptr<1, 4>();
-    if (kp <= 128) return kernel_ptr<2, 4>();
-    return kernel_ptr<4, 4>();
+    if (kp <= 16) return (const void *)k_worker<1, 1>;
+    if (kp <= 32) return (const void *)k_worker<1, 2>;
+    if (kp <= 64) return (const void *)k_worker<1, 4>;
+    if (kp <= 128) return (const void *)k_worker<2, 4>;
+    return (const void *)k_worker<4, 4>;
 }
 
 }  // namespace
 
-size_t train_lds_bytes(int32_t kp, int32_t slots) { return worker_lds_bytes(kp, slots); }
+size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots) { return lds_bytes(kp, nw, slots); }
 
-int32_t train_group(int32_t kp, int32_t slots, size_t max_lds_per_block) {
-    const size_t per = worker_lds_bytes(kp, slots);
-    for (int32_t g = 4; g > 1; g >>= 1)
-        if ((size_t)g * per <= max_lds_per_block) return g;
-    return 1;
-}
-
-hipError_t train_max_workers(int32_t kp, int32_t slots, int32_t group, int32_t *max_workers) {
+hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t *max_workers) {
     int dev = 0, cus = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)group * worker_lds_bytes(kp, slots);
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(kp), 128 * group, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(kp), 64 * (nw + 1), lds_bytes(kp, nw, slots));
     if (e != hipSuccess) return e;
-    *max_workers = nb * cus * group;
+    *max_workers = nb * cus;
     return hipSuccess;
 }
 
-hipError_t launch_train(const TrainArgs &a, int32_t p, uint32_t *abort_flag, hipStream_t st) {
-    const size_t lds = (size_t)a.group * worker_lds_bytes(a.kp, a.slots);
-    const int32_t blocks = (p + a.group - 1) / a.group;
-    if (a.kp <= 16) return launch_t<1, 1>(a, blocks, lds, abort_flag, st);
-    if (a.kp <= 32) return launch_t<1, 2>(a, blocks, lds, abort_flag, st);
-    if (a.kp <= 64) return launch_t<1, 4>(a, blocks, lds, abort_flag, st);
-    if (a.kp <= 128) return launch_t<2, 4>(a, blocks, lds, abort_flag, st);
-    return launch_t<4, 4>(a, blocks, lds, abort_flag, st);
+hipError_t launch_train(const TrainArgs &a, hipStream_t st) {
+    if (a.kp <= 16) return launch_t<1, 1>(a, st);
+    if (a.kp <= 32) return launch_t<1, 2>(a, st);
+    if (a.kp <= 64) return launch_t<1, 4>(a, st);
+    if (a.kp <= 128) return launch_t<2, 4>(a, st);
+    return launch_t<4, 4>(a, st);
 }
 
 }  // namespace nomad

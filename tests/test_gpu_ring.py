@@ -52,25 +52,25 @@ def oracle_run(prob, W0, H0, hp, P, seed, epochs):
 
 
 CASES = [
-    # m, n, nnz, k, P, degrees, LDS slots, loads per chunk (0 = library default)
-    (300, 200, 6_000, 3, 4, "uniform", 4, 2),         # tiny slot budget: constant eviction
+    # m, n, nnz, k, P, degrees, compute waves per worker, item slots (0 = library default)
+    (300, 200, 6_000, 3, 4, "uniform", 3, 2),         # two item slots: constant slot reuse
     (2_000, 1_000, 90_000, 16, 64, "uniform", 0, 0),  # the tiny workload's shape
     (500, 80, 10_000, 100, 16, "uniform", 0, 0),      # k = 100 (two floats per lane)
     (400, 300, 20_000, 130, 32, "uniform", 0, 0),     # four floats per lane
-    (200, 150, 9_000, 256, 8, "uniform", 0, 0),       # largest k
-    (50, 3_000, 8_000, 32, 7, "uniform", 6, 3),       # wide matrix, odd worker count
+    (200, 150, 9_000, 256, 8, "uniform", 4, 0),       # largest k
+    (50, 3_000, 8_000, 32, 7, "uniform", 15, 1),      # wide matrix, odd worker count, one slot
     (3_000, 500, 60_000, 64, 24, "zipf", 8, 4),       # skewed degrees
     (700, 90, 5_000, 16, 1, "uniform", 0, 0),         # a single worker
-    (257, 129, 3_001, 5, 3, "zipf", 2, 2),            # ragged sizes, odd k, two slots
-    (1_200, 900, 50_000, 100, 40, "zipf", 96, 32),    # roomy slots: rows cached across items
+    (257, 129, 3_001, 5, 3, "zipf", 1, 2),            # ragged sizes, odd k, one compute wave
+    (1_200, 900, 50_000, 100, 40, "zipf", 6, 16),     # rows repeated inside the prefetch window
 ]
 
 
-@pytest.mark.parametrize("m,n,nnz,k,P,deg,slots,loads", CASES)
-def test_ring_one_epoch_matches_oracle(m, n, nnz, k, P, deg, slots, loads):
+@pytest.mark.parametrize("m,n,nnz,k,P,deg,nw,slots", CASES)
+def test_ring_one_epoch_matches_oracle(m, n, nnz, k, P, deg, nw, slots):
     prob, W0, H0, hp = make(m, n, nnz, k=k, seed=m + n + k, degrees=deg)
     seed = 1234 + P
-    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [1], lds_slots=slots, loads_per_chunk=loads)
+    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [1], waves_per_worker=nw, item_slots=slots)
     Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 1)
     assert rel(W, Wo) < TOL_1EPOCH and rel(H, Ho) < TOL_1EPOCH, (rel(W, Wo), rel(H, Ho))
     # evaluation: same factors, FP64 on both sides
@@ -86,14 +86,43 @@ def test_ring_one_epoch_matches_oracle(m, n, nnz, k, P, deg, slots, loads):
 def test_ring_multi_epoch_and_split_calls():
     prob, W0, H0, hp = make(1_500, 700, 40_000, k=24, seed=5, beta=0.05, gamma=1.5)
     P, seed = 12, 99
-    _, W1, H1 = gpu_run(prob, W0, H0, hp, P, seed, [3], lds_slots=6, loads_per_chunk=3)
-    m2, W2, H2 = gpu_run(prob, W0, H0, hp, P, seed, [1, 2], lds_slots=6, loads_per_chunk=3)
+    _, W1, H1 = gpu_run(prob, W0, H0, hp, P, seed, [3], waves_per_worker=5, item_slots=8)
+    m2, W2, H2 = gpu_run(prob, W0, H0, hp, P, seed, [1, 2], waves_per_worker=5, item_slots=8)
     # the ring schedule is one fixed serial order: identical on every run and call split
     assert np.array_equal(W1, W2) and np.array_equal(H1, H2)
     Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 3)
     assert rel(W1, Wo) < 3 * TOL_1EPOCH and rel(H1, Ho) < 3 * TOL_1EPOCH
     st = m2.train(0)
     assert st.epochs_done == 3 and st.updates == 0
+
+
+def test_ring_independent_of_waves_and_slots():
+    """Every row and item sees its updates in the same order whatever the number of
+    compute waves per worker and item slots: the factors are bitwise identical."""
+    prob, W0, H0, hp = make(2_500, 600, 70_000, k=100, seed=13, degrees="zipf")
+    P, seed = 16, 5
+    ref = None
+    for nw, slots in [(1, 1), (4, 8), (8, 64), (15, 2)]:
+        m, W, H = gpu_run(prob, W0, H0, hp, P, seed, [2], waves_per_worker=nw, item_slots=slots)
+        m.close()
+        if ref is None:
+            ref = (W, H)
+        else:
+            assert np.array_equal(W, ref[0]) and np.array_equal(H, ref[1]), (nw, slots)
+    Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 2)
+    assert rel(ref[0], Wo) < 2 * TOL_1EPOCH and rel(ref[1], Ho) < 2 * TOL_1EPOCH
+
+
+def test_ring_many_epochs_in_one_call():
+    """A call longer than one launch (64 epochs) continues the step-size counter and the
+    item counters across launches."""
+    prob, W0, H0, hp = make(300, 120, 4_000, k=8, seed=2, beta=0.3, gamma=1.0)
+    P, seed = 4, 3
+    _, Wa, Ha = gpu_run(prob, W0, H0, hp, P, seed, [70])
+    _, Wb, Hb = gpu_run(prob, W0, H0, hp, P, seed, [30, 40])
+    assert np.array_equal(Wa, Wb) and np.array_equal(Ha, Hb)
+    Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 70)
+    assert rel(Wa, Wo) < 1e-4 and rel(Ha, Ho) < 1e-4
 
 
 def test_ring_deterministic_across_contexts():
@@ -157,7 +186,7 @@ def test_trace_records_every_item_visit_and_replays():
     per-item visit numbers; replaying it in the oracle reproduces the GPU factors."""
     prob, W0, H0, hp = make(600, 300, 12_000, k=16, seed=21)
     P, seed, E = 6, 17, 2
-    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [E], record_trace=True, lds_slots=5, loads_per_chunk=3)
+    model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [E], record_trace=True, waves_per_worker=3, item_slots=4)
     tr = model.trace()
     row, col = prob.row.numpy(), prob.col.numpy()
     rs = oracle.partition(prob.m, row, P)
