@@ -37,7 +37,7 @@ def bytes_per_update(k: int, s_w: int, s_h: int, n: int, nnz_train: int, p_ref: 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1312_0193_amd", "csrc", "train.hip")
 KERNEL_NAME = "k_worker"
-COUNTERS = os.path.join(ROOT, "profiles", "k_train_medium_counters.txt")
+COUNTERS = os.path.join(ROOT, "profiles", "k_worker_medium_counters.txt")
 COPY_BYTES = 2 << 30  # calibration copy: 2 GiB read + 2 GiB written per dispatch
 
 
@@ -180,7 +180,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "medium: 480189x17770, 100M Zipf(1.1) cells, 1.4M held out, int 1-5 ratings, "
                                "k=100, lambda=0.05, ring schedule, FP32",
-                   "global_batch": nnz, "workers": P, "test_rmse": rmse,
+                   "global_batch": nnz, "workers": P, "waves_per_worker": model.cfg.waves_per_worker,
+                   "item_slots": model.cfg.item_slots, "test_rmse": rmse,
                    "epochs_trained": args.warmup + args.steps, "kernel_source": kernel_source_hash()},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,

@@ -243,6 +243,23 @@ __device__ __forceinline__ uint32_t lds_off(const void *p) {
         : "memory")
 
 __device__ __forceinline__ void dma16(const void *src, uint32_t lds, uint64_t mask) { NOMAD_DMA16(""); }
+// Scalar base address plus a 32-bit lane offset.
+__device__ __forceinline__ void dma16s(const void *base, uint32_t voff, uint32_t lds, uint64_t mask) {
+    uint64_t saved;
+    uint32_t m0s;
+    asm volatile(
+        "s_mov_b32 %1, m0\n\t"
+        "s_mov_b64 %0, exec\n\t"
+        "s_and_b64 exec, exec, %5\n\t"
+        "s_mov_b32 m0, %4\n\t"
+        "s_nop 0\n\t"
+        "global_load_lds_dwordx4 %2, %3\n\t"
+        "s_mov_b64 exec, %0\n\t"
+        "s_mov_b32 m0, %1"
+        : "=&s"(saved), "=&s"(m0s)
+        : "v"(voff), "s"(base), "s"(lds), "s"(mask)
+        : "memory");
+}
 // Device-coherent form (sc1), for items handed over by other workers.
 __device__ __forceinline__ void dma16_coherent(const void *src, uint32_t lds, uint64_t mask) { NOMAD_DMA16(" sc1"); }
 
@@ -316,8 +333,11 @@ struct ComputeWave {
         while (bstart >= cnt) bstart -= cnt;
     }
 
+    __device__ __forceinline__ const lds_u32 *rec_ptr(int64_t y) const {
+        return recs + ((uint32_t)(y >> 6) % 3u * 64u + (uint32_t)(y & 63)) * 3u;
+    }
     __device__ __forceinline__ RatingRec record(int64_t y) {
-        const lds_u32 *p = recs + ((uint32_t)(y >> 6) % 3u * 64u + (uint32_t)(y & 63)) * 3u;
+        const lds_u32 *p = rec_ptr(y);
         RatingRec r;
         r.row = __builtin_amdgcn_readfirstlane((int)p[0]);
         r.r = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane((int)p[1]));
@@ -329,78 +349,27 @@ struct ComputeWave {
         if (lane == 0) a.dummy[(int64_t)q * kMaxWaves + w] = 0.0f;
     }
 
-    // Start loading the row of rating y into slot u (or into the spare slot if a rating
-    // still in the window updates the same row: that one hands its result on).
-    __device__ __forceinline__ void issue(int64_t y, int u) {
+    // Start loading the row of rating y (row id `row`) into slot u, or into the spare
+    // slot if a rating still in the window updates the same row (that one hands its
+    // result on).  Past the end of the launch a placeholder load keeps the count.
+    __device__ __forceinline__ void issue(int64_t y, int u, int row) {
+        const uint32_t voff = (uint32_t)(lane & 63) * 16u;
         if (y < total) {
             if ((y & 63) == 0 && y > 0) load_batch((y >> 6) + 1);
-            const int row = record(y).row;
             const uint64_t same = __builtin_amdgcn_ballot_w64(win == row) & ~(1ull << u);
             win = lane == u ? row : win;
-            const float *src = a.W + (int64_t)row * kp + (lane & 63) * 4;
             const uint32_t dst = rows_lds + (uint32_t)((same ? D : u) * kp * 4);
-            dma16(src, dst, row_mask);
+            dma16s(a.W + (int64_t)row * kp, voff, dst, row_mask);
         } else {
             win = lane == u ? -1 : win;
-            dma16(a.W + (lane & 63) * 4, rows_lds + (uint32_t)(D * kp * 4), row_mask);
+            dma16s(a.W, voff, rows_lds + (uint32_t)(D * kp * 4), row_mask);
         }
     }
 
-    // Update rating y in window slot u (section 2.3: one residual, both vectors from
-    // their values before the update).
-    __device__ __forceinline__ bool step(int64_t y, int u, float (&h)[VEC], int xbase, float s, float c) {
-        const RatingRec rec = record(y);
-        const int X = xbase + (int)(rec.info & kInfoXMask);
-        const int slot = X & (a.slots - 1);
-        if (rec.info & kInfoFirst) {
-            // This wave's part of visit X starts: wait for the item, from the memory wave
-            // (first wave of the visit) or from the wave before.
-            const uint32_t pw = (rec.info >> kInfoPrevShift) & kInfoPrevMask;
-            const int32_t *word = pw ? &L.flag[pw - 1] : &L.ctl[0];
-            const uint64_t t0 = tick(a.timing);
-            if (!wait_above(word, X, L, a.abort_flag, lane, a.diag, q, w, (int)pw)) return false;
-            compiler_fence();
-            t_wait += tick(a.timing) - t0;
-            lload<VEC>(items + (size_t)slot * kp, h);
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) h[v] = on ? h[v] : 0.0f;
-        }
+    // Wait until at most 2(D-1) memory operations are outstanding: the row load of the
+    // rating that follows the one just issued (issued D - 1 steps ago) is then complete.
+    __device__ __forceinline__ void wait_next_row() {
         asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (D - 1)) : "memory");
-        float wv[VEC];
-        lload<VEC>(rows + u * kp + loff, wv);
-        // Lanes beyond the vector width hold h = 0 and copies of finite elements in wv, so
-        // they add nothing to the dot product; their se is 0, so their h stays 0.
-        float d = 0.0f;
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) d = fmaf(wv[v], h[v], d);
-        d = wave_sum<NR16>(d);
-        const float se0 = s * (rec.r - d);
-        const float se = on ? se0 : 0.0f;
-        float nw[VEC];
-#pragma unroll
-        for (int v = 0; v < VEC; ++v) {
-            nw[v] = fmaf(se, h[v], c * wv[v]);
-            h[v] = fmaf(se, wv[v], c * h[v]);
-        }
-        // Hand the row on to the next rating of the window that uses it, or store it.
-        const uint64_t same = __builtin_amdgcn_ballot_w64(win == rec.row) & ~(1ull << u);
-        if (same) {
-            ++forwarded;
-            const uint64_t full = (1ull << D) - 1ull;
-            const uint64_t rot = ((same >> (u + 1)) | (same << (D - u - 1))) & full;
-            int t = u + 1 + (int)__builtin_ctzll(rot);
-            if (t >= D) t -= D;
-            if (on) lstore<VEC>(rows + t * kp + loff, nw);
-            placeholder_store();
-        } else {
-            if (on) vstore<VEC>(a.W + (int64_t)rec.row * kp + loff, nw);
-        }
-        if (rec.info & kInfoLast) {
-            if (on) lstore<VEC>(items + (size_t)slot * kp, h);
-            wait_lgkm();
-            if (lane == 0) sync_store(&L.flag[w], X + 1);
-        }
-        return true;
     }
 
     __device__ void run() {
@@ -410,9 +379,16 @@ struct ComputeWave {
         load_batch(1);
         wait_vm();
         for (int u = 0; u < D; ++u) {
-            issue(u, u);
+            issue(u, u, record(u).row);
             placeholder_store();
         }
+        // Carried from step to step: the records of ratings y and y + 1, the row of the
+        // rating issued next (y + D), and the row vector of rating y.
+        RatingRec rc = record(0), rn = record(1);
+        int irow = record(D).row;
+        float wv[VEC];
+        wait_next_row();
+        lload<VEC>(rows + loff, wv);
         float h[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) h[v] = 0.0f;
@@ -421,12 +397,70 @@ struct ComputeWave {
         int64_t left = cnt;
         float s = a.step_s[0];
         float c = a.step_c[0];
+        const uint64_t full = (1ull << D) - 1ull;
         int64_t y = 0;
         int u = 0;
         for (; y < total; ++y) {
-            if (!step(y, u, h, xbase, s, c)) break;
-            issue(y + D, u);
+            // Records for the next step, read now and used at the end of the step.
+            const lds_u32 *pa = rec_ptr(y + 2);
+            const int ra0 = (int)pa[0], ra1 = (int)pa[1], ra2 = (int)pa[2];
+            const int rb0 = (int)rec_ptr(y + D + 1)[0];
+            const int X = xbase + (int)(rc.info & kInfoXMask);
+            const int slot = X & (a.slots - 1);
+            if (rc.info & kInfoFirst) {
+                // This wave's part of visit X starts: wait for the item, from the memory
+                // wave (first wave of the visit) or from the wave before.
+                const uint32_t pw = (rc.info >> kInfoPrevShift) & kInfoPrevMask;
+                const int32_t *word = pw ? &L.flag[pw - 1] : &L.ctl[0];
+                const uint64_t t0 = tick(a.timing);
+                if (!wait_above(word, X, L, a.abort_flag, lane, a.diag, q, w, (int)pw)) break;
+                compiler_fence();
+                t_wait += tick(a.timing) - t0;
+                lload<VEC>(items + (size_t)slot * kp, h);
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) h[v] = on ? h[v] : 0.0f;
+            }
+            // Section 2.3: one residual, both vectors from their values before the update.
+            // Lanes beyond the vector width hold h = 0 and copies of finite elements in wv,
+            // so they add nothing to the dot product; their se is 0, so their h stays 0.
+            float d = 0.0f;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) d = fmaf(wv[v], h[v], d);
+            d = wave_sum<NR16>(d);
+            const float se0 = s * (rc.r - d);
+            const float se = on ? se0 : 0.0f;
+            float nw[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                nw[v] = fmaf(se, h[v], c * wv[v]);
+                h[v] = fmaf(se, wv[v], c * h[v]);
+            }
+            // Hand the row on to the next rating of the window that uses it, or store it.
+            const uint64_t same = __builtin_amdgcn_ballot_w64(win == rc.row) & ~(1ull << u);
+            if (same) {
+                ++forwarded;
+                const uint64_t rot = ((same >> (u + 1)) | (same << (D - u - 1))) & full;
+                int t = u + 1 + (int)__builtin_ctzll(rot);
+                if (t >= D) t -= D;
+                if (on) lstore<VEC>(rows + t * kp + loff, nw);
+                placeholder_store();
+            } else {
+                if (on) vstore<VEC>(a.W + (int64_t)rc.row * kp + loff, nw);
+            }
+            if (rc.info & kInfoLast) {
+                if (on) lstore<VEC>(items + (size_t)slot * kp, h);
+                wait_lgkm();
+                if (lane == 0) sync_store(&L.flag[w], X + 1);
+            }
+            issue(y + D, u, irow);
             if (++u == D) u = 0;
+            wait_next_row();
+            lload<VEC>(rows + u * kp + loff, wv);
+            rc = rn;
+            rn.row = __builtin_amdgcn_readfirstlane(ra0);
+            rn.r = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(ra1));
+            rn.info = (uint32_t)__builtin_amdgcn_readfirstlane(ra2);
+            irow = __builtin_amdgcn_readfirstlane(rb0);
             if (--left == 0) {
                 left = cnt;
                 ++e;
