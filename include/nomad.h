@@ -74,6 +74,8 @@ typedef struct {
     int32_t waves_per_worker; /* compute wavefronts of a worker, 1..15; 0 = 8 */
     int32_t item_slots;  /* items a worker holds in LDS at once: a power of two, 1..64;
                             0 = as many as LDS allows, up to 64 */
+    int32_t window;      /* rows a compute wave keeps in flight: 8, 16 or 32 (other values in
+                            1..32 are rounded up); 0 = as many as LDS allows, up to 32 */
     int32_t record_trace;    /* 1 = record every (worker, item) visit for replay */
     int32_t collect_stats;   /* 1 = time the phases of every worker (nomad_get_worker_stats);
                                 counts are always collected */

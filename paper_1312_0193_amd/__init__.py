@@ -27,6 +27,7 @@ class NomadConfig(C.Structure):
     _fields_ = [("k", C.c_int32), ("lambda_", C.c_float), ("alpha", C.c_float), ("beta", C.c_float),
                 ("gamma", C.c_float), ("sched", C.c_int32), ("dtype", C.c_int32), ("rounding", C.c_int32),
                 ("workers", C.c_int32), ("waves_per_worker", C.c_int32), ("item_slots", C.c_int32),
+                ("window", C.c_int32),
                 ("record_trace", C.c_int32), ("collect_stats", C.c_int32), ("seed", C.c_uint64)]
 
 
@@ -126,13 +127,14 @@ class Stats:
 
 
 def make_config(k: int, lam: float, alpha: float, beta: float, gamma: float, *, sched="ring", dtype="fp32",
-                rounding="rne", workers=0, waves_per_worker=0, item_slots=0, record_trace=False,
+                rounding="rne", workers=0, waves_per_worker=0, item_slots=0, window=0, record_trace=False,
                 collect_stats=False, seed=0) -> NomadConfig:
     cfg = NomadConfig()
     load().nomad_config_default(C.byref(cfg))
     cfg.k, cfg.lambda_, cfg.alpha, cfg.beta, cfg.gamma = k, lam, alpha, beta, gamma
     cfg.sched, cfg.dtype, cfg.rounding = SCHED[sched], DTYPE[dtype], ROUND[rounding]
     cfg.workers, cfg.waves_per_worker, cfg.item_slots = workers, waves_per_worker, item_slots
+    cfg.window = window
     cfg.record_trace = int(bool(record_trace))
     cfg.collect_stats = int(bool(collect_stats))
     cfg.seed = seed

@@ -17,6 +17,7 @@ struct nomad_ctx {
     int64_t m = 0, n = 0, nnz = 0;
     int32_t k = 0, kp = 0, p = 0;
     int32_t nw = 0, slots = 0;         // compute waves and item slots per worker
+    int32_t window = 0;                // rows a compute wave keeps in flight
     int32_t cus = 0, max_lds = 0;
     hipStream_t stream = nullptr;
     Plan plan;
@@ -66,8 +67,6 @@ nomad_status hip_fail(nomad_ctx *ctx, hipError_t e, const char *what) {
         if (_e != hipSuccess) return hip_fail((ctx), _e, (what)); \
     } while (0)
 
-int32_t round_up4(int32_t k) { return (k + 3) & ~3; }
-
 void release(nomad_ctx *c) {
     if (!c) return;
     nomad::free_plan(&c->plan);
@@ -102,6 +101,7 @@ void nomad_config_default(nomad_config *cfg) {
     cfg->workers = 0;
     cfg->waves_per_worker = 0;
     cfg->item_slots = 0;
+    cfg->window = 0;
     cfg->record_trace = 0;
     cfg->collect_stats = 0;
     cfg->seed = 0;
@@ -141,7 +141,7 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     c->n = n;
     c->nnz = nnz;
     c->k = cfg->k;
-    c->kp = round_up4(cfg->k);
+    c->kp = nomad::padded_k(cfg->k);
     c->stream = (hipStream_t)hip_stream;
 
     auto bail = [&](nomad_status st) {
@@ -161,20 +161,36 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     const int32_t nw = cfg->waves_per_worker > 0 ? cfg->waves_per_worker : nomad::kDefaultWaves;
     if (nw < 1 || nw > nomad::kMaxWaves)
         return bail(fail(c, NOMAD_EINVAL, "nomad_init: waves_per_worker=%d outside [1,%d]", nw, nomad::kMaxWaves));
+    if (cfg->window < 0 || cfg->window > nomad::kMaxWindow)
+        return bail(fail(c, NOMAD_EINVAL, "nomad_init: window=%d outside [0,%d]", cfg->window, nomad::kMaxWindow));
+    // Item slots and the compute waves' row windows share the LDS: by default deep windows
+    // come first, then item slots.
     int32_t slots = cfg->item_slots;
+    int32_t window = cfg->window <= 0 ? nomad::kMaxWindow : (cfg->window <= 8 ? 8 : (cfg->window <= 16 ? 16 : 32));
+    const bool auto_window = cfg->window <= 0;
+    auto fits = [&](int32_t s_, int32_t w_) { return nomad::train_lds_bytes(c->kp, nw, s_, w_) <= (size_t)max_lds; };
     if (slots <= 0) {
         slots = nomad::kMaxItemSlots;
-        while (slots > 8 && nomad::train_lds_bytes(c->kp, nw, slots) > (size_t)max_lds) slots >>= 1;
+        while (!fits(slots, window)) {
+            if (slots > 32) slots >>= 1;
+            else if (auto_window && window > 16) window >>= 1;
+            else if (slots > 16) slots >>= 1;
+            else if (auto_window && window > 8) window >>= 1;
+            else if (slots > 8) slots >>= 1;
+            else break;
+        }
+    } else if (auto_window) {
+        while (!fits(slots, window) && window > 8) window >>= 1;
     }
     if (slots < 1 || slots > nomad::kMaxItemSlots || (slots & (slots - 1)) != 0)
         return bail(fail(c, NOMAD_EINVAL, "nomad_init: item_slots=%d must be a power of two in [1,%d]", slots,
                          nomad::kMaxItemSlots));
-    const size_t lds = nomad::train_lds_bytes(c->kp, nw, slots);
+    const size_t lds = nomad::train_lds_bytes(c->kp, nw, slots, window);
     if (lds > (size_t)max_lds)
-        return bail(fail(c, NOMAD_EINVAL, "nomad_init: %d compute waves and %d item slots need %zu bytes of LDS for "
-                         "k=%d, device allows %d", nw, slots, lds, c->k, max_lds));
+        return bail(fail(c, NOMAD_EINVAL, "nomad_init: %d compute waves, %d item slots and a window of %d rows need "
+                         "%zu bytes of LDS for k=%d, device allows %d", nw, slots, window, lds, c->k, max_lds));
     int32_t maxw = 0;
-    hipError_t he = nomad::train_max_workers(c->kp, nw, slots, &maxw);
+    hipError_t he = nomad::train_max_workers(c->kp, nw, slots, window, &maxw);
     if (he != hipSuccess) return bail(hip_fail(c, he, "nomad_init: occupancy query"));
     int32_t p = cfg->workers;
     if (p <= 0) p = maxw < cus ? maxw : cus;
@@ -186,6 +202,8 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     c->p = p;
     c->nw = nw;
     c->slots = slots;
+    c->window = window;
+    c->cfg.window = window;
     c->cus = cus;
     c->max_lds = max_lds;
     c->cfg.workers = p;
@@ -224,7 +242,7 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     if ((e = hipEventRecord(c->ev0, st)) != hipSuccess) return bail(hip_fail(c, e, "nomad_init: event"));
     int code = 0;
     char msg[256] = {0};
-    e = nomad::build_plan(&c->plan, m, n, nnz, d_row, d_col, d_val, p, nw, cfg->seed, st, &code, msg,
+    e = nomad::build_plan(&c->plan, m, n, nnz, d_row, d_col, d_val, p, nw, window, cfg->seed, st, &code, msg,
                           sizeof(msg));
     if (e != hipSuccess) return bail(hip_fail(c, e, "nomad_init: layout"));
     if (code != 0) return bail(fail(c, (nomad_status)code, "nomad_init: %s", msg));
@@ -270,6 +288,7 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         a.p = c->p;
         a.nw = c->nw;
         a.slots = c->slots;
+        a.window = c->window;
         a.lambda = c->cfg.lambda;
         if (c->cfg.record_trace) {
             const int64_t need = c->plan.nvisits * (int64_t)epochs;

@@ -14,7 +14,9 @@
 //      of the wave in the visit, the wave before it in the visit); per visit: item,
 //      ordinal, visits of the item per epoch, last wave;
 //   7. the ratings of each wave gathered into one stream, in processing order (a stable
-//      sort by (worker, wave)).
+//      sort by (worker, wave));
+//   8. in each wave's stream, the ratings whose row is used again within the next D
+//      ratings (the rows a wave keeps in flight): those rows are handed on on chip.
 #include <hipcub/hipcub.hpp>
 
 #include <cstdio>
@@ -188,6 +190,7 @@ __global__ void k_records(const int32_t *srow, const int32_t *scol, const float 
         r.row = srow[e];
         r.r = sval[e];
         r.info = x | (first ? kInfoFirst : 0u) | (last ? kInfoLast : 0u) | (prev << kInfoPrevShift);
+        r.fwd = 0;
         rec[e] = r;
         key3[e] = (uint32_t)q * (uint32_t)nw + (uint32_t)w;
         if (is_start[e]) {
@@ -199,12 +202,43 @@ __global__ void k_records(const int32_t *srow, const int32_t *scol, const float 
     }
 }
 
+// Rows used again inside the window: for every rating of a wave's stream (taken
+// cyclically, as the stream repeats every epoch) the distance back to the previous rating
+// of the same row if it is below D, and the matching forward distance at that earlier
+// rating.  One thread per wave; the rows of a wave are its own, so `last` (m entries, -1 on
+// entry) is shared without conflicts.
+__global__ void k_forward(RatingRec *recs, const int64_t *rbase, int64_t nwt, int32_t D, int64_t *last) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nwt) return;
+    RatingRec *r = recs + rbase[t];
+    const int64_t cnt = rbase[t + 1] - rbase[t];
+    for (int64_t p = 0; p < 2 * cnt; ++p) {
+        const int64_t pos = p < cnt ? p : p - cnt;
+        const int32_t row = r[pos].row;
+        if (p >= cnt) {
+            const int64_t prev = last[row];
+            const int64_t d = p - prev;
+            if (prev >= 0 && d < D) {
+                r[pos].fwd |= (uint32_t)d << 8;
+                const int64_t src = pos - d >= 0 ? pos - d : pos - d + cnt;
+                r[src].fwd |= (uint32_t)d;
+            }
+        }
+        last[row] = p;
+    }
+    for (int64_t p = 0; p < cnt; ++p) last[r[p].row] = -1;
+}
+
 __global__ void k_count_keys(const uint32_t *key, int64_t nnz, unsigned long long *cnt) {
     GRID_LOOP(e, nnz) atomicAdd(&cnt[key[e]], 1ull);
 }
 
 __global__ void k_permute_recs(const uint32_t *idx, const RatingRec *in, int64_t nnz, RatingRec *out) {
     GRID_LOOP(e, nnz) out[e] = in[idx[e]];
+}
+
+__global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v) {
+    GRID_LOOP(e, n) p[e] = v;
 }
 
 __global__ void k_iota(uint32_t *p, int64_t n) {
@@ -259,8 +293,8 @@ void free_plan(Plan *pl) {
     } while (0)
 
 hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
-                      const float *d_val, int32_t p, int32_t nw, uint64_t seed, hipStream_t st, int *err_code,
-                      char *msg, size_t msg_len) {
+                      const float *d_val, int32_t p, int32_t nw, int32_t window, uint64_t seed, hipStream_t st,
+                      int *err_code, char *msg, size_t msg_len) {
     hipError_t rc = hipSuccess;
     *err_code = 0;
     *pl = Plan();
@@ -450,6 +484,17 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
         CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, (const int64_t *)kcount, pl->rbase, nwt + 1, st));
         CK(tmp.need(need));
         CK(hipcub::DeviceScan::ExclusiveSum(tmp.p, need, (const int64_t *)kcount, pl->rbase, nwt + 1, st));
+    }
+    if (nnz > 0) {
+        int64_t *last = nullptr;
+        CK(dalloc(&last, m));
+        hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(m)), dim3(kThreads), 0, st, last, m, (int64_t)-1);
+        hipLaunchKernelGGL(k_forward, dim3(grid_for(nwt, 64)), dim3(64), 0, st, pl->recs, pl->rbase, nwt, window,
+                           last);
+        hipError_t fe = hipGetLastError();
+        if (fe == hipSuccess) fe = hipStreamSynchronize(st);
+        (void)hipFree(last);
+        CK(fe);
     }
     {
         std::vector<int64_t> vb(p + 1);

@@ -17,8 +17,9 @@
 //     (rows ascending), through LDS.  A visit of item j at worker q may start once every
 //     earlier visit of j in the ring order has finished; a per-item counter of finished
 //     visits records that.
-//   * Each wave reads its ratings as one stream in processing order: 12-byte records
-//     (row, rating, visit information).
+//   * Each wave reads its ratings as one stream in processing order: 16-byte records
+//     (row, rating, visit information, and where the row is used again inside the
+//     wave's window of rows in flight).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,7 +32,8 @@ constexpr int kMaxWaves = 15;       // compute waves per worker (plus one memory
 constexpr int kDefaultWaves = 8;
 constexpr int kMaxItemSlots = 64;   // items a worker holds in LDS at once
 constexpr int kMaxWorkers = 4096;
-constexpr int kMaxEpochsPerLaunch = 64;  // a call runs longer epoch counts as several launches
+constexpr int kMaxEpochsPerLaunch = 64;
+constexpr int kMaxWindow = 32;           // rows a compute wave keeps in flight  // a call runs longer epoch counts as several launches
 
 // Visit information of a rating record.
 constexpr uint32_t kInfoXBits = 23;                       // visit index x within the epoch
@@ -41,10 +43,14 @@ constexpr uint32_t kInfoLast = 1u << 24;                  // last rating of the 
 constexpr uint32_t kInfoPrevShift = 25;                   // 1 + wave that precedes it in the visit,
 constexpr uint32_t kInfoPrevMask = 15u;                   // 0 = first wave of the visit
 
-struct RatingRec {
+// A rating of a wave's stream.  fwd: distance (in the stream, cyclically) to the next
+// rating of the same row if it is less than the window D, else 0 (bits 0-7), and the same
+// for the previous rating of the row (bits 8-15).
+struct alignas(16) RatingRec {
     int32_t row;
     float r;
     uint32_t info;
+    uint32_t fwd;
 };
 
 // One visit of a worker (16 bytes), in processing order.
@@ -55,7 +61,7 @@ struct alignas(16) VisitRec {
     int32_t lastw;   // last wave of the worker holding ratings of the item
 };
 
-static_assert(sizeof(RatingRec) == 12, "RatingRec layout");
+static_assert(sizeof(RatingRec) == 16, "RatingRec layout");
 static_assert(sizeof(VisitRec) == 16, "VisitRec layout");
 
 // Per-worker counters of a training call (100 MHz constant-clock ticks unless a count).
@@ -117,6 +123,7 @@ struct TrainArgs {
     int32_t p;                  // workers
     int32_t nw;                 // compute waves per worker
     int32_t slots;              // item slots per worker (<= 64)
+    int32_t window;             // D: rows a compute wave keeps in flight (8, 16 or 32)
     int32_t epoch0, epochs;     // epochs done before the launch, epochs of the launch
     float lambda;
     // per epoch of the launch: step size s_t (eq. stepsize_method) and 1 - s_t * lambda
@@ -132,15 +139,17 @@ struct TrainArgs {
 
 // layout.hip: build the layout; err_code receives 0 or a nomad_status value.
 hipError_t build_plan(Plan *plan, int64_t m, int64_t n, int64_t nnz, const int32_t *d_row,
-                      const int32_t *d_col, const float *d_val, int32_t p, int32_t nw, uint64_t seed,
-                      hipStream_t stream, int *err_code, char *msg, size_t msg_len);
+                      const int32_t *d_col, const float *d_val, int32_t p, int32_t nw, int32_t window,
+                      uint64_t seed, hipStream_t stream, int *err_code, char *msg, size_t msg_len);
 void free_plan(Plan *plan);
 
 // train.hip
-size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots);
+size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window);
 hipError_t launch_train(const TrainArgs &a, hipStream_t stream);
 // Workers of `nw` compute waves that can be resident at once on the device.
-hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t *max_workers);
+hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t *max_workers);
+// Row stride of the factors for k: a whole number of 16-byte pieces per lane of a wave.
+inline int32_t padded_k(int32_t k) { return k <= 64 ? 64 : (k <= 128 ? 128 : 256); }
 
 // eval.hip: FP64 RMSE / objective with a deterministic compensated sum.
 hipError_t eval_sums(const float *W, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,

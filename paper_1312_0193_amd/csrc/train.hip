@@ -140,37 +140,36 @@ __device__ __forceinline__ void sync_store(int32_t *p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Prefetch window (ratings in flight) of a compute wave for VEC floats per lane.
-template <int VEC>
-constexpr int window() { return VEC == 4 ? 8 : 16; }
 
-__host__ __device__ inline int window_for_kp(int kp) { return kp > 128 ? 8 : 16; }
 
 // ---------------------------------------------------------------------------------------
-// LDS of a worker: item slots, forwarding slots of every compute wave, and the words the
-// waves synchronise on.
+// LDS of a worker: item slots, the row slots and record ring of every compute wave, and
+// the words the waves synchronise on.
+constexpr int kRecBatch = 64;   // records a compute wave stages with one load
+constexpr int kRecRing = 3;     // batches a compute wave holds
+
 struct Lds {
     float *items;     // slots x kp
     float *rows;      // nw x (D + 1) x kp: row slots of every compute wave
-    uint32_t *recs;   // nw x 3 x 192: record batches of every compute wave
+    RatingRec *recs;  // nw x kRecRing x kRecBatch: staged records of every compute wave
     int32_t *flag;    // nw: 1 + the last visit each compute wave finished
     int32_t *ctl;     // [0] visits loaded, [1] stop
 };
 
-__host__ __device__ inline size_t lds_bytes(int kp, int nw, int slots) {
-    return ((size_t)slots * kp + (size_t)nw * (window_for_kp(kp) + 1) * kp) * sizeof(float) +
-           (size_t)nw * 3 * 192 * 4 + (kMaxWaves + 1 + 4) * 4;
+__host__ __device__ inline size_t lds_bytes(int kp, int nw, int slots, int window) {
+    return ((size_t)slots * kp + (size_t)nw * (window + 1) * kp) * sizeof(float) +
+           (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec) + (kMaxWaves + 1 + 4) * 4;
 }
 
-__device__ __forceinline__ Lds lds_layout(void *base, int kp, int nw, int slots) {
+__device__ __forceinline__ Lds lds_layout(void *base, int kp, int nw, int slots, int window) {
     char *p = (char *)base;
     Lds L;
     L.items = (float *)p;
     p += (size_t)slots * kp * sizeof(float);
     L.rows = (float *)p;
-    p += (size_t)nw * (window_for_kp(kp) + 1) * kp * sizeof(float);
-    L.recs = (uint32_t *)p;
-    p += (size_t)nw * 3 * 192 * 4;
+    p += (size_t)nw * (window + 1) * kp * sizeof(float);
+    L.recs = (RatingRec *)p;
+    p += (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec);
     L.flag = (int32_t *)p;
     p += (kMaxWaves + 1) * 4;
     L.ctl = (int32_t *)p;
@@ -220,7 +219,9 @@ __device__ __forceinline__ bool wait_above(const int32_t *p, int x, const Lds &L
 // LDS-DMA loads, written as asm so that the compiler neither sees them as LDS writes (it
 // would then wait for every outstanding memory operation before each LDS read) nor counts
 // them; the waits for them are explicit.  m0 holds the LDS address of lane 0's data; lane
-// l writes at m0 + l * (bytes per lane).  Lanes outside `mask` do nothing.
+// l writes at m0 + l * (bytes per lane).  Lanes outside `mask` do nothing.  m0 and exec
+// are restored; the exec mask is set with an instruction that writes SCC, so SCC is
+// declared clobbered (the compiler keeps carries of 64-bit scalar arithmetic in SCC).
 
 __device__ __forceinline__ uint32_t lds_off(const void *p) {
     return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)p;
@@ -240,11 +241,25 @@ __device__ __forceinline__ uint32_t lds_off(const void *p) {
         "s_mov_b32 m0, %1"                                  \
         : "=&s"(saved), "=&s"(m0s)                          \
         : "v"(src), "s"(lds), "s"(mask)                     \
-        : "memory")
+        : "memory", "scc")
 
-__device__ __forceinline__ void dma16(const void *src, uint32_t lds, uint64_t mask) { NOMAD_DMA16(""); }
+// Scalar operands go through readfirstlane: the compiler may otherwise hand a value it
+// cannot prove uniform to an "s" operand in a vector register.
+__device__ __forceinline__ uint32_t sgpr32(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint64_t sgpr64(uint64_t x) {
+    return (uint64_t)sgpr32((uint32_t)x) | ((uint64_t)sgpr32((uint32_t)(x >> 32)) << 32);
+}
+
+__device__ __forceinline__ void dma16(const void *src, uint32_t lds_, uint64_t mask_) {
+    const uint32_t lds = sgpr32(lds_);
+    const uint64_t mask = sgpr64(mask_);
+    NOMAD_DMA16("");
+}
 // Scalar base address plus a 32-bit lane offset.
-__device__ __forceinline__ void dma16s(const void *base, uint32_t voff, uint32_t lds, uint64_t mask) {
+__device__ __forceinline__ void dma16s(const void *base_, uint32_t voff, uint32_t lds_, uint64_t mask_) {
+    const void *base = (const void *)sgpr64((uint64_t)(uintptr_t)base_);
+    const uint32_t lds = sgpr32(lds_);
+    const uint64_t mask = sgpr64(mask_);
     uint64_t saved;
     uint32_t m0s;
     asm volatile(
@@ -258,12 +273,17 @@ __device__ __forceinline__ void dma16s(const void *base, uint32_t voff, uint32_t
         "s_mov_b32 m0, %1"
         : "=&s"(saved), "=&s"(m0s)
         : "v"(voff), "s"(base), "s"(lds), "s"(mask)
-        : "memory");
+        : "memory", "scc");
 }
 // Device-coherent form (sc1), for items handed over by other workers.
-__device__ __forceinline__ void dma16_coherent(const void *src, uint32_t lds, uint64_t mask) { NOMAD_DMA16(" sc1"); }
+__device__ __forceinline__ void dma16_coherent(const void *src, uint32_t lds_, uint64_t mask_) {
+    const uint32_t lds = sgpr32(lds_);
+    const uint64_t mask = sgpr64(mask_);
+    NOMAD_DMA16(" sc1");
+}
 
-__device__ __forceinline__ void dma4(const void *src, uint32_t lds) {
+__device__ __forceinline__ void dma4(const void *src, uint32_t lds_) {
+    const uint32_t lds = sgpr32(lds_);
     uint32_t m0s;
     asm volatile(
         "s_mov_b32 %0, m0\n\t"
@@ -279,132 +299,152 @@ __device__ __forceinline__ void dma4(const void *src, uint32_t lds) {
 // ---------------------------------------------------------------------------------------
 // Compute wave.
 //
-// The rows of the next D ratings are in flight into D LDS slots.  Step y updates rating y
-// (slot y mod D) and then starts the load of rating y + D into the same slot.  Every step
-// issues exactly one row load (into the wave's spare slot when the row is handed on
-// instead) and one store (a 4-byte placeholder when the row is handed on), so when step y
-// begins at least 2(D-1) memory operations were issued after the load of its row, and
-// "s_waitcnt vmcnt(2D-2)" is enough to see that load complete.  Record batches (64
-// ratings) are loaded one batch ahead into a ring of three; they only add operations.
+// Rows: the rows of the next D ratings are in flight into D LDS slots: step y updates
+// rating y (slot y mod D) and then starts loading the row of rating y + D into that slot.
+// Every step issues exactly one row load and one store, so at the end of step y
+// 2(D-2) memory operations have been issued after the load of rating y + 2's row, and
+// "s_waitcnt vmcnt(2D-4)" sees that load complete; step y + 1 reads that row from LDS at
+// its start, before its own update, so the read overlaps the update.  A row used again
+// within the window is not re-read: the layout marks, in each record, the distance to the
+// next use of its row and back to the previous one; the earlier update writes its result
+// into the later rating's slot (or, for the very next rating, hands it on in registers),
+// and the later rating's load goes to a spare slot.  (The earlier update is still
+// stored, so a window reaching past the end of the launch loses nothing.)
+//
+// Records: staged in LDS 64 at a time by one LDS-DMA load, two batches ahead, in a ring of
+// three batches; a record is read with one broadcast LDS read.  (Records read through the
+// scalar cache would put the scalar-memory latency into every step: scalar loads and LDS
+// reads share one counter and scalar loads complete out of order.)
+//
+// Vectors are padded to 64 * VEC floats, so every lane holds VEC elements.
 
-template <int VEC, int NR16, int D>
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4v lds_u32x4;
+typedef uint32_t u32x2v __attribute__((ext_vector_type(2)));
+
+template <int VEC, int D>
 struct ComputeWave {
-    static_assert(2 * (D - 1) <= 63, "vmcnt range");
+    static_assert(2 * (D - 2) <= 63 && D >= 4, "vmcnt range");
     const TrainArgs &a;
     const Lds &L;
     const int q, w, lane, kp;
-    const bool on;            // lane holds elements of the vectors
-    const int loff;           // first element of the lane (0 for lanes beyond the width)
+    const int loff;           // first element of the lane
     const RatingRec *rs;      // the wave's stream
     const int64_t cnt;        // ratings per epoch
     const int64_t total;      // ratings of the launch
     lds_float *const rows;    // D + 1 row slots (the last one takes loads that are not used)
     const uint32_t rows_lds;
-    const lds_u32 *const recs;  // 3 x 64 records (as dwords)
-    const uint32_t recs_lds;
+    const uint32_t recs_lds;  // record ring: kRecRing x kRecBatch records
     lds_float *const items;
     const uint64_t row_mask;  // lanes that load a row (16 bytes each)
-    int64_t bstart = 0;       // stream position of the next record batch to load
-    int win = -1;             // lane u: row of the rating in window slot u (-1: none)
+    int64_t bpos = 0;         // stream position of the next record batch
+    int bent = 0;             // ring entry of the next record batch
     uint64_t forwarded = 0, t_wait = 0;
 
     __device__ ComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0, int64_t cnt_)
-        : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), on(lane_ * VEC < a_.kp), loff(on ? lane_ * VEC : 0),
+        : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC),
           rs(a_.recs + r0), cnt(cnt_), total(cnt_ * a_.epochs),
-          rows(to_lds(L_.rows) + (size_t)w_ * (D + 1) * a_.kp),
+          rows(to_lds(L_.rows) + (size_t)w_ * (D + 1) * a_.kp + lane_ * VEC),
           rows_lds(lds_off(L_.rows) + (uint32_t)(w_ * (D + 1) * a_.kp * 4)),
-          recs((const lds_u32 *)(L_.recs + (size_t)w_ * 3 * 192)), recs_lds(lds_off(L_.recs) + (uint32_t)(w_ * 3 * 192 * 4)),
-          items(to_lds(L_.items) + (on ? lane_ * VEC : 0)),
+          recs_lds(lds_off(L_.recs) + (uint32_t)(w_ * kRecRing * kRecBatch * (int)sizeof(RatingRec))),
+          items(to_lds(L_.items) + lane_ * VEC),
           row_mask((a_.kp >> 2) >= 64 ? ~0ull : ((1ull << (a_.kp >> 2)) - 1ull)) {}
 
-    // Load the records of batch b (64 ratings from stream position bstart) into ring
-    // entry b mod 3: three dword loads of 64 lanes.
-    __device__ __forceinline__ void load_batch(int64_t b) {
-        const uint32_t *src = (const uint32_t *)rs;
-        const uint32_t dst = recs_lds + (uint32_t)b % 3u * 192u * 4u;
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int dwi = 64 * t + lane;  // dword of the batch
-            int64_t rec = bstart + dwi / 3;
-            while (rec >= cnt) rec -= cnt;
-            dma4(src + rec * 3 + dwi % 3, dst + (uint32_t)(t * 256));
-        }
-        bstart += 64;
-        while (bstart >= cnt) bstart -= cnt;
+    __device__ __forceinline__ void load_row(int row, int slot) {
+        dma16s(a.W + (int64_t)row * kp, (uint32_t)(lane & 63) * 16u, rows_lds + (uint32_t)(slot * kp * 4), row_mask);
     }
-
-    __device__ __forceinline__ const lds_u32 *rec_ptr(int64_t y) const {
-        return recs + ((uint32_t)(y >> 6) % 3u * 64u + (uint32_t)(y & 63)) * 3u;
-    }
-    __device__ __forceinline__ RatingRec record(int64_t y) {
-        const lds_u32 *p = rec_ptr(y);
-        RatingRec r;
-        r.row = __builtin_amdgcn_readfirstlane((int)p[0]);
-        r.r = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane((int)p[1]));
-        r.info = (uint32_t)__builtin_amdgcn_readfirstlane((int)p[2]);
-        return r;
-    }
-
     __device__ __forceinline__ void placeholder_store() {
         if (lane == 0) a.dummy[(int64_t)q * kMaxWaves + w] = 0.0f;
     }
-
-    // Start loading the row of rating y (row id `row`) into slot u, or into the spare
-    // slot if a rating still in the window updates the same row (that one hands its
-    // result on).  Past the end of the launch a placeholder load keeps the count.
-    __device__ __forceinline__ void issue(int64_t y, int u, int row) {
-        const uint32_t voff = (uint32_t)(lane & 63) * 16u;
-        if (y < total) {
-            if ((y & 63) == 0 && y > 0) load_batch((y >> 6) + 1);
-            const uint64_t same = __builtin_amdgcn_ballot_w64(win == row) & ~(1ull << u);
-            win = lane == u ? row : win;
-            const uint32_t dst = rows_lds + (uint32_t)((same ? D : u) * kp * 4);
-            dma16s(a.W + (int64_t)row * kp, voff, dst, row_mask);
-        } else {
-            win = lane == u ? -1 : win;
-            dma16s(a.W, voff, rows_lds + (uint32_t)(D * kp * 4), row_mask);
-        }
+    // Stage the next kRecBatch records of the stream (taken cyclically): lane l loads one.
+    __device__ __forceinline__ void load_batch() {
+        int64_t pos = bpos + lane;
+        while (pos >= cnt) pos -= cnt;
+        dma16(rs + pos, recs_lds + (uint32_t)(bent * kRecBatch * (int)sizeof(RatingRec)), ~0ull);
+        bpos += kRecBatch;
+        while (bpos >= cnt) bpos -= cnt;
+        bent = bent == kRecRing - 1 ? 0 : bent + 1;
     }
-
-    // Wait until at most 2(D-1) memory operations are outstanding: the row load of the
-    // rating that follows the one just issued (issued D - 1 steps ago) is then complete.
-    __device__ __forceinline__ void wait_next_row() {
-        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (D - 1)) : "memory");
+    // LDS address of the record after the one at `ad`, in ring order.
+    __device__ __forceinline__ uint32_t rec_next(uint32_t ad) const {
+        ad += (uint32_t)sizeof(RatingRec);
+        return ad == recs_lds + (uint32_t)(kRecRing * kRecBatch * sizeof(RatingRec)) ? recs_lds : ad;
+    }
+    // A staged record: one LDS read that every lane makes at the same address, then the
+    // fields as scalars (done where they are needed, so that the read overlaps the work in
+    // between).
+    __device__ __forceinline__ u32x4v rec_read(uint32_t ad) const { return *(const lds_u32x4 *)(uintptr_t)ad; }
+    __device__ __forceinline__ static RatingRec rec_of(const u32x4v v) {
+        RatingRec r;
+        r.row = __builtin_amdgcn_readfirstlane((int)v.x);
+        r.r = __int_as_float(__builtin_amdgcn_readfirstlane((int)v.y));
+        r.info = (uint32_t)__builtin_amdgcn_readfirstlane((int)v.z);
+        r.fwd = (uint32_t)__builtin_amdgcn_readfirstlane((int)v.w);
+        return r;
+    }
+    __device__ __forceinline__ RatingRec rec_at(uint32_t ad) const { return rec_of(rec_read(ad)); }
+    // Only the row and the forwarding distances of a staged record (all that a row load
+    // needs; reading dwords that are not used would let the compiler give their registers
+    // to other values while the read is in flight, and wait for it there).
+    __device__ __forceinline__ u32x2v rec_read_rf(uint32_t ad) const {
+        const lds_u32 *p = (const lds_u32 *)(uintptr_t)ad;
+        return u32x2v{p[0], p[3]};
     }
 
     __device__ void run() {
         if (total <= 0) return;
         const uint64_t t_start = tick(a.timing);
-        load_batch(0);
-        load_batch(1);
+        load_batch();
+        load_batch();
         wait_vm();
-        for (int u = 0; u < D; ++u) {
-            issue(u, u, record(u).row);
+        // Prologue: the rows of ratings 0..D-1, each load followed by a placeholder store
+        // (as every later step issues one load and one store).
+        uint32_t ai = recs_lds;  // record of the next rating to issue
+        int64_t ip = 0;          // next rating to issue
+        for (; ip < D; ++ip) {
+            if (ip < total) {
+                const RatingRec ir = rec_at(ai);
+                const int prv = (int)((ir.fwd >> 8) & 255u);
+                load_row(ir.row, (prv && prv <= ip) ? D : (int)ip);
+            } else {
+                load_row(0, D);
+            }
             placeholder_store();
+            ai = rec_next(ai);
         }
-        // Carried from step to step: the records of ratings y and y + 1, the row of the
-        // rating issued next (y + D), and the row vector of rating y.
-        RatingRec rc = record(0), rn = record(1);
-        int irow = record(D).row;
-        float wv[VEC];
-        wait_next_row();
-        lload<VEC>(rows + loff, wv);
-        float h[VEC];
+        // State at the top of step y: rc = record of rating y (scalars), vn = record of
+        // y + 1 and vi = record of y + D (LDS reads issued in the step before), wn = the row
+        // of rating y as read from its slot, and (f1, nwp) = whether rating y - 1 hands
+        // its row on to rating y in registers, and that row.
+        RatingRec rc = rec_at(recs_lds);
+        u32x4v vn = rec_read(recs_lds + (uint32_t)sizeof(RatingRec));
+        u32x2v vi = rec_read_rf(ai);
+        ai = rec_next(ai);                                            // record of y + D + 1
+        uint32_t an = recs_lds + 2u * (uint32_t)sizeof(RatingRec);   // record of y + 2
+        float h[VEC], wn[VEC], nwp[VEC];
+        bool f1 = false;
 #pragma unroll
-        for (int v = 0; v < VEC; ++v) h[v] = 0.0f;
+        for (int v = 0; v < VEC; ++v) h[v] = nwp[v] = 0.0f;
+        asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (D - 2)) : "memory");
+        lload<VEC>(rows, wn);
         const int nv = (int)(a.vbase[q + 1] - a.vbase[q]);
         int e = 0, xbase = 0;
         int64_t left = cnt;
-        float s = a.step_s[0];
-        float c = a.step_c[0];
-        const uint64_t full = (1ull << D) - 1ull;
+        // Step sizes of the launch's epochs, lane e holding epoch e's (read with readlane:
+        // a scalar memory load inside the loop would put its latency into every step).
+        const float s_tab = a.step_s[lane < a.epochs ? lane : 0];
+        const float c_tab = a.step_c[lane < a.epochs ? lane : 0];
+        float s = __shfl(s_tab, 0);
+        float c = __shfl(c_tab, 0);
         int64_t y = 0;
-        int u = 0;
         for (; y < total; ++y) {
-            // Records for the next step, read now and used at the end of the step.
-            const lds_u32 *pa = rec_ptr(y + 2);
-            const int ra0 = (int)pa[0], ra1 = (int)pa[1], ra2 = (int)pa[2];
-            const int rb0 = (int)rec_ptr(y + D + 1)[0];
+            const int u = (int)(y & (D - 1));
+            float wv[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) wv[v] = f1 ? nwp[v] : wn[v];
+            const RatingRec rn = rec_of(vn);
+            const int irow = __builtin_amdgcn_readfirstlane((int)vi.x);
+            const uint32_t ifwd = (uint32_t)__builtin_amdgcn_readfirstlane((int)vi.y);
             const int X = xbase + (int)(rc.info & kInfoXMask);
             const int slot = X & (a.slots - 1);
             if (rc.info & kInfoFirst) {
@@ -417,58 +457,61 @@ struct ComputeWave {
                 compiler_fence();
                 t_wait += tick(a.timing) - t0;
                 lload<VEC>(items + (size_t)slot * kp, h);
-#pragma unroll
-                for (int v = 0; v < VEC; ++v) h[v] = on ? h[v] : 0.0f;
             }
             // Section 2.3: one residual, both vectors from their values before the update.
-            // Lanes beyond the vector width hold h = 0 and copies of finite elements in wv,
-            // so they add nothing to the dot product; their se is 0, so their h stays 0.
             float d = 0.0f;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) d = fmaf(wv[v], h[v], d);
-            d = wave_sum<NR16>(d);
-            const float se0 = s * (rc.r - d);
-            const float se = on ? se0 : 0.0f;
+            d = wave_sum<4>(d);
+            // Reads for the next step: the row of rating y + 1 (its load completed in the
+            // step before), the records of y + 2 and y + D + 1.
+            lload<VEC>(rows + ((u + 1) & (D - 1)) * kp, wn);
+            vn = rec_read(an);
+            an = rec_next(an);
+            vi = rec_read_rf(ai);
+            ai = rec_next(ai);
+            const float se = s * (rc.r - d);
             float nw[VEC];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
                 nw[v] = fmaf(se, h[v], c * wv[v]);
                 h[v] = fmaf(se, wv[v], c * h[v]);
             }
-            // Hand the row on to the next rating of the window that uses it, or store it.
-            const uint64_t same = __builtin_amdgcn_ballot_w64(win == rc.row) & ~(1ull << u);
-            if (same) {
-                ++forwarded;
-                const uint64_t rot = ((same >> (u + 1)) | (same << (D - u - 1))) & full;
-                int t = u + 1 + (int)__builtin_ctzll(rot);
-                if (t >= D) t -= D;
-                if (on) lstore<VEC>(rows + t * kp + loff, nw);
-                placeholder_store();
-            } else {
-                if (on) vstore<VEC>(a.W + (int64_t)rc.row * kp + loff, nw);
-            }
+            // Hand the row on to its next use inside the window (the very next rating takes
+            // it in registers), and store it.
+            const int nxt = (int)(rc.fwd & 255u);
+            if (nxt > 1) lstore<VEC>(rows + ((u + nxt) & (D - 1)) * kp, nw);
+            forwarded += nxt != 0;
+            vstore<VEC>(a.W + (int64_t)rc.row * kp + loff, nw);
+            f1 = nxt == 1;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) nwp[v] = nw[v];
             if (rc.info & kInfoLast) {
-                if (on) lstore<VEC>(items + (size_t)slot * kp, h);
+                lstore<VEC>(items + (size_t)slot * kp, h);
                 wait_lgkm();
                 if (lane == 0) sync_store(&L.flag[w], X + 1);
             }
-            issue(y + D, u, irow);
-            if (++u == D) u = 0;
-            wait_next_row();
-            lload<VEC>(rows + u * kp + loff, wv);
+            if ((y & (kRecBatch - 1)) == 0) load_batch();
+            // Start loading the row of rating ip = y + D into slot u (or into the spare slot
+            // if an update inside the window hands it on).
+            if (ip < total) {
+                const int prv = (int)((ifwd >> 8) & 255u);
+                load_row(irow, (prv && prv <= ip) ? D : u);
+            } else {
+                load_row(0, D);
+            }
+            ++ip;
+            // The row of rating y + 2, read in the next step.  (Not timed: the clock read is
+            // a scalar-memory operation, and waiting for it would wait for the LDS reads
+            // issued above.)
+            asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (D - 2)) : "memory");
             rc = rn;
-            rn.row = __builtin_amdgcn_readfirstlane(ra0);
-            rn.r = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(ra1));
-            rn.info = (uint32_t)__builtin_amdgcn_readfirstlane(ra2);
-            irow = __builtin_amdgcn_readfirstlane(rb0);
             if (--left == 0) {
                 left = cnt;
                 ++e;
                 xbase += nv;
-                if (e < a.epochs) {
-                    s = a.step_s[e];
-                    c = a.step_c[e];
-                }
+                s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s_tab), e & 63));
+                c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c_tab), e & 63));
             }
         }
         wait_vm();
@@ -746,23 +789,22 @@ struct MemoryWave {
     }
 };
 
-template <int VEC, int NR16>
+template <int VEC, int D>
 __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
     extern __shared__ float4 lds4[];
-    constexpr int D = window<VEC>();
     // The wave index is the same in every lane: say so, so that everything derived from it
     // lives in scalar registers.
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int q = blockIdx.x;
-    const Lds L = lds_layout(lds4, a.kp, a.nw, a.slots);
+    const Lds L = lds_layout(lds4, a.kp, a.nw, a.slots, D);
     if (threadIdx.x < kMaxWaves + 1) L.flag[threadIdx.x] = 0;
     if (threadIdx.x < 2) L.ctl[threadIdx.x] = 0;
     __syncthreads();
     if (q >= a.p || a.epochs <= 0) return;
     if (wave < a.nw) {
         const int64_t i0 = a.rbase[(int64_t)q * a.nw + wave], i1 = a.rbase[(int64_t)q * a.nw + wave + 1];
-        ComputeWave<VEC, NR16, D> cw(a, L, q, wave, lane, i0, i1 - i0);
+        ComputeWave<VEC, D> cw(a, L, q, wave, lane, i0, i1 - i0);
         cw.run();
     } else if (wave == a.nw) {
         MemoryWave mw(a, L, q, lane);
@@ -770,43 +812,56 @@ __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
     }
 }
 
-template <int VEC, int NR16>
+template <int VEC, int D>
 hipError_t launch_t(const TrainArgs &a, hipStream_t st) {
-    const size_t lds = lds_bytes(a.kp, a.nw, a.slots);
-    hipLaunchKernelGGL((k_worker<VEC, NR16>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D);
+    hipLaunchKernelGGL((k_worker<VEC, D>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
     return hipGetLastError();
 }
 
-const void *pick_kernel(int kp) {
-    if (kp <= 16) return (const void *)k_worker<1, 1>;
-    if (kp <= 32) return (const void *)k_worker<1, 2>;
-    if (kp <= 64) return (const void *)k_worker<1, 4>;
-    if (kp <= 128) return (const void *)k_worker<2, 4>;
-    return (const void *)k_worker<4, 4>;
+template <int VEC>
+const void *pick_d(int window) {
+    if (window <= 8) return (const void *)k_worker<VEC, 8>;
+    if (window <= 16) return (const void *)k_worker<VEC, 16>;
+    return (const void *)k_worker<VEC, 32>;
+}
+
+const void *pick_kernel(int kp, int window) {
+    if (kp <= 64) return pick_d<1>(window);
+    if (kp <= 128) return pick_d<2>(window);
+    return pick_d<4>(window);
+}
+
+template <int VEC>
+hipError_t launch_v(const TrainArgs &a, hipStream_t st) {
+    if (a.window <= 8) return launch_t<VEC, 8>(a, st);
+    if (a.window <= 16) return launch_t<VEC, 16>(a, st);
+    return launch_t<VEC, 32>(a, st);
 }
 
 }  // namespace
 
-size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots) { return lds_bytes(kp, nw, slots); }
+size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window) {
+    return lds_bytes(kp, nw, slots, window);
+}
 
-hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t *max_workers) {
+hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t *max_workers) {
     int dev = 0, cus = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(kp), 64 * (nw + 1), lds_bytes(kp, nw, slots));
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(kp, window), 64 * (nw + 1),
+                                                     lds_bytes(kp, nw, slots, window));
     if (e != hipSuccess) return e;
     *max_workers = nb * cus;
     return hipSuccess;
 }
 
 hipError_t launch_train(const TrainArgs &a, hipStream_t st) {
-    if (a.kp <= 16) return launch_t<1, 1>(a, st);
-    if (a.kp <= 32) return launch_t<1, 2>(a, st);
-    if (a.kp <= 64) return launch_t<1, 4>(a, st);
-    if (a.kp <= 128) return launch_t<2, 4>(a, st);
-    return launch_t<4, 4>(a, st);
+    if (a.kp <= 64) return launch_v<1>(a, st);
+    if (a.kp <= 128) return launch_v<2>(a, st);
+    return launch_v<4>(a, st);
 }
 
 }  // namespace nomad

@@ -113,6 +113,23 @@ def test_ring_independent_of_waves_and_slots():
     assert rel(ref[0], Wo) < 2 * TOL_1EPOCH and rel(ref[1], Ho) < 2 * TOL_1EPOCH
 
 
+def test_ring_independent_of_row_windows():
+    """The number of rows a compute wave keeps in flight changes when rows are loaded and
+    which repeated rows are handed on on chip, never the order of the updates."""
+    prob, W0, H0, hp = make(900, 300, 60_000, k=64, seed=17, degrees="zipf")
+    P, seed = 6, 9
+    ref = None
+    for win in [8, 16, 32, 0]:
+        m, W, H = gpu_run(prob, W0, H0, hp, P, seed, [2], window=win)
+        m.close()
+        if ref is None:
+            ref = (W, H)
+        else:
+            assert np.array_equal(W, ref[0]) and np.array_equal(H, ref[1]), win
+    Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 2)
+    assert rel(ref[0], Wo) < 2 * TOL_1EPOCH and rel(ref[1], Ho) < 2 * TOL_1EPOCH
+
+
 def test_ring_many_epochs_in_one_call():
     """A call longer than one launch (64 epochs) continues the step-size counter and the
     item counters across launches."""
