@@ -57,7 +57,19 @@ typedef enum {
  *     3.4); workers take groups in arrival order, so the serial order depends on timing. */
 typedef enum { NOMAD_SCHED_RING = 0, NOMAD_SCHED_PERM = 1 } nomad_sched;
 
-/* Storage type of W and H in device memory; arithmetic is always FP32. */
+/* Storage type of W in device memory (H is always held in FP32); arithmetic is always
+ * FP32.  NOMAD_BF16: W is rounded to bfloat16 once at nomad_init (nearest-even) and every
+ * updated w_i is rounded to bfloat16 before it is stored, by the nomad_round rule:
+ *   RNE         nearest, ties to even;
+ *   STOCHASTIC  the FP32 result's 16 low bits plus 16 random bits, truncated (the magnitude
+ *               rounds up with probability equal to the discarded fraction).  The random
+ *               bits of element l of the update of rating (i, j) in epoch t are the low
+ *               (l even) or high (l odd) half of lowbias32(c + l/2), with
+ *               c = lowbias32(s ^ i*0x9E3779B1 ^ j*0x85EBCA77 ^ t*0xC2B2AE3D) in 32-bit
+ *               arithmetic, s = the low 32 bits of nomad_config.seed, lowbias32 = C. Wellons'
+ *               integer hash (x ^= x>>16; x *= 0x7feb352d; x ^= x>>15; x *= 0x846ca68b;
+ *               x ^= x>>16).
+ * nomad_get_factors returns W widened to FP32 (exact). */
 typedef enum { NOMAD_FP32 = 0, NOMAD_BF16 = 1 } nomad_dtype;
 typedef enum { NOMAD_ROUND_RNE = 0, NOMAD_ROUND_STOCHASTIC = 1 } nomad_round;
 
@@ -79,7 +91,8 @@ typedef struct {
     int32_t record_trace;    /* 1 = record every (worker, item) visit for replay */
     int32_t collect_stats;   /* 1 = time the phases of every worker (nomad_get_worker_stats);
                                 counts are always collected */
-    uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing */
+    uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing,
+                           stochastic rounding */
 } nomad_config;
 
 typedef struct {

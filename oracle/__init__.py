@@ -58,6 +58,14 @@ def _load():
         common = [i64, i64, i64, P, P, P, i32, dbl, dbl, dbl, dbl, i32, u64]
         lib.orc_train_ring.restype = C.c_int
         lib.orc_train_ring.argtypes = common + [i32, i32, P, P, P]
+        lib.orc_lowbias32.restype = C.c_uint32
+        lib.orc_lowbias32.argtypes = [C.c_uint32]
+        lib.orc_sr_bits.restype = C.c_uint32
+        lib.orc_sr_bits.argtypes = [C.c_uint32, i64, i64, i64, i32]
+        lib.orc_round_bf16.restype = dbl
+        lib.orc_round_bf16.argtypes = [dbl, i32, C.c_uint32]
+        lib.orc_train_ring_bf16.restype = C.c_int
+        lib.orc_train_ring_bf16.argtypes = common + [i32, i32, i32, C.c_uint32, P, P, P]
         lib.orc_train_ring_interleaved.restype = C.c_int
         lib.orc_train_ring_interleaved.argtypes = common + [i32, i32, u64, P, P, P]
         lib.orc_train_perm.restype = C.c_int
@@ -153,6 +161,31 @@ def train_ring(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, epoch0=0
         _check(lib.orc_train_ring(*args, _p(W), _p(H), C.byref(st)))
     else:
         _check(lib.orc_train_ring_interleaved(*args, interleave_seed, _p(W), _p(H), C.byref(st)))
+    return W, H, st
+
+
+def lowbias32(x: int) -> int:
+    return int(_load().orc_lowbias32(x & 0xFFFFFFFF))
+
+
+def sr_bits(seed: int, i: int, j: int, t: int, l: int) -> int:
+    return int(_load().orc_sr_bits(seed & 0xFFFFFFFF, i, j, t, l))
+
+
+def round_bf16(x: float, rounding: int = 0, bits: int = 0) -> float:
+    """x rounded to FP32, then to bfloat16 (0 nearest-even, 1 stochastic with `bits`)."""
+    return float(_load().orc_round_bf16(float(x), rounding, bits & 0xFFFFFFFF))
+
+
+def train_ring_bf16(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, rounding, sr_seed, epoch0=0):
+    """Ring order with w_i stored in bfloat16 (rounding 0 nearest-even, 1 stochastic)."""
+    row, col, val = _coo(row, col, val)
+    W = _factors(W0, m, hp.k)
+    H = _factors(H0, n, hp.k)
+    st = Stats()
+    _check(_load().orc_train_ring_bf16(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha,
+                                       hp.beta, hp.gamma, p, seed, epoch0, epochs, rounding, sr_seed & 0xFFFFFFFF,
+                                       _p(W), _p(H), C.byref(st)))
     return W, H, st
 
 

@@ -36,6 +36,13 @@
  *   orc_train_uniform -- Algorithm 1 literally: recipient uniform over all p workers, t is
  *                       the per-(worker,item) visit count, stop after a number of updates.
  *   orc_replay       -- re-execute a recorded sequence of (worker, item, t, seq) visits.
+ *   orc_train_ring_bf16 -- the ring order with the rows w_i stored in bfloat16 (the
+ *                       storage form of the benchmark's BF16 configuration; the paper
+ *                       itself works in FP32/FP64): the update is computed in FP64 from
+ *                       the stored values, rounded to FP32, then to bfloat16 (nearest-even,
+ *                       or stochastically with a counter hash).  Parity unpinned beyond
+ *                       the rounding primitives: there is no closed form for a BF16 SGD
+ *                       trajectory.
  *   orc_rmse / orc_objective -- test RMSE of section 5.1 and J(W,H) of eq. (obj_fcn),
  *                       with FP64 dot products and Neumaier-compensated sums.
  */
@@ -363,6 +370,99 @@ int orc_train_ring_interleaved(int64_t m, int64_t n, int64_t nnz, const int32_t 
     free(pos); free(done); free(live);
     layout_free(&L);
     return rc;
+}
+
+/* ------------------------------------------------------------------------------- */
+/* bfloat16 storage: the upper 16 bits of an IEEE single.                            */
+/* ------------------------------------------------------------------------------- */
+
+/* Integer hash "lowbias32" (C. Wellons, hash-prospector, 2018). */
+uint32_t orc_lowbias32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+/* The 16 random bits of element l of the update of rating (i, j) in epoch t: a key
+ * c = lowbias32(seed ^ i*0x9E3779B1 ^ j*0x85EBCA77 ^ t*0xC2B2AE3D) (32-bit arithmetic),
+ * then the word lowbias32(c + l/2), whose low half serves even l and high half odd l. */
+uint32_t orc_sr_bits(uint32_t seed, int64_t i, int64_t j, int64_t t, int32_t l)
+{
+    const uint32_t key = seed ^ ((uint32_t)i * 0x9E3779B1U) ^ ((uint32_t)j * 0x85EBCA77U) ^
+                         ((uint32_t)t * 0xC2B2AE3DU);
+    const uint32_t c = orc_lowbias32(key);
+    const uint32_t word = orc_lowbias32(c + (uint32_t)(l >> 1));
+    return (l & 1) ? (word >> 16) : (word & 0xFFFFU);
+}
+
+/* x rounded to FP32, then to bfloat16: rounding = 0 nearest-even (ties to the even
+ * bfloat16), 1 stochastic (the 16 discarded bits are compared with `bits`: the magnitude
+ * rounds up with probability equal to the discarded fraction).  Returns the bfloat16
+ * value as a double.  Finite inputs only. */
+double orc_round_bf16(double x, int32_t rounding, uint32_t bits)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if (rounding == 0)
+        u = u + 0x7FFFU + ((u >> 16) & 1U);
+    else
+        u = u + (bits & 0xFFFFU);
+    u &= 0xFFFF0000U;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+/* The ring order (as orc_train_ring) with w_i stored in bfloat16: W is rounded to
+ * bfloat16 (nearest-even) on entry, and every update's new w_i is rounded with
+ * orc_round_bf16 before it is stored; h_j, the residual and the update are FP64. */
+int orc_train_ring_bf16(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                        const float *val, int32_t k, double lambda, double alpha, double beta,
+                        double gamma, int32_t p, uint64_t seed, int32_t epoch0, int32_t epochs,
+                        int32_t rounding, uint32_t sr_seed, double *W, double *H, orc_stats *st)
+{
+    int rc = check_common(k, p, epochs);
+    if (rc) return rc;
+    if (rounding != 0 && rounding != 1) return ORC_EINVAL;
+    layout L;
+    rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
+    if (rc) return rc;
+    if (st) memset(st, 0, sizeof(*st));
+    for (int64_t x = 0; x < m * (int64_t)k; ++x) W[x] = orc_round_bf16(W[x], 0, 0);
+    int64_t *cursor = (int64_t *)malloc(sizeof(int64_t) * ((size_t)p + 1));
+    if (!cursor) { layout_free(&L); return ORC_ENOMEM; }
+    for (int32_t e = 0; e < epochs; ++e) {
+        const int64_t t = epoch0 + e;
+        double s_t = orc_step(alpha, beta, gamma, (double)t);
+        for (int32_t q = 0; q < p; ++q) cursor[q] = L.wvis[q];
+        for (int32_t sub = 0; sub < p; ++sub) {
+            for (int32_t q = 0; q < p; ++q) {
+                while (cursor[q] < L.wvis[q + 1] &&
+                       L.ratings[L.visits[cursor[q]].begin].s == sub) {
+                    const visit *V = &L.visits[cursor[q]];
+                    double *h = H + (int64_t)V->j * k;
+                    for (int64_t x = V->begin; x < V->end; ++x) {
+                        const rating *r = &L.ratings[x];
+                        double *w = W + (int64_t)r->i * k;
+                        orc_update(k, w, h, r->r, s_t, lambda);
+                        for (int32_t l = 0; l < k; ++l)
+                            w[l] = orc_round_bf16(w[l], rounding,
+                                                  rounding ? orc_sr_bits(sr_seed, r->i, r->j, t, l) : 0);
+                        if (st) st->updates++;
+                    }
+                    if (st && V->end > V->begin) st->visits++;
+                    cursor[q]++;
+                }
+            }
+        }
+    }
+    free(cursor);
+    layout_free(&L);
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------------- */

@@ -21,7 +21,9 @@ struct nomad_ctx {
     int32_t cus = 0, max_lds = 0;
     hipStream_t stream = nullptr;
     Plan plan;
-    float *W = nullptr, *H = nullptr;  // m x kp, n x kp (row stride kp, padding kept at 0)
+    void *W = nullptr;                 // m x kp, FP32 or bfloat16 (row stride kp, padding kept at 0)
+    float *H = nullptr;                // n x kp FP32
+    int32_t wbytes = 4;                // bytes per stored element of W
     uint32_t *tok_done = nullptr;      // n item counters + 1 abort word
     float *dummy = nullptr;            // target of the workers' placeholder stores
     int32_t *diag = nullptr;           // 8 words describing a wait that ran out of time
@@ -130,9 +132,12 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     if (!d_W0 || !d_H0) return fail(nullptr, NOMAD_EINVAL, "nomad_init: initial factors are NULL");
     if (cfg->sched != NOMAD_SCHED_RING)
         return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init: schedule %d is not provided by this build", cfg->sched);
-    if (cfg->dtype != NOMAD_FP32)
-        return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init: storage type %d is not provided by this build",
+    if (cfg->dtype != NOMAD_FP32 && cfg->dtype != NOMAD_BF16)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: storage type %d is not one of NOMAD_FP32, NOMAD_BF16",
                     cfg->dtype);
+    if (cfg->rounding != NOMAD_ROUND_RNE && cfg->rounding != NOMAD_ROUND_STOCHASTIC)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: rounding %d is not one of NOMAD_ROUND_RNE, "
+                    "NOMAD_ROUND_STOCHASTIC", cfg->rounding);
 
     nomad_ctx *c = new (std::nothrow) nomad_ctx();
     if (!c) return fail(nullptr, NOMAD_ENOMEM, "nomad_init: host allocation failed");
@@ -142,6 +147,7 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     c->nnz = nnz;
     c->k = cfg->k;
     c->kp = nomad::padded_k(cfg->k);
+    c->wbytes = cfg->dtype == NOMAD_BF16 ? 2 : 4;
     c->stream = (hipStream_t)hip_stream;
 
     auto bail = [&](nomad_status st) {
@@ -168,7 +174,9 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     int32_t slots = cfg->item_slots;
     int32_t window = cfg->window <= 0 ? nomad::kMaxWindow : (cfg->window <= 8 ? 8 : (cfg->window <= 16 ? 16 : 32));
     const bool auto_window = cfg->window <= 0;
-    auto fits = [&](int32_t s_, int32_t w_) { return nomad::train_lds_bytes(c->kp, nw, s_, w_) <= (size_t)max_lds; };
+    auto fits = [&](int32_t s_, int32_t w_) {
+        return nomad::train_lds_bytes(c->kp, nw, s_, w_, c->wbytes) <= (size_t)max_lds;
+    };
     if (slots <= 0) {
         slots = nomad::kMaxItemSlots;
         while (!fits(slots, window)) {
@@ -185,12 +193,12 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     if (slots < 1 || slots > nomad::kMaxItemSlots || (slots & (slots - 1)) != 0)
         return bail(fail(c, NOMAD_EINVAL, "nomad_init: item_slots=%d must be a power of two in [1,%d]", slots,
                          nomad::kMaxItemSlots));
-    const size_t lds = nomad::train_lds_bytes(c->kp, nw, slots, window);
+    const size_t lds = nomad::train_lds_bytes(c->kp, nw, slots, window, c->wbytes);
     if (lds > (size_t)max_lds)
         return bail(fail(c, NOMAD_EINVAL, "nomad_init: %d compute waves, %d item slots and a window of %d rows need "
                          "%zu bytes of LDS for k=%d, device allows %d", nw, slots, window, lds, c->k, max_lds));
     int32_t maxw = 0;
-    hipError_t he = nomad::train_max_workers(c->kp, nw, slots, window, &maxw);
+    hipError_t he = nomad::train_max_workers(c->kp, nw, slots, window, c->wbytes, &maxw);
     if (he != hipSuccess) return bail(hip_fail(c, he, "nomad_init: occupancy query"));
     int32_t p = cfg->workers;
     if (p <= 0) p = maxw < cus ? maxw : cus;
@@ -211,7 +219,7 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     c->cfg.item_slots = slots;
 
     hipError_t e;
-    if ((e = hipMalloc(&c->W, sizeof(float) * (size_t)m * c->kp)) != hipSuccess)
+    if ((e = hipMalloc(&c->W, (size_t)c->wbytes * (size_t)m * c->kp)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: W"));
     if ((e = hipMalloc(&c->H, sizeof(float) * (size_t)n * c->kp)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: H"));
@@ -229,12 +237,14 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: events"));
     hipStream_t st = c->stream;
-    if ((e = hipMemsetAsync(c->W, 0, sizeof(float) * (size_t)m * c->kp, st)) != hipSuccess ||
+    if ((e = hipMemsetAsync(c->W, 0, (size_t)c->wbytes * (size_t)m * c->kp, st)) != hipSuccess ||
         (e = hipMemsetAsync(c->H, 0, sizeof(float) * (size_t)n * c->kp, st)) != hipSuccess ||
         (e = hipMemsetAsync(c->tok_done, 0, sizeof(uint32_t) * (size_t)(n + 1), st)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: clear"));
-    if ((e = hipMemcpy2DAsync(c->W, sizeof(float) * c->kp, d_W0, sizeof(float) * c->k, sizeof(float) * c->k, m,
-                              hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+    if ((e = c->wbytes == 2
+                 ? nomad::to_bf16(d_W0, c->k, (uint16_t *)c->W, c->kp, m, st)
+                 : hipMemcpy2DAsync(c->W, sizeof(float) * c->kp, d_W0, sizeof(float) * c->k, sizeof(float) * c->k, m,
+                                    hipMemcpyDeviceToDevice, st)) != hipSuccess ||
         (e = hipMemcpy2DAsync(c->H, sizeof(float) * c->kp, d_H0, sizeof(float) * c->k, sizeof(float) * c->k, n,
                               hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: copy initial factors"));
@@ -285,6 +295,9 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         a.dummy = c->dummy;
         a.diag = c->diag;
         a.kp = c->kp;
+        a.wbytes = c->wbytes;
+        a.rounding = c->cfg.rounding == NOMAD_ROUND_STOCHASTIC ? 1 : 0;
+        a.sr_seed = (uint32_t)c->cfg.seed;
         a.p = c->p;
         a.nw = c->nw;
         a.slots = c->slots;
@@ -369,7 +382,7 @@ nomad_status nomad_eval_rmse(nomad_ctx *c, int64_t nnz, const int32_t *d_row, co
     double sq = 0.0, obj = 0.0;
     int bad = 0;
     if (nnz > 0) {
-        HIPTRY(c, nomad::eval_sums(c->W, c->H, c->k, c->kp, c->m, c->n, nnz, d_row, d_col, d_val, c->cfg.lambda, &sq,
+        HIPTRY(c, nomad::eval_sums(c->W, c->wbytes, c->H, c->k, c->kp, c->m, c->n, nnz, d_row, d_col, d_val, c->cfg.lambda, &sq,
                                    &obj, &bad, c->eval_scratch, c->eval_scratch_bytes, c->stream),
                "eval");
         if (bad) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: rating index out of range");
@@ -382,9 +395,12 @@ nomad_status nomad_eval_rmse(nomad_ctx *c, int64_t nnz, const int32_t *d_row, co
 nomad_status nomad_get_factors(nomad_ctx *c, float *d_W, float *d_H) {
     if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_factors: NULL context");
     if (!d_W || !d_H) return fail(c, NOMAD_EINVAL, "nomad_get_factors: NULL output");
-    HIPTRY(c, hipMemcpy2DAsync(d_W, sizeof(float) * c->k, c->W, sizeof(float) * c->kp, sizeof(float) * c->k, c->m,
-                               hipMemcpyDeviceToDevice, c->stream),
-           "get_factors");
+    if (c->wbytes == 2)
+        HIPTRY(c, nomad::from_bf16((const uint16_t *)c->W, c->kp, d_W, c->k, c->m, c->stream), "get_factors");
+    else
+        HIPTRY(c, hipMemcpy2DAsync(d_W, sizeof(float) * c->k, c->W, sizeof(float) * c->kp, sizeof(float) * c->k, c->m,
+                                   hipMemcpyDeviceToDevice, c->stream),
+               "get_factors");
     HIPTRY(c, hipMemcpy2DAsync(d_H, sizeof(float) * c->k, c->H, sizeof(float) * c->kp, sizeof(float) * c->k, c->n,
                                hipMemcpyDeviceToDevice, c->stream),
            "get_factors");

@@ -26,7 +26,13 @@ __device__ __forceinline__ Comp neu_merge(Comp a, Comp b) {
     return a;
 }
 
-__global__ __launch_bounds__(kThreads) void k_eval_partial(const float *W, const float *H, int32_t k,
+// Element l of row i of W stored as FP32 (wbytes 4) or bfloat16 (wbytes 2).
+__device__ __forceinline__ double w_at(const void *W, int32_t wbytes, int64_t x) {
+    if (wbytes == 2) return (double)__uint_as_float((uint32_t)((const uint16_t *)W)[x] << 16);
+    return (double)((const float *)W)[x];
+}
+
+__global__ __launch_bounds__(kThreads) void k_eval_partial(const void *W, int32_t wbytes, const float *H, int32_t k,
                                                           int32_t kp, int64_t m, int64_t n, int64_t nnz,
                                                           const int32_t *row, const int32_t *col,
                                                           const float *val, double lambda, Comp *part,
@@ -40,11 +46,11 @@ __global__ __launch_bounds__(kThreads) void k_eval_partial(const float *W, const
             atomicOr(bad, 1);
             continue;
         }
-        const float *w = W + (int64_t)i * kp;
+        const int64_t wi = (int64_t)i * kp;
         const float *h = H + (int64_t)j * kp;
         double d = 0.0, ww = 0.0, hh = 0.0;
         for (int32_t l = 0; l < k; ++l) {
-            const double wl = (double)w[l], hl = (double)h[l];
+            const double wl = w_at(W, wbytes, wi + l), hl = (double)h[l];
             d += wl * hl;
             ww += wl * wl;
             hh += hl * hl;
@@ -92,11 +98,42 @@ __global__ __launch_bounds__(kThreads) void k_eval_final(const Comp *part, int n
     }
 }
 
+// FP32 rows of width k -> bfloat16 rows of width kp (nearest-even; the pad is left alone).
+__global__ void k_to_bf16(const float *src, int32_t k, uint16_t *dst, int32_t kp, int64_t rows) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < rows * k; x += stride) {
+        const int64_t i = x / k, l = x - i * k;
+        const uint32_t u = __float_as_uint(src[x]);
+        dst[i * kp + l] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    }
+}
+
+// bfloat16 rows of width kp -> FP32 rows of width k (exact).
+__global__ void k_from_bf16(const uint16_t *src, int32_t kp, float *dst, int32_t k, int64_t rows) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < rows * k; x += stride) {
+        const int64_t i = x / k, l = x - i * k;
+        dst[x] = __uint_as_float((uint32_t)src[i * kp + l] << 16);
+    }
+}
+
 }  // namespace
+
+hipError_t to_bf16(const float *src, int32_t k, uint16_t *dst, int32_t kp, int64_t rows, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_bf16, dim3(2048), dim3(256), 0, st, src, k, dst, kp, rows);
+    return hipGetLastError();
+}
+
+hipError_t from_bf16(const uint16_t *src, int32_t kp, float *dst, int32_t k, int64_t rows, hipStream_t st) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_from_bf16, dim3(2048), dim3(256), 0, st, src, kp, dst, k, rows);
+    return hipGetLastError();
+}
 
 size_t eval_scratch_bytes() { return sizeof(Comp) * 2 * kBlocks + 2 * sizeof(double) + 64; }
 
-hipError_t eval_sums(const float *W, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,
+hipError_t eval_sums(const void *W, int32_t wbytes, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,
                      int64_t nnz, const int32_t *row, const int32_t *col, const float *val,
                      double lambda, double *h_sq_err, double *h_obj, int *h_bad_index, void *scratch,
                      size_t scratch_bytes, hipStream_t st) {
@@ -106,7 +143,7 @@ hipError_t eval_sums(const float *W, const float *H, int32_t k, int32_t kp, int6
     int32_t *bad = (int32_t *)(out + 2);
     hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_eval_partial, dim3(kBlocks), dim3(kThreads), 0, st, W, H, k, kp, m, n, nnz, row,
+    hipLaunchKernelGGL(k_eval_partial, dim3(kBlocks), dim3(kThreads), 0, st, W, wbytes, H, k, kp, m, n, nnz, row,
                        col, val, lambda, part, bad);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_eval_final, dim3(1), dim3(kThreads), 0, st, part, kBlocks, out);

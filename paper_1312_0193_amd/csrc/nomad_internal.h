@@ -109,7 +109,7 @@ struct Plan {
 // Arguments of the training kernel.
 struct TrainArgs {
     int64_t m, n;
-    float *W;                   // m x kp
+    void *W;                    // m x kp, FP32 or bfloat16 (wbytes per element)
     float *H;                   // n x kp
     const RatingRec *recs;
     const int64_t *rbase;
@@ -120,6 +120,9 @@ struct TrainArgs {
     float *dummy;               // p x kMaxWaves words: target of placeholder stores
     int32_t *diag;              // 8 words: the first wait that ran out of time (see train.hip)
     int32_t kp;
+    int32_t wbytes;             // 4: W in FP32; 2: W in bfloat16
+    int32_t rounding;           // bfloat16 stores: 0 nearest-even, 1 stochastic
+    uint32_t sr_seed;           // stochastic rounding: seed of the counter hash
     int32_t p;                  // workers
     int32_t nw;                 // compute waves per worker
     int32_t slots;              // item slots per worker (<= 64)
@@ -144,18 +147,22 @@ hipError_t build_plan(Plan *plan, int64_t m, int64_t n, int64_t nnz, const int32
 void free_plan(Plan *plan);
 
 // train.hip
-size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window);
+size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes);
 hipError_t launch_train(const TrainArgs &a, hipStream_t stream);
 // Workers of `nw` compute waves that can be resident at once on the device.
-hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t *max_workers);
+hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
+                             int32_t *max_workers);
 // Row stride of the factors for k: a whole number of 16-byte pieces per lane of a wave.
 inline int32_t padded_k(int32_t k) { return k <= 64 ? 64 : (k <= 128 ? 128 : 256); }
 
 // eval.hip: FP64 RMSE / objective with a deterministic compensated sum.
-hipError_t eval_sums(const float *W, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,
+hipError_t eval_sums(const void *W, int32_t wbytes, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,
                      int64_t nnz, const int32_t *row, const int32_t *col, const float *val,
                      double lambda, double *h_sq_err, double *h_obj, int *h_bad_index,
                      void *scratch, size_t scratch_bytes, hipStream_t stream);
+// FP32 rows (width k) to bfloat16 rows (width kp; nearest-even), and back (exact).
+hipError_t to_bf16(const float *src, int32_t k, uint16_t *dst, int32_t kp, int64_t rows, hipStream_t st);
+hipError_t from_bf16(const uint16_t *src, int32_t kp, float *dst, int32_t k, int64_t rows, hipStream_t st);
 size_t eval_scratch_bytes();
 
 }  // namespace nomad

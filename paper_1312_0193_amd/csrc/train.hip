@@ -150,26 +150,29 @@ constexpr int kRecRing = 3;     // batches a compute wave holds
 
 struct Lds {
     float *items;     // slots x kp
-    float *rows;      // nw x (D + 1) x kp: row slots of every compute wave
+    char *rows;       // nw x (D + 1) x kp elements of W's storage type: row slots of every compute wave
     RatingRec *recs;  // nw x kRecRing x kRecBatch: staged records of every compute wave
+    int32_t *item;    // kMaxItemSlots: the item in each slot
     int32_t *flag;    // nw: 1 + the last visit each compute wave finished
     int32_t *ctl;     // [0] visits loaded, [1] stop
 };
 
-__host__ __device__ inline size_t lds_bytes(int kp, int nw, int slots, int window) {
-    return ((size_t)slots * kp + (size_t)nw * (window + 1) * kp) * sizeof(float) +
-           (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec) + (kMaxWaves + 1 + 4) * 4;
+__host__ __device__ inline size_t lds_bytes(int kp, int nw, int slots, int window, int wbytes) {
+    return (size_t)slots * kp * sizeof(float) + (size_t)nw * (window + 1) * kp * wbytes +
+           (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec) + (kMaxItemSlots + kMaxWaves + 1 + 4) * 4;
 }
 
-__device__ __forceinline__ Lds lds_layout(void *base, int kp, int nw, int slots, int window) {
+__device__ __forceinline__ Lds lds_layout(void *base, int kp, int nw, int slots, int window, int wbytes) {
     char *p = (char *)base;
     Lds L;
     L.items = (float *)p;
     p += (size_t)slots * kp * sizeof(float);
-    L.rows = (float *)p;
-    p += (size_t)nw * (window + 1) * kp * sizeof(float);
+    L.rows = p;
+    p += (size_t)nw * (window + 1) * kp * wbytes;
     L.recs = (RatingRec *)p;
     p += (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec);
+    L.item = (int32_t *)p;
+    p += kMaxItemSlots * 4;
     L.flag = (int32_t *)p;
     p += (kMaxWaves + 1) * 4;
     L.ctl = (int32_t *)p;
@@ -321,37 +324,139 @@ __device__ __forceinline__ void dma4(const void *src, uint32_t lds_) {
 typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) u32x4v lds_u32x4;
 typedef uint32_t u32x2v __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(3))) u32x2v lds_u32x2;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) char lds_char;
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
 
-template <int VEC, int D>
+// Integer hash "lowbias32" (C. Wellons, hash-prospector): the counter-based generator of
+// the stochastic rounding bits.
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+// VEC elements of a row in W's storage type (FP32, or bfloat16 = the upper half of an
+// FP32) to and from FP32 registers, in LDS and in global memory.  The bfloat16 values
+// stored are exactly the registers' values (rounded before).
+template <int VEC, bool BF>
+__device__ __forceinline__ void row_lload(const lds_char *p, float (&v)[VEC]) {
+    if constexpr (!BF) {
+        lload<VEC>((const lds_float *)p, v);
+    } else if constexpr (VEC == 1) {
+        v[0] = __uint_as_float((uint32_t)*(const lds_u16 *)p << 16);
+    } else if constexpr (VEC == 2) {
+        const uint32_t t = *(const lds_u32 *)p;
+        v[0] = __uint_as_float(t << 16);
+        v[1] = __uint_as_float(t & 0xFFFF0000u);
+    } else {
+        const u32x2v t = *(const lds_u32x2 *)p;
+        v[0] = __uint_as_float(t.x << 16);
+        v[1] = __uint_as_float(t.x & 0xFFFF0000u);
+        v[2] = __uint_as_float(t.y << 16);
+        v[3] = __uint_as_float(t.y & 0xFFFF0000u);
+    }
+}
+template <int VEC>
+__device__ __forceinline__ uint32_t bf_pair(const float (&v)[VEC], int i) {
+    return (__float_as_uint(v[i]) >> 16) | (__float_as_uint(v[i + 1]) & 0xFFFF0000u);
+}
+template <int VEC, bool BF>
+__device__ __forceinline__ void row_lstore(lds_char *p, const float (&v)[VEC]) {
+    if constexpr (!BF) {
+        lstore<VEC>((lds_float *)p, v);
+    } else if constexpr (VEC == 1) {
+        *(lds_u16 *)p = (uint16_t)(__float_as_uint(v[0]) >> 16);
+    } else if constexpr (VEC == 2) {
+        *(lds_u32 *)p = bf_pair<VEC>(v, 0);
+    } else {
+        *(lds_u32x2 *)p = u32x2v{bf_pair<VEC>(v, 0), bf_pair<VEC>(v, 2)};
+    }
+}
+template <int VEC, bool BF>
+__device__ __forceinline__ void row_gstore(char *p, const float (&v)[VEC]) {
+    if constexpr (!BF) {
+        vstore<VEC>((float *)p, v);
+    } else if constexpr (VEC == 1) {
+        *(uint16_t *)p = (uint16_t)(__float_as_uint(v[0]) >> 16);
+    } else if constexpr (VEC == 2) {
+        *(uint32_t *)p = bf_pair<VEC>(v, 0);
+    } else {
+        *(uint2 *)p = make_uint2(bf_pair<VEC>(v, 0), bf_pair<VEC>(v, 2));
+    }
+}
+
+template <int VEC, int D, bool BF>
 struct ComputeWave {
     static_assert(2 * (D - 2) <= 63 && D >= 4, "vmcnt range");
+    static constexpr int ES = BF ? 2 : 4;  // bytes per stored element of W
     const TrainArgs &a;
     const Lds &L;
     const int q, w, lane, kp;
     const int loff;           // first element of the lane
+    const int rb;             // bytes of a stored row
     const RatingRec *rs;      // the wave's stream
     const int64_t cnt;        // ratings per epoch
     const int64_t total;      // ratings of the launch
-    lds_float *const rows;    // D + 1 row slots (the last one takes loads that are not used)
+    lds_char *const rows;     // D + 1 row slots (the last one takes loads that are not used), at the lane's elements
     const uint32_t rows_lds;
     const uint32_t recs_lds;  // record ring: kRecRing x kRecBatch records
     lds_float *const items;
     const uint64_t row_mask;  // lanes that load a row (16 bytes each)
+    char *const wlane;        // W at the lane's elements of row 0
     int64_t bpos = 0;         // stream position of the next record batch
     int bent = 0;             // ring entry of the next record batch
     uint64_t forwarded = 0, t_wait = 0;
 
     __device__ ComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0, int64_t cnt_)
-        : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC),
+        : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC), rb(a_.kp * ES),
           rs(a_.recs + r0), cnt(cnt_), total(cnt_ * a_.epochs),
-          rows(to_lds(L_.rows) + (size_t)w_ * (D + 1) * a_.kp + lane_ * VEC),
-          rows_lds(lds_off(L_.rows) + (uint32_t)(w_ * (D + 1) * a_.kp * 4)),
+          rows((lds_char *)L_.rows + (size_t)w_ * (D + 1) * a_.kp * ES + lane_ * VEC * ES),
+          rows_lds(lds_off(L_.rows) + (uint32_t)(w_ * (D + 1) * a_.kp * ES)),
           recs_lds(lds_off(L_.recs) + (uint32_t)(w_ * kRecRing * kRecBatch * (int)sizeof(RatingRec))),
           items(to_lds(L_.items) + lane_ * VEC),
-          row_mask((a_.kp >> 2) >= 64 ? ~0ull : ((1ull << (a_.kp >> 2)) - 1ull)) {}
+          row_mask((a_.kp * ES / 16) >= 64 ? ~0ull : ((1ull << (a_.kp * ES / 16)) - 1ull)),
+          wlane((char *)a_.W + lane_ * VEC * ES) {}
 
     __device__ __forceinline__ void load_row(int row, int slot) {
-        dma16s(a.W + (int64_t)row * kp, (uint32_t)(lane & 63) * 16u, rows_lds + (uint32_t)(slot * kp * 4), row_mask);
+        dma16s((const char *)a.W + (int64_t)row * rb, (uint32_t)(lane & 63) * 16u, rows_lds + (uint32_t)(slot * rb),
+               row_mask);
+    }
+    // The stored form of an updated row: bfloat16 rounding of the FP32 result, nearest-even
+    // (the hardware conversion, two elements per instruction) or stochastic: the low 16 bits
+    // plus random bits, truncated; the bits of element l come from the half (l mod 2) of a
+    // hash of (key of the rating, l / 2), the key hashing (seed, row, item, epoch).
+    __device__ __forceinline__ void round_row(float (&v)[VEC], int row, int item, int t) const {
+        if constexpr (BF) {
+            if (a.rounding == 0) {
+                if constexpr (VEC == 1) {
+                    v[0] = (float)(__bf16)v[0];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < VEC; i += 2) {
+                        const uint32_t pk = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{v[i], v[i + 1]}, bf16x2v));
+                        v[i] = __uint_as_float(pk << 16);
+                        v[i + 1] = __uint_as_float(pk & 0xFFFF0000u);
+                    }
+                }
+            } else {
+                const uint32_t key = a.sr_seed ^ ((uint32_t)row * 0x9E3779B1u) ^ ((uint32_t)item * 0x85EBCA77u) ^
+                                     ((uint32_t)t * 0xC2B2AE3Du);
+                const uint32_t c = lowbias32(key);
+                uint32_t word = 0;  // the hash word of the current pair of elements
+#pragma unroll
+                for (int i = 0; i < VEC; ++i) {
+                    const int l = loff + i;
+                    if (VEC == 1 || (i & 1) == 0) word = lowbias32(c + (uint32_t)(l >> 1));
+                    const uint32_t bits = (l & 1) ? (word >> 16) : (word & 0xFFFFu);
+                    v[i] = __uint_as_float((__float_as_uint(v[i]) + bits) & 0xFFFF0000u);
+                }
+            }
+        }
     }
     __device__ __forceinline__ void placeholder_store() {
         if (lane == 0) a.dummy[(int64_t)q * kMaxWaves + w] = 0.0f;
@@ -426,7 +531,7 @@ struct ComputeWave {
 #pragma unroll
         for (int v = 0; v < VEC; ++v) h[v] = nwp[v] = 0.0f;
         asm volatile("s_waitcnt vmcnt(%0)" ::"n"(2 * (D - 2)) : "memory");
-        lload<VEC>(rows, wn);
+        row_lload<VEC, BF>(rows, wn);
         const int nv = (int)(a.vbase[q + 1] - a.vbase[q]);
         int e = 0, xbase = 0;
         int64_t left = cnt;
@@ -436,6 +541,7 @@ struct ComputeWave {
         const float c_tab = a.step_c[lane < a.epochs ? lane : 0];
         float s = __shfl(s_tab, 0);
         float c = __shfl(c_tab, 0);
+        int item = 0;  // the item of the current visit (read with it, for the rounding hash)
         int64_t y = 0;
         for (; y < total; ++y) {
             const int u = (int)(y & (D - 1));
@@ -457,6 +563,7 @@ struct ComputeWave {
                 compiler_fence();
                 t_wait += tick(a.timing) - t0;
                 lload<VEC>(items + (size_t)slot * kp, h);
+                if constexpr (BF) item = __builtin_amdgcn_readfirstlane(L.item[slot]);
             }
             // Section 2.3: one residual, both vectors from their values before the update.
             float d = 0.0f;
@@ -465,7 +572,7 @@ struct ComputeWave {
             d = wave_sum<4>(d);
             // Reads for the next step: the row of rating y + 1 (its load completed in the
             // step before), the records of y + 2 and y + D + 1.
-            lload<VEC>(rows + ((u + 1) & (D - 1)) * kp, wn);
+            row_lload<VEC, BF>(rows + ((u + 1) & (D - 1)) * rb, wn);
             vn = rec_read(an);
             an = rec_next(an);
             vi = rec_read_rf(ai);
@@ -479,10 +586,11 @@ struct ComputeWave {
             }
             // Hand the row on to its next use inside the window (the very next rating takes
             // it in registers), and store it.
+            round_row(nw, rc.row, item, a.epoch0 + e);
             const int nxt = (int)(rc.fwd & 255u);
-            if (nxt > 1) lstore<VEC>(rows + ((u + nxt) & (D - 1)) * kp, nw);
+            if (nxt > 1) row_lstore<VEC, BF>(rows + ((u + nxt) & (D - 1)) * rb, nw);
             forwarded += nxt != 0;
-            vstore<VEC>(a.W + (int64_t)rc.row * kp + loff, nw);
+            row_gstore<VEC, BF>(wlane + (int64_t)rc.row * rb, nw);
             f1 = nxt == 1;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) nwp[v] = nw[v];
@@ -688,6 +796,7 @@ struct MemoryWave {
                         f_j = j;
                         f_lw = lw;
                         f_tk = tk;
+                        L.item[lane] = j;
                     }
                     if (a.trace) {
                         int64_t base = 0;
@@ -758,7 +867,10 @@ struct MemoryWave {
                     __hip_atomic_store(a.tok_done + pub_j, pub_tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 npub = 0;
             }
-            if (nl > 0 && lane == 0) sync_store(&L.ctl[0], Xl);
+            if (nl > 0) {
+                wait_lgkm();  // the slots' item ids are written before the visits are announced
+                if (lane == 0) sync_store(&L.ctl[0], Xl);
+            }
             if (progress) {
                 t_prog = wall_clock64();
             } else {
@@ -789,7 +901,7 @@ struct MemoryWave {
     }
 };
 
-template <int VEC, int D>
+template <int VEC, int D, bool BF>
 __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
     extern __shared__ float4 lds4[];
     // The wave index is the same in every lane: say so, so that everything derived from it
@@ -797,14 +909,14 @@ __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int q = blockIdx.x;
-    const Lds L = lds_layout(lds4, a.kp, a.nw, a.slots, D);
+    const Lds L = lds_layout(lds4, a.kp, a.nw, a.slots, D, BF ? 2 : 4);
     if (threadIdx.x < kMaxWaves + 1) L.flag[threadIdx.x] = 0;
     if (threadIdx.x < 2) L.ctl[threadIdx.x] = 0;
     __syncthreads();
     if (q >= a.p || a.epochs <= 0) return;
     if (wave < a.nw) {
         const int64_t i0 = a.rbase[(int64_t)q * a.nw + wave], i1 = a.rbase[(int64_t)q * a.nw + wave + 1];
-        ComputeWave<VEC, D> cw(a, L, q, wave, lane, i0, i1 - i0);
+        ComputeWave<VEC, D, BF> cw(a, L, q, wave, lane, i0, i1 - i0);
         cw.run();
     } else if (wave == a.nw) {
         MemoryWave mw(a, L, q, lane);
@@ -812,56 +924,64 @@ __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
     }
 }
 
-template <int VEC, int D>
+template <int VEC, int D, bool BF>
 hipError_t launch_t(const TrainArgs &a, hipStream_t st) {
-    const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D);
-    hipLaunchKernelGGL((k_worker<VEC, D>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D, BF ? 2 : 4);
+    hipLaunchKernelGGL((k_worker<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
     return hipGetLastError();
 }
 
-template <int VEC>
+template <int VEC, bool BF>
 const void *pick_d(int window) {
-    if (window <= 8) return (const void *)k_worker<VEC, 8>;
-    if (window <= 16) return (const void *)k_worker<VEC, 16>;
-    return (const void *)k_worker<VEC, 32>;
+    if (window <= 8) return (const void *)k_worker<VEC, 8, BF>;
+    if (window <= 16) return (const void *)k_worker<VEC, 16, BF>;
+    return (const void *)k_worker<VEC, 32, BF>;
 }
 
+template <bool BF>
 const void *pick_kernel(int kp, int window) {
-    if (kp <= 64) return pick_d<1>(window);
-    if (kp <= 128) return pick_d<2>(window);
-    return pick_d<4>(window);
+    if (kp <= 64) return pick_d<1, BF>(window);
+    if (kp <= 128) return pick_d<2, BF>(window);
+    return pick_d<4, BF>(window);
 }
 
-template <int VEC>
+template <int VEC, bool BF>
 hipError_t launch_v(const TrainArgs &a, hipStream_t st) {
-    if (a.window <= 8) return launch_t<VEC, 8>(a, st);
-    if (a.window <= 16) return launch_t<VEC, 16>(a, st);
-    return launch_t<VEC, 32>(a, st);
+    if (a.window <= 8) return launch_t<VEC, 8, BF>(a, st);
+    if (a.window <= 16) return launch_t<VEC, 16, BF>(a, st);
+    return launch_t<VEC, 32, BF>(a, st);
+}
+
+template <bool BF>
+hipError_t launch_b(const TrainArgs &a, hipStream_t st) {
+    if (a.kp <= 64) return launch_v<1, BF>(a, st);
+    if (a.kp <= 128) return launch_v<2, BF>(a, st);
+    return launch_v<4, BF>(a, st);
 }
 
 }  // namespace
 
-size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window) {
-    return lds_bytes(kp, nw, slots, window);
+size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes) {
+    return lds_bytes(kp, nw, slots, window, wbytes);
 }
 
-hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t *max_workers) {
+hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
+                             int32_t *max_workers) {
     int dev = 0, cus = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pick_kernel(kp, window), 64 * (nw + 1),
-                                                     lds_bytes(kp, nw, slots, window));
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &nb, wbytes == 2 ? pick_kernel<true>(kp, window) : pick_kernel<false>(kp, window), 64 * (nw + 1),
+        lds_bytes(kp, nw, slots, window, wbytes));
     if (e != hipSuccess) return e;
     *max_workers = nb * cus;
     return hipSuccess;
 }
 
 hipError_t launch_train(const TrainArgs &a, hipStream_t st) {
-    if (a.kp <= 64) return launch_v<1>(a, st);
-    if (a.kp <= 128) return launch_v<2>(a, st);
-    return launch_v<4>(a, st);
+    return a.wbytes == 2 ? launch_b<true>(a, st) : launch_b<false>(a, st);
 }
 
 }  // namespace nomad
