@@ -159,7 +159,38 @@ nomad_status nomad_get_trace(nomad_ctx *ctx, int64_t *len, int32_t *h_buf, int64
  *   10..15 zero */
 nomad_status nomad_get_worker_stats(nomad_ctx *ctx, int64_t *h_stats, int64_t cap);
 
-/* Free every resource of the context.  NULL is ignored. */
+/* One problem of a batch (nomad_init_batched): the arguments of nomad_init that differ
+ * between problems.  Arrays as in nomad_init (device, caller-owned, read during the call). */
+typedef struct {
+    int64_t m, n, nnz;
+    const int32_t *d_row, *d_col;
+    const float *d_val;
+    const float *d_W0, *d_H0;  /* m x k and n x k FP32, row-major */
+    int32_t k;                 /* 1..256; the batch stores every problem at the largest padded k */
+    float lambda, alpha, beta, gamma;
+} nomad_problem_desc;
+
+/* Several independent problems trained together: every nomad_train_epochs call on the
+ * returned batch context runs all of them, each in its own ring order (section 3.1,
+ * Algorithm 1) exactly as it would alone with the same worker count, in one launch.
+ * `common` gives the fields the problems share (schedule, storage type, rounding, waves,
+ * item slots, window, seed, collect_stats); its k, lambda, alpha, beta and gamma are ignored
+ * and its `workers` is the total (0 = as many as can be resident; window 0 means 8 here,
+ * which lets more workers share a compute unit).  Problem b gets
+ * max(1, about workers * nnz_b / sum nnz) workers (largest remainders).  EINVAL if a
+ * problem is invalid (the message names it) or there are more problems than workers;
+ * ENOTIMPL with record_trace.  Problems are read back through nomad_batch_problem. */
+nomad_status nomad_init_batched(nomad_ctx **out, int32_t nprob, const nomad_problem_desc *descs,
+                                const nomad_config *common, void *hip_stream);
+
+/* The context of problem b of a batch, for nomad_eval_rmse, nomad_get_factors,
+ * nomad_get_partition and nomad_get_worker_stats (owned by the batch: nomad_destroy on it
+ * does nothing, nomad_train_epochs on it is ESTATE).  Those calls on the batch itself are
+ * ESTATE.  Callers that keep it must not use it after the batch is destroyed. */
+nomad_status nomad_batch_problem(nomad_ctx *batch, int32_t b, nomad_ctx **problem);
+
+/* Free every resource of the context (of a batch: of all its problems).  NULL, and a
+ * problem of a batch, are ignored. */
 void nomad_destroy(nomad_ctx *ctx);
 
 /* Message of the last failure on ctx, or of the last failure of the calling thread

@@ -31,6 +31,13 @@ class NomadConfig(C.Structure):
                 ("record_trace", C.c_int32), ("collect_stats", C.c_int32), ("seed", C.c_uint64)]
 
 
+class NomadProblemDesc(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64), ("d_row", C.c_void_p),
+                ("d_col", C.c_void_p), ("d_val", C.c_void_p), ("d_W0", C.c_void_p), ("d_H0", C.c_void_p),
+                ("k", C.c_int32), ("lambda_", C.c_float), ("alpha", C.c_float), ("beta", C.c_float),
+                ("gamma", C.c_float)]
+
+
 class NomadStats(C.Structure):
     _fields_ = [("seconds", C.c_double), ("updates", C.c_uint64), ("epochs_done", C.c_uint64),
                 ("layout_seconds", C.c_double)]
@@ -74,6 +81,10 @@ def load() -> C.CDLL:
     lib.nomad_get_trace.argtypes = [P, C.POINTER(i64), P, i64]
     lib.nomad_get_worker_stats.restype = C.c_int
     lib.nomad_get_worker_stats.argtypes = [P, P, i64]
+    lib.nomad_init_batched.restype = C.c_int
+    lib.nomad_init_batched.argtypes = [C.POINTER(P), i32, C.POINTER(NomadProblemDesc), C.POINTER(NomadConfig), P]
+    lib.nomad_batch_problem.restype = C.c_int
+    lib.nomad_batch_problem.argtypes = [P, i32, C.POINTER(P)]
     lib.nomad_destroy.restype = None
     lib.nomad_destroy.argtypes = [P]
     lib.nomad_last_error.restype = C.c_char_p
@@ -223,7 +234,8 @@ class Nomad:
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
-            load().nomad_destroy(self.ctx)
+            if getattr(self, "_owned", True):
+                load().nomad_destroy(self.ctx)
             self.ctx = None
 
     def __del__(self):
@@ -237,3 +249,57 @@ class Nomad:
 
     def __exit__(self, *a):
         self.close()
+
+
+class NomadBatch:
+    """Several independent problems trained together by one launch per call (wraps a batch
+    nomad_ctx).  `problems`: dicts with m, n, row, col, val, W0, H0, k, lam, alpha, beta,
+    gamma; keyword arguments are the shared configuration (workers = total)."""
+
+    def __init__(self, problems, **kw):
+        lib = load()
+        self.cfg = make_config(1, 0.0, 0.0, 0.0, 0.0, **kw)
+        self._keep = []
+        descs = (NomadProblemDesc * len(problems))()
+        for d, pr in zip(descs, problems):
+            row, col, val = _dev_i32(pr["row"]), _dev_i32(pr["col"]), _dev_f32(pr["val"])
+            W0, H0 = _dev_f32(pr["W0"]), _dev_f32(pr["H0"])
+            k = int(pr["k"])
+            if tuple(W0.shape) != (int(pr["m"]), k) or tuple(H0.shape) != (int(pr["n"]), k):
+                raise ValueError("W0 must be m x k and H0 n x k")
+            self._keep += [row, col, val, W0, H0]
+            d.m, d.n, d.nnz = int(pr["m"]), int(pr["n"]), int(row.numel())
+            d.d_row, d.d_col, d.d_val, d.d_W0, d.d_H0 = _ptr(row), _ptr(col), _ptr(val), _ptr(W0), _ptr(H0)
+            d.k, d.lambda_, d.alpha, d.beta, d.gamma = k, pr["lam"], pr["alpha"], pr["beta"], pr["gamma"]
+        ctx = C.c_void_p()
+        _check(lib.nomad_init_batched(C.byref(ctx), len(problems), descs, C.byref(self.cfg), _stream_handle()))
+        self._keep = []  # the inputs are copied by the call
+        self.ctx = ctx
+        self.problems = []
+        for b, pr in enumerate(problems):
+            sub = C.c_void_p()
+            _check(lib.nomad_batch_problem(self.ctx, b, C.byref(sub)), self.ctx)
+            view = Nomad.__new__(Nomad)
+            view.m, view.n, view.k = int(pr["m"]), int(pr["n"]), int(pr["k"])
+            view.ctx, view._owned, view.nnz = sub, False, int(pr["row"].numel())
+            self.problems.append(view)
+
+    def train(self, epochs: int) -> Stats:
+        if self.ctx is None:
+            raise NomadError(NOMAD_ESTATE, "batch destroyed")
+        st = NomadStats()
+        _check(load().nomad_train_epochs(self.ctx, int(epochs), C.byref(st)), self.ctx)
+        return Stats(st.seconds, st.updates, st.epochs_done, st.layout_seconds)
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            for v in self.problems:
+                v.ctx = None
+            load().nomad_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

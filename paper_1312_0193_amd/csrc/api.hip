@@ -39,6 +39,15 @@ struct nomad_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double layout_seconds = 0.0;
     std::string err;
+    // A batch (nomad_init_batched): its problems, each a full context of its own, trained
+    // together by one launch.
+    std::vector<nomad_ctx *> members;
+    nomad_ctx *owner = nullptr;        // set in a problem of a batch
+    nomad::Shape shape{};
+    nomad::TrainArgs *d_descs = nullptr;  // per problem: its launch arguments
+    int32_t *d_wg = nullptr;           // per workgroup: its problem
+    std::vector<int32_t> wg0;          // per problem: its first workgroup
+    int32_t total_wg = 0;
 };
 
 namespace {
@@ -71,6 +80,13 @@ nomad_status hip_fail(nomad_ctx *ctx, hipError_t e, const char *what) {
 
 void release(nomad_ctx *c) {
     if (!c) return;
+    for (nomad_ctx *m : c->members) {
+        release(m);
+        delete m;
+    }
+    c->members.clear();
+    (void)hipFree(c->d_descs);
+    (void)hipFree(c->d_wg);
     nomad::free_plan(&c->plan);
     (void)hipFree(c->W);
     (void)hipFree(c->H);
@@ -83,6 +99,62 @@ void release(nomad_ctx *c) {
     (void)hipFree(c->eval_scratch);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+}
+
+// Launch shape: compute waves, item slots and row window of a worker (LDS-fitted as the
+// configuration asks), and how many workers can be resident at once.
+nomad_status choose_shape(const nomad_config *cfg, int32_t kp, int32_t wbytes, nomad::Shape *out, nomad_ctx *ec) {
+    // Workers, compute waves per worker and item slots.  By default one worker runs on
+    // every CU with eight compute waves, and holds up to 64 items (fewer if LDS is short).
+    int dev = 0, max_lds = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return fail(ec, NOMAD_EDEVICE, "nomad_init: no usable HIP device");
+    const int32_t nw = cfg->waves_per_worker > 0 ? cfg->waves_per_worker : nomad::kDefaultWaves;
+    if (nw < 1 || nw > nomad::kMaxWaves)
+        return fail(ec, NOMAD_EINVAL, "nomad_init: waves_per_worker=%d outside [1,%d]", nw, nomad::kMaxWaves);
+    if (cfg->window < 0 || cfg->window > nomad::kMaxWindow)
+        return fail(ec, NOMAD_EINVAL, "nomad_init: window=%d outside [0,%d]", cfg->window, nomad::kMaxWindow);
+    // Item slots and the compute waves' row windows share the LDS: by default deep windows
+    // come first, then item slots.
+    int32_t slots = cfg->item_slots;
+    int32_t window = cfg->window <= 0 ? nomad::kMaxWindow : (cfg->window <= 8 ? 8 : (cfg->window <= 16 ? 16 : 32));
+    const bool auto_window = cfg->window <= 0;
+    auto fits = [&](int32_t s_, int32_t w_) {
+        return nomad::train_lds_bytes(kp, nw, s_, w_, wbytes) <= (size_t)max_lds;
+    };
+    if (slots <= 0) {
+        slots = nomad::kMaxItemSlots;
+        while (!fits(slots, window)) {
+            if (slots > 32) slots >>= 1;
+            else if (auto_window && window > 16) window >>= 1;
+            else if (slots > 16) slots >>= 1;
+            else if (auto_window && window > 8) window >>= 1;
+            else if (slots > 8) slots >>= 1;
+            else break;
+        }
+    } else if (auto_window) {
+        while (!fits(slots, window) && window > 8) window >>= 1;
+    }
+    if (slots < 1 || slots > nomad::kMaxItemSlots || (slots & (slots - 1)) != 0)
+        return fail(ec, NOMAD_EINVAL, "nomad_init: item_slots=%d must be a power of two in [1,%d]", slots,
+                    nomad::kMaxItemSlots);
+    const size_t lds = nomad::train_lds_bytes(kp, nw, slots, window, wbytes);
+    if (lds > (size_t)max_lds)
+        return fail(ec, NOMAD_EINVAL, "nomad_init: %d compute waves, %d item slots and a window of %d rows need "
+                    "%zu bytes of LDS for padded k=%d, device allows %d", nw, slots, window, lds, kp, max_lds);
+    int32_t maxw = 0;
+    hipError_t he = nomad::train_max_workers(kp, nw, slots, window, wbytes, &maxw);
+    if (he != hipSuccess) return hip_fail(ec, he, "nomad_init: occupancy query");
+    out->kp = kp;
+    out->nw = nw;
+    out->slots = slots;
+    out->window = window;
+    out->maxw = maxw;
+    out->cus = cus;
+    out->max_lds = max_lds;
+    return NOMAD_OK;
 }
 
 }  // namespace
@@ -109,9 +181,10 @@ void nomad_config_default(nomad_config *cfg) {
     cfg->seed = 0;
 }
 
-nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int64_t n, int64_t nnz,
-                        const int32_t *d_row, const int32_t *d_col, const float *d_val, const float *d_W0,
-                        const float *d_H0, void *hip_stream) {
+// nomad_init with an optional launch shape imposed (the problems of a batch share one).
+static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t m, int64_t n, int64_t nnz,
+                              const int32_t *d_row, const int32_t *d_col, const float *d_val, const float *d_W0,
+                              const float *d_H0, void *hip_stream, const nomad::Shape *forced) {
     if (!out) return fail(nullptr, NOMAD_EINVAL, "nomad_init: out is NULL");
     *out = nullptr;
     if (!cfg) return fail(nullptr, NOMAD_EINVAL, "nomad_init: cfg is NULL");
@@ -146,7 +219,7 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     c->n = n;
     c->nnz = nnz;
     c->k = cfg->k;
-    c->kp = nomad::padded_k(cfg->k);
+    c->kp = forced ? forced->kp : nomad::padded_k(cfg->k);
     c->wbytes = cfg->dtype == NOMAD_BF16 ? 2 : 4;
     c->stream = (hipStream_t)hip_stream;
 
@@ -157,49 +230,14 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
         return st;
     };
 
-    // Workers, compute waves per worker and item slots.  By default one worker runs on
-    // every CU with eight compute waves, and holds up to 64 items (fewer if LDS is short).
-    int dev = 0, max_lds = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return bail(fail(c, NOMAD_EDEVICE, "nomad_init: no usable HIP device"));
-    const int32_t nw = cfg->waves_per_worker > 0 ? cfg->waves_per_worker : nomad::kDefaultWaves;
-    if (nw < 1 || nw > nomad::kMaxWaves)
-        return bail(fail(c, NOMAD_EINVAL, "nomad_init: waves_per_worker=%d outside [1,%d]", nw, nomad::kMaxWaves));
-    if (cfg->window < 0 || cfg->window > nomad::kMaxWindow)
-        return bail(fail(c, NOMAD_EINVAL, "nomad_init: window=%d outside [0,%d]", cfg->window, nomad::kMaxWindow));
-    // Item slots and the compute waves' row windows share the LDS: by default deep windows
-    // come first, then item slots.
-    int32_t slots = cfg->item_slots;
-    int32_t window = cfg->window <= 0 ? nomad::kMaxWindow : (cfg->window <= 8 ? 8 : (cfg->window <= 16 ? 16 : 32));
-    const bool auto_window = cfg->window <= 0;
-    auto fits = [&](int32_t s_, int32_t w_) {
-        return nomad::train_lds_bytes(c->kp, nw, s_, w_, c->wbytes) <= (size_t)max_lds;
-    };
-    if (slots <= 0) {
-        slots = nomad::kMaxItemSlots;
-        while (!fits(slots, window)) {
-            if (slots > 32) slots >>= 1;
-            else if (auto_window && window > 16) window >>= 1;
-            else if (slots > 16) slots >>= 1;
-            else if (auto_window && window > 8) window >>= 1;
-            else if (slots > 8) slots >>= 1;
-            else break;
-        }
-    } else if (auto_window) {
-        while (!fits(slots, window) && window > 8) window >>= 1;
+    nomad::Shape sh;
+    if (forced) {
+        sh = *forced;
+    } else {
+        const nomad_status ss = choose_shape(cfg, c->kp, c->wbytes, &sh, c);
+        if (ss != NOMAD_OK) return bail(ss);
     }
-    if (slots < 1 || slots > nomad::kMaxItemSlots || (slots & (slots - 1)) != 0)
-        return bail(fail(c, NOMAD_EINVAL, "nomad_init: item_slots=%d must be a power of two in [1,%d]", slots,
-                         nomad::kMaxItemSlots));
-    const size_t lds = nomad::train_lds_bytes(c->kp, nw, slots, window, c->wbytes);
-    if (lds > (size_t)max_lds)
-        return bail(fail(c, NOMAD_EINVAL, "nomad_init: %d compute waves, %d item slots and a window of %d rows need "
-                         "%zu bytes of LDS for k=%d, device allows %d", nw, slots, window, lds, c->k, max_lds));
-    int32_t maxw = 0;
-    hipError_t he = nomad::train_max_workers(c->kp, nw, slots, window, c->wbytes, &maxw);
-    if (he != hipSuccess) return bail(hip_fail(c, he, "nomad_init: occupancy query"));
+    const int32_t nw = sh.nw, slots = sh.slots, window = sh.window, maxw = sh.maxw, cus = sh.cus, max_lds = sh.max_lds;
     int32_t p = cfg->workers;
     if (p <= 0) p = maxw < cus ? maxw : cus;
     if (p < 1 || p > nomad::kMaxWorkers)
@@ -269,40 +307,141 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
     return NOMAD_OK;
 }
 
+nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int64_t n, int64_t nnz,
+                        const int32_t *d_row, const int32_t *d_col, const float *d_val, const float *d_W0,
+                        const float *d_H0, void *hip_stream) {
+    return init_impl(out, cfg, m, n, nnz, d_row, d_col, d_val, d_W0, d_H0, hip_stream, nullptr);
+}
+
+// Launch arguments of context c that do not depend on the call.
+static void fill_args(nomad_ctx *c, nomad::TrainArgs &a) {
+    a.m = c->m;
+    a.n = c->n;
+    a.W = c->W;
+    a.H = c->H;
+    a.recs = c->plan.recs;
+    a.rbase = c->plan.rbase;
+    a.visits = c->plan.visits;
+    a.vbase = c->plan.vbase;
+    a.tok_done = c->tok_done;
+    a.abort_flag = c->tok_done + c->n;
+    a.dummy = c->dummy;
+    a.diag = c->diag;
+    a.kp = c->kp;
+    a.wbytes = c->wbytes;
+    a.rounding = c->cfg.rounding == NOMAD_ROUND_STOCHASTIC ? 1 : 0;
+    a.sr_seed = (uint32_t)c->cfg.seed;
+    a.p = c->p;
+    a.nw = c->nw;
+    a.slots = c->slots;
+    a.window = c->window;
+    a.lambda = c->cfg.lambda;
+    a.alpha = c->cfg.alpha;
+    a.beta = c->cfg.beta;
+    a.gamma = c->cfg.gamma;
+    a.wstats = c->wstats;
+    a.timing = c->cfg.collect_stats != 0;
+}
+
+// Checks before a call of `epochs` epochs on context c.
+static nomad_status check_epochs(nomad_ctx *c, int32_t epochs, const char *who) {
+    if (c->epochs_done + epochs > (int64_t)INT32_MAX / 2)
+        return fail(c, NOMAD_EINVAL, "%s: epoch counter would overflow", who);
+    if ((int64_t)nomad::kMaxEpochsPerLaunch * c->plan.max_worker_visits >= (int64_t)INT32_MAX)
+        return fail(c, NOMAD_EINVAL, "%s: %lld visits per epoch on the busiest worker are too many", who,
+                    (long long)c->plan.max_worker_visits);
+    return NOMAD_OK;
+}
+
+// The abort word of context c after a launch: NOMAD_OK, or the failure it records.
+static nomad_status check_abort(nomad_ctx *c, const char *who) {
+    uint32_t aborted = 0;
+    HIPTRY(c, hipMemcpy(&aborted, c->tok_done + c->n, sizeof(uint32_t), hipMemcpyDeviceToHost), "train: flag");
+    if (aborted == 2)
+        return fail(c, NOMAD_EDEVICE, "%s: malformed layout detected; the factors are undefined", who);
+    if (aborted) {
+        int32_t d[8] = {0};
+        (void)hipMemcpy(d, c->diag, sizeof(d), hipMemcpyDeviceToHost);
+        return fail(c, NOMAD_EDEVICE, "%s: a worker waited beyond the time limit (worker %d, wave %d, %d %d %d %d "
+                    "%d %d); the factors are undefined", who, d[0] - 1, d[1], d[2], d[3], d[4], d[5], d[6], d[7]);
+    }
+    return NOMAD_OK;
+}
+
+// nomad_train_epochs of a batch: every problem runs `epochs` epochs, all in one launch per
+// kMaxEpochsPerLaunch epochs.
+static nomad_status train_batch(nomad_ctx *c, int32_t epochs, nomad_stats *out) {
+    for (nomad_ctx *m : c->members) {
+        const nomad_status st = check_epochs(m, epochs, "nomad_train_epochs");
+        if (st != NOMAD_OK) return fail(c, st, "%s", m->err.c_str());
+    }
+    hipStream_t st = c->stream;
+    double seconds = 0.0;
+    if (epochs > 0) {
+        const size_t np = c->members.size();
+        std::vector<nomad::TrainArgs> h(np);
+        for (nomad_ctx *m : c->members) {
+            HIPTRY(c, hipMemsetAsync(m->tok_done + m->n, 0, sizeof(uint32_t), st), "train: reset");
+            HIPTRY(c, hipMemsetAsync(m->diag, 0, sizeof(int32_t) * 8, st), "train: reset");
+            HIPTRY(c, hipMemsetAsync(m->wstats, 0, sizeof(int64_t) * nomad::kWStatCount * (size_t)m->p, st),
+                   "train: reset");
+        }
+        HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
+        for (int32_t done = 0; done < epochs;) {
+            const int32_t ne = std::min(epochs - done, (int32_t)nomad::kMaxEpochsPerLaunch);
+            for (size_t b = 0; b < np; ++b) {
+                nomad::TrainArgs a{};
+                fill_args(c->members[b], a);
+                a.epoch0 = (int32_t)(c->members[b]->epochs_done + done);
+                a.epochs = ne;
+                a.wg0 = c->wg0[b];
+                h[b] = a;
+            }
+            HIPTRY(c, hipMemcpyAsync(c->d_descs, h.data(), sizeof(nomad::TrainArgs) * np, hipMemcpyHostToDevice, st),
+                   "train: arguments");
+            HIPTRY(c, nomad::launch_train_batch(h[0], c->total_wg, c->d_descs, c->d_wg, st), "train: launch");
+            // the host arguments are rewritten by the next launch
+            HIPTRY(c, hipStreamSynchronize(st), "train: kernel");
+            done += ne;
+        }
+        HIPTRY(c, hipEventRecord(c->ev1, st), "train: event");
+        HIPTRY(c, hipEventSynchronize(c->ev1), "train: kernel");
+        float ms = 0.0f;
+        HIPTRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1), "train: timing");
+        seconds = ms * 1e-3;
+        for (size_t b = 0; b < np; ++b) {
+            const nomad_status ab = check_abort(c->members[b], "nomad_train_epochs");
+            if (ab != NOMAD_OK)
+                return fail(c, ab, "problem %zu of the batch: %s", b, c->members[b]->err.c_str());
+        }
+        for (nomad_ctx *m : c->members) m->epochs_done += epochs;
+        c->epochs_done += epochs;
+    }
+    if (out) {
+        memset(out, 0, sizeof(*out));
+        out->seconds = seconds;
+        out->updates = (uint64_t)c->nnz * (uint64_t)epochs;
+        out->epochs_done = (uint64_t)c->epochs_done;
+        out->layout_seconds = c->layout_seconds;
+    }
+    return NOMAD_OK;
+}
+
 nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) {
     if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_train_epochs: NULL context");
+    if (c->owner) return fail(c, NOMAD_ESTATE, "nomad_train_epochs: this problem belongs to a batch; train the batch");
     if (epochs < 0) return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epochs=%d < 0", epochs);
-    if (c->epochs_done + epochs > (int64_t)INT32_MAX / 2)
-        return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epoch counter would overflow");
-    if ((int64_t)nomad::kMaxEpochsPerLaunch * c->plan.max_worker_visits >= (int64_t)INT32_MAX)
-        return fail(c, NOMAD_EINVAL, "nomad_train_epochs: %lld visits per epoch on the busiest worker are too many",
-                    (long long)c->plan.max_worker_visits);
+    if (!c->members.empty()) return train_batch(c, epochs, out);
+    {
+        const nomad_status ce = check_epochs(c, epochs, "nomad_train_epochs");
+        if (ce != NOMAD_OK) return ce;
+    }
     if (out) memset(out, 0, sizeof(*out));
     hipStream_t st = c->stream;
     double seconds = 0.0;
     if (epochs > 0) {
         nomad::TrainArgs a{};
-        a.m = c->m;
-        a.n = c->n;
-        a.W = c->W;
-        a.H = c->H;
-        a.recs = c->plan.recs;
-        a.rbase = c->plan.rbase;
-        a.visits = c->plan.visits;
-        a.vbase = c->plan.vbase;
-        a.tok_done = c->tok_done;
-        a.abort_flag = c->tok_done + c->n;
-        a.dummy = c->dummy;
-        a.diag = c->diag;
-        a.kp = c->kp;
-        a.wbytes = c->wbytes;
-        a.rounding = c->cfg.rounding == NOMAD_ROUND_STOCHASTIC ? 1 : 0;
-        a.sr_seed = (uint32_t)c->cfg.seed;
-        a.p = c->p;
-        a.nw = c->nw;
-        a.slots = c->slots;
-        a.window = c->window;
-        a.lambda = c->cfg.lambda;
+        fill_args(c, a);
         if (c->cfg.record_trace) {
             const int64_t need = c->plan.nvisits * (int64_t)epochs;
             if (need > c->trace_cap) {
@@ -321,23 +460,13 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         HIPTRY(c, hipMemsetAsync(c->tok_done + c->n, 0, sizeof(uint32_t), st), "train: reset");
         HIPTRY(c, hipMemsetAsync(c->diag, 0, sizeof(int32_t) * 8, st), "train: reset");
         HIPTRY(c, hipMemsetAsync(c->wstats, 0, sizeof(int64_t) * nomad::kWStatCount * (size_t)c->p, st), "train: reset");
-        a.wstats = c->wstats;
-        a.timing = c->cfg.collect_stats != 0;
         HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
-        // Launches of at most kMaxEpochsPerLaunch epochs, each with its step sizes
-        // s_t = alpha / (1 + beta t^gamma), t = epochs done (every rating is updated once
-        // per epoch), eq. (stepsize_method).
+        // Launches of at most kMaxEpochsPerLaunch epochs (the kernel takes the step sizes
+        // of a launch's epochs from its lanes).
         for (int32_t done = 0; done < epochs;) {
             const int32_t ne = std::min(epochs - done, (int32_t)nomad::kMaxEpochsPerLaunch);
             a.epoch0 = (int32_t)(c->epochs_done + done);
             a.epochs = ne;
-            for (int32_t e = 0; e < ne; ++e) {
-                const double t = (double)(a.epoch0 + e);
-                const float s = (float)((double)c->cfg.alpha /
-                                        (1.0 + (double)c->cfg.beta * (t > 0.0 ? std::pow(t, (double)c->cfg.gamma) : 0.0)));
-                a.step_s[e] = s;
-                a.step_c[e] = 1.0f - s * c->cfg.lambda;
-            }
             HIPTRY(c, nomad::launch_train(a, st), "train: launch");
             done += ne;
         }
@@ -346,17 +475,9 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         float ms = 0.0f;
         HIPTRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1), "train: timing");
         seconds = ms * 1e-3;
-        uint32_t aborted = 0;
-        HIPTRY(c, hipMemcpy(&aborted, c->tok_done + c->n, sizeof(uint32_t), hipMemcpyDeviceToHost), "train: flag");
-        if (aborted == 2)
-            return fail(c, NOMAD_EDEVICE, "nomad_train_epochs: malformed layout detected; the factors are "
-                        "undefined");
-        if (aborted) {
-            int32_t d[8] = {0};
-            (void)hipMemcpy(d, c->diag, sizeof(d), hipMemcpyDeviceToHost);
-            return fail(c, NOMAD_EDEVICE, "nomad_train_epochs: a worker waited beyond the time limit (worker %d, "
-                        "wave %d, %d %d %d %d %d %d); the factors are undefined", d[0] - 1, d[1], d[2], d[3], d[4],
-                        d[5], d[6], d[7]);
+        {
+            const nomad_status ab = check_abort(c, "nomad_train_epochs");
+            if (ab != NOMAD_OK) return ab;
         }
         if (c->cfg.record_trace) {
             HIPTRY(c, hipMemcpy(&c->trace_count, c->trace_len, sizeof(int64_t), hipMemcpyDeviceToHost), "trace");
@@ -376,6 +497,8 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
 nomad_status nomad_eval_rmse(nomad_ctx *c, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
                              const float *d_val, double *rmse_out, double *objective_out) {
     if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_eval_rmse: NULL context");
+    if (!c->members.empty())
+        return fail(c, NOMAD_ESTATE, "nomad_eval_rmse: a batch; use nomad_batch_problem for one of its problems");
     if (!rmse_out) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: rmse_out is NULL");
     if (nnz < 0) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: nnz < 0");
     if (nnz > 0 && (!d_row || !d_col || !d_val)) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: NULL arrays");
@@ -394,6 +517,8 @@ nomad_status nomad_eval_rmse(nomad_ctx *c, int64_t nnz, const int32_t *d_row, co
 
 nomad_status nomad_get_factors(nomad_ctx *c, float *d_W, float *d_H) {
     if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_factors: NULL context");
+    if (!c->members.empty())
+        return fail(c, NOMAD_ESTATE, "nomad_get_factors: a batch; use nomad_batch_problem for one of its problems");
     if (!d_W || !d_H) return fail(c, NOMAD_EINVAL, "nomad_get_factors: NULL output");
     if (c->wbytes == 2)
         HIPTRY(c, nomad::from_bf16((const uint16_t *)c->W, c->kp, d_W, c->k, c->m, c->stream), "get_factors");
@@ -410,6 +535,8 @@ nomad_status nomad_get_factors(nomad_ctx *c, float *d_W, float *d_H) {
 
 nomad_status nomad_get_partition(nomad_ctx *c, int32_t *p_out, int64_t *h_row_start, int64_t cap) {
     if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_partition: NULL context");
+    if (!c->members.empty())
+        return fail(c, NOMAD_ESTATE, "nomad_get_partition: a batch; use nomad_batch_problem for one of its problems");
     if (p_out) *p_out = c->p;
     if (h_row_start) {
         if (cap < c->p + 1) return fail(c, NOMAD_EINVAL, "nomad_get_partition: cap < p + 1");
@@ -420,6 +547,8 @@ nomad_status nomad_get_partition(nomad_ctx *c, int32_t *p_out, int64_t *h_row_st
 
 nomad_status nomad_get_trace(nomad_ctx *c, int64_t *len, int32_t *h_buf, int64_t cap) {
     if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_trace: NULL context");
+    if (!c->members.empty())
+        return fail(c, NOMAD_ESTATE, "nomad_get_trace: a batch; use nomad_batch_problem for one of its problems");
     if (!len) return fail(c, NOMAD_EINVAL, "nomad_get_trace: len is NULL");
     *len = c->trace_count;
     if (h_buf && c->trace_count > 0) {
@@ -431,6 +560,8 @@ nomad_status nomad_get_trace(nomad_ctx *c, int64_t *len, int32_t *h_buf, int64_t
 
 nomad_status nomad_get_worker_stats(nomad_ctx *c, int64_t *h_stats, int64_t cap) {
     if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_worker_stats: NULL context");
+    if (!c->members.empty())
+        return fail(c, NOMAD_ESTATE, "nomad_get_worker_stats: a batch; use nomad_batch_problem for one of its problems");
     if (!h_stats || cap < (int64_t)nomad::kWStatCount * c->p)
         return fail(c, NOMAD_EINVAL, "nomad_get_worker_stats: need room for %d values", nomad::kWStatCount * c->p);
     HIPTRY(c, hipMemcpy(h_stats, c->wstats, sizeof(int64_t) * nomad::kWStatCount * (size_t)c->p, hipMemcpyDeviceToHost),
@@ -438,8 +569,130 @@ nomad_status nomad_get_worker_stats(nomad_ctx *c, int64_t *h_stats, int64_t cap)
     return NOMAD_OK;
 }
 
+nomad_status nomad_init_batched(nomad_ctx **out, int32_t nprob, const nomad_problem_desc *descs,
+                                const nomad_config *common, void *hip_stream) {
+    if (!out) return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: out is NULL");
+    *out = nullptr;
+    if (!common || !descs) return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: NULL argument");
+    if (nprob < 1) return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: nprob=%d < 1", nprob);
+    if (common->record_trace) return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init_batched: traces are per problem only");
+    if (common->dtype != NOMAD_FP32 && common->dtype != NOMAD_BF16)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: storage type %d is not one of NOMAD_FP32, NOMAD_BF16",
+                    common->dtype);
+    int32_t kp = 0;
+    uint64_t total_nnz = 0;
+    for (int32_t b = 0; b < nprob; ++b) {
+        if (descs[b].k < 1 || descs[b].k > nomad::kMaxK)
+            return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: problem %d: k=%d outside [1,%d]", b, descs[b].k,
+                        nomad::kMaxK);
+        if (descs[b].nnz < 0) return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: problem %d: nnz < 0", b);
+        kp = std::max(kp, nomad::padded_k(descs[b].k));
+        total_nnz += (uint64_t)descs[b].nnz;
+    }
+    // With the window left to the library, a batch takes the smallest one: problems are
+    // many and mostly small, so more (resident) workers beat deeper row windows.
+    nomad_config shape_cfg = *common;
+    if (shape_cfg.window <= 0) shape_cfg.window = 8;
+    nomad::Shape sh;
+    {
+        const nomad_status ss = choose_shape(&shape_cfg, kp, common->dtype == NOMAD_BF16 ? 2 : 4, &sh, nullptr);
+        if (ss != NOMAD_OK) return ss;
+    }
+    int32_t T = common->workers > 0 ? common->workers : std::min(sh.maxw, nomad::kMaxWorkers);
+    if (T > sh.maxw)
+        return fail(nullptr, NOMAD_EDEVICE, "nomad_init_batched: %d workers cannot all be resident (device holds %d)",
+                    T, sh.maxw);
+    if (nprob > T)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: %d problems need at least one worker each; %d fit",
+                    nprob, T);
+    // Workers per problem in proportion to its ratings (at least one each), largest
+    // remainders first.
+    std::vector<int32_t> pb(nprob, 1);
+    {
+        std::vector<double> quota(nprob, 1.0);
+        int32_t used = 0;
+        for (int32_t b = 0; b < nprob; ++b) {
+            quota[b] = total_nnz ? (double)T * (double)descs[b].nnz / (double)total_nnz : 1.0;
+            pb[b] = std::max(1, (int32_t)quota[b]);
+            used += pb[b];
+        }
+        while (used > T) {  // only possible through the "at least one" rule
+            int32_t best = -1;
+            for (int32_t b = 0; b < nprob; ++b)
+                if (pb[b] > 1 && (best < 0 || pb[b] - quota[b] > pb[best] - quota[best])) best = b;
+            --pb[best];
+            --used;
+        }
+        while (used < T && total_nnz) {
+            int32_t best = 0;
+            for (int32_t b = 1; b < nprob; ++b)
+                if (quota[b] - pb[b] > quota[best] - pb[best]) best = b;
+            ++pb[best];
+            ++used;
+        }
+    }
+    nomad_ctx *c = new (std::nothrow) nomad_ctx();
+    if (!c) return fail(nullptr, NOMAD_ENOMEM, "nomad_init_batched: host allocation failed");
+    auto bail = [&](nomad_status st) {
+        g_last_error = c->err;
+        release(c);
+        delete c;
+        return st;
+    };
+    c->cfg = *common;
+    c->stream = (hipStream_t)hip_stream;
+    c->shape = sh;
+    c->kp = kp;
+    c->nw = sh.nw;
+    c->slots = sh.slots;
+    c->window = sh.window;
+    std::vector<int32_t> wg_prob;
+    for (int32_t b = 0; b < nprob; ++b) {
+        nomad_config cb = *common;
+        cb.k = descs[b].k;
+        cb.lambda = descs[b].lambda;
+        cb.alpha = descs[b].alpha;
+        cb.beta = descs[b].beta;
+        cb.gamma = descs[b].gamma;
+        cb.workers = pb[b];
+        nomad_ctx *m = nullptr;
+        const nomad_status st = init_impl(&m, &cb, descs[b].m, descs[b].n, descs[b].nnz, descs[b].d_row,
+                                          descs[b].d_col, descs[b].d_val, descs[b].d_W0, descs[b].d_H0, hip_stream, &sh);
+        if (st != NOMAD_OK) return bail(fail(c, st, "nomad_init_batched: problem %d: %s", b, g_last_error.c_str()));
+        m->owner = c;
+        c->members.push_back(m);
+        c->wg0.push_back((int32_t)wg_prob.size());
+        for (int32_t q = 0; q < pb[b]; ++q) wg_prob.push_back(b);
+        c->nnz += descs[b].nnz;
+        c->layout_seconds += m->layout_seconds;
+    }
+    c->total_wg = (int32_t)wg_prob.size();
+    c->p = c->total_wg;
+    hipError_t e;
+    if ((e = hipMalloc(&c->d_descs, sizeof(nomad::TrainArgs) * (size_t)nprob)) != hipSuccess ||
+        (e = hipMalloc(&c->d_wg, sizeof(int32_t) * wg_prob.size())) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init_batched: launch tables"));
+    if ((e = hipMemcpy(c->d_wg, wg_prob.data(), sizeof(int32_t) * wg_prob.size(), hipMemcpyHostToDevice)) !=
+        hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init_batched: launch tables"));
+    if ((e = hipEventCreate(&c->ev0)) != hipSuccess || (e = hipEventCreate(&c->ev1)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init_batched: events"));
+    *out = c;
+    return NOMAD_OK;
+}
+
+nomad_status nomad_batch_problem(nomad_ctx *c, int32_t b, nomad_ctx **problem) {
+    if (!problem) return fail(c, NOMAD_EINVAL, "nomad_batch_problem: problem is NULL");
+    *problem = nullptr;
+    if (!c || c->members.empty()) return fail(c, NOMAD_ESTATE, "nomad_batch_problem: not a batch");
+    if (b < 0 || b >= (int32_t)c->members.size())
+        return fail(c, NOMAD_EINVAL, "nomad_batch_problem: b=%d outside [0,%zu)", b, c->members.size());
+    *problem = c->members[b];
+    return NOMAD_OK;
+}
+
 void nomad_destroy(nomad_ctx *c) {
-    if (!c) return;
+    if (!c || c->owner) return;  // a problem of a batch goes with its batch
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     release(c);
     delete c;

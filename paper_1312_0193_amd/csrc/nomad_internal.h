@@ -107,6 +107,13 @@ struct Plan {
 };
 
 // Arguments of the training kernel.
+// Launch shape of a worker, shared by every problem of a batched launch.
+struct Shape {
+    int32_t kp, nw, slots, window;
+    int32_t maxw;          // workers that can be resident at once with this shape
+    int32_t cus, max_lds;  // device figures
+};
+
 struct TrainArgs {
     int64_t m, n;
     void *W;                    // m x kp, FP32 or bfloat16 (wbytes per element)
@@ -128,9 +135,9 @@ struct TrainArgs {
     int32_t slots;              // item slots per worker (<= 64)
     int32_t window;             // D: rows a compute wave keeps in flight (8, 16 or 32)
     int32_t epoch0, epochs;     // epochs done before the launch, epochs of the launch
+    int32_t wg0;                // first workgroup of this problem in a batched launch (else 0)
     float lambda;
-    // per epoch of the launch: step size s_t (eq. stepsize_method) and 1 - s_t * lambda
-    float step_s[kMaxEpochsPerLaunch], step_c[kMaxEpochsPerLaunch];
+    double alpha, beta, gamma;  // step size s_t = alpha / (1 + beta t^gamma), eq. (stepsize_method)
     int64_t *wstats;            // per worker kWStatCount counters
     bool timing;                // also time the phases (costs clock reads)
     int32_t *trace;             // optional: 4 ints per visit
@@ -149,6 +156,11 @@ void free_plan(Plan *plan);
 // train.hip
 size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes);
 hipError_t launch_train(const TrainArgs &a, hipStream_t stream);
+// Several problems in one launch: d_descs[b] describes problem b (its wg0 = first
+// workgroup), d_wg_prob[g] = the problem of workgroup g; `shape` gives the launch shape
+// shared by all (kp, storage type, nw, slots, window).
+hipError_t launch_train_batch(const TrainArgs &shape, int32_t workgroups, const TrainArgs *d_descs,
+                              const int32_t *d_wg_prob, hipStream_t stream);
 // Workers of `nw` compute waves that can be resident at once on the device.
 hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
                              int32_t *max_workers);

@@ -536,9 +536,12 @@ struct ComputeWave {
         int e = 0, xbase = 0;
         int64_t left = cnt;
         // Step sizes of the launch's epochs, lane e holding epoch e's (read with readlane:
-        // a scalar memory load inside the loop would put its latency into every step).
-        const float s_tab = a.step_s[lane < a.epochs ? lane : 0];
-        const float c_tab = a.step_c[lane < a.epochs ? lane : 0];
+        // a scalar memory load inside the loop would put its latency into every step):
+        // s_t = alpha / (1 + beta t^gamma) in double, t = epochs done (every rating is
+        // updated once per epoch), rounded to float; and 1 - s_t lambda in float.
+        const double tl = (double)(a.epoch0 + lane);
+        const float s_tab = (float)(a.alpha / (1.0 + a.beta * (tl > 0.0 ? pow(tl, a.gamma) : 0.0)));
+        const float c_tab = 1.0f - s_tab * a.lambda;
         float s = __shfl(s_tab, 0);
         float c = __shfl(c_tab, 0);
         int item = 0;  // the item of the current visit (read with it, for the rounding hash)
@@ -901,14 +904,14 @@ struct MemoryWave {
     }
 };
 
+// One worker: workgroup q of the problem described by `a`.
 template <int VEC, int D, bool BF>
-__global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
+__device__ __forceinline__ void worker_body(const TrainArgs &a, int q) {
     extern __shared__ float4 lds4[];
     // The wave index is the same in every lane: say so, so that everything derived from it
     // lives in scalar registers.
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const int q = blockIdx.x;
     const Lds L = lds_layout(lds4, a.kp, a.nw, a.slots, D, BF ? 2 : 4);
     if (threadIdx.x < kMaxWaves + 1) L.flag[threadIdx.x] = 0;
     if (threadIdx.x < 2) L.ctl[threadIdx.x] = 0;
@@ -925,9 +928,27 @@ __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
 }
 
 template <int VEC, int D, bool BF>
-hipError_t launch_t(const TrainArgs &a, hipStream_t st) {
+__global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
+    worker_body<VEC, D, BF>(a, blockIdx.x);
+}
+
+// Several independent problems in one launch: workgroup g runs worker g - wg0 of problem
+// wg_prob[g]; every problem has its own layout, factors and item counters.
+template <int VEC, int D, bool BF>
+__global__ __launch_bounds__(1024) void k_worker_batch(const TrainArgs *__restrict__ descs,
+                                                       const int32_t *__restrict__ wg_prob) {
+    const TrainArgs a = descs[wg_prob[blockIdx.x]];
+    worker_body<VEC, D, BF>(a, (int)blockIdx.x - a.wg0);
+}
+
+// A batched launch when `descs` is given (a.p then = total workgroups), else one problem.
+template <int VEC, int D, bool BF>
+hipError_t launch_t(const TrainArgs &a, const TrainArgs *descs, const int32_t *wg_prob, hipStream_t st) {
     const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D, BF ? 2 : 4);
-    hipLaunchKernelGGL((k_worker<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    if (descs)
+        hipLaunchKernelGGL((k_worker_batch<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, descs, wg_prob);
+    else
+        hipLaunchKernelGGL((k_worker<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
     return hipGetLastError();
 }
 
@@ -946,17 +967,17 @@ const void *pick_kernel(int kp, int window) {
 }
 
 template <int VEC, bool BF>
-hipError_t launch_v(const TrainArgs &a, hipStream_t st) {
-    if (a.window <= 8) return launch_t<VEC, 8, BF>(a, st);
-    if (a.window <= 16) return launch_t<VEC, 16, BF>(a, st);
-    return launch_t<VEC, 32, BF>(a, st);
+hipError_t launch_v(const TrainArgs &a, const TrainArgs *d, const int32_t *g, hipStream_t st) {
+    if (a.window <= 8) return launch_t<VEC, 8, BF>(a, d, g, st);
+    if (a.window <= 16) return launch_t<VEC, 16, BF>(a, d, g, st);
+    return launch_t<VEC, 32, BF>(a, d, g, st);
 }
 
 template <bool BF>
-hipError_t launch_b(const TrainArgs &a, hipStream_t st) {
-    if (a.kp <= 64) return launch_v<1, BF>(a, st);
-    if (a.kp <= 128) return launch_v<2, BF>(a, st);
-    return launch_v<4, BF>(a, st);
+hipError_t launch_b(const TrainArgs &a, const TrainArgs *d, const int32_t *g, hipStream_t st) {
+    if (a.kp <= 64) return launch_v<1, BF>(a, d, g, st);
+    if (a.kp <= 128) return launch_v<2, BF>(a, d, g, st);
+    return launch_v<4, BF>(a, d, g, st);
 }
 
 }  // namespace
@@ -981,7 +1002,14 @@ hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t wind
 }
 
 hipError_t launch_train(const TrainArgs &a, hipStream_t st) {
-    return a.wbytes == 2 ? launch_b<true>(a, st) : launch_b<false>(a, st);
+    return a.wbytes == 2 ? launch_b<true>(a, nullptr, nullptr, st) : launch_b<false>(a, nullptr, nullptr, st);
+}
+
+hipError_t launch_train_batch(const TrainArgs &shape, int32_t workgroups, const TrainArgs *d_descs,
+                              const int32_t *d_wg_prob, hipStream_t st) {
+    TrainArgs a = shape;
+    a.p = workgroups;
+    return a.wbytes == 2 ? launch_b<true>(a, d_descs, d_wg_prob, st) : launch_b<false>(a, d_descs, d_wg_prob, st);
 }
 
 }  // namespace nomad

@@ -12,7 +12,7 @@ def test_header_declares_the_boundary():
     names = set(nm.declared_functions())
     for want in ("nomad_init", "nomad_train_epochs", "nomad_eval_rmse", "nomad_get_factors",
                  "nomad_get_partition", "nomad_get_trace", "nomad_destroy", "nomad_last_error",
-                 "nomad_config_default"):
+                 "nomad_config_default", "nomad_init_batched", "nomad_batch_problem"):
         assert want in names
 
 
@@ -42,7 +42,8 @@ def test_binding_structs_match_the_c_header(tmp_path):
     gcc = shutil.which("gcc")
     if gcc is None:
         pytest.skip("no C compiler")
-    fields = {"nomad_config": nm.NomadConfig, "nomad_stats": nm.NomadStats}
+    fields = {"nomad_config": nm.NomadConfig, "nomad_stats": nm.NomadStats,
+              "nomad_problem_desc": nm.NomadProblemDesc}
     lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "nomad.h"', "int main(void) {"]
     for cname, cls in fields.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

@@ -1,0 +1,137 @@
+"""The batched form: several independent problems trained by one launch per call.
+
+Pins (the batched-independence property): every problem of a batch ends bitwise equal
+to the same problem trained alone with the same number of workers, and within the ring
+tolerance (1e-5 after one epoch, FP32 vs FP64) of the oracle's ring order at that worker
+count.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1312_0193_amd as nm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_1EPOCH = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+def problems(specs, seed0=100):
+    out = []
+    for b, (m, n, nnz, k, lam) in enumerate(specs):
+        prob = synth.small_case(m, n, nnz, seed=seed0 + b, degrees="uniform", k=k, lam=lam, alpha=0.01, beta=1e-4,
+                                gamma=1.0, test_frac=0.1)
+        W0, H0 = synth.init_factors(m, n, k, seed0 + b)
+        out.append(dict(m=m, n=n, row=prob.row, col=prob.col, val=prob.val, W0=W0, H0=H0, k=k, lam=lam,
+                        alpha=0.01, beta=1e-4, gamma=1.0, prob=prob))
+    return out
+
+
+SPECS = [
+    # m, n, nnz, k, lambda: sizes spanning two orders of magnitude, k in {16, 32, 64}
+    (2_000, 1_000, 60_000, 16, 0.05),
+    (300, 500, 8_000, 32, 0.01),
+    (1_500, 200, 30_000, 64, 0.1),
+    (120, 90, 2_000, 16, 0.05),
+    (4_000, 800, 90_000, 32, 0.05),
+    (50, 40, 400, 64, 0.01),
+]
+
+
+def test_batch_matches_problems_alone_and_oracle():
+    probs = problems(SPECS)
+    print(f"[case] batch of {len(probs)} problems, 40 workers", flush=True)
+    batch = nm.NomadBatch(probs, workers=40, seed=3)
+    st = batch.train(1)
+    assert st.updates == sum(int(p["row"].numel()) for p in probs)
+    workers = [v.workers for v in batch.problems]
+    assert sum(workers) == 40 and min(workers) >= 1
+    # more ratings, more workers
+    nnz = [p["row"].numel() for p in probs]
+    assert workers[int(np.argmax(nnz))] == max(workers)
+    for b, (p, view) in enumerate(zip(probs, batch.problems)):
+        Wb, Hb = (x.cpu().double().numpy() for x in view.factors())
+        print(f"[case] problem {b} alone, {workers[b]} workers", flush=True)
+        alone = nm.Nomad(p["m"], p["n"], p["row"], p["col"], p["val"], p["W0"], p["H0"], k=p["k"], lam=p["lam"],
+                         alpha=p["alpha"], beta=p["beta"], gamma=p["gamma"], workers=workers[b], seed=3)
+        alone.train(1)
+        Wa, Ha = (x.cpu().double().numpy() for x in alone.factors())
+        alone.close()
+        assert np.array_equal(Wa, Wb) and np.array_equal(Ha, Hb), b
+        hp = oracle.Hyper(p["k"], f32(p["lam"]), f32(p["alpha"]), f32(p["beta"]), f32(p["gamma"]))
+        Wo, Ho, _ = oracle.train_ring(p["m"], p["n"], p["row"].numpy(), p["col"].numpy(), p["val"].numpy(),
+                                      p["W0"].numpy(), p["H0"].numpy(), hp, workers[b], 3, 1)
+        assert rel(Wb, Wo) < TOL_1EPOCH and rel(Hb, Ho) < TOL_1EPOCH, (b, rel(Wb, Wo), rel(Hb, Ho))
+        # evaluation through the problem's view
+        pr = p["prob"]
+        r_gpu, _ = view.evaluate(pr.test_row, pr.test_col, pr.test_val)
+        r_orc = oracle.rmse(p["m"], p["n"], pr.test_row.numpy(), pr.test_col.numpy(), pr.test_val.numpy(), Wb, Hb)
+        assert abs(r_gpu - r_orc) <= 1e-12 * max(1.0, r_orc)
+    batch.close()
+
+
+def test_batch_continues_across_calls_and_launches():
+    probs = problems(SPECS[:3], seed0=200)
+    print("[case] batch 3 problems, calls [2, 65]", flush=True)
+    batch = nm.NomadBatch(probs, workers=24, seed=1)
+    batch.train(2)
+    batch.train(65)  # two launches
+    workers = [v.workers for v in batch.problems]
+    for b, (p, view) in enumerate(zip(probs, batch.problems)):
+        Wb, Hb = (x.cpu().double().numpy() for x in view.factors())
+        alone = nm.Nomad(p["m"], p["n"], p["row"], p["col"], p["val"], p["W0"], p["H0"], k=p["k"], lam=p["lam"],
+                         alpha=p["alpha"], beta=p["beta"], gamma=p["gamma"], workers=workers[b], seed=1)
+        alone.train(67)
+        Wa, Ha = (x.cpu().double().numpy() for x in alone.factors())
+        alone.close()
+        assert np.array_equal(Wa, Wb) and np.array_equal(Ha, Hb), b
+    batch.close()
+
+
+def test_batch_bf16_and_empty_problem():
+    probs = problems(SPECS[1:3], seed0=300)
+    e = torch.zeros(0, dtype=torch.int32)
+    W0, H0 = synth.init_factors(10, 7, 16, 9)
+    probs.append(dict(m=10, n=7, row=e, col=e, val=torch.zeros(0), W0=W0, H0=H0, k=16, lam=0.05, alpha=0.01,
+                      beta=1e-4, gamma=1.0))
+    print("[case] batch with an empty problem, bf16", flush=True)
+    batch = nm.NomadBatch(probs, workers=12, seed=2, dtype="bf16", rounding="stochastic")
+    batch.train(2)
+    W, H = batch.problems[2].factors()
+    assert torch.equal(H.cpu(), H0)  # nothing to update
+    for b, p in enumerate(probs[:2]):
+        alone = nm.Nomad(p["m"], p["n"], p["row"], p["col"], p["val"], p["W0"], p["H0"], k=p["k"], lam=p["lam"],
+                         alpha=p["alpha"], beta=p["beta"], gamma=p["gamma"], workers=batch.problems[b].workers,
+                         seed=2, dtype="bf16", rounding="stochastic")
+        alone.train(2)
+        assert all(torch.equal(x, y) for x, y in zip(alone.factors(), batch.problems[b].factors())), b
+        alone.close()
+    batch.close()
+
+
+def test_batch_errors():
+    probs = problems(SPECS[:3], seed0=400)
+    with pytest.raises(nm.NomadError, match="EINVAL"):
+        nm.NomadBatch(probs, workers=2)  # fewer workers than problems
+    bad = [dict(probs[0]), probs[1]]
+    bad[0]["row"] = bad[0]["row"].clone()
+    bad[0]["row"][0] = bad[0]["m"] + 5
+    with pytest.raises(nm.NomadError, match="problem 0"):
+        nm.NomadBatch(bad, workers=8)
+    batch = nm.NomadBatch(probs, workers=8)
+    lib = nm.load()
+    W = torch.empty(probs[0]["m"], probs[0]["k"], device="cuda")
+    H = torch.empty(probs[0]["n"], probs[0]["k"], device="cuda")
+    assert lib.nomad_get_factors(batch.ctx, W.data_ptr(), H.data_ptr()) == nm.NOMAD_ESTATE
+    assert lib.nomad_train_epochs(batch.problems[0].ctx, 1, None) == nm.NOMAD_ESTATE
+    batch.close()
