@@ -52,9 +52,16 @@ typedef enum {
  *     with g(j) = (q+s) mod p in ascending j; items then pass from q to q-1.  Every
  *     rating is updated once per epoch and the result is one fixed serial order of
  *     updates, independent of timing.
- *   PERM: asynchronous.  Each group of items visits the workers holding its ratings in
- *     an order drawn afresh every epoch (the random-permutation circulation of section
- *     3.4); workers take groups in arrival order, so the serial order depends on timing. */
+ *   PERM: asynchronous (Algorithm 1 with the random-permutation circulation of section
+ *     3.4).  Every worker has a lock-free inbound queue of items and takes them in arrival
+ *     order.  In epoch e item j visits the workers holding its ratings in the order of
+ *     key(q) = lowbias32(lowbias32(r ^ j) ^ e*0x9E3779B9 ^ q*0x85EBCA77) (ties by the
+ *     worker's rank among the holders), r = 0x6a09e667 ^ the two 32-bit halves of
+ *     nomad_config.seed: a fresh pseudo-random permutation every epoch, so every rating is
+ *     updated once per epoch and t = epochs done.  At the start of a call every item is
+ *     queued at its first worker (each queue in ascending item order).  The serial order
+ *     depends on timing (record_trace gives it); with one worker it is the ring order.
+ *     Not available in batches. */
 typedef enum { NOMAD_SCHED_RING = 0, NOMAD_SCHED_PERM = 1 } nomad_sched;
 
 /* Storage type of W in device memory (H is always held in FP32); arithmetic is always

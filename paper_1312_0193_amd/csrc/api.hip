@@ -39,6 +39,12 @@ struct nomad_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     double layout_seconds = 0.0;
     std::string err;
+    // Asynchronous schedule: inbound queues, item state, seeding scratch.
+    uint64_t *queue = nullptr;
+    uint32_t *qtail = nullptr, *parked = nullptr;
+    int32_t *itep = nullptr, *ihop = nullptr;
+    void *async_scratch = nullptr;
+    size_t async_scratch_bytes = 0;
     // A batch (nomad_init_batched): its problems, each a full context of its own, trained
     // together by one launch.
     std::vector<nomad_ctx *> members;
@@ -87,6 +93,12 @@ void release(nomad_ctx *c) {
     c->members.clear();
     (void)hipFree(c->d_descs);
     (void)hipFree(c->d_wg);
+    (void)hipFree(c->queue);
+    (void)hipFree(c->qtail);
+    (void)hipFree(c->parked);
+    (void)hipFree(c->itep);
+    (void)hipFree(c->ihop);
+    (void)hipFree(c->async_scratch);
     nomad::free_plan(&c->plan);
     (void)hipFree(c->W);
     (void)hipFree(c->H);
@@ -203,8 +215,9 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
     if (nnz > 0 && (!d_row || !d_col || !d_val))
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: rating arrays are NULL");
     if (!d_W0 || !d_H0) return fail(nullptr, NOMAD_EINVAL, "nomad_init: initial factors are NULL");
-    if (cfg->sched != NOMAD_SCHED_RING)
-        return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init: schedule %d is not provided by this build", cfg->sched);
+    if (cfg->sched != NOMAD_SCHED_RING && cfg->sched != NOMAD_SCHED_PERM)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: schedule %d is not one of NOMAD_SCHED_RING, NOMAD_SCHED_PERM",
+                    cfg->sched);
     if (cfg->dtype != NOMAD_FP32 && cfg->dtype != NOMAD_BF16)
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: storage type %d is not one of NOMAD_FP32, NOMAD_BF16",
                     cfg->dtype);
@@ -294,6 +307,20 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
                           sizeof(msg));
     if (e != hipSuccess) return bail(hip_fail(c, e, "nomad_init: layout"));
     if (code != 0) return bail(fail(c, (nomad_status)code, "nomad_init: %s", msg));
+    if (cfg->sched == NOMAD_SCHED_PERM) {
+        if ((e = nomad::build_async_tables(&c->plan, st)) != hipSuccess)
+            return bail(hip_fail(c, e, "nomad_init: asynchronous tables"));
+        const int64_t nv = c->plan.nvisits > 0 ? c->plan.nvisits : 1;
+        c->async_scratch_bytes = nomad::async_scratch_bytes(n, p);
+        if ((e = hipMalloc(&c->queue, sizeof(uint64_t) * (size_t)nv)) != hipSuccess ||
+            (e = hipMalloc(&c->qtail, sizeof(uint32_t) * (size_t)p)) != hipSuccess ||
+            (e = hipMalloc(&c->parked, sizeof(uint32_t))) != hipSuccess ||
+            (e = hipMalloc(&c->itep, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
+            (e = hipMalloc(&c->ihop, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
+            (e = hipMalloc(&c->async_scratch, c->async_scratch_bytes)) != hipSuccess ||
+            (e = hipMemsetAsync(c->ihop, 0, sizeof(int32_t) * (size_t)n, st)) != hipSuccess)
+            return bail(hip_fail(c, e, "nomad_init: queues"));
+    }
     if ((e = hipEventRecord(c->ev1, st)) != hipSuccess || (e = hipEventSynchronize(c->ev1)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: event"));
     float ms = 0.0f;
@@ -463,11 +490,35 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
         // Launches of at most kMaxEpochsPerLaunch epochs (the kernel takes the step sizes
         // of a launch's epochs from its lanes).
+        if (c->cfg.sched == NOMAD_SCHED_PERM) {
+            a.sched = 1;
+            a.hold = c->plan.hold;
+            a.hx = c->plan.hx;
+            a.hitem = c->plan.hitem;
+            a.hoff = c->plan.hoff;
+            a.xoff = c->plan.xoff;
+            a.queue = c->queue;
+            a.qtail = c->qtail;
+            a.itep = c->itep;
+            a.ihop = c->ihop;
+            a.parked = c->parked;
+            a.active = c->plan.active;
+            a.route_seed = (uint32_t)(c->cfg.seed >> 32) ^ (uint32_t)c->cfg.seed ^ 0x6a09e667u;
+        }
         for (int32_t done = 0; done < epochs;) {
             const int32_t ne = std::min(epochs - done, (int32_t)nomad::kMaxEpochsPerLaunch);
             a.epoch0 = (int32_t)(c->epochs_done + done);
             a.epochs = ne;
-            HIPTRY(c, nomad::launch_train(a, st), "train: launch");
+            if (c->cfg.sched == NOMAD_SCHED_PERM) {
+                const int64_t nv = c->plan.nvisits > 0 ? c->plan.nvisits : 1;
+                HIPTRY(c, hipMemsetAsync(c->queue, 0, sizeof(uint64_t) * (size_t)nv, st), "train: reset");
+                HIPTRY(c, hipMemsetAsync(c->qtail, 0, sizeof(uint32_t) * (size_t)c->p, st), "train: reset");
+                HIPTRY(c, hipMemsetAsync(c->parked, 0, sizeof(uint32_t), st), "train: reset");
+                HIPTRY(c, nomad::launch_train_async(a, c->plan.vbase, c->async_scratch, c->async_scratch_bytes, st),
+                       "train: launch");
+            } else {
+                HIPTRY(c, nomad::launch_train(a, st), "train: launch");
+            }
             done += ne;
         }
         HIPTRY(c, hipEventRecord(c->ev1, st), "train: event");
@@ -576,6 +627,8 @@ nomad_status nomad_init_batched(nomad_ctx **out, int32_t nprob, const nomad_prob
     if (!common || !descs) return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: NULL argument");
     if (nprob < 1) return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: nprob=%d < 1", nprob);
     if (common->record_trace) return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init_batched: traces are per problem only");
+    if (common->sched != NOMAD_SCHED_RING)
+        return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init_batched: batches run the ring schedule");
     if (common->dtype != NOMAD_FP32 && common->dtype != NOMAD_BF16)
         return fail(nullptr, NOMAD_EINVAL, "nomad_init_batched: storage type %d is not one of NOMAD_FP32, NOMAD_BF16",
                     common->dtype);

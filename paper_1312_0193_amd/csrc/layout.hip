@@ -274,6 +274,63 @@ struct Tmp {
     ~Tmp() { (void)hipFree(p); }
 };
 
+// Worker of each visit, and the visit's item as a sort key.
+__global__ void k_visit_owner(const int64_t *vbase, int32_t p, const VisitRec *visits, int64_t nv, int32_t *vq,
+                              uint32_t *vj, uint32_t *vidx) {
+    GRID_LOOP(v, nv) {
+        vq[v] = find_block(vbase, p, v);
+        vj[v] = (uint32_t)visits[v].j;
+        vidx[v] = (uint32_t)v;
+    }
+}
+
+// Holder entries in (item, worker) order, and the number of holders of each item.
+__global__ void k_holders(const uint32_t *vidx_sorted, const int32_t *vq, const int64_t *vbase, const VisitRec *visits,
+                          int64_t nv, int32_t *hold, int32_t *hx, int32_t *hitem, unsigned long long *cnt) {
+    GRID_LOOP(i, nv) {
+        const int64_t v = vidx_sorted[i];
+        const int32_t q = vq[v];
+        hold[i] = q;
+        hx[i] = (int32_t)(v - vbase[q]);
+        hitem[i] = visits[v].j;
+        atomicAdd(&cnt[visits[v].j], 1ull);
+    }
+}
+
+__global__ void k_count_active(const int64_t *hoff, int64_t n, unsigned long long *active) {
+    GRID_LOOP(j, n) {
+        if (hoff[j + 1] > hoff[j]) atomicAdd(active, 1ull);
+    }
+}
+
+// xoff at the first record of each (visit, wave): every record that starts its wave's part
+// of a visit.
+__global__ void k_xoff_first(const RatingRec *recs, int64_t nnz, const int64_t *rbase, int64_t nwt, int32_t nw,
+                             const int64_t *vbase, int32_t *xoff) {
+    GRID_LOOP(e, nnz) {
+        const uint32_t info = recs[e].info;
+        if (!(info & kInfoFirst)) continue;
+        const int32_t t = find_block(rbase, (int32_t)nwt, e);
+        const int32_t q = t / nw, w = t - q * nw;
+        const int64_t v = vbase[q] + (int64_t)(info & kInfoXMask);
+        xoff[v * nw + w] = (int32_t)(e - rbase[t]);
+    }
+}
+
+// Visits without records in a wave start where the wave's next visit does (one thread per
+// wave, backwards over its worker's visits).
+__global__ void k_xoff_fill(const int64_t *rbase, int64_t nwt, int32_t nw, const int64_t *vbase, int32_t *xoff) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= nwt) return;
+    const int32_t q = (int32_t)(t / nw), w = (int32_t)(t - (int64_t)q * nw);
+    int32_t next = (int32_t)(rbase[t + 1] - rbase[t]);
+    for (int64_t v = vbase[q + 1] - 1; v >= vbase[q]; --v) {
+        int32_t &o = xoff[v * nw + w];
+        if (o < 0) o = next;
+        else next = o;
+    }
+}
+
 }  // namespace
 
 void free_plan(Plan *pl) {
@@ -283,6 +340,11 @@ void free_plan(Plan *pl) {
     (void)hipFree(pl->recs);
     (void)hipFree(pl->vbase);
     (void)hipFree(pl->visits);
+    (void)hipFree(pl->hold);
+    (void)hipFree(pl->hx);
+    (void)hipFree(pl->hitem);
+    (void)hipFree(pl->hoff);
+    (void)hipFree(pl->xoff);
     *pl = Plan();
 }
 
@@ -291,6 +353,67 @@ void free_plan(Plan *pl) {
         hipError_t _e = (x);                    \
         if (_e != hipSuccess) { rc = _e; goto done; } \
     } while (0)
+
+hipError_t build_async_tables(Plan *pl, hipStream_t st) {
+    hipError_t rc = hipSuccess;
+    const int64_t nv = pl->nvisits, n = pl->n, nwt = (int64_t)pl->p * pl->nw;
+    int32_t *vq = nullptr;
+    uint32_t *vj = nullptr, *vj_s = nullptr, *vidx = nullptr, *vidx_s = nullptr;
+    unsigned long long *cnt = nullptr, *act = nullptr;
+    Tmp tmp;
+    CK(dalloc(&pl->hold, nv > 0 ? nv : 1));
+    CK(dalloc(&pl->hx, nv > 0 ? nv : 1));
+    CK(dalloc(&pl->hitem, nv > 0 ? nv : 1));
+    CK(dalloc(&pl->hoff, n + 1));
+    CK(dalloc(&pl->xoff, nv * pl->nw > 0 ? nv * pl->nw : 1));
+    CK(dalloc(&cnt, n + 1));
+    CK(dalloc(&act, 1));
+    CK(hipMemsetAsync(cnt, 0, sizeof(unsigned long long) * (n + 1), st));
+    CK(hipMemsetAsync(act, 0, sizeof(unsigned long long), st));
+    if (nv > 0) {
+        CK(dalloc(&vq, nv)); CK(dalloc(&vj, nv)); CK(dalloc(&vj_s, nv)); CK(dalloc(&vidx, nv)); CK(dalloc(&vidx_s, nv));
+        hipLaunchKernelGGL(k_visit_owner, dim3(grid_for(nv)), dim3(kThreads), 0, st, pl->vbase, pl->p, pl->visits,
+                           nv, vq, vj, vidx);
+        CK(hipGetLastError());
+        const int eb = bits_for((uint64_t)(n > 1 ? n - 1 : 1));
+        size_t need = 0;
+        CK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, vj, vj_s, vidx, vidx_s, nv, 0, eb, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceRadixSort::SortPairs(tmp.p, need, vj, vj_s, vidx, vidx_s, nv, 0, eb, st));
+        hipLaunchKernelGGL(k_holders, dim3(grid_for(nv)), dim3(kThreads), 0, st, vidx_s, vq, pl->vbase, pl->visits, nv,
+                           pl->hold, pl->hx, pl->hitem, cnt);
+        CK(hipGetLastError());
+    }
+    {
+        size_t need = 0;
+        CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, (const int64_t *)cnt, pl->hoff, n + 1, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp.p, need, (const int64_t *)cnt, pl->hoff, n + 1, st));
+    }
+    hipLaunchKernelGGL(k_count_active, dim3(grid_for(n)), dim3(kThreads), 0, st, pl->hoff, n, act);
+    CK(hipGetLastError());
+    if (nv > 0) {
+        CK(hipMemsetAsync(pl->xoff, 0xFF, sizeof(int32_t) * nv * pl->nw, st));
+        if (pl->nnz > 0) {
+            hipLaunchKernelGGL(k_xoff_first, dim3(grid_for(pl->nnz)), dim3(kThreads), 0, st, pl->recs, pl->nnz,
+                               pl->rbase, nwt, pl->nw, pl->vbase, pl->xoff);
+            CK(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_xoff_fill, dim3(grid_for(nwt, 64)), dim3(64), 0, st, pl->rbase, nwt, pl->nw, pl->vbase,
+                           pl->xoff);
+        CK(hipGetLastError());
+    }
+    {
+        unsigned long long a = 0;
+        CK(hipMemcpyAsync(&a, act, sizeof(a), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        pl->active = (int64_t)a;
+    }
+done:
+    (void)hipFree(vq); (void)hipFree(vj); (void)hipFree(vj_s); (void)hipFree(vidx); (void)hipFree(vidx_s);
+    (void)hipFree(cnt); (void)hipFree(act);
+    return rc;
+}
 
 hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
                       const float *d_val, int32_t p, int32_t nw, int32_t window, uint64_t seed, hipStream_t st,

@@ -104,6 +104,15 @@ struct Plan {
     VisitRec *visits = nullptr;
     int64_t nvisits = 0;            // (worker, item) visits per epoch
     int64_t max_worker_visits = 0;
+    // Asynchronous schedules (build_async_tables).  A worker's "local item" x is the item of
+    // its visit vbase[q] + x; the ring order's record streams are grouped by local item.
+    int32_t *hold = nullptr;   // nvisits holder entries, grouped by item (workers ascending): the worker
+    int32_t *hx = nullptr;     //   the item's local index at that worker
+    int32_t *hitem = nullptr;  //   the item
+    int64_t *hoff = nullptr;   // n + 1: item j's holder entries are [hoff[j], hoff[j+1])
+    int32_t *xoff = nullptr;   // nvisits * nw: first record of local item x in wave w's stream, relative to
+                               //   the stream start (the end is the next local item's entry, or the stream end)
+    int64_t active = 0;        // items with at least one rating
 };
 
 // Arguments of the training kernel.
@@ -140,6 +149,19 @@ struct TrainArgs {
     double alpha, beta, gamma;  // step size s_t = alpha / (1 + beta t^gamma), eq. (stepsize_method)
     int64_t *wstats;            // per worker kWStatCount counters
     bool timing;                // also time the phases (costs clock reads)
+    // Asynchronous schedules (sched 1): the plan's holder and offset tables, the inbound
+    // queues and the items' state.
+    int32_t sched;              // 0 ring, 1 random permutation per epoch (asynchronous)
+    const int32_t *hold, *hx, *hitem;
+    const int64_t *hoff;
+    const int32_t *xoff;
+    uint64_t *queue;            // nvisits: worker q's inbound queue is [vbase[q], vbase[q+1])
+    uint32_t *qtail;            // p: pushes into each queue during the launch
+    int32_t *itep;              // n: epoch of each item's next visit
+    int32_t *ihop;              // n: visits of each item since the call began
+    uint32_t *parked;           // items that finished the launch's epochs
+    int64_t active;             // items with at least one rating
+    uint32_t route_seed;
     int32_t *trace;             // optional: 4 ints per visit
     int64_t *trace_len;         // optional counter
     int64_t trace_cap;
@@ -152,10 +174,18 @@ hipError_t build_plan(Plan *plan, int64_t m, int64_t n, int64_t nnz, const int32
                       const int32_t *d_col, const float *d_val, int32_t p, int32_t nw, int32_t window,
                       uint64_t seed, hipStream_t stream, int *err_code, char *msg, size_t msg_len);
 void free_plan(Plan *plan);
+// The tables of the asynchronous schedules, from a built plan.
+hipError_t build_async_tables(Plan *plan, hipStream_t stream);
 
 // train.hip
 size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes);
 hipError_t launch_train(const TrainArgs &a, hipStream_t stream);
+// Asynchronous schedules: queue every item at the first worker of its visiting order for
+// epoch a.epoch0 (each worker's queue in ascending item order), then run the launch.
+// Scratch: 3 n + (p + 1) words at `scratch` plus the sort's temporary storage.
+hipError_t launch_train_async(const TrainArgs &a, const int64_t *vbase, void *scratch, size_t scratch_bytes,
+                              hipStream_t stream);
+size_t async_scratch_bytes(int64_t n, int32_t p);
 // Several problems in one launch: d_descs[b] describes problem b (its wg0 = first
 // workgroup), d_wg_prob[g] = the problem of workgroup g; `shape` gives the launch shape
 // shared by all (kp, storage type, nw, slots, window).

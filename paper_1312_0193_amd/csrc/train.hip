@@ -32,6 +32,8 @@
 #include <cmath>
 #include <utility>
 
+#include <hipcub/hipcub.hpp>
+
 #include "nomad_internal.h"
 
 namespace nomad {
@@ -153,13 +155,15 @@ struct Lds {
     char *rows;       // nw x (D + 1) x kp elements of W's storage type: row slots of every compute wave
     RatingRec *recs;  // nw x kRecRing x kRecBatch: staged records of every compute wave
     int32_t *item;    // kMaxItemSlots: the item in each slot
+    int32_t *sx;      // kMaxItemSlots: asynchronous schedules: the item's local index at the worker
+    int32_t *se;      // kMaxItemSlots: asynchronous schedules: the visit's epoch, relative to the launch
     int32_t *flag;    // nw: 1 + the last visit each compute wave finished
     int32_t *ctl;     // [0] visits loaded, [1] stop
 };
 
 __host__ __device__ inline size_t lds_bytes(int kp, int nw, int slots, int window, int wbytes) {
     return (size_t)slots * kp * sizeof(float) + (size_t)nw * (window + 1) * kp * wbytes +
-           (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec) + (kMaxItemSlots + kMaxWaves + 1 + 4) * 4;
+           (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec) + (3 * kMaxItemSlots + kMaxWaves + 1 + 4) * 4;
 }
 
 __device__ __forceinline__ Lds lds_layout(void *base, int kp, int nw, int slots, int window, int wbytes) {
@@ -172,6 +176,10 @@ __device__ __forceinline__ Lds lds_layout(void *base, int kp, int nw, int slots,
     L.recs = (RatingRec *)p;
     p += (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec);
     L.item = (int32_t *)p;
+    p += kMaxItemSlots * 4;
+    L.sx = (int32_t *)p;
+    p += kMaxItemSlots * 4;
+    L.se = (int32_t *)p;
     p += kMaxItemSlots * 4;
     L.flag = (int32_t *)p;
     p += (kMaxWaves + 1) * 4;
@@ -390,6 +398,41 @@ __device__ __forceinline__ void row_gstore(char *p, const float (&v)[VEC]) {
     }
 }
 
+// The stored form of an updated row: bfloat16 rounding of the FP32 result, nearest-even
+// (the hardware conversion, two elements per instruction) or stochastic: the low 16 bits
+// plus random bits, truncated; the bits of element l come from the half (l mod 2) of a
+// hash of (key of the rating, l / 2), the key hashing (seed, row, item, epoch).
+template <int VEC, bool BF>
+__device__ __forceinline__ void round_stored(const TrainArgs &a, int loff, float (&v)[VEC], int row, int item,
+                                         int t) {
+    if constexpr (BF) {
+        if (a.rounding == 0) {
+            if constexpr (VEC == 1) {
+                v[0] = (float)(__bf16)v[0];
+            } else {
+#pragma unroll
+                for (int i = 0; i < VEC; i += 2) {
+                    const uint32_t pk = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{v[i], v[i + 1]}, bf16x2v));
+                    v[i] = __uint_as_float(pk << 16);
+                    v[i + 1] = __uint_as_float(pk & 0xFFFF0000u);
+                }
+            }
+        } else {
+            const uint32_t key = a.sr_seed ^ ((uint32_t)row * 0x9E3779B1u) ^ ((uint32_t)item * 0x85EBCA77u) ^
+                                 ((uint32_t)t * 0xC2B2AE3Du);
+            const uint32_t c = lowbias32(key);
+            uint32_t word = 0;  // the hash word of the current pair of elements
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+                const int l = loff + i;
+                if (VEC == 1 || (i & 1) == 0) word = lowbias32(c + (uint32_t)(l >> 1));
+                const uint32_t bits = (l & 1) ? (word >> 16) : (word & 0xFFFFu);
+                v[i] = __uint_as_float((__float_as_uint(v[i]) + bits) & 0xFFFF0000u);
+            }
+        }
+    }
+}
+
 template <int VEC, int D, bool BF>
 struct ComputeWave {
     static_assert(2 * (D - 2) <= 63 && D >= 4, "vmcnt range");
@@ -426,37 +469,8 @@ struct ComputeWave {
         dma16s((const char *)a.W + (int64_t)row * rb, (uint32_t)(lane & 63) * 16u, rows_lds + (uint32_t)(slot * rb),
                row_mask);
     }
-    // The stored form of an updated row: bfloat16 rounding of the FP32 result, nearest-even
-    // (the hardware conversion, two elements per instruction) or stochastic: the low 16 bits
-    // plus random bits, truncated; the bits of element l come from the half (l mod 2) of a
-    // hash of (key of the rating, l / 2), the key hashing (seed, row, item, epoch).
     __device__ __forceinline__ void round_row(float (&v)[VEC], int row, int item, int t) const {
-        if constexpr (BF) {
-            if (a.rounding == 0) {
-                if constexpr (VEC == 1) {
-                    v[0] = (float)(__bf16)v[0];
-                } else {
-#pragma unroll
-                    for (int i = 0; i < VEC; i += 2) {
-                        const uint32_t pk = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{v[i], v[i + 1]}, bf16x2v));
-                        v[i] = __uint_as_float(pk << 16);
-                        v[i + 1] = __uint_as_float(pk & 0xFFFF0000u);
-                    }
-                }
-            } else {
-                const uint32_t key = a.sr_seed ^ ((uint32_t)row * 0x9E3779B1u) ^ ((uint32_t)item * 0x85EBCA77u) ^
-                                     ((uint32_t)t * 0xC2B2AE3Du);
-                const uint32_t c = lowbias32(key);
-                uint32_t word = 0;  // the hash word of the current pair of elements
-#pragma unroll
-                for (int i = 0; i < VEC; ++i) {
-                    const int l = loff + i;
-                    if (VEC == 1 || (i & 1) == 0) word = lowbias32(c + (uint32_t)(l >> 1));
-                    const uint32_t bits = (l & 1) ? (word >> 16) : (word & 0xFFFFu);
-                    v[i] = __uint_as_float((__float_as_uint(v[i]) + bits) & 0xFFFF0000u);
-                }
-            }
-        }
+        round_stored<VEC, BF>(a, loff, v, row, item, t);
     }
     __device__ __forceinline__ void placeholder_store() {
         if (lane == 0) a.dummy[(int64_t)q * kMaxWaves + w] = 0.0f;
@@ -904,6 +918,365 @@ struct MemoryWave {
     }
 };
 
+// ---------------------------------------------------------------------------------------
+// Asynchronous schedule: Algorithm 1 with the random-permutation circulation of section
+// 3.4.  Every worker has an inbound queue of items in device memory (lock-free: a producer
+// reserves a position with an atomic increment of the queue's tail and writes the entry
+// (position + 1, holder entry) with one 64-bit device-coherent store; the consumer reads
+// positions in order and takes an entry once its position matches).  A worker takes items
+// in arrival order; after its last compute wave is done with an item it writes h_j back
+// (device-coherent), passes it to the next worker of the item's visiting order for the
+// epoch, or parks it after the launch's last epoch.  The visiting order of item j in epoch
+// e is its holders sorted by a hash of (seed, j, e, worker): a fresh pseudo-random
+// permutation every epoch, so every rating is updated once per epoch and t = e.
+
+// Position of holder `q` (entry `rank` of the item's holder list) in the visiting order of
+// item j for epoch e: larger keys come later.
+__device__ __forceinline__ uint64_t route_key(uint32_t seed, int j, int e, int q, int rank) {
+    const uint32_t k = lowbias32(lowbias32(seed ^ (uint32_t)j) ^ ((uint32_t)e * 0x9E3779B9u) ^ ((uint32_t)q * 0x85EBCA77u));
+    return ((uint64_t)k << 32) | (uint32_t)rank;
+}
+
+// The holder entry that comes first in item j's visiting order for epoch e (after `after`
+// if given), or -1 if none does.
+__device__ __forceinline__ int64_t route_next(const TrainArgs &a, int j, int e, uint64_t after, bool use_after) {
+    const int64_t hb = a.hoff[j], nh = a.hoff[j + 1] - hb;
+    uint64_t best = ~0ull;
+    for (int64_t r = 0; r < nh; ++r) {
+        const uint64_t k = route_key(a.route_seed, j, e, a.hold[hb + r], (int)r);
+        if ((!use_after || k > after) && k < best) best = k;
+    }
+    return best == ~0ull ? -1 : hb + (int64_t)(uint32_t)best;
+}
+
+// W's stored row elements of the lane to FP32 registers (global memory).
+template <int VEC, bool BF>
+__device__ __forceinline__ void row_gload(const char *p, float (&v)[VEC]) {
+    if constexpr (!BF) {
+        vload<VEC>((const float *)p, v);
+    } else if constexpr (VEC == 1) {
+        v[0] = __uint_as_float((uint32_t)*(const uint16_t *)p << 16);
+    } else if constexpr (VEC == 2) {
+        const uint32_t t = *(const uint32_t *)p;
+        v[0] = __uint_as_float(t << 16);
+        v[1] = __uint_as_float(t & 0xFFFF0000u);
+    } else {
+        const uint2 t = *(const uint2 *)p;
+        v[0] = __uint_as_float(t.x << 16);
+        v[1] = __uint_as_float(t.x & 0xFFFF0000u);
+        v[2] = __uint_as_float(t.y << 16);
+        v[3] = __uint_as_float(t.y & 0xFFFF0000u);
+    }
+}
+
+// Compute wave of the asynchronous schedule: takes the worker's visits in the order the
+// memory wave announces them; for each, runs the SGD updates of its own ratings of the
+// item (its rows, ascending) and passes the item to the next wave.
+template <int VEC, bool BF>
+struct AsyncComputeWave {
+    static constexpr int ES = BF ? 2 : 4;
+    const TrainArgs &a;
+    const Lds &L;
+    const int q, w, lane, kp, loff, rb;
+    const RatingRec *rs;  // the wave's records, grouped by local item
+    const int64_t cnt;
+    const int64_t vb;     // first visit record of the worker (local item 0)
+    const int nv;         // local items
+    lds_float *const items;
+    char *const wlane;
+    uint64_t nrat = 0, t_wait = 0;
+
+    __device__ AsyncComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0, int64_t cnt_)
+        : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC), rb(a_.kp * ES), rs(a_.recs + r0),
+          cnt(cnt_), vb(a_.vbase[q_]), nv((int)(a_.vbase[q_ + 1] - a_.vbase[q_])),
+          items(to_lds(L_.items) + lane_ * VEC), wlane((char *)a_.W + lane_ * VEC * ES) {}
+
+    // Wait until visit X reaches this wave.  False when the worker stops with no such visit.
+    __device__ __forceinline__ bool wait_visit(const int32_t *word, int X) {
+        if (sync_load(word) > X) return true;
+        const uint64_t t0 = wall_clock64();
+        while (sync_load(word) <= X) {
+            if (sync_load(&L.ctl[1])) return sync_load(word) > X;
+            if (wall_clock64() - t0 > kWaitLimitTicks) {
+                if (lane == 0) {
+                    note_timeout(a.diag, q, w, X, sync_load(word), 100, sync_load(&L.ctl[0]));
+                    raise_abort(a.abort_flag, L, 1u);
+                }
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        return true;
+    }
+
+    __device__ void run() {
+        const double tl = (double)(a.epoch0 + lane);
+        const float s_tab = (float)(a.alpha / (1.0 + a.beta * (tl > 0.0 ? pow(tl, a.gamma) : 0.0)));
+        const float c_tab = 1.0f - s_tab * a.lambda;
+        const int32_t *word = w == 0 ? &L.ctl[0] : &L.flag[w - 1];
+        for (int X = 0;; ++X) {
+            const uint64_t t0 = tick(a.timing);
+            if (!wait_visit(word, X)) break;
+            compiler_fence();
+            t_wait += tick(a.timing) - t0;
+            const int sl = X & (a.slots - 1);
+            const int x = __builtin_amdgcn_readfirstlane(L.sx[sl]);
+            const int erel = __builtin_amdgcn_readfirstlane(L.se[sl]);
+            const int item = __builtin_amdgcn_readfirstlane(L.item[sl]);
+            const int64_t v = vb + x;
+            const int64_t b = a.xoff[v * a.nw + w];
+            const int64_t e = x + 1 < nv ? (int64_t)a.xoff[(v + 1) * a.nw + w] : cnt;
+            if (b < e) {
+                float h[VEC];
+                lload<VEC>(items + (size_t)sl * kp, h);
+                const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s_tab), erel & 63));
+                const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c_tab), erel & 63));
+                for (int64_t r = b; r < e; ++r) {
+                    const u32x4v rv = *(const u32x4v *)(rs + r);
+                    const int row = __builtin_amdgcn_readfirstlane((int)rv.x);
+                    const float rating = __int_as_float(__builtin_amdgcn_readfirstlane((int)rv.y));
+                    float wv[VEC];
+                    row_gload<VEC, BF>(wlane + (int64_t)row * rb, wv);
+                    // Section 2.3: one residual, both vectors from their values before the update.
+                    float d = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) d = fmaf(wv[i], h[i], d);
+                    d = wave_sum<4>(d);
+                    const float se = s * (rating - d);
+                    float nw[VEC];
+#pragma unroll
+                    for (int i = 0; i < VEC; ++i) {
+                        nw[i] = fmaf(se, h[i], c * wv[i]);
+                        h[i] = fmaf(se, wv[i], c * h[i]);
+                    }
+                    round_stored<VEC, BF>(a, loff, nw, row, item, a.epoch0 + erel);
+                    row_gstore<VEC, BF>(wlane + (int64_t)row * rb, nw);
+                }
+                nrat += (uint64_t)(e - b);
+                lstore<VEC>(items + (size_t)sl * kp, h);
+                wait_lgkm();
+            }
+            if (lane == 0) sync_store(&L.flag[w], X + 1);
+        }
+        wait_vm();
+        if (a.wstats && lane == 0) {
+            unsigned long long *ws = (unsigned long long *)(a.wstats + (int64_t)q * kWStatCount);
+            atomicAdd(&ws[kWStatItemWait], (unsigned long long)t_wait);
+            atomicAdd(&ws[kWStatRatings], (unsigned long long)nrat);
+        }
+    }
+};
+
+// Memory wave of the asynchronous schedule.
+struct AsyncMemoryWave {
+    const TrainArgs &a;
+    const Lds &L;
+    MemoryWave io;        // item loads and write-backs
+    const int q, lane, S;
+    const int64_t qb;     // inbound queue: [qb, qb + cap)
+    const int64_t cap;
+    int Xl = 0, Xr = 0;   // visits taken / passed on
+    int64_t head = 0;     // next queue position to take
+    // lane s < S: the visit in slot s: item, holder entry, epoch, visit number of the item
+    int f_j = 0, f_g = 0, f_e = 0, f_seq = 0;
+    uint64_t iters = 0, misses = 0;
+
+    __device__ AsyncMemoryWave(const TrainArgs &a_, const Lds &L_, int q_, int lane_)
+        : a(a_), L(L_), io(a_, L_, q_, lane_), q(q_), lane(lane_), S(a_.slots), qb(a_.vbase[q_]),
+          cap(a_.vbase[q_ + 1] - a_.vbase[q_]) {}
+
+    __device__ void run() {
+        const uint64_t t_start = tick(a.timing);
+        const int Smask = S - 1;
+        uint64_t t_prog = wall_clock64();
+        while (true) {
+            ++iters;
+            bool progress = false;
+            // 1. Pass on the visits the last compute wave has finished (in order).
+            {
+                int nr = sync_load(&L.flag[a.nw - 1]) - Xr;
+                if (nr > 64) nr = 64;
+                if (nr > 0) {
+                    const int X = Xr + lane;
+                    const int sl = X & Smask;
+                    const int j = __shfl(f_j, sl), g = __shfl(f_g, sl), e = __shfl(f_e, sl), seq = __shfl(f_seq, sl);
+                    io.write_back(j, sl, nr);
+                    int64_t ng = -1;
+                    int ne = e;
+                    if (lane < nr) {
+                        const int64_t hb = a.hoff[j];
+                        const uint64_t cur = route_key(a.route_seed, j, e, q, (int)(g - hb));
+                        ng = route_next(a, j, e, cur, true);
+                        if (ng < 0 && e + 1 < a.epoch0 + a.epochs) {
+                            ne = e + 1;
+                            ng = route_next(a, j, ne, 0, false);
+                        }
+                        if (ng >= 0) __hip_atomic_store(a.itep + j, ne, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(a.ihop + j, seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    wait_vm();  // the items and their state are in place before they move on
+                    if (lane < nr && ng >= 0) {
+                        const int q2 = a.hold[ng];
+                        const int64_t b2 = a.vbase[q2], cap2 = a.vbase[q2 + 1] - b2;
+                        const uint32_t pos = atomicAdd(a.qtail + q2, 1u);
+                        const uint64_t ent = ((uint64_t)(pos + 1u) << 32) | (uint32_t)ng;
+                        __hip_atomic_store(a.queue + b2 + (int64_t)(pos % (uint64_t)cap2), ent, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    const int np = __popcll(__builtin_amdgcn_ballot_w64(lane < nr && ng < 0));
+                    if (np > 0 && lane == 0) atomicAdd(a.parked, (uint32_t)np);
+                    Xr += nr;
+                    progress = true;
+                }
+            }
+            // 2. Take over arrived items, in arrival order, as far as slots allow.
+            {
+                int room = Xr + S - Xl;
+                if (room > 64) room = 64;
+                if (room > 0 && cap > 0) {
+                    uint64_t ent = 0;
+                    bool valid = false;
+                    if (lane < room) {
+                        ent = __hip_atomic_load(a.queue + qb + (head + lane) % cap, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+                        valid = (uint32_t)(ent >> 32) == (uint32_t)(head + lane + 1);
+                    }
+                    const int nt = leading_run(__builtin_amdgcn_ballot_w64(valid));
+                    if (nt > 0) {
+                        int j = 0, x = 0, e = 0, seq = 0;
+                        const int g = (int)(uint32_t)ent;
+                        if (lane < nt) {
+                            j = a.hitem[g];
+                            x = a.hx[g];
+                            e = __hip_atomic_load(a.itep + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            seq = __hip_atomic_load(a.ihop + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                        for (int t = 0; t < nt; ++t) io.load_item(__shfl(j, t), (Xl + t) & Smask);
+                        if (lane < nt) {
+                            const int sl = (Xl + lane) & Smask;
+                            L.sx[sl] = x;
+                            L.se[sl] = e - a.epoch0;
+                            L.item[sl] = j;
+                        }
+                        {
+                            const int t = (lane - Xl) & Smask;
+                            const int tj = __shfl(j, t), tg = __shfl(g, t), te = __shfl(e, t), ts = __shfl(seq, t);
+                            if (lane < S && t < nt) {
+                                f_j = tj;
+                                f_g = tg;
+                                f_e = te;
+                                f_seq = ts;
+                            }
+                        }
+                        if (a.trace) {
+                            int64_t base = 0;
+                            if (lane == 0)
+                                base = (int64_t)atomicAdd((unsigned long long *)a.trace_len, (unsigned long long)nt);
+                            base = __shfl(base, 0);
+                            if (lane < nt && base + lane < a.trace_cap) {
+                                int32_t *tr = a.trace + 4 * (base + lane);
+                                tr[0] = q;
+                                tr[1] = j;
+                                tr[2] = e;
+                                tr[3] = seq;
+                            }
+                        }
+                        head += nt;
+                        Xl += nt;
+                        wait_vm();    // the item vectors are in LDS
+                        wait_lgkm();  // and so are the slots' descriptions
+                        if (lane == 0) sync_store(&L.ctl[0], Xl);
+                        progress = true;
+                    } else if (room > 0) {
+                        ++misses;
+                    }
+                }
+            }
+            // 3. Done when every item has finished the launch's epochs and nothing is held.
+            if (Xr == Xl &&
+                (int64_t)__hip_atomic_load(a.parked, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.active)
+                break;
+            if (progress) {
+                t_prog = wall_clock64();
+            } else {
+                if (sync_load(&L.ctl[1]) != 0 ||
+                    __hip_atomic_load(a.abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                    break;
+                if (wall_clock64() - t_prog > kWaitLimitTicks) {
+                    if (lane == 0) {
+                        note_timeout(a.diag, q, -1, Xr, Xl, (int)head, (int)__hip_atomic_load(
+                                         a.parked, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                        raise_abort(a.abort_flag, L, 1u);
+                    }
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        wait_vm();
+        if (lane == 0) sync_store(&L.ctl[1], 1);  // compute waves: no more visits
+        if (a.wstats && lane == 0) {
+            unsigned long long *ws = (unsigned long long *)(a.wstats + (int64_t)q * kWStatCount);
+            atomicAdd(&ws[kWStatMemTotal], (unsigned long long)(tick(a.timing) - t_start));
+            atomicAdd(&ws[kWStatMemIters], (unsigned long long)iters);
+            atomicAdd(&ws[kWStatVisits], (unsigned long long)Xl);
+            atomicAdd(&ws[kWStatPollMiss], (unsigned long long)misses);
+        }
+    }
+};
+
+template <int VEC, bool BF>
+__global__ __launch_bounds__(1024) void k_worker_async(TrainArgs a) {
+    extern __shared__ float4 lds4[];
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int q = blockIdx.x;
+    const Lds L = lds_layout(lds4, a.kp, a.nw, a.slots, 0, BF ? 2 : 4);
+    if (threadIdx.x < kMaxWaves + 1) L.flag[threadIdx.x] = 0;
+    if (threadIdx.x < 2) L.ctl[threadIdx.x] = 0;
+    __syncthreads();
+    if (q >= a.p || a.epochs <= 0) return;
+    if (wave < a.nw) {
+        const int64_t i0 = a.rbase[(int64_t)q * a.nw + wave], i1 = a.rbase[(int64_t)q * a.nw + wave + 1];
+        AsyncComputeWave<VEC, BF> cw(a, L, q, wave, lane, i0, i1 - i0);
+        cw.run();
+    } else if (wave == a.nw) {
+        AsyncMemoryWave mw(a, L, q, lane);
+        mw.run();
+    }
+}
+
+// Seeding: the first holder of every item in the launch's first epoch (sort key = that
+// worker; p for an item without ratings), and the item's epoch.
+__global__ void k_seed_first(TrainArgs a, int64_t n, uint32_t *key, uint32_t *val, int32_t *first) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += stride) {
+        const int64_t g = route_next(a, (int)j, a.epoch0, 0, false);
+        first[j] = (int32_t)g;
+        key[j] = g >= 0 ? (uint32_t)a.hold[g] : (uint32_t)a.p;
+        val[j] = (uint32_t)j;
+        a.itep[j] = a.epoch0;
+    }
+}
+
+// Queue entry i of the sorted seeding order: position i - (first position of its worker).
+__global__ void k_seed_write(TrainArgs a, int64_t n, const uint32_t *key_s, const uint32_t *val_s,
+                             const int32_t *first) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t q = key_s[i];
+        if (q >= (uint32_t)a.p) continue;
+        int64_t lo = 0, hi = i;  // first position of worker q in the sorted keys
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (key_s[mid] < q) lo = mid + 1; else hi = mid;
+        }
+        const uint32_t pos = (uint32_t)(i - lo);
+        a.queue[a.vbase[q] + pos] = ((uint64_t)(pos + 1u) << 32) | (uint32_t)first[val_s[i]];
+        atomicAdd(a.qtail + q, 1u);
+    }
+}
+
 // One worker: workgroup q of the problem described by `a`.
 template <int VEC, int D, bool BF>
 __device__ __forceinline__ void worker_body(const TrainArgs &a, int q) {
@@ -1003,6 +1376,45 @@ hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t wind
 
 hipError_t launch_train(const TrainArgs &a, hipStream_t st) {
     return a.wbytes == 2 ? launch_b<true>(a, nullptr, nullptr, st) : launch_b<false>(a, nullptr, nullptr, st);
+}
+
+size_t async_scratch_bytes(int64_t n, int32_t p) {
+    size_t sort_bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                             (uint32_t *)nullptr, (uint32_t *)nullptr, (int)(n > 0 ? n : 1), 0, 32);
+    (void)p;
+    return (size_t)(5 * (n > 0 ? n : 1)) * 4 + sort_bytes + 256;
+}
+
+hipError_t launch_train_async(const TrainArgs &a, const int64_t *vbase, void *scratch, size_t scratch_bytes,
+                              hipStream_t st) {
+    (void)vbase;
+    const int64_t n = a.n;
+    if (scratch_bytes < async_scratch_bytes(n, a.p)) return hipErrorInvalidValue;
+    uint32_t *key = (uint32_t *)scratch, *val = key + n, *key_s = val + n, *val_s = key_s + n;
+    int32_t *first = (int32_t *)(val_s + n);
+    void *tmp = (void *)(((uintptr_t)(first + n) + 255) & ~(uintptr_t)255);
+    size_t tmp_bytes = scratch_bytes - ((char *)tmp - (char *)scratch);
+    hipError_t e;
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_seed_first, dim3(grid > 0 ? grid : 1), dim3(256), 0, st, a, n, key, val, first);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, key, key_s, val, val_s, (int)n, 0, 32, st)) !=
+        hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_seed_write, dim3(grid > 0 ? grid : 1), dim3(256), 0, st, a, n, key_s, val_s, first);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t lds = lds_bytes(a.kp, a.nw, a.slots, 0, a.wbytes);
+    if (a.wbytes == 2) {
+        if (a.kp <= 64) hipLaunchKernelGGL((k_worker_async<1, true>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+        else if (a.kp <= 128) hipLaunchKernelGGL((k_worker_async<2, true>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+        else hipLaunchKernelGGL((k_worker_async<4, true>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    } else {
+        if (a.kp <= 64) hipLaunchKernelGGL((k_worker_async<1, false>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+        else if (a.kp <= 128) hipLaunchKernelGGL((k_worker_async<2, false>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+        else hipLaunchKernelGGL((k_worker_async<4, false>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_train_batch(const TrainArgs &shape, int32_t workgroups, const TrainArgs *d_descs,

@@ -1,0 +1,145 @@
+"""The asynchronous schedule (random-permutation circulation, NOMAD_SCHED_PERM) on the GPU.
+
+Its serial order depends on timing, so parity is checked three ways:
+  * exactly, through the recorded visit trace: replaying it in the oracle (each worker's
+    visits in its order, each item's visits in its order) reproduces the GPU factors to
+    the FP32 tolerance, and the trace shows every item visiting every worker that holds
+    its ratings exactly once per epoch;
+  * exactly, with one worker, where the schedule is the ring order;
+  * statistically, against the oracle's own asynchronous emulation: test RMSE after
+    several epochs agrees within 1e-3 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1312_0193_amd as nm
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_1EPOCH = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def make(m, n, nnz, *, k, seed, degrees="uniform", lam=0.05, alpha=0.01, beta=1e-4, gamma=1.0):
+    prob = synth.small_case(m, n, nnz, seed=seed, degrees=degrees, k=k, lam=lam, alpha=alpha, beta=beta,
+                            gamma=gamma, test_frac=0.1)
+    W0, H0 = synth.init_factors(m, n, k, seed)
+    f = lambda x: float(np.float32(x))  # noqa: E731
+    return prob, W0, H0, oracle.Hyper(k, f(lam), f(alpha), f(beta), f(gamma))
+
+
+def run(prob, W0, H0, hp, P, seed, calls, **kw):
+    print(f"[case] perm m={prob.m} n={prob.n} nnz={prob.nnz} k={hp.k} P={P} calls={calls} {kw}", flush=True)
+    model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
+                     beta=hp.beta, gamma=hp.gamma, workers=P, seed=seed, sched="perm", **kw)
+    for e in calls:
+        model.train(e)
+    W, H = model.factors()
+    return model, W.cpu().double().numpy(), H.cpu().double().numpy()
+
+
+def holders(prob, P):
+    row, col = prob.row.numpy(), prob.col.numpy()
+    rs = oracle.partition(prob.m, row, P)
+    q_of = np.searchsorted(rs, row, "right") - 1
+    return {(int(q), int(j)) for q, j in zip(q_of, col)}
+
+
+@pytest.mark.parametrize("case", [
+    # m, n, nnz, k, P, degrees, waves, slots
+    (600, 300, 12_000, 16, 6, "uniform", 3, 4),
+    (2_000, 1_000, 60_000, 100, 32, "zipf", 0, 0),
+    (400, 250, 15_000, 64, 64, "uniform", 8, 2),
+])
+def test_perm_trace_covers_every_visit_once_per_epoch_and_replays(case):
+    m, n, nnz, k, P, degrees, nw, slots = case
+    prob, W0, H0, hp = make(m, n, nnz, k=k, seed=m + P, degrees=degrees)
+    E, seed = 3, 5
+    model, W, H = run(prob, W0, H0, hp, P, seed, [E], record_trace=True, waves_per_worker=nw, item_slots=slots,
+                      collect_stats=True)
+    tr = model.trace()
+    st = model.worker_stats()
+    model.close()
+    vis = holders(prob, P)
+    assert len(tr) == E * len(vis)
+    assert int(st[:, 6].sum()) == E * prob.nnz  # every rating updated once per epoch
+    for e in range(E):
+        te = tr[tr[:, 2] == e]
+        got = sorted((int(a), int(b)) for a, b in te[:, :2])
+        assert got == sorted(vis), e  # each (worker, item) exactly once in epoch e
+    for j in np.unique(tr[:, 1]):
+        seqs = tr[tr[:, 1] == j, 3]
+        assert np.array_equal(np.sort(seqs), np.arange(len(seqs)))
+        # an item's epochs do not overlap: its visits of epoch e come before those of e + 1
+        ep = tr[tr[:, 1] == j][np.argsort(seqs), 2]
+        assert np.all(np.diff(ep) >= 0)
+    order = np.argsort(tr[:, 0], kind="stable")
+    t2 = tr[order]
+    Wr, Hr, _ = oracle.replay(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
+                              H0.numpy(), hp, P, seed, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
+    assert rel(W, Wr) < 2 * TOL_1EPOCH and rel(H, Hr) < 2 * TOL_1EPOCH, (rel(W, Wr), rel(H, Hr))
+
+
+def test_perm_visiting_orders_differ_between_epochs():
+    """The circulation draws a new order every epoch (it is not the ring's fixed one)."""
+    prob, W0, H0, hp = make(800, 60, 20_000, k=16, seed=3)
+    P = 16
+    model, _, _ = run(prob, W0, H0, hp, P, 9, [2], record_trace=True)
+    tr = model.trace()
+    model.close()
+    differ = 0
+    for j in np.unique(tr[:, 1]):
+        rows = tr[tr[:, 1] == j]
+        rows = rows[np.argsort(rows[:, 3])]
+        o0 = rows[rows[:, 2] == 0, 0]
+        o1 = rows[rows[:, 2] == 1, 0]
+        differ += int(not np.array_equal(o0, o1))
+    assert differ >= len(np.unique(tr[:, 1])) // 2
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(waves_per_worker=3, item_slots=2), dict(dtype="bf16")])
+def test_perm_one_worker_is_the_ring_order(kw):
+    prob, W0, H0, hp = make(500, 200, 10_000, k=32, seed=8)
+    _, Wp, Hp = run(prob, W0, H0, hp, 1, 2, [2, 1], **kw)
+    ring = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
+                    beta=hp.beta, gamma=hp.gamma, workers=1, seed=2, **kw)
+    ring.train(3)
+    Wr, Hr = (x.cpu().double().numpy() for x in ring.factors())
+    ring.close()
+    assert np.array_equal(Wp, Wr) and np.array_equal(Hp, Hr)
+
+
+def test_perm_many_epochs_across_launches():
+    prob, W0, H0, hp = make(300, 120, 5_000, k=16, seed=12)
+    model, W, H = run(prob, W0, H0, hp, 8, 4, [66], record_trace=True)  # two launches
+    tr = model.trace()
+    model.close()
+    assert len(tr) == 66 * len(holders(prob, 8))
+    order = np.argsort(tr[:, 0], kind="stable")
+    t2 = tr[order]
+    Wr, Hr, _ = oracle.replay(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
+                              H0.numpy(), hp, 8, 4, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
+    assert rel(W, Wr) < 1e-4 and rel(H, Hr) < 1e-4
+
+
+def test_perm_rmse_matches_oracle_emulation():
+    """Statistical parity with the oracle's asynchronous emulation (its own random
+    interleaving and routing) on the tiny workload after 10 epochs."""
+    prob = synth.tiny()
+    hpd = prob.hp
+    W0, H0 = synth.init_factors(prob.m, prob.n, hpd["k"], 1)
+    f = lambda x: float(np.float32(x))  # noqa: E731
+    hp = oracle.Hyper(hpd["k"], f(hpd["lam"]), f(hpd["alpha"]), f(hpd["beta"]), f(hpd["gamma"]))
+    P, E = 16, 10
+    model, W, H = run(prob, W0, H0, hp, P, 1, [E])
+    r_gpu, _ = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
+    model.close()
+    Wo, Ho, _ = oracle.train_perm(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
+                                  H0.numpy(), hp, P, 1, E, 77)
+    r_orc = oracle.rmse(prob.m, prob.n, prob.test_row.numpy(), prob.test_col.numpy(), prob.test_val.numpy(), Wo, Ho)
+    assert abs(r_gpu - r_orc) < 1e-3 * r_orc, (r_gpu, r_orc)
