@@ -971,7 +971,10 @@ __device__ __forceinline__ void row_gload(const char *p, float (&v)[VEC]) {
 
 // Compute wave of the asynchronous schedule: takes the worker's visits in the order the
 // memory wave announces them; for each, runs the SGD updates of its own ratings of the
-// item (its rows, ascending) and passes the item to the next wave.
+// item (its rows, ascending) and passes the item to the next wave.  A visit's records are
+// read 64 at a time into lane registers (one vector load; lane l holds the l-th); the row
+// of the next rating is loaded while the current one is updated (rows of one visit are
+// distinct, so the load never overtakes a store of the same row).
 template <int VEC, bool BF>
 struct AsyncComputeWave {
     static constexpr int ES = BF ? 2 : 4;
@@ -1009,11 +1012,31 @@ struct AsyncComputeWave {
         return true;
     }
 
+    // One update (section 2.3: one residual, both vectors from their values before it).
+    __device__ __forceinline__ void update(float (&h)[VEC], const float (&wv)[VEC], int row, float rating, float s,
+                                           float c, int item, int t) {
+        float d = 0.0f;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) d = fmaf(wv[i], h[i], d);
+        d = wave_sum<4>(d);
+        const float se = s * (rating - d);
+        float nw[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            nw[i] = fmaf(se, h[i], c * wv[i]);
+            h[i] = fmaf(se, wv[i], c * h[i]);
+        }
+        round_stored<VEC, BF>(a, loff, nw, row, item, t);
+        row_gstore<VEC, BF>(wlane + (int64_t)row * rb, nw);
+    }
+
     __device__ void run() {
         const double tl = (double)(a.epoch0 + lane);
         const float s_tab = (float)(a.alpha / (1.0 + a.beta * (tl > 0.0 ? pow(tl, a.gamma) : 0.0)));
         const float c_tab = 1.0f - s_tab * a.lambda;
         const int32_t *word = w == 0 ? &L.ctl[0] : &L.flag[w - 1];
+        typedef const __attribute__((address_space(4))) int32_t *cint;
+        const cint xo = (cint)a.xoff;
         for (int X = 0;; ++X) {
             const uint64_t t0 = tick(a.timing);
             if (!wait_visit(word, X)) break;
@@ -1021,36 +1044,52 @@ struct AsyncComputeWave {
             t_wait += tick(a.timing) - t0;
             const int sl = X & (a.slots - 1);
             const int x = __builtin_amdgcn_readfirstlane(L.sx[sl]);
-            const int erel = __builtin_amdgcn_readfirstlane(L.se[sl]);
-            const int item = __builtin_amdgcn_readfirstlane(L.item[sl]);
             const int64_t v = vb + x;
-            const int64_t b = a.xoff[v * a.nw + w];
-            const int64_t e = x + 1 < nv ? (int64_t)a.xoff[(v + 1) * a.nw + w] : cnt;
+            const int64_t b = xo[v * a.nw + w];
+            const int64_t e = x + 1 < nv ? (int64_t)xo[(v + 1) * a.nw + w] : cnt;
             if (b < e) {
+                const int erel = __builtin_amdgcn_readfirstlane(L.se[sl]);
+                const int item = __builtin_amdgcn_readfirstlane(L.item[sl]);
+                const int t = a.epoch0 + erel;
                 float h[VEC];
                 lload<VEC>(items + (size_t)sl * kp, h);
                 const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s_tab), erel & 63));
                 const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c_tab), erel & 63));
-                for (int64_t r = b; r < e; ++r) {
-                    const u32x4v rv = *(const u32x4v *)(rs + r);
-                    const int row = __builtin_amdgcn_readfirstlane((int)rv.x);
-                    const float rating = __int_as_float(__builtin_amdgcn_readfirstlane((int)rv.y));
-                    float wv[VEC];
-                    row_gload<VEC, BF>(wlane + (int64_t)row * rb, wv);
-                    // Section 2.3: one residual, both vectors from their values before the update.
-                    float d = 0.0f;
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) d = fmaf(wv[i], h[i], d);
-                    d = wave_sum<4>(d);
-                    const float se = s * (rating - d);
-                    float nw[VEC];
-#pragma unroll
-                    for (int i = 0; i < VEC; ++i) {
-                        nw[i] = fmaf(se, h[i], c * wv[i]);
-                        h[i] = fmaf(se, wv[i], c * h[i]);
+                for (int64_t r0 = b; r0 < e; r0 += 64) {
+                    const int nb = (int)(e - r0 < 64 ? e - r0 : 64);
+                    // lane l: record r0 + l (row, rating)
+                    int crow = 0;
+                    float crat = 0.0f;
+                    if (lane < nb) {
+                        const u32x2v rv = *(const u32x2v *)(rs + r0 + lane);
+                        crow = (int)rv.x;
+                        crat = __uint_as_float(rv.y);
                     }
-                    round_stored<VEC, BF>(a, loff, nw, row, item, a.epoch0 + erel);
-                    row_gstore<VEC, BF>(wlane + (int64_t)row * rb, nw);
+                    // two row buffers, each loaded one update before it is used
+                    float wa[VEC], wb[VEC];
+                    int ra = __builtin_amdgcn_readlane(crow, 0), rbw = 0;
+                    row_gload<VEC, BF>(wlane + (int64_t)ra * rb, wa);
+                    // (pairs in a branch-free body with unconditional loads, the one after the
+                    // last pair clamped to the batch's last rating, so that the compiler can
+                    // count them: a conditional load or store makes it wait for everything)
+                    const int npair = nb & ~1;
+                    // a store after the first load, as every pass of the loop leaves one after its
+                    // last load: the compiler then finds the same count on both ways into the loop
+                    a.dummy[(int64_t)q * kMaxWaves + w] = 0.0f;  // every lane: no branch
+                    for (int l = 0; l < npair; l += 2) {
+                        rbw = __builtin_amdgcn_readlane(crow, l + 1);
+                        row_gload<VEC, BF>(wlane + (int64_t)rbw * rb, wb);
+                        update(h, wa, ra, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l)), s, c,
+                               item, t);
+                        const int ra2 = __builtin_amdgcn_readlane(crow, l + 2 < nb ? l + 2 : nb - 1);
+                        row_gload<VEC, BF>(wlane + (int64_t)ra2 * rb, wa);
+                        update(h, wb, rbw, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + 1)),
+                               s, c, item, t);
+                        ra = ra2;
+                    }
+                    if (nb & 1)
+                        update(h, wa, ra, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), nb - 1)), s,
+                               c, item, t);
                 }
                 nrat += (uint64_t)(e - b);
                 lstore<VEC>(items + (size_t)sl * kp, h);
@@ -1225,13 +1264,13 @@ struct AsyncMemoryWave {
     }
 };
 
-template <int VEC, bool BF>
+template <int VEC, int D, bool BF>
 __global__ __launch_bounds__(1024) void k_worker_async(TrainArgs a) {
     extern __shared__ float4 lds4[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     const int q = blockIdx.x;
-    const Lds L = lds_layout(lds4, a.kp, a.nw, a.slots, 0, BF ? 2 : 4);
+    const Lds L = lds_layout(lds4, a.kp, a.nw, a.slots, D, BF ? 2 : 4);
     if (threadIdx.x < kMaxWaves + 1) L.flag[threadIdx.x] = 0;
     if (threadIdx.x < 2) L.ctl[threadIdx.x] = 0;
     __syncthreads();
@@ -1378,6 +1417,30 @@ hipError_t launch_train(const TrainArgs &a, hipStream_t st) {
     return a.wbytes == 2 ? launch_b<true>(a, nullptr, nullptr, st) : launch_b<false>(a, nullptr, nullptr, st);
 }
 
+namespace {
+template <int VEC, int D, bool BF>
+hipError_t launch_async_t(const TrainArgs &a, hipStream_t st) {
+    const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D, BF ? 2 : 4);
+    hipLaunchKernelGGL((k_worker_async<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    return hipGetLastError();
+}
+template <int VEC, bool BF>
+hipError_t launch_async_v(const TrainArgs &a, hipStream_t st) {
+    if (a.window <= 8) return launch_async_t<VEC, 8, BF>(a, st);
+    if (a.window <= 16) return launch_async_t<VEC, 16, BF>(a, st);
+    return launch_async_t<VEC, 32, BF>(a, st);
+}
+template <bool BF>
+hipError_t launch_async_k(const TrainArgs &a, hipStream_t st) {
+    if (a.kp <= 64) return launch_async_v<1, BF>(a, st);
+    if (a.kp <= 128) return launch_async_v<2, BF>(a, st);
+    return launch_async_v<4, BF>(a, st);
+}
+hipError_t launch_async_b(const TrainArgs &a, hipStream_t st) {
+    return a.wbytes == 2 ? launch_async_k<true>(a, st) : launch_async_k<false>(a, st);
+}
+}  // namespace
+
 size_t async_scratch_bytes(int64_t n, int32_t p) {
     size_t sort_bytes = 0;
     (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (uint32_t *)nullptr, (uint32_t *)nullptr,
@@ -1404,17 +1467,7 @@ hipError_t launch_train_async(const TrainArgs &a, const int64_t *vbase, void *sc
         return e;
     hipLaunchKernelGGL(k_seed_write, dim3(grid > 0 ? grid : 1), dim3(256), 0, st, a, n, key_s, val_s, first);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t lds = lds_bytes(a.kp, a.nw, a.slots, 0, a.wbytes);
-    if (a.wbytes == 2) {
-        if (a.kp <= 64) hipLaunchKernelGGL((k_worker_async<1, true>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
-        else if (a.kp <= 128) hipLaunchKernelGGL((k_worker_async<2, true>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
-        else hipLaunchKernelGGL((k_worker_async<4, true>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
-    } else {
-        if (a.kp <= 64) hipLaunchKernelGGL((k_worker_async<1, false>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
-        else if (a.kp <= 128) hipLaunchKernelGGL((k_worker_async<2, false>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
-        else hipLaunchKernelGGL((k_worker_async<4, false>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
-    }
-    return hipGetLastError();
+    return launch_async_b(a, st);
 }
 
 hipError_t launch_train_batch(const TrainArgs &shape, int32_t workgroups, const TrainArgs *d_descs,
