@@ -1065,31 +1065,38 @@ struct AsyncComputeWave {
                         crow = (int)rv.x;
                         crat = __uint_as_float(rv.y);
                     }
-                    // two row buffers, each loaded one update before it is used
-                    float wa[VEC], wb[VEC];
-                    int ra = __builtin_amdgcn_readlane(crow, 0), rbw = 0;
-                    row_gload<VEC, BF>(wlane + (int64_t)ra * rb, wa);
-                    // (pairs in a branch-free body with unconditional loads, the one after the
-                    // last pair clamped to the batch's last rating, so that the compiler can
-                    // count them: a conditional load or store makes it wait for everything)
-                    const int npair = nb & ~1;
-                    // a store after the first load, as every pass of the loop leaves one after its
-                    // last load: the compiler then finds the same count on both ways into the loop
-                    a.dummy[(int64_t)q * kMaxWaves + w] = 0.0f;  // every lane: no branch
-                    for (int l = 0; l < npair; l += 2) {
-                        rbw = __builtin_amdgcn_readlane(crow, l + 1);
-                        row_gload<VEC, BF>(wlane + (int64_t)rbw * rb, wb);
-                        update(h, wa, ra, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l)), s, c,
-                               item, t);
-                        const int ra2 = __builtin_amdgcn_readlane(crow, l + 2 < nb ? l + 2 : nb - 1);
-                        row_gload<VEC, BF>(wlane + (int64_t)ra2 * rb, wa);
-                        update(h, wb, rbw, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + 1)),
-                               s, c, item, t);
-                        ra = ra2;
+                    // Sixteen row buffers: the row of rating l + 16 is loaded while rating l is
+                    // updated.  Groups of four updates run in a branch-free body with
+                    // unconditional loads (indices past the batch clamped to its last rating),
+                    // and the way into the loop leaves the same pattern of loads and stores as
+                    // a pass of it, so that the compiler's wait counts stay exact (a
+                    // conditional load or store makes it wait for everything).
+                    constexpr int NB = 16;
+                    float wbuf[NB][VEC];
+                    int rbuf[NB];
+                    float dummy0 = 0.0f;
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        rbuf[k] = __builtin_amdgcn_readlane(crow, k < nb ? k : nb - 1);
+                        row_gload<VEC, BF>(wlane + (int64_t)rbuf[k] * rb, wbuf[k]);
+                        if (k + 1 < NB) a.dummy[(int64_t)q * kMaxWaves + w] = dummy0;  // every lane: no branch
                     }
-                    if (nb & 1)
-                        update(h, wa, ra, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), nb - 1)), s,
-                               c, item, t);
+                    int l = 0;
+                    for (; l + NB <= nb; l += NB) {
+#pragma unroll
+                        for (int k = 0; k < NB; ++k) {
+                            update(h, wbuf[k], rbuf[k],
+                                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, c, item, t);
+                            const int nl = l + k + NB;
+                            rbuf[k] = __builtin_amdgcn_readlane(crow, nl < nb ? nl : nb - 1);
+                            row_gload<VEC, BF>(wlane + (int64_t)rbuf[k] * rb, wbuf[k]);
+                        }
+                    }
+#pragma unroll
+                    for (int k = 0; k < NB - 1; ++k)
+                        if (l + k < nb)
+                            update(h, wbuf[k], rbuf[k],
+                                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, c, item, t);
                 }
                 nrat += (uint64_t)(e - b);
                 lstore<VEC>(items + (size_t)sl * kp, h);
@@ -1426,9 +1433,7 @@ hipError_t launch_async_t(const TrainArgs &a, hipStream_t st) {
 }
 template <int VEC, bool BF>
 hipError_t launch_async_v(const TrainArgs &a, hipStream_t st) {
-    if (a.window <= 8) return launch_async_t<VEC, 8, BF>(a, st);
-    if (a.window <= 16) return launch_async_t<VEC, 16, BF>(a, st);
-    return launch_async_t<VEC, 32, BF>(a, st);
+    return launch_async_t<VEC, 8, BF>(a, st);  // the row window of the LDS layout is not used here
 }
 template <bool BF>
 hipError_t launch_async_k(const TrainArgs &a, hipStream_t st) {
