@@ -3,8 +3,9 @@
 A step is one epoch of NOMAD SGD (every training rating updated once) over the
 Netflix-shaped medium workload: 480,189 x 17,770, 100M Zipf(1.1) cells (1.4M held out),
 integer 1..5 ratings from a planted rank-30 model, k = 100, lambda = 0.05, FP32 factors,
-fixed token-passing (ring) schedule.  Inputs are synthetic, generated on the GPU and
-resident in HBM before timing starts.
+asynchronous schedule with the random-permutation circulation (--sched ring for the fixed
+token-passing order).  Inputs are synthetic, generated on the GPU and resident in HBM
+before timing starts.
 
 Prints one JSON line (stdout).  Progress goes to stderr.
 """
@@ -36,8 +37,7 @@ def bytes_per_update(k: int, s_w: int, s_h: int, n: int, nnz_train: int, p_ref: 
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1312_0193_amd", "csrc", "train.hip")
-KERNEL_NAME = "k_worker"
-COUNTERS = os.path.join(ROOT, "profiles", "k_worker_medium_counters.txt")
+KERNELS = {"perm": "k_worker_async", "ring": "k_worker"}
 COPY_BYTES = 2 << 30  # calibration copy: 2 GiB read + 2 GiB written per dispatch
 
 
@@ -47,14 +47,19 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def counters_path(kernel: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}_medium_counters.txt")
+
+
+def measured_traffic(kernel: str):
     """HBM bytes per training launch from the committed rocprofv3 counter summary, each
     counter scaled by what it reads for a plain copy of known size; None when the
     summary is missing or was taken on a different kernel source."""
-    if not os.path.exists(COUNTERS):
+    path = counters_path(kernel)
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(COUNTERS):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -80,10 +85,10 @@ def copy_calibrate(reps=3):
     print(json.dumps({"copy_bytes": COPY_BYTES, "reps": reps}), flush=True)
 
 
-def cpu_baseline(prob, W0, H0, hp, P, seed, row_fraction=0.1):
+def cpu_baseline(prob, W0, H0, hp, P, seed, sched, row_fraction=0.1):
     """The FP64 oracle on a bounded sample: the ratings of the first row_fraction of the
     rows (rows carry random Zipf weights, so this is a uniform row sample), one epoch of
-    the same ring schedule, one core."""
+    the same schedule (its asynchronous emulation for perm), one core."""
     import numpy as np
 
     import oracle
@@ -95,12 +100,16 @@ def cpu_baseline(prob, W0, H0, hp, P, seed, row_fraction=0.1):
     W = W0[:m_s].cpu().numpy()
     H = H0.cpu().numpy()
     log(f"cpu baseline: oracle on rows [0,{m_s}) = {r.size} ratings")
+    h = oracle.Hyper(hp["k"], hp["lam"], hp["alpha"], hp["beta"], hp["gamma"])
     t0 = time.perf_counter()
-    oracle.train_ring(m_s, prob.n, r, c, v, W, H, oracle.Hyper(hp["k"], hp["lam"], hp["alpha"], hp["beta"],
-                                                               hp["gamma"]), P, seed, 1)
+    if sched == "perm":
+        oracle.train_perm(m_s, prob.n, r, c, v, W, H, h, P, seed, 1, 1)
+    else:
+        oracle.train_ring(m_s, prob.n, r, c, v, W, H, h, P, seed, 1)
     dt = time.perf_counter() - t0
+    what = "random-permutation schedule (asynchronous emulation)" if sched == "perm" else "ring order"
     return {"value": r.size / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 epoch, ring order, {P} workers, FP64, rows [0,{m_s}) of the workload "
+            "sample": f"1 epoch, {what}, {P} workers, FP64, rows [0,{m_s}) of the workload "
                       f"({r.size} ratings), layout included, {dt:.1f} s"}
 
 
@@ -112,6 +121,8 @@ def main():
     ap.add_argument("--workers", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0, help="compute waves per worker (0 = library default)")
     ap.add_argument("--item-slots", type=int, default=0, help="item slots per worker (0 = library default)")
+    ap.add_argument("--sched", choices=["perm", "ring"], default="perm",
+                    help="perm: asynchronous random-permutation circulation; ring: fixed token-passing order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="run only the plain copy used to calibrate the HBM byte counters")
@@ -141,7 +152,7 @@ def main():
     seed = 2
     model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp["k"], lam=hp["lam"],
                      alpha=hp["alpha"], beta=hp["beta"], gamma=hp["gamma"], workers=args.workers, seed=seed,
-                     waves_per_worker=args.waves, item_slots=args.item_slots)
+                     waves_per_worker=args.waves, item_slots=args.item_slots, sched=args.sched)
     P = model.workers
     st0 = model.train(0)
     log(f"layout {st0.layout_seconds:.3f} s, workers {P}")
@@ -164,7 +175,8 @@ def main():
     B = bytes_per_update(hp["k"], 4, 4, prob.n, nnz)
     avg_kernel = sum(ksec) / len(ksec)
     achieved = B * nnz / avg_kernel
-    traffic = measured_traffic()
+    kernel = KERNELS[args.sched]
+    traffic = measured_traffic(kernel)
     out = {
         "metric": METRIC,
         "value": value,
@@ -179,18 +191,18 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "medium: 480189x17770, 100M Zipf(1.1) cells, 1.4M held out, int 1-5 ratings, "
-                               "k=100, lambda=0.05, ring schedule, FP32",
+                               f"k=100, lambda=0.05, {args.sched} schedule, FP32",
                    "global_batch": nnz, "workers": P, "waves_per_worker": model.cfg.waves_per_worker,
                    "item_slots": model.cfg.item_slots, "test_rmse": rmse,
                    "epochs_trained": args.warmup + args.steps, "kernel_source": kernel_source_hash()},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
-                     "bytes_per_update": B, "kernel": KERNEL_NAME, "avg_kernel_ms": avg_kernel * 1e3},
+                     "bytes_per_update": B, "kernel": kernel, "avg_kernel_ms": avg_kernel * 1e3},
     }
     model.close()
     if not args.no_cpu_baseline:
         W0c, H0c = W0.cpu(), H0.cpu()
-        out["cpu_baseline"] = cpu_baseline(prob, W0c, H0c, hp, P, seed)
+        out["cpu_baseline"] = cpu_baseline(prob, W0c, H0c, hp, P, seed, args.sched)
     print(json.dumps(out), flush=True)
 
 
