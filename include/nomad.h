@@ -61,8 +61,14 @@ typedef enum {
  *     updated once per epoch and t = epochs done.  At the start of a call every item is
  *     queued at its first worker (each queue in ascending item order).  The serial order
  *     depends on timing (record_trace gives it); with one worker it is the ring order.
- *     Not available in batches. */
-typedef enum { NOMAD_SCHED_RING = 0, NOMAD_SCHED_PERM = 1 } nomad_sched;
+ *     Not available in batches.
+ *   UNIFORM: asynchronous, Algorithm 1 as printed: after a visit an item goes to a worker
+ *     drawn uniformly from all p (move v of item j: lowbias32(lowbias32(r ^ 0x2545F491 ^ j)
+ *     + v*0x9E3779B9) scaled to [0, p)), also to workers holding none of its ratings,
+ *     which pass it on.  t = the number of earlier visits of the item to the worker (kept
+ *     across calls).  A call of E epochs stops moving items once E * nnz updates are done;
+ *     visits already under way complete, so nomad_stats.updates can exceed E * nnz. */
+typedef enum { NOMAD_SCHED_RING = 0, NOMAD_SCHED_PERM = 1, NOMAD_SCHED_UNIFORM = 2 } nomad_sched;
 
 /* Storage type of W in device memory (H is always held in FP32); arithmetic is always
  * FP32.  NOMAD_BF16: W is rounded to bfloat16 once at nomad_init (nearest-even) and every

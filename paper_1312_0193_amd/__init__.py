@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libnomad.so")
 HEADER = os.path.join(ROOT, "include", "nomad.h")
 
 NOMAD_OK, NOMAD_EINVAL, NOMAD_ENOMEM, NOMAD_EDEVICE, NOMAD_ESTATE, NOMAD_ENOTIMPL = range(6)
-SCHED = {"ring": 0, "perm": 1}
+SCHED = {"ring": 0, "perm": 1, "uniform": 2}
 DTYPE = {"fp32": 0, "bf16": 1}
 ROUND = {"rne": 0, "stochastic": 1}
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENOTIMPL"}

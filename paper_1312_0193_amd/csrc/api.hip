@@ -42,7 +42,9 @@ struct nomad_ctx {
     // Asynchronous schedule: inbound queues, item state, seeding scratch.
     uint64_t *queue = nullptr;
     uint32_t *qtail = nullptr, *parked = nullptr;
-    int32_t *itep = nullptr, *ihop = nullptr;
+    int32_t *itep = nullptr, *ihop = nullptr, *tvis = nullptr;
+    unsigned long long *upd = nullptr;
+    int64_t queue_len = 0;
     void *async_scratch = nullptr;
     size_t async_scratch_bytes = 0;
     // A batch (nomad_init_batched): its problems, each a full context of its own, trained
@@ -98,6 +100,8 @@ void release(nomad_ctx *c) {
     (void)hipFree(c->parked);
     (void)hipFree(c->itep);
     (void)hipFree(c->ihop);
+    (void)hipFree(c->tvis);
+    (void)hipFree(c->upd);
     (void)hipFree(c->async_scratch);
     nomad::free_plan(&c->plan);
     (void)hipFree(c->W);
@@ -215,9 +219,9 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
     if (nnz > 0 && (!d_row || !d_col || !d_val))
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: rating arrays are NULL");
     if (!d_W0 || !d_H0) return fail(nullptr, NOMAD_EINVAL, "nomad_init: initial factors are NULL");
-    if (cfg->sched != NOMAD_SCHED_RING && cfg->sched != NOMAD_SCHED_PERM)
-        return fail(nullptr, NOMAD_EINVAL, "nomad_init: schedule %d is not one of NOMAD_SCHED_RING, NOMAD_SCHED_PERM",
-                    cfg->sched);
+    if (cfg->sched != NOMAD_SCHED_RING && cfg->sched != NOMAD_SCHED_PERM && cfg->sched != NOMAD_SCHED_UNIFORM)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: schedule %d is not one of NOMAD_SCHED_RING, NOMAD_SCHED_PERM, "
+                    "NOMAD_SCHED_UNIFORM", cfg->sched);
     if (cfg->dtype != NOMAD_FP32 && cfg->dtype != NOMAD_BF16)
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: storage type %d is not one of NOMAD_FP32, NOMAD_BF16",
                     cfg->dtype);
@@ -307,18 +311,24 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
                           sizeof(msg));
     if (e != hipSuccess) return bail(hip_fail(c, e, "nomad_init: layout"));
     if (code != 0) return bail(fail(c, (nomad_status)code, "nomad_init: %s", msg));
-    if (cfg->sched == NOMAD_SCHED_PERM) {
+    if (cfg->sched == NOMAD_SCHED_PERM || cfg->sched == NOMAD_SCHED_UNIFORM) {
         if ((e = nomad::build_async_tables(&c->plan, st)) != hipSuccess)
             return bail(hip_fail(c, e, "nomad_init: asynchronous tables"));
         const int64_t nv = c->plan.nvisits > 0 ? c->plan.nvisits : 1;
+        // permutation: a worker's queue holds its local items; uniform routing: any item
+        c->queue_len = cfg->sched == NOMAD_SCHED_UNIFORM ? (int64_t)p * n : nv;
         c->async_scratch_bytes = nomad::async_scratch_bytes(n, p);
-        if ((e = hipMalloc(&c->queue, sizeof(uint64_t) * (size_t)nv)) != hipSuccess ||
+        if ((e = hipMalloc(&c->queue, sizeof(uint64_t) * (size_t)c->queue_len)) != hipSuccess ||
+            (e = hipMalloc(&c->tvis, sizeof(int32_t) * (size_t)nv)) != hipSuccess ||
+            (e = hipMalloc(&c->upd, sizeof(unsigned long long))) != hipSuccess ||
+            (e = hipMemsetAsync(c->tvis, 0, sizeof(int32_t) * (size_t)nv, st)) != hipSuccess ||
             (e = hipMalloc(&c->qtail, sizeof(uint32_t) * (size_t)p)) != hipSuccess ||
             (e = hipMalloc(&c->parked, sizeof(uint32_t))) != hipSuccess ||
             (e = hipMalloc(&c->itep, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
             (e = hipMalloc(&c->ihop, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
             (e = hipMalloc(&c->async_scratch, c->async_scratch_bytes)) != hipSuccess ||
-            (e = hipMemsetAsync(c->ihop, 0, sizeof(int32_t) * (size_t)n, st)) != hipSuccess)
+            (e = hipMemsetAsync(c->ihop, 0, sizeof(int32_t) * (size_t)n, st)) != hipSuccess ||
+            (e = hipMemsetAsync(c->itep, 0, sizeof(int32_t) * (size_t)n, st)) != hipSuccess)
             return bail(hip_fail(c, e, "nomad_init: queues"));
     }
     if ((e = hipEventRecord(c->ev1, st)) != hipSuccess || (e = hipEventSynchronize(c->ev1)) != hipSuccess)
@@ -470,7 +480,10 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         nomad::TrainArgs a{};
         fill_args(c, a);
         if (c->cfg.record_trace) {
-            const int64_t need = c->plan.nvisits * (int64_t)epochs;
+            // uniform routing visits holders a random number of times: room for three times
+            // the expected count
+            const int64_t need = c->plan.nvisits * (int64_t)epochs * (c->cfg.sched == NOMAD_SCHED_UNIFORM ? 3 : 1) +
+                                 (c->cfg.sched == NOMAD_SCHED_UNIFORM ? 1024 : 0);
             if (need > c->trace_cap) {
                 (void)hipFree(c->trace);
                 c->trace = nullptr;
@@ -488,10 +501,14 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         HIPTRY(c, hipMemsetAsync(c->diag, 0, sizeof(int32_t) * 8, st), "train: reset");
         HIPTRY(c, hipMemsetAsync(c->wstats, 0, sizeof(int64_t) * nomad::kWStatCount * (size_t)c->p, st), "train: reset");
         HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
-        // Launches of at most kMaxEpochsPerLaunch epochs (the kernel takes the step sizes
-        // of a launch's epochs from its lanes).
-        if (c->cfg.sched == NOMAD_SCHED_PERM) {
-            a.sched = 1;
+        const bool async = c->cfg.sched == NOMAD_SCHED_PERM || c->cfg.sched == NOMAD_SCHED_UNIFORM;
+        const bool uniform = c->cfg.sched == NOMAD_SCHED_UNIFORM;
+        if (async) {
+            a.sched = uniform ? 2 : 1;
+            a.tvis = c->tvis;
+            a.hcnt = c->plan.hcnt;
+            a.upd = c->upd;
+            a.budget = (unsigned long long)c->nnz * (unsigned long long)epochs;
             a.hold = c->plan.hold;
             a.hx = c->plan.hx;
             a.hitem = c->plan.hitem;
@@ -505,13 +522,15 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
             a.active = c->plan.active;
             a.route_seed = (uint32_t)(c->cfg.seed >> 32) ^ (uint32_t)c->cfg.seed ^ 0x6a09e667u;
         }
+        if (uniform) HIPTRY(c, hipMemsetAsync(c->upd, 0, sizeof(unsigned long long), st), "train: reset");
+        // Launches of at most kMaxEpochsPerLaunch epochs (one launch per call for uniform
+        // routing, which stops on its update budget instead).
         for (int32_t done = 0; done < epochs;) {
-            const int32_t ne = std::min(epochs - done, (int32_t)nomad::kMaxEpochsPerLaunch);
+            const int32_t ne = uniform ? epochs : std::min(epochs - done, (int32_t)nomad::kMaxEpochsPerLaunch);
             a.epoch0 = (int32_t)(c->epochs_done + done);
             a.epochs = ne;
-            if (c->cfg.sched == NOMAD_SCHED_PERM) {
-                const int64_t nv = c->plan.nvisits > 0 ? c->plan.nvisits : 1;
-                HIPTRY(c, hipMemsetAsync(c->queue, 0, sizeof(uint64_t) * (size_t)nv, st), "train: reset");
+            if (async) {
+                HIPTRY(c, hipMemsetAsync(c->queue, 0, sizeof(uint64_t) * (size_t)c->queue_len, st), "train: reset");
                 HIPTRY(c, hipMemsetAsync(c->qtail, 0, sizeof(uint32_t) * (size_t)c->p, st), "train: reset");
                 HIPTRY(c, hipMemsetAsync(c->parked, 0, sizeof(uint32_t), st), "train: reset");
                 HIPTRY(c, nomad::launch_train_async(a, c->plan.vbase, c->async_scratch, c->async_scratch_bytes, st),
@@ -539,6 +558,11 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
     if (out) {
         out->seconds = seconds;
         out->updates = (uint64_t)c->nnz * (uint64_t)epochs;
+        if (c->cfg.sched == NOMAD_SCHED_UNIFORM && epochs > 0) {
+            unsigned long long u = 0;
+            HIPTRY(c, hipMemcpy(&u, c->upd, sizeof(u), hipMemcpyDeviceToHost), "train: update count");
+            out->updates = (uint64_t)u;
+        }
         out->epochs_done = (uint64_t)c->epochs_done;
         out->layout_seconds = c->layout_seconds;
     }

@@ -284,15 +284,27 @@ __global__ void k_visit_owner(const int64_t *vbase, int32_t p, const VisitRec *v
     }
 }
 
+// Ratings of each visit (worker q's local item x = visit vbase[q] + x).
+__global__ void k_visit_ratings(const RatingRec *recs, int64_t nnz, const int64_t *rbase, int64_t nwt, int32_t nw,
+                                const int64_t *vbase, unsigned int *vcnt) {
+    GRID_LOOP(e, nnz) {
+        const int32_t t = find_block(rbase, (int32_t)nwt, e);
+        const int32_t q = t / nw;
+        atomicAdd(&vcnt[vbase[q] + (int64_t)(recs[e].info & kInfoXMask)], 1u);
+    }
+}
+
 // Holder entries in (item, worker) order, and the number of holders of each item.
 __global__ void k_holders(const uint32_t *vidx_sorted, const int32_t *vq, const int64_t *vbase, const VisitRec *visits,
-                          int64_t nv, int32_t *hold, int32_t *hx, int32_t *hitem, unsigned long long *cnt) {
+                          const unsigned int *vcnt, int64_t nv, int32_t *hold, int32_t *hx, int32_t *hitem,
+                          int32_t *hcnt, unsigned long long *cnt) {
     GRID_LOOP(i, nv) {
         const int64_t v = vidx_sorted[i];
         const int32_t q = vq[v];
         hold[i] = q;
         hx[i] = (int32_t)(v - vbase[q]);
         hitem[i] = visits[v].j;
+        hcnt[i] = (int32_t)vcnt[v];
         atomicAdd(&cnt[visits[v].j], 1ull);
     }
 }
@@ -343,6 +355,7 @@ void free_plan(Plan *pl) {
     (void)hipFree(pl->hold);
     (void)hipFree(pl->hx);
     (void)hipFree(pl->hitem);
+    (void)hipFree(pl->hcnt);
     (void)hipFree(pl->hoff);
     (void)hipFree(pl->xoff);
     *pl = Plan();
@@ -360,10 +373,12 @@ hipError_t build_async_tables(Plan *pl, hipStream_t st) {
     int32_t *vq = nullptr;
     uint32_t *vj = nullptr, *vj_s = nullptr, *vidx = nullptr, *vidx_s = nullptr;
     unsigned long long *cnt = nullptr, *act = nullptr;
+    unsigned int *vcnt = nullptr;
     Tmp tmp;
     CK(dalloc(&pl->hold, nv > 0 ? nv : 1));
     CK(dalloc(&pl->hx, nv > 0 ? nv : 1));
     CK(dalloc(&pl->hitem, nv > 0 ? nv : 1));
+    CK(dalloc(&pl->hcnt, nv > 0 ? nv : 1));
     CK(dalloc(&pl->hoff, n + 1));
     CK(dalloc(&pl->xoff, nv * pl->nw > 0 ? nv * pl->nw : 1));
     CK(dalloc(&cnt, n + 1));
@@ -372,6 +387,13 @@ hipError_t build_async_tables(Plan *pl, hipStream_t st) {
     CK(hipMemsetAsync(act, 0, sizeof(unsigned long long), st));
     if (nv > 0) {
         CK(dalloc(&vq, nv)); CK(dalloc(&vj, nv)); CK(dalloc(&vj_s, nv)); CK(dalloc(&vidx, nv)); CK(dalloc(&vidx_s, nv));
+        CK(dalloc(&vcnt, nv));
+        CK(hipMemsetAsync(vcnt, 0, sizeof(unsigned int) * nv, st));
+        if (pl->nnz > 0) {
+            hipLaunchKernelGGL(k_visit_ratings, dim3(grid_for(pl->nnz)), dim3(kThreads), 0, st, pl->recs, pl->nnz,
+                               pl->rbase, nwt, pl->nw, pl->vbase, vcnt);
+            CK(hipGetLastError());
+        }
         hipLaunchKernelGGL(k_visit_owner, dim3(grid_for(nv)), dim3(kThreads), 0, st, pl->vbase, pl->p, pl->visits,
                            nv, vq, vj, vidx);
         CK(hipGetLastError());
@@ -380,8 +402,8 @@ hipError_t build_async_tables(Plan *pl, hipStream_t st) {
         CK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, vj, vj_s, vidx, vidx_s, nv, 0, eb, st));
         CK(tmp.need(need));
         CK(hipcub::DeviceRadixSort::SortPairs(tmp.p, need, vj, vj_s, vidx, vidx_s, nv, 0, eb, st));
-        hipLaunchKernelGGL(k_holders, dim3(grid_for(nv)), dim3(kThreads), 0, st, vidx_s, vq, pl->vbase, pl->visits, nv,
-                           pl->hold, pl->hx, pl->hitem, cnt);
+        hipLaunchKernelGGL(k_holders, dim3(grid_for(nv)), dim3(kThreads), 0, st, vidx_s, vq, pl->vbase, pl->visits,
+                           vcnt, nv, pl->hold, pl->hx, pl->hitem, pl->hcnt, cnt);
         CK(hipGetLastError());
     }
     {
@@ -411,7 +433,7 @@ hipError_t build_async_tables(Plan *pl, hipStream_t st) {
     }
 done:
     (void)hipFree(vq); (void)hipFree(vj); (void)hipFree(vj_s); (void)hipFree(vidx); (void)hipFree(vidx_s);
-    (void)hipFree(cnt); (void)hipFree(act);
+    (void)hipFree(cnt); (void)hipFree(act); (void)hipFree(vcnt);
     return rc;
 }
 

@@ -109,6 +109,7 @@ struct Plan {
     int32_t *hold = nullptr;   // nvisits holder entries, grouped by item (workers ascending): the worker
     int32_t *hx = nullptr;     //   the item's local index at that worker
     int32_t *hitem = nullptr;  //   the item
+    int32_t *hcnt = nullptr;   //   the worker's ratings of the item
     int64_t *hoff = nullptr;   // n + 1: item j's holder entries are [hoff[j], hoff[j+1])
     int32_t *xoff = nullptr;   // nvisits * nw: first record of local item x in wave w's stream, relative to
                                //   the stream start (the end is the next local item's entry, or the stream end)
@@ -151,13 +152,18 @@ struct TrainArgs {
     bool timing;                // also time the phases (costs clock reads)
     // Asynchronous schedules (sched 1): the plan's holder and offset tables, the inbound
     // queues and the items' state.
-    int32_t sched;              // 0 ring, 1 random permutation per epoch (asynchronous)
+    int32_t sched;              // 0 ring, 1 random permutation per epoch, 2 uniform routing (both asynchronous)
     const int32_t *hold, *hx, *hitem;
     const int64_t *hoff;
     const int32_t *xoff;
-    uint64_t *queue;            // nvisits: worker q's inbound queue is [vbase[q], vbase[q+1])
+    uint64_t *queue;            // permutation: nvisits, worker q's inbound queue is [vbase[q], vbase[q+1]);
+                                // uniform routing: p * n, worker q's is [q n, (q + 1) n)
+    int32_t *tvis;              // uniform routing: per holder entry, visits so far (t of the next one)
+    const int32_t *hcnt;        // per holder entry: the worker's ratings of the item
+    unsigned long long *upd;    // uniform routing: updates applied in the call
+    unsigned long long budget;  // uniform routing: updates after which items stop moving
     uint32_t *qtail;            // p: pushes into each queue during the launch
-    int32_t *itep;              // n: epoch of each item's next visit
+    int32_t *itep;              // n: permutation: epoch of each item's next visit; uniform: moves so far
     int32_t *ihop;              // n: visits of each item since the call began
     uint32_t *parked;           // items that finished the launch's epochs
     int64_t active;             // items with at least one rating

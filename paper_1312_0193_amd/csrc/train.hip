@@ -156,14 +156,15 @@ struct Lds {
     RatingRec *recs;  // nw x kRecRing x kRecBatch: staged records of every compute wave
     int32_t *item;    // kMaxItemSlots: the item in each slot
     int32_t *sx;      // kMaxItemSlots: asynchronous schedules: the item's local index at the worker
-    int32_t *se;      // kMaxItemSlots: asynchronous schedules: the visit's epoch, relative to the launch
+    int32_t *se;      // kMaxItemSlots: asynchronous schedules: the visit's step counter t
+    float *ss, *sc;   // kMaxItemSlots: asynchronous schedules: the visit's step size s_t and 1 - s_t lambda
     int32_t *flag;    // nw: 1 + the last visit each compute wave finished
     int32_t *ctl;     // [0] visits loaded, [1] stop
 };
 
 __host__ __device__ inline size_t lds_bytes(int kp, int nw, int slots, int window, int wbytes) {
     return (size_t)slots * kp * sizeof(float) + (size_t)nw * (window + 1) * kp * wbytes +
-           (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec) + (3 * kMaxItemSlots + kMaxWaves + 1 + 4) * 4;
+           (size_t)nw * kRecRing * kRecBatch * sizeof(RatingRec) + (5 * kMaxItemSlots + kMaxWaves + 1 + 4) * 4;
 }
 
 __device__ __forceinline__ Lds lds_layout(void *base, int kp, int nw, int slots, int window, int wbytes) {
@@ -180,6 +181,10 @@ __device__ __forceinline__ Lds lds_layout(void *base, int kp, int nw, int slots,
     L.sx = (int32_t *)p;
     p += kMaxItemSlots * 4;
     L.se = (int32_t *)p;
+    p += kMaxItemSlots * 4;
+    L.ss = (float *)p;
+    p += kMaxItemSlots * 4;
+    L.sc = (float *)p;
     p += kMaxItemSlots * 4;
     L.flag = (int32_t *)p;
     p += (kMaxWaves + 1) * 4;
@@ -1031,9 +1036,6 @@ struct AsyncComputeWave {
     }
 
     __device__ void run() {
-        const double tl = (double)(a.epoch0 + lane);
-        const float s_tab = (float)(a.alpha / (1.0 + a.beta * (tl > 0.0 ? pow(tl, a.gamma) : 0.0)));
-        const float c_tab = 1.0f - s_tab * a.lambda;
         const int32_t *word = w == 0 ? &L.ctl[0] : &L.flag[w - 1];
         typedef const __attribute__((address_space(4))) int32_t *cint;
         const cint xo = (cint)a.xoff;
@@ -1043,18 +1045,20 @@ struct AsyncComputeWave {
             compiler_fence();
             t_wait += tick(a.timing) - t0;
             const int sl = X & (a.slots - 1);
-            const int x = __builtin_amdgcn_readfirstlane(L.sx[sl]);
-            const int64_t v = vb + x;
-            const int64_t b = xo[v * a.nw + w];
-            const int64_t e = x + 1 < nv ? (int64_t)xo[(v + 1) * a.nw + w] : cnt;
+            const int x = __builtin_amdgcn_readfirstlane(L.sx[sl]);  // -1: the worker holds no rating of the item
+            int64_t b = 0, e = 0;
+            if (x >= 0) {
+                const int64_t v = vb + x;
+                b = xo[v * a.nw + w];
+                e = x + 1 < nv ? (int64_t)xo[(v + 1) * a.nw + w] : cnt;
+            }
             if (b < e) {
-                const int erel = __builtin_amdgcn_readfirstlane(L.se[sl]);
+                const int t = __builtin_amdgcn_readfirstlane(L.se[sl]);
                 const int item = __builtin_amdgcn_readfirstlane(L.item[sl]);
-                const int t = a.epoch0 + erel;
                 float h[VEC];
                 lload<VEC>(items + (size_t)sl * kp, h);
-                const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s_tab), erel & 63));
-                const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c_tab), erel & 63));
+                const float s = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(L.ss[sl])));
+                const float c = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(L.sc[sl])));
                 for (int64_t r0 = b; r0 < e; r0 += 64) {
                     const int nb = (int)(e - r0 < 64 ? e - r0 : 64);
                     // lane l: record r0 + l (row, rating)
@@ -1113,23 +1117,58 @@ struct AsyncComputeWave {
     }
 };
 
-// Memory wave of the asynchronous schedule.
+// Holder entry of worker q in item j's holder list, or -1 (binary search: the list is in
+// ascending worker order).
+__device__ __forceinline__ int64_t holder_entry(const TrainArgs &a, int j, int q) {
+    int64_t lo = a.hoff[j], hi = a.hoff[j + 1];
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.hold[mid] < q) lo = mid + 1; else hi = mid;
+    }
+    return (lo < a.hoff[j + 1] && a.hold[lo] == q) ? lo : -1;
+}
+
+// Uniform routing (Algorithm 1 as printed): the next worker of item j after its v-th move.
+__device__ __forceinline__ int route_uniform(uint32_t seed, int j, int v, int p) {
+    const uint32_t k = lowbias32(lowbias32(seed ^ 0x2545F491u ^ (uint32_t)j) + (uint32_t)v * 0x9E3779B9u);
+    return (int)(((uint64_t)k * (uint64_t)(uint32_t)p) >> 32);
+}
+
+// Memory wave of the asynchronous schedules.
+//   Queue entries: (position + 1) << 32 | payload, the payload being a holder entry (random
+//   permutation: items only go to workers holding their ratings; worker q's queue has room
+//   for its local items) or an item (uniform routing: any item may come; room for n).
+//   Per visit the wave works out t (epoch, or the number of earlier visits of the item to
+//   this worker) and the step size, for the compute waves.
 struct AsyncMemoryWave {
     const TrainArgs &a;
     const Lds &L;
     MemoryWave io;        // item loads and write-backs
     const int q, lane, S;
+    const bool uni;       // uniform routing
     const int64_t qb;     // inbound queue: [qb, qb + cap)
     const int64_t cap;
     int Xl = 0, Xr = 0;   // visits taken / passed on
     int64_t head = 0;     // next queue position to take
-    // lane s < S: the visit in slot s: item, holder entry, epoch, visit number of the item
-    int f_j = 0, f_g = 0, f_e = 0, f_seq = 0;
+    // lane s < S: the visit in slot s: item, holder entry (-1 if none), step counter t, visit
+    // number of the item, moves of the item
+    int f_j = 0, f_g = 0, f_t = 0, f_seq = 0;
     uint64_t iters = 0, misses = 0;
 
     __device__ AsyncMemoryWave(const TrainArgs &a_, const Lds &L_, int q_, int lane_)
-        : a(a_), L(L_), io(a_, L_, q_, lane_), q(q_), lane(lane_), S(a_.slots), qb(a_.vbase[q_]),
-          cap(a_.vbase[q_ + 1] - a_.vbase[q_]) {}
+        : a(a_), L(L_), io(a_, L_, q_, lane_), q(q_), lane(lane_), S(a_.slots), uni(a_.sched == 2),
+          qb(a_.sched == 2 ? (int64_t)q_ * a_.n : a_.vbase[q_]),
+          cap(a_.sched == 2 ? a_.n : a_.vbase[q_ + 1] - a_.vbase[q_]) {}
+
+    // Push item j (payload `pay`) to worker q2's queue.
+    __device__ __forceinline__ void push(int q2, uint32_t pay) {
+        const int64_t b2 = uni ? (int64_t)q2 * a.n : a.vbase[q2];
+        const int64_t cap2 = uni ? a.n : a.vbase[q2 + 1] - b2;
+        const uint32_t pos = atomicAdd(a.qtail + q2, 1u);
+        const uint64_t ent = ((uint64_t)(pos + 1u) << 32) | pay;
+        __hip_atomic_store(a.queue + b2 + (int64_t)(pos % (uint64_t)cap2), ent, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
 
     __device__ void run() {
         const uint64_t t_start = tick(a.timing);
@@ -1145,31 +1184,51 @@ struct AsyncMemoryWave {
                 if (nr > 0) {
                     const int X = Xr + lane;
                     const int sl = X & Smask;
-                    const int j = __shfl(f_j, sl), g = __shfl(f_g, sl), e = __shfl(f_e, sl), seq = __shfl(f_seq, sl);
+                    const int j = __shfl(f_j, sl), g = __shfl(f_g, sl), t = __shfl(f_t, sl), seq = __shfl(f_seq, sl);
                     io.write_back(j, sl, nr);
-                    int64_t ng = -1;
-                    int ne = e;
+                    int dest = -1;      // next worker, -1: the item is parked
+                    uint32_t pay = 0;
+                    int ne = t;
+                    unsigned long long done_upd = 0;
                     if (lane < nr) {
-                        const int64_t hb = a.hoff[j];
-                        const uint64_t cur = route_key(a.route_seed, j, e, q, (int)(g - hb));
-                        ng = route_next(a, j, e, cur, true);
-                        if (ng < 0 && e + 1 < a.epoch0 + a.epochs) {
-                            ne = e + 1;
-                            ng = route_next(a, j, ne, 0, false);
+                        if (uni) {
+                            if (g >= 0) {
+                                a.tvis[g] = t + 1;
+                                done_upd = (unsigned long long)a.hcnt[g];
+                            }
+                        } else {
+                            const int64_t hb = a.hoff[j];
+                            const uint64_t cur = route_key(a.route_seed, j, t, q, (int)(g - hb));
+                            int64_t ng = route_next(a, j, t, cur, true);
+                            if (ng < 0 && t + 1 < a.epoch0 + a.epochs) {
+                                ne = t + 1;
+                                ng = route_next(a, j, ne, 0, false);
+                            }
+                            if (ng >= 0) {
+                                dest = a.hold[ng];
+                                pay = (uint32_t)ng;
+                                __hip_atomic_store(a.itep + j, ne, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            }
                         }
-                        if (ng >= 0) __hip_atomic_store(a.itep + j, ne, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(a.ihop + j, seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (g >= 0) __hip_atomic_store(a.ihop + j, seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    if (uni) {
+                        // updates of these visits, then: keep the items moving until the budget is met
+                        unsigned long long sum = done_upd;
+                        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+                        unsigned long long before = 0;
+                        if (lane == 0) before = atomicAdd(a.upd, sum);
+                        before = __shfl(before, 0);
+                        if (lane < nr && before + sum < a.budget) {
+                            const int moves = __hip_atomic_load(a.itep + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            dest = route_uniform(a.route_seed, j, moves, a.p);
+                            pay = (uint32_t)j;
+                            __hip_atomic_store(a.itep + j, moves + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
                     }
                     wait_vm();  // the items and their state are in place before they move on
-                    if (lane < nr && ng >= 0) {
-                        const int q2 = a.hold[ng];
-                        const int64_t b2 = a.vbase[q2], cap2 = a.vbase[q2 + 1] - b2;
-                        const uint32_t pos = atomicAdd(a.qtail + q2, 1u);
-                        const uint64_t ent = ((uint64_t)(pos + 1u) << 32) | (uint32_t)ng;
-                        __hip_atomic_store(a.queue + b2 + (int64_t)(pos % (uint64_t)cap2), ent, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    const int np = __popcll(__builtin_amdgcn_ballot_w64(lane < nr && ng < 0));
+                    if (lane < nr && dest >= 0) push(dest, pay);
+                    const int np = __popcll(__builtin_amdgcn_ballot_w64(lane < nr && dest < 0));
                     if (np > 0 && lane == 0) atomicAdd(a.parked, (uint32_t)np);
                     Xr += nr;
                     progress = true;
@@ -1189,41 +1248,61 @@ struct AsyncMemoryWave {
                     }
                     const int nt = leading_run(__builtin_amdgcn_ballot_w64(valid));
                     if (nt > 0) {
-                        int j = 0, x = 0, e = 0, seq = 0;
-                        const int g = (int)(uint32_t)ent;
+                        int j = 0, x = -1, t = 0, seq = 0, g = -1;
+                        float sv = 0.0f, cv = 0.0f;
                         if (lane < nt) {
-                            j = a.hitem[g];
-                            x = a.hx[g];
-                            e = __hip_atomic_load(a.itep + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            const uint32_t pay = (uint32_t)ent;
+                            if (uni) {
+                                j = (int)pay;
+                                g = (int)holder_entry(a, j, q);
+                                if (g >= 0) t = a.tvis[g];
+                            } else {
+                                g = (int)pay;
+                                j = a.hitem[g];
+                                t = __hip_atomic_load(a.itep + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            }
+                            if (g >= 0) x = a.hx[g];
                             seq = __hip_atomic_load(a.ihop + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            // s_t = alpha / (1 + beta t^gamma) (eq. stepsize_method) in double,
+                            // rounded to float; and 1 - s_t lambda in float
+                            const double td = (double)t;
+                            sv = (float)(a.alpha / (1.0 + a.beta * (td > 0.0 ? pow(td, a.gamma) : 0.0)));
+                            cv = 1.0f - sv * a.lambda;
                         }
-                        for (int t = 0; t < nt; ++t) io.load_item(__shfl(j, t), (Xl + t) & Smask);
+                        for (int k = 0; k < nt; ++k) io.load_item(__shfl(j, k), (Xl + k) & Smask);
                         if (lane < nt) {
                             const int sl = (Xl + lane) & Smask;
                             L.sx[sl] = x;
-                            L.se[sl] = e - a.epoch0;
+                            L.se[sl] = t;
+                            L.ss[sl] = sv;
+                            L.sc[sl] = cv;
                             L.item[sl] = j;
                         }
                         {
-                            const int t = (lane - Xl) & Smask;
-                            const int tj = __shfl(j, t), tg = __shfl(g, t), te = __shfl(e, t), ts = __shfl(seq, t);
-                            if (lane < S && t < nt) {
+                            const int k = (lane - Xl) & Smask;
+                            const int tj = __shfl(j, k), tg = __shfl(g, k), tt = __shfl(t, k), ts = __shfl(seq, k);
+                            if (lane < S && k < nt) {
                                 f_j = tj;
                                 f_g = tg;
-                                f_e = te;
+                                f_t = tt;
                                 f_seq = ts;
                             }
                         }
                         if (a.trace) {
+                            // the visits that update something (uniform routing also visits
+                            // workers holding no rating of the item)
+                            const uint64_t rec = __builtin_amdgcn_ballot_w64(lane < nt && g >= 0);
+                            const int nrec = __popcll(rec);
                             int64_t base = 0;
-                            if (lane == 0)
-                                base = (int64_t)atomicAdd((unsigned long long *)a.trace_len, (unsigned long long)nt);
+                            if (lane == 0 && nrec > 0)
+                                base = (int64_t)atomicAdd((unsigned long long *)a.trace_len, (unsigned long long)nrec);
                             base = __shfl(base, 0);
-                            if (lane < nt && base + lane < a.trace_cap) {
-                                int32_t *tr = a.trace + 4 * (base + lane);
+                            const int rank = __popcll(rec & ((1ull << lane) - 1ull));
+                            if (lane < nt && g >= 0 && base + rank < a.trace_cap) {
+                                int32_t *tr = a.trace + 4 * (base + rank);
                                 tr[0] = q;
                                 tr[1] = j;
-                                tr[2] = e;
+                                tr[2] = t;
                                 tr[3] = seq;
                             }
                         }
@@ -1238,7 +1317,7 @@ struct AsyncMemoryWave {
                     }
                 }
             }
-            // 3. Done when every item has finished the launch's epochs and nothing is held.
+            // 3. Done when every item has stopped moving and nothing is held.
             if (Xr == Xl &&
                 (int64_t)__hip_atomic_load(a.parked, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.active)
                 break;
@@ -1292,20 +1371,33 @@ __global__ __launch_bounds__(1024) void k_worker_async(TrainArgs a) {
     }
 }
 
-// Seeding: the first holder of every item in the launch's first epoch (sort key = that
-// worker; p for an item without ratings), and the item's epoch.
+// Seeding: the first worker of every item (sort key; p for an item without ratings) and the
+// payload of its queue entry.  Random permutation: the first holder of the item's visiting
+// order for epoch a.epoch0 (payload: that holder entry).  Uniform routing: a uniformly
+// random worker, the item's next move (payload: the item).
 __global__ void k_seed_first(TrainArgs a, int64_t n, uint32_t *key, uint32_t *val, int32_t *first) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += stride) {
-        const int64_t g = route_next(a, (int)j, a.epoch0, 0, false);
-        first[j] = (int32_t)g;
-        key[j] = g >= 0 ? (uint32_t)a.hold[g] : (uint32_t)a.p;
         val[j] = (uint32_t)j;
-        a.itep[j] = a.epoch0;
+        if (a.sched == 2) {
+            if (a.hoff[j + 1] > a.hoff[j]) {
+                const int mv = a.itep[j];
+                key[j] = (uint32_t)route_uniform(a.route_seed, (int)j, mv, a.p);
+                first[j] = (int32_t)j;
+                a.itep[j] = mv + 1;
+            } else {
+                key[j] = (uint32_t)a.p;
+                first[j] = -1;
+            }
+        } else {
+            const int64_t g = route_next(a, (int)j, a.epoch0, 0, false);
+            first[j] = (int32_t)g;
+            key[j] = g >= 0 ? (uint32_t)a.hold[g] : (uint32_t)a.p;
+            a.itep[j] = a.epoch0;
+        }
     }
 }
 
-// Queue entry i of the sorted seeding order: position i - (first position of its worker).
 __global__ void k_seed_write(TrainArgs a, int64_t n, const uint32_t *key_s, const uint32_t *val_s,
                              const int32_t *first) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1318,7 +1410,8 @@ __global__ void k_seed_write(TrainArgs a, int64_t n, const uint32_t *key_s, cons
             if (key_s[mid] < q) lo = mid + 1; else hi = mid;
         }
         const uint32_t pos = (uint32_t)(i - lo);
-        a.queue[a.vbase[q] + pos] = ((uint64_t)(pos + 1u) << 32) | (uint32_t)first[val_s[i]];
+        const int64_t qb = a.sched == 2 ? (int64_t)q * a.n : a.vbase[q];
+        a.queue[qb + pos] = ((uint64_t)(pos + 1u) << 32) | (uint32_t)first[val_s[i]];
         atomicAdd(a.qtail + q, 1u);
     }
 }

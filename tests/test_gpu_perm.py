@@ -1,4 +1,5 @@
-"""The asynchronous schedule (random-permutation circulation, NOMAD_SCHED_PERM) on the GPU.
+"""The asynchronous schedules on the GPU: the random-permutation circulation
+(NOMAD_SCHED_PERM) and uniform routing (NOMAD_SCHED_UNIFORM).
 
 Its serial order depends on timing, so parity is checked three ways:
   * exactly, through the recorded visit trace: replaying it in the oracle (each worker's
@@ -143,3 +144,75 @@ def test_perm_rmse_matches_oracle_emulation():
                                   H0.numpy(), hp, P, 1, E, 77)
     r_orc = oracle.rmse(prob.m, prob.n, prob.test_row.numpy(), prob.test_col.numpy(), prob.test_val.numpy(), Wo, Ho)
     assert abs(r_gpu - r_orc) < 1e-3 * r_orc, (r_gpu, r_orc)
+
+
+# ---------------------------------------------------------------------------------------
+# Uniform routing (NOMAD_SCHED_UNIFORM): Algorithm 1 as printed.
+
+
+def test_uniform_trace_replays_and_counts_updates():
+    prob, W0, H0, hp = make(700, 250, 14_000, k=32, seed=31)
+    P, seed, E = 12, 6, 2
+    print("[case] uniform routing", flush=True)
+    model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
+                     beta=hp.beta, gamma=hp.gamma, workers=P, seed=seed, sched="uniform", record_trace=True,
+                     collect_stats=True)
+    st = model.train(E)
+    tr = model.trace()
+    ws = model.worker_stats()
+    W, H = (x.cpu().double().numpy() for x in model.factors())
+    model.close()
+    assert st.updates >= E * prob.nnz
+    assert int(ws[:, 6].sum()) == st.updates  # ratings updated by the compute waves
+    assert int(ws[:, 2].sum()) > len(tr)      # some visits went to workers without ratings of the item
+    vis = holders(prob, P)
+    assert {(int(a), int(b)) for a, b in tr[:, :2]} <= vis
+    for j in np.unique(tr[:, 1]):
+        rows = tr[tr[:, 1] == j]
+        assert np.array_equal(np.sort(rows[:, 3]), np.arange(len(rows)))
+    # t counts the item's earlier visits to the worker
+    for (q, j) in list(vis)[:200]:
+        ts = np.sort(tr[(tr[:, 0] == q) & (tr[:, 1] == j), 2])
+        assert np.array_equal(ts, np.arange(len(ts)))
+    order = np.argsort(tr[:, 0], kind="stable")
+    t2 = tr[order]
+    Wr, Hr, _ = oracle.replay(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
+                              H0.numpy(), hp, P, seed, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
+    assert rel(W, Wr) < 2e-5 and rel(H, Hr) < 2e-5, (rel(W, Wr), rel(H, Hr))
+
+
+def test_uniform_rmse_matches_oracle_emulation():
+    prob = synth.tiny()
+    hpd = prob.hp
+    W0, H0 = synth.init_factors(prob.m, prob.n, hpd["k"], 1)
+    f = lambda x: float(np.float32(x))  # noqa: E731
+    hp = oracle.Hyper(hpd["k"], f(hpd["lam"]), f(hpd["alpha"]), f(hpd["beta"]), f(hpd["gamma"]))
+    P, E = 16, 10
+    print("[case] uniform routing, tiny workload", flush=True)
+    model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
+                     beta=hp.beta, gamma=hp.gamma, workers=P, seed=1, sched="uniform")
+    st = model.train(E)
+    r_gpu, _ = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
+    model.close()
+    Wo, Ho, _ = oracle.train_uniform(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(),
+                                     W0.numpy(), H0.numpy(), hp, P, 1, st.updates, 77)
+    r_orc = oracle.rmse(prob.m, prob.n, prob.test_row.numpy(), prob.test_col.numpy(), prob.test_val.numpy(), Wo, Ho)
+    assert abs(r_gpu - r_orc) < 2e-3 * r_orc, (r_gpu, r_orc)
+
+
+def test_uniform_continues_per_pair_counts_across_calls():
+    prob, W0, H0, hp = make(300, 100, 4_000, k=16, seed=33)
+    print("[case] uniform routing, calls [1, 1]", flush=True)
+    model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
+                     beta=hp.beta, gamma=hp.gamma, workers=6, seed=2, sched="uniform", record_trace=True)
+    model.train(1)
+    t1 = model.trace()
+    model.train(1)
+    t2 = model.trace()
+    model.close()
+    # the second call's t of a (worker, item) pair continues after the first call's visits
+    for (q, j) in {(int(a), int(b)) for a, b in t1[:, :2]}:
+        n1 = int(((t1[:, 0] == q) & (t1[:, 1] == j)).sum())
+        later = t2[(t2[:, 0] == q) & (t2[:, 1] == j), 2]
+        if later.size:
+            assert later.min() == n1
