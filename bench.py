@@ -37,7 +37,7 @@ def bytes_per_update(k: int, s_w: int, s_h: int, n: int, nnz_train: int, p_ref: 
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1312_0193_amd", "csrc", "train.hip")
-KERNELS = {"perm": "k_worker_async", "ring": "k_worker"}
+KERNELS = {"perm": "k_worker_async", "uniform": "k_worker_async", "ring": "k_worker"}
 COPY_BYTES = 2 << 30  # calibration copy: 2 GiB read + 2 GiB written per dispatch
 
 
@@ -104,10 +104,13 @@ def cpu_baseline(prob, W0, H0, hp, P, seed, sched, row_fraction=0.1):
     t0 = time.perf_counter()
     if sched == "perm":
         oracle.train_perm(m_s, prob.n, r, c, v, W, H, h, P, seed, 1, 1)
+    elif sched == "uniform":
+        oracle.train_uniform(m_s, prob.n, r, c, v, W, H, h, P, seed, r.size, 1)
     else:
         oracle.train_ring(m_s, prob.n, r, c, v, W, H, h, P, seed, 1)
     dt = time.perf_counter() - t0
-    what = "random-permutation schedule (asynchronous emulation)" if sched == "perm" else "ring order"
+    what = {"perm": "random-permutation schedule (asynchronous emulation)",
+            "uniform": "uniform routing (asynchronous emulation, |sample| updates)", "ring": "ring order"}[sched]
     return {"value": r.size / dt, "unit": "updates/s", "cores": 1, "kind": "oracle",
             "sample": f"1 epoch, {what}, {P} workers, FP64, rows [0,{m_s}) of the workload "
                       f"({r.size} ratings), layout included, {dt:.1f} s"}
@@ -121,8 +124,10 @@ def main():
     ap.add_argument("--workers", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0, help="compute waves per worker (0 = library default)")
     ap.add_argument("--item-slots", type=int, default=0, help="item slots per worker (0 = library default)")
-    ap.add_argument("--sched", choices=["perm", "ring"], default="perm",
-                    help="perm: asynchronous random-permutation circulation; ring: fixed token-passing order")
+    ap.add_argument("--sched", choices=["perm", "uniform", "ring"], default="perm",
+                    help="perm: asynchronous random-permutation circulation; uniform: asynchronous uniform "
+                         "routing (Algorithm 1 as printed; an epoch = |training ratings| updates); ring: fixed "
+                         "token-passing order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibrate", action="store_true",
                     help="run only the plain copy used to calibrate the HBM byte counters")
@@ -162,19 +167,21 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ksec = []
+    updates = 0
     for step in range(args.steps):
         s = model.train(1)
         ksec.append(s.seconds)
+        updates += s.updates
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     log("epoch kernel ms: " + " ".join(f"{x * 1e3:.2f}" for x in ksec))
     nnz = prob.nnz
-    value = args.steps * nnz / wall
+    value = updates / wall
     rmse, obj = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
     log(f"test RMSE after {args.warmup + args.steps} epochs: {rmse:.5f}")
     B = bytes_per_update(hp["k"], 4, 4, prob.n, nnz)
     avg_kernel = sum(ksec) / len(ksec)
-    achieved = B * nnz / avg_kernel
+    achieved = B * (updates / args.steps) / avg_kernel
     kernel = KERNELS[args.sched]
     traffic = measured_traffic(kernel)
     out = {
