@@ -476,7 +476,11 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
     if (out) memset(out, 0, sizeof(*out));
     hipStream_t st = c->stream;
     double seconds = 0.0;
-    if (epochs > 0) {
+    if (epochs > 0 && c->nnz == 0) {
+        // No ratings: every epoch is empty and no item has a worker to visit.
+        c->trace_count = 0;
+        c->epochs_done += epochs;
+    } else if (epochs > 0) {
         nomad::TrainArgs a{};
         fill_args(c, a);
         if (c->cfg.record_trace) {
@@ -558,7 +562,7 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
     if (out) {
         out->seconds = seconds;
         out->updates = (uint64_t)c->nnz * (uint64_t)epochs;
-        if (c->cfg.sched == NOMAD_SCHED_UNIFORM && epochs > 0) {
+        if (c->cfg.sched == NOMAD_SCHED_UNIFORM && epochs > 0 && c->nnz > 0) {
             unsigned long long u = 0;
             HIPTRY(c, hipMemcpy(&u, c->upd, sizeof(u), hipMemcpyDeviceToHost), "train: update count");
             out->updates = (uint64_t)u;

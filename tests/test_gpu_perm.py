@@ -12,6 +12,7 @@ Its serial order depends on timing, so parity is checked three ways:
 """
 import numpy as np
 import pytest
+import torch
 
 import oracle
 import paper_1312_0193_amd as nm
@@ -216,3 +217,82 @@ def test_uniform_continues_per_pair_counts_across_calls():
         later = t2[(t2[:, 0] == q) & (t2[:, 1] == j), 2]
         if later.size:
             assert later.min() == n1
+
+
+# ---------------------------------------------------------------------------------------
+# Degenerate cases of both asynchronous schedules.
+
+
+@pytest.mark.parametrize("sched", ["perm", "uniform"])
+def test_async_empty_and_single_rating(sched):
+    k = 8
+    W0, H0 = synth.init_factors(10, 6, k, 1)
+    e = torch.zeros(0, dtype=torch.int32)
+    print(f"[case] {sched}, no ratings", flush=True)
+    model = nm.Nomad(10, 6, e, e, e.float(), W0, H0, k=k, lam=0.1, alpha=0.1, beta=0.0, gamma=1.0, workers=4,
+                     sched=sched, record_trace=True)
+    st = model.train(3)
+    W, H = model.factors()
+    assert st.updates == 0 and st.epochs_done == 3
+    assert len(model.trace()) == 0
+    assert torch.equal(W.cpu(), W0) and torch.equal(H.cpu(), H0)
+    model.close()
+    # one rating: a single item with a single holder, so every order is the ring's
+    row, col, val = (torch.tensor([7], dtype=torch.int32), torch.tensor([2], dtype=torch.int32),
+                     torch.tensor([3.0]))
+    print(f"[case] {sched}, one rating", flush=True)
+    model = nm.Nomad(10, 6, row, col, val, W0, H0, k=k, lam=0.1, alpha=0.1, beta=0.0, gamma=1.0, workers=4,
+                     sched=sched)
+    st = model.train(2)
+    assert st.updates == 2
+    W, H = model.factors()
+    model.close()
+    Wo, Ho, _ = oracle.train_ring(10, 6, row.numpy(), col.numpy(), val.numpy(), W0.numpy(), H0.numpy(),
+                                  oracle.Hyper(k, float(np.float32(0.1)), float(np.float32(0.1)), 0.0, 1.0), 4, 0, 2)
+    assert rel(W.cpu().double().numpy(), Wo) < 1e-6 and rel(H.cpu().double().numpy(), Ho) < 1e-6
+
+
+@pytest.mark.parametrize("sched", ["perm", "uniform"])
+def test_async_more_workers_than_items(sched):
+    """Three items among 64 workers: most workers never hold one, the items' chains are
+    the whole computation."""
+    prob, W0, H0, hp = make(200, 3, 500, k=16, seed=41)
+    P, seed, E = 64, 3, 3
+    print(f"[case] {sched}, n=3 P=64", flush=True)
+    model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
+                     beta=hp.beta, gamma=hp.gamma, workers=P, seed=seed, sched=sched, record_trace=True)
+    st = model.train(E)
+    tr = model.trace()
+    W, H = (x.cpu().double().numpy() for x in model.factors())
+    model.close()
+    vis = holders(prob, P)
+    if sched == "perm":
+        assert st.updates == E * prob.nnz and len(tr) == E * len(vis)
+    else:
+        assert st.updates >= E * prob.nnz
+    assert {(int(a), int(b)) for a, b in tr[:, :2]} <= vis
+    order = np.argsort(tr[:, 0], kind="stable")
+    t2 = tr[order]
+    Wr, Hr, _ = oracle.replay(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
+                              H0.numpy(), hp, P, seed, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
+    assert rel(W, Wr) < 2e-5 and rel(H, Hr) < 2e-5, (rel(W, Wr), rel(H, Hr))
+
+
+@pytest.mark.parametrize("sched", ["perm", "uniform"])
+def test_async_bf16_rmse_close_to_fp32(sched):
+    """The BF16 storage form under an asynchronous schedule: after several epochs its
+    test RMSE is within 1% of the FP32 form's."""
+    prob = synth.tiny()
+    hpd = prob.hp
+    W0, H0 = synth.init_factors(prob.m, prob.n, hpd["k"], 1)
+    out = {}
+    for dt in ("fp32", "bf16"):
+        print(f"[case] {sched} {dt}, tiny workload", flush=True)
+        kw = dict(dtype="bf16", rounding="stochastic") if dt == "bf16" else {}
+        model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hpd["k"], lam=hpd["lam"],
+                         alpha=hpd["alpha"], beta=hpd["beta"], gamma=hpd["gamma"], workers=16, seed=1, sched=sched,
+                         **kw)
+        model.train(8)
+        out[dt], _ = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
+        model.close()
+    assert abs(out["bf16"] - out["fp32"]) < 1e-2 * out["fp32"], out
