@@ -96,7 +96,7 @@ typedef struct {
     int32_t rounding;   /* nomad_round, used when dtype = NOMAD_BF16 */
     int32_t workers;    /* p, number of workers (workgroups, all resident at once);
                            0 = one per compute unit */
-    int32_t waves_per_worker; /* compute wavefronts of a worker, 1..15; 0 = 8 */
+    int32_t waves_per_worker; /* compute wavefronts of a worker, 1..15; 0 = 8 (ring), 4 (asynchronous) */
     int32_t item_slots;  /* items a worker holds in LDS at once: a power of two, 1..64;
                             0 = as many as LDS allows, up to 64 */
     int32_t window;      /* rows a compute wave keeps in flight: 8, 16 or 32 (other values in

@@ -121,13 +121,16 @@ void release(nomad_ctx *c) {
 // configuration asks), and how many workers can be resident at once.
 nomad_status choose_shape(const nomad_config *cfg, int32_t kp, int32_t wbytes, nomad::Shape *out, nomad_ctx *ec) {
     // Workers, compute waves per worker and item slots.  By default one worker runs on
-    // every CU with eight compute waves, and holds up to 64 items (fewer if LDS is short).
+    // every CU with eight compute waves (four under the asynchronous schedules), and holds
+    // up to 64 items (fewer if LDS is short).
     int dev = 0, max_lds = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return fail(ec, NOMAD_EDEVICE, "nomad_init: no usable HIP device");
-    const int32_t nw = cfg->waves_per_worker > 0 ? cfg->waves_per_worker : nomad::kDefaultWaves;
+    const bool async = cfg->sched == NOMAD_SCHED_PERM || cfg->sched == NOMAD_SCHED_UNIFORM;
+    const int32_t nw = cfg->waves_per_worker > 0 ? cfg->waves_per_worker
+                                                 : (async ? nomad::kDefaultWavesAsync : nomad::kDefaultWaves);
     if (nw < 1 || nw > nomad::kMaxWaves)
         return fail(ec, NOMAD_EINVAL, "nomad_init: waves_per_worker=%d outside [1,%d]", nw, nomad::kMaxWaves);
     if (cfg->window < 0 || cfg->window > nomad::kMaxWindow)

@@ -47,34 +47,20 @@ __device__ __forceinline__ float rl_f(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
-// Cross-row steps of a wavefront sum, on gfx950's lane swaps.  With the same value in
-// both operands, v_permlane16_swap leaves rows (0,0,2,2) in one register and (1,1,3,3)
-// in the other; v_permlane32_swap leaves the lower half in both halves of one register
-// and the upper half in the other.  Written as asm: the compiler's own form of these
-// swaps returns the first result in place of the second.  The s_nop pairs cover the
-// VALU-to-swap and swap-to-VALU hazards.
-__device__ __forceinline__ float swap_add16(float x) {
-    float y = x;
-    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
-    return x + y;
-}
-__device__ __forceinline__ float swap_add32(float x) {
-    float y = x;
-    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(x), "+v"(y));
-    return x + y;
-}
-
-// Sum over the first NR16 16-lane rows of x, returned in every lane (lanes beyond the
-// active rows must hold 0): butterfly within each row with DPP, then the row swaps.
-template <int NR16>
-__device__ __forceinline__ float wave_sum(float x) {
+// Sum of x over the wavefront, returned as a wave-uniform value: a butterfly within each
+// 16-lane row with DPP (every lane of row r then holds its row sum S_r), then the row
+// broadcasts add lane 15 of rows 0 and 2 into rows 1 and 3 and lane 31 into rows 2 and
+// 3, and lane 63, (S_2 + S_3) + (S_0 + S_1), is read into a scalar register.  The sum
+// ends in one lane instead of all of them, which takes fewer dependent steps than lane
+// swaps that leave it everywhere; the additions pair the same terms.
+__device__ __forceinline__ float wave_total(float x) {
     x += DPP_F(x, 0xB1, 0xF, true);   // quad_perm [1,0,3,2]
     x += DPP_F(x, 0x4E, 0xF, true);   // quad_perm [2,3,0,1]
     x += DPP_F(x, 0x124, 0xF, true);  // row_ror 4
     x += DPP_F(x, 0x128, 0xF, true);  // row_ror 8
-    if constexpr (NR16 >= 2) x = swap_add16(x);
-    if constexpr (NR16 >= 4) x = swap_add32(x);
-    return x;
+    x += DPP_F(x, 0x142, 0xA, false);  // row_bcast 15 into rows 1, 3
+    x += DPP_F(x, 0x143, 0xC, false);  // row_bcast 31 into rows 2, 3
+    return rl_f(x, 63);
 }
 
 typedef __attribute__((address_space(3))) float lds_float;
@@ -591,7 +577,7 @@ struct ComputeWave {
             float d = 0.0f;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) d = fmaf(wv[v], h[v], d);
-            d = wave_sum<4>(d);
+            d = wave_total(d);
             // Reads for the next step: the row of rating y + 1 (its load completed in the
             // step before), the records of y + 2 and y + D + 1.
             row_lload<VEC, BF>(rows + ((u + 1) & (D - 1)) * rb, wn);
@@ -603,7 +589,7 @@ struct ComputeWave {
             float nw[VEC];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                nw[v] = fmaf(se, h[v], c * wv[v]);
+                nw[v] = fmaf(c, wv[v], se * h[v]);
                 h[v] = fmaf(se, wv[v], c * h[v]);
             }
             // Hand the row on to its next use inside the window (the very next rating takes
@@ -991,13 +977,17 @@ struct AsyncComputeWave {
     const int64_t vb;     // first visit record of the worker (local item 0)
     const int nv;         // local items
     lds_float *const items;
-    char *const wlane;
+    char *const W;
+    const uint32_t lb;    // the lane's byte offset inside a row
     uint64_t nrat = 0, t_wait = 0;
 
     __device__ AsyncComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0, int64_t cnt_)
         : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC), rb(a_.kp * ES), rs(a_.recs + r0),
           cnt(cnt_), vb(a_.vbase[q_]), nv((int)(a_.vbase[q_ + 1] - a_.vbase[q_])),
-          items(to_lds(L_.items) + lane_ * VEC), wlane((char *)a_.W + lane_ * VEC * ES) {}
+          items(to_lds(L_.items) + lane_ * VEC), W((char *)a_.W), lb((uint32_t)(lane_ * VEC * ES)) {}
+
+    // The lane's part of row `row` (uniform).
+    __device__ __forceinline__ char *lane_row(int row) const { return W + (int64_t)row * rb + lb; }
 
     // Wait until visit X reaches this wave.  False when the worker stops with no such visit.
     __device__ __forceinline__ bool wait_visit(const int32_t *word, int X) {
@@ -1023,16 +1013,18 @@ struct AsyncComputeWave {
         float d = 0.0f;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) d = fmaf(wv[i], h[i], d);
-        d = wave_sum<4>(d);
+        d = wave_total(d);
         const float se = s * (rating - d);
         float nw[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
-            nw[i] = fmaf(se, h[i], c * wv[i]);
+            // c * w enters through the FMA, after the residual: a separate product would be
+            // scheduled early, for rows of later ratings, and wait for their loads there.
+            nw[i] = fmaf(c, wv[i], se * h[i]);
             h[i] = fmaf(se, wv[i], c * h[i]);
         }
         round_stored<VEC, BF>(a, loff, nw, row, item, t);
-        row_gstore<VEC, BF>(wlane + (int64_t)row * rb, nw);
+        row_gstore<VEC, BF>(lane_row(row), nw);
     }
 
     __device__ void run() {
@@ -1078,12 +1070,13 @@ struct AsyncComputeWave {
                     constexpr int NB = 16;
                     float wbuf[NB][VEC];
                     int rbuf[NB];
-                    float dummy0 = 0.0f;
 #pragma unroll
                     for (int k = 0; k < NB; ++k) {
                         rbuf[k] = __builtin_amdgcn_readlane(crow, k < nb ? k : nb - 1);
-                        row_gload<VEC, BF>(wlane + (int64_t)rbuf[k] * rb, wbuf[k]);
-                        if (k + 1 < NB) a.dummy[(int64_t)q * kMaxWaves + w] = dummy0;  // every lane: no branch
+                        row_gload<VEC, BF>(lane_row(rbuf[k]), wbuf[k]);
+                        // every lane, no branch; a different value each time, so that no
+                        // store is merged into another
+                        if (k + 1 < NB) a.dummy[(int64_t)q * kMaxWaves + w] = (float)k;
                     }
                     int l = 0;
                     for (; l + NB <= nb; l += NB) {
@@ -1093,7 +1086,7 @@ struct AsyncComputeWave {
                                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, c, item, t);
                             const int nl = l + k + NB;
                             rbuf[k] = __builtin_amdgcn_readlane(crow, nl < nb ? nl : nb - 1);
-                            row_gload<VEC, BF>(wlane + (int64_t)rbuf[k] * rb, wbuf[k]);
+                            row_gload<VEC, BF>(lane_row(rbuf[k]), wbuf[k]);
                         }
                     }
 #pragma unroll
