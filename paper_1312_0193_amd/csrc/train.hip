@@ -143,7 +143,7 @@ struct Lds {
     int32_t *item;    // kMaxItemSlots: the item in each slot
     int32_t *sx;      // kMaxItemSlots: asynchronous schedules: the item's local index at the worker
     int32_t *se;      // kMaxItemSlots: asynchronous schedules: the visit's step counter t
-    float *ss, *sc;   // kMaxItemSlots: asynchronous schedules: the visit's step size s_t and 1 - s_t lambda
+    float *ss, *sc;   // kMaxItemSlots: asynchronous schedules: the visit's step size s_t and s_t lambda
     int32_t *flag;    // nw: 1 + the last visit each compute wave finished
     int32_t *ctl;     // [0] visits loaded, [1] stop
 };
@@ -543,12 +543,12 @@ struct ComputeWave {
         // Step sizes of the launch's epochs, lane e holding epoch e's (read with readlane:
         // a scalar memory load inside the loop would put its latency into every step):
         // s_t = alpha / (1 + beta t^gamma) in double, t = epochs done (every rating is
-        // updated once per epoch), rounded to float; and 1 - s_t lambda in float.
+        // updated once per epoch), rounded to float; and s_t lambda, rounded from double.
         const double tl = (double)(a.epoch0 + lane);
         const float s_tab = (float)(a.alpha / (1.0 + a.beta * (tl > 0.0 ? pow(tl, a.gamma) : 0.0)));
-        const float c_tab = 1.0f - s_tab * a.lambda;
+        const float sl_tab = (float)((double)s_tab * (double)a.lambda);
         float s = __shfl(s_tab, 0);
-        float c = __shfl(c_tab, 0);
+        float sl = __shfl(sl_tab, 0);
         int item = 0;  // the item of the current visit (read with it, for the rounding hash)
         int64_t y = 0;
         for (; y < total; ++y) {
@@ -589,8 +589,8 @@ struct ComputeWave {
             float nw[VEC];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
-                nw[v] = fmaf(c, wv[v], se * h[v]);
-                h[v] = fmaf(se, wv[v], c * h[v]);
+                nw[v] = fmaf(-sl, wv[v], fmaf(se, h[v], wv[v]));
+                h[v] = fmaf(se, wv[v], fmaf(-sl, h[v], h[v]));
             }
             // Hand the row on to its next use inside the window (the very next rating takes
             // it in registers), and store it.
@@ -627,7 +627,7 @@ struct ComputeWave {
                 ++e;
                 xbase += nv;
                 s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(s_tab), e & 63));
-                c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c_tab), e & 63));
+                sl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(sl_tab), e & 63));
             }
         }
         wait_vm();
@@ -1009,7 +1009,7 @@ struct AsyncComputeWave {
 
     // One update (section 2.3: one residual, both vectors from their values before it).
     __device__ __forceinline__ void update(float (&h)[VEC], const float (&wv)[VEC], int row, float rating, float s,
-                                           float c, int item, int t) {
+                                           float sl, int item, int t) {
         float d = 0.0f;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) d = fmaf(wv[i], h[i], d);
@@ -1018,10 +1018,11 @@ struct AsyncComputeWave {
         float nw[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
-            // c * w enters through the FMA, after the residual: a separate product would be
-            // scheduled early, for rows of later ratings, and wait for their loads there.
-            nw[i] = fmaf(c, wv[i], se * h[i]);
-            h[i] = fmaf(se, wv[i], c * h[i]);
+            // w + se h - s lambda w as two FMAs, the first after the residual: a product of
+            // w alone would be scheduled early, for rows of later ratings, and wait for
+            // their loads there.
+            nw[i] = fmaf(-sl, wv[i], fmaf(se, h[i], wv[i]));
+            h[i] = fmaf(se, wv[i], fmaf(-sl, h[i], h[i]));
         }
         round_stored<VEC, BF>(a, loff, nw, row, item, t);
         row_gstore<VEC, BF>(lane_row(row), nw);
@@ -1050,7 +1051,7 @@ struct AsyncComputeWave {
                 float h[VEC];
                 lload<VEC>(items + (size_t)sl * kp, h);
                 const float s = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(L.ss[sl])));
-                const float c = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(L.sc[sl])));
+                const float slam = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(L.sc[sl])));
                 for (int64_t r0 = b; r0 < e; r0 += 64) {
                     const int nb = (int)(e - r0 < 64 ? e - r0 : 64);
                     // lane l: record r0 + l (row, rating)
@@ -1083,7 +1084,7 @@ struct AsyncComputeWave {
 #pragma unroll
                         for (int k = 0; k < NB; ++k) {
                             update(h, wbuf[k], rbuf[k],
-                                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, c, item, t);
+                                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, slam, item, t);
                             const int nl = l + k + NB;
                             rbuf[k] = __builtin_amdgcn_readlane(crow, nl < nb ? nl : nb - 1);
                             row_gload<VEC, BF>(lane_row(rbuf[k]), wbuf[k]);
@@ -1093,7 +1094,7 @@ struct AsyncComputeWave {
                     for (int k = 0; k < NB - 1; ++k)
                         if (l + k < nb)
                             update(h, wbuf[k], rbuf[k],
-                                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, c, item, t);
+                                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, slam, item, t);
                 }
                 nrat += (uint64_t)(e - b);
                 lstore<VEC>(items + (size_t)sl * kp, h);
@@ -1257,10 +1258,10 @@ struct AsyncMemoryWave {
                             if (g >= 0) x = a.hx[g];
                             seq = __hip_atomic_load(a.ihop + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                             // s_t = alpha / (1 + beta t^gamma) (eq. stepsize_method) in double,
-                            // rounded to float; and 1 - s_t lambda in float
+                            // rounded to float; and s_t lambda, rounded from double
                             const double td = (double)t;
                             sv = (float)(a.alpha / (1.0 + a.beta * (td > 0.0 ? pow(td, a.gamma) : 0.0)));
-                            cv = 1.0f - sv * a.lambda;
+                            cv = (float)((double)sv * (double)a.lambda);
                         }
                         for (int k = 0; k < nt; ++k) io.load_item(__shfl(j, k), (Xl + k) & Smask);
                         if (lane < nt) {
