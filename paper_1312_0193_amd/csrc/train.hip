@@ -47,20 +47,22 @@ __device__ __forceinline__ float rl_f(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
-// Sum of x over the wavefront, returned as a wave-uniform value: a butterfly within each
-// 16-lane row with DPP (every lane of row r then holds its row sum S_r), then the row
-// broadcasts add lane 15 of rows 0 and 2 into rows 1 and 3 and lane 31 into rows 2 and
-// 3, and lane 63, (S_2 + S_3) + (S_0 + S_1), is read into a scalar register.  The sum
+// Sum of x over the wavefront, valid in lane 63 only: a butterfly within each 16-lane row
+// with DPP (every lane of row r then holds its row sum S_r), then the row broadcasts add
+// lane 15 into row 1 and lane 47 into row 3, and lane 31 into row 3, so that lane 63 holds
+// (S_2 + S_3) + (S_0 + S_1); the other lanes hold partial or undefined values.  The sum
 // ends in one lane instead of all of them, which takes fewer dependent steps than lane
-// swaps that leave it everywhere; the additions pair the same terms.
-__device__ __forceinline__ float wave_total(float x) {
+// swaps that leave it everywhere; the additions pair the same terms.  The caller finishes
+// its scalar arithmetic in lane 63 and reads the result from there.
+__device__ __forceinline__ float wave_sum_last(float x) {
     x += DPP_F(x, 0xB1, 0xF, true);   // quad_perm [1,0,3,2]
     x += DPP_F(x, 0x4E, 0xF, true);   // quad_perm [2,3,0,1]
     x += DPP_F(x, 0x124, 0xF, true);  // row_ror 4
     x += DPP_F(x, 0x128, 0xF, true);  // row_ror 8
-    x += DPP_F(x, 0x142, 0xA, false);  // row_bcast 15 into rows 1, 3
-    x += DPP_F(x, 0x143, 0xC, false);  // row_bcast 31 into rows 2, 3
-    return rl_f(x, 63);
+    // the disabled rows' values are left undefined (no register to clear first)
+    x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x142, 0xA, 0xF, false));
+    x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x143, 0xC, 0xF, false));
+    return x;
 }
 
 typedef __attribute__((address_space(3))) float lds_float;
@@ -577,7 +579,7 @@ struct ComputeWave {
             float d = 0.0f;
 #pragma unroll
             for (int v = 0; v < VEC; ++v) d = fmaf(wv[v], h[v], d);
-            d = wave_total(d);
+            d = wave_sum_last(d);
             // Reads for the next step: the row of rating y + 1 (its load completed in the
             // step before), the records of y + 2 and y + D + 1.
             row_lload<VEC, BF>(rows + ((u + 1) & (D - 1)) * rb, wn);
@@ -585,7 +587,7 @@ struct ComputeWave {
             an = rec_next(an);
             vi = rec_read_rf(ai);
             ai = rec_next(ai);
-            const float se = s * (rc.r - d);
+            const float se = rl_f(s * (rc.r - d), 63);
             float nw[VEC];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
@@ -1013,8 +1015,8 @@ struct AsyncComputeWave {
         float d = 0.0f;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) d = fmaf(wv[i], h[i], d);
-        d = wave_total(d);
-        const float se = s * (rating - d);
+        d = wave_sum_last(d);
+        const float se = rl_f(s * (rating - d), 63);
         float nw[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
