@@ -202,6 +202,25 @@ nomad_status nomad_init_batched(nomad_ctx **out, int32_t nprob, const nomad_prob
  * ESTATE.  Callers that keep it must not use it after the batch is destroyed. */
 nomad_status nomad_batch_problem(nomad_ctx *batch, int32_t b, nomad_ctx **problem);
 
+/* Capture a batch's launch sequence for `epochs` epochs into a HIP graph owned by the
+ * batch: kernels that clear the problems' abort words, diagnostics and statistics (no
+ * memset nodes), then per launch of up to 64 epochs a kernel that sets the problems'
+ * epoch counts and the batched worker launch.  Later nomad_train_epochs calls on the batch
+ * with exactly `epochs` epochs upload the problems' launch arguments (their epochs done so
+ * far) and replay the graph on the batch's stream; other epoch counts launch directly.
+ * Results are those of direct launches.  epochs = 0 drops the graph.  ESTATE if `batch` is
+ * not a batch; EINVAL if epochs < 0; EDEVICE if the capture fails. */
+nomad_status nomad_batch_graph(nomad_ctx *batch, int32_t epochs);
+
+/* Launch-shape autotuner for a batch: builds the batch (nomad_init_batched) with each
+ * candidate shape — workers = 1 or 2 per CU, 4 or 8 compute waves, a row window of 8 or 16;
+ * a field of `common` that is set (> 0) stays fixed — trains each for two epochs from the
+ * problems' initial factors (the caller's arrays are only read) and writes the config of
+ * the fastest epoch into *best (and its seconds into *best_seconds if not NULL).  Shapes
+ * that do not fit the device are skipped; EDEVICE if none fits, with the last reason. */
+nomad_status nomad_tune_batched(int32_t nprob, const nomad_problem_desc *descs, const nomad_config *common,
+                                void *hip_stream, nomad_config *best, double *best_seconds);
+
 /* Free every resource of the context (of a batch: of all its problems).  NULL, and a
  * problem of a batch, are ignored. */
 void nomad_destroy(nomad_ctx *ctx);

@@ -85,6 +85,11 @@ def load() -> C.CDLL:
     lib.nomad_init_batched.argtypes = [C.POINTER(P), i32, C.POINTER(NomadProblemDesc), C.POINTER(NomadConfig), P]
     lib.nomad_batch_problem.restype = C.c_int
     lib.nomad_batch_problem.argtypes = [P, i32, C.POINTER(P)]
+    lib.nomad_batch_graph.restype = C.c_int
+    lib.nomad_batch_graph.argtypes = [P, i32]
+    lib.nomad_tune_batched.restype = C.c_int
+    lib.nomad_tune_batched.argtypes = [i32, C.POINTER(NomadProblemDesc), C.POINTER(NomadConfig), P,
+                                       C.POINTER(NomadConfig), C.POINTER(C.c_double)]
     lib.nomad_destroy.restype = None
     lib.nomad_destroy.argtypes = [P]
     lib.nomad_last_error.restype = C.c_char_p
@@ -251,26 +256,53 @@ class Nomad:
         self.close()
 
 
+def _problem_descs(problems):
+    """nomad_problem_desc array for `problems` and the device tensors it points into."""
+    keep = []
+    descs = (NomadProblemDesc * len(problems))()
+    for d, pr in zip(descs, problems):
+        row, col, val = _dev_i32(pr["row"]), _dev_i32(pr["col"]), _dev_f32(pr["val"])
+        W0, H0 = _dev_f32(pr["W0"]), _dev_f32(pr["H0"])
+        k = int(pr["k"])
+        if tuple(W0.shape) != (int(pr["m"]), k) or tuple(H0.shape) != (int(pr["n"]), k):
+            raise ValueError("W0 must be m x k and H0 n x k")
+        keep += [row, col, val, W0, H0]
+        d.m, d.n, d.nnz = int(pr["m"]), int(pr["n"]), int(row.numel())
+        d.d_row, d.d_col, d.d_val, d.d_W0, d.d_H0 = _ptr(row), _ptr(col), _ptr(val), _ptr(W0), _ptr(H0)
+        d.k, d.lambda_, d.alpha, d.beta, d.gamma = k, pr["lam"], pr["alpha"], pr["beta"], pr["gamma"]
+    return descs, keep
+
+
+def tune_batched(problems, **kw):
+    """nomad_tune_batched: the fastest launch shape for a batch of `problems`.  Returns
+    (dict(workers=, waves_per_worker=, window=), seconds of its epoch)."""
+    lib = load()
+    cfg = make_config(1, 0.0, 0.0, 0.0, 0.0, **kw)
+    descs, keep = _problem_descs(problems)
+    best = NomadConfig()
+    sec = C.c_double()
+    _check(lib.nomad_tune_batched(len(problems), descs, C.byref(cfg), _stream_handle(), C.byref(best),
+                                  C.byref(sec)))
+    del keep
+    return dict(workers=best.workers, waves_per_worker=best.waves_per_worker, window=best.window), sec.value
+
+
 class NomadBatch:
     """Several independent problems trained together by one launch per call (wraps a batch
     nomad_ctx).  `problems`: dicts with m, n, row, col, val, W0, H0, k, lam, alpha, beta,
-    gamma; keyword arguments are the shared configuration (workers = total)."""
+    gamma; keyword arguments are the shared configuration (workers = total).  With
+    autotune=True the launch shape (workers, compute waves, row window) left unset in the
+    keywords is picked by nomad_tune_batched first (kept in .tuned)."""
 
-    def __init__(self, problems, **kw):
+    def __init__(self, problems, autotune=False, **kw):
         lib = load()
+        self.tuned = None
+        if autotune:
+            shape, sec = tune_batched(problems, **kw)
+            self.tuned = dict(shape, seconds=sec)
+            kw = dict(kw, **shape)
         self.cfg = make_config(1, 0.0, 0.0, 0.0, 0.0, **kw)
-        self._keep = []
-        descs = (NomadProblemDesc * len(problems))()
-        for d, pr in zip(descs, problems):
-            row, col, val = _dev_i32(pr["row"]), _dev_i32(pr["col"]), _dev_f32(pr["val"])
-            W0, H0 = _dev_f32(pr["W0"]), _dev_f32(pr["H0"])
-            k = int(pr["k"])
-            if tuple(W0.shape) != (int(pr["m"]), k) or tuple(H0.shape) != (int(pr["n"]), k):
-                raise ValueError("W0 must be m x k and H0 n x k")
-            self._keep += [row, col, val, W0, H0]
-            d.m, d.n, d.nnz = int(pr["m"]), int(pr["n"]), int(row.numel())
-            d.d_row, d.d_col, d.d_val, d.d_W0, d.d_H0 = _ptr(row), _ptr(col), _ptr(val), _ptr(W0), _ptr(H0)
-            d.k, d.lambda_, d.alpha, d.beta, d.gamma = k, pr["lam"], pr["alpha"], pr["beta"], pr["gamma"]
+        descs, self._keep = _problem_descs(problems)
         ctx = C.c_void_p()
         _check(lib.nomad_init_batched(C.byref(ctx), len(problems), descs, C.byref(self.cfg), _stream_handle()))
         self._keep = []  # the inputs are copied by the call
@@ -283,6 +315,12 @@ class NomadBatch:
             view.m, view.n, view.k = int(pr["m"]), int(pr["n"]), int(pr["k"])
             view.ctx, view._owned, view.nnz = sub, False, int(pr["row"].numel())
             self.problems.append(view)
+
+    def graph(self, epochs: int):
+        """nomad_batch_graph: later train(epochs) calls replay a captured HIP graph (0 drops it)."""
+        if self.ctx is None:
+            raise NomadError(NOMAD_ESTATE, "batch destroyed")
+        _check(load().nomad_batch_graph(self.ctx, int(epochs)), self.ctx)
 
     def train(self, epochs: int) -> Stats:
         if self.ctx is None:

@@ -56,6 +56,8 @@ struct nomad_ctx {
     int32_t *d_wg = nullptr;           // per workgroup: its problem
     std::vector<int32_t> wg0;          // per problem: its first workgroup
     int32_t total_wg = 0;
+    hipGraphExec_t graph = nullptr;    // a batch's captured launch sequence (nomad_batch_graph)
+    int32_t graph_epochs = 0;          // the epochs it runs
 };
 
 namespace {
@@ -93,6 +95,8 @@ void release(nomad_ctx *c) {
         delete m;
     }
     c->members.clear();
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
     (void)hipFree(c->d_descs);
     (void)hipFree(c->d_wg);
     (void)hipFree(c->queue);
@@ -417,7 +421,34 @@ static nomad_status train_batch(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
     }
     hipStream_t st = c->stream;
     double seconds = 0.0;
-    if (epochs > 0) {
+    if (epochs > 0 && c->graph && epochs == c->graph_epochs) {
+        // The captured sequence: the problems' launch arguments as of now, then the graph
+        // (resets, then per launch its epoch count and the workers).
+        const size_t np = c->members.size();
+        std::vector<nomad::TrainArgs> h(np);
+        for (size_t b = 0; b < np; ++b) {
+            fill_args(c->members[b], h[b]);
+            h[b].epoch0 = (int32_t)c->members[b]->epochs_done;
+            h[b].epochs = 0;
+            h[b].wg0 = c->wg0[b];
+        }
+        HIPTRY(c, hipMemcpyAsync(c->d_descs, h.data(), sizeof(nomad::TrainArgs) * np, hipMemcpyHostToDevice, st),
+               "train: arguments");
+        HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
+        HIPTRY(c, hipGraphLaunch(c->graph, st), "train: graph launch");
+        HIPTRY(c, hipEventRecord(c->ev1, st), "train: event");
+        HIPTRY(c, hipEventSynchronize(c->ev1), "train: kernel");
+        float ms = 0.0f;
+        HIPTRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1), "train: timing");
+        seconds = ms * 1e-3;
+        for (size_t b = 0; b < np; ++b) {
+            const nomad_status ab = check_abort(c->members[b], "nomad_train_epochs");
+            if (ab != NOMAD_OK)
+                return fail(c, ab, "problem %zu of the batch: %s", b, c->members[b]->err.c_str());
+        }
+        for (nomad_ctx *m : c->members) m->epochs_done += epochs;
+        c->epochs_done += epochs;
+    } else if (epochs > 0) {
         const size_t np = c->members.size();
         std::vector<nomad::TrainArgs> h(np);
         for (nomad_ctx *m : c->members) {
@@ -772,6 +803,95 @@ nomad_status nomad_batch_problem(nomad_ctx *c, int32_t b, nomad_ctx **problem) {
     if (b < 0 || b >= (int32_t)c->members.size())
         return fail(c, NOMAD_EINVAL, "nomad_batch_problem: b=%d outside [0,%zu)", b, c->members.size());
     *problem = c->members[b];
+    return NOMAD_OK;
+}
+
+nomad_status nomad_batch_graph(nomad_ctx *c, int32_t epochs) {
+    if (!c || c->members.empty()) return fail(c, NOMAD_ESTATE, "nomad_batch_graph: not a batch");
+    if (epochs < 0) return fail(c, NOMAD_EINVAL, "nomad_batch_graph: epochs=%d < 0", epochs);
+    if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    c->graph = nullptr;
+    c->graph_epochs = 0;
+    if (epochs == 0) return NOMAD_OK;
+    const int32_t np = (int32_t)c->members.size();
+    nomad::TrainArgs shape{};
+    fill_args(c->members[0], shape);  // the launch shape all problems share
+    // Capture on a private stream (the batch's may be the null stream, which cannot be
+    // captured); the graph is replayed on the batch's stream.
+    hipStream_t cs = nullptr;
+    HIPTRY(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "nomad_batch_graph: stream");
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        e = nomad::launch_batch_reset(c->d_descs, np, cs);
+        int32_t prev = 0;
+        for (int32_t done = 0; e == hipSuccess && done < epochs;) {
+            const int32_t ne = std::min(epochs - done, (int32_t)nomad::kMaxEpochsPerLaunch);
+            e = nomad::launch_batch_epochs(c->d_descs, np, ne, prev, cs);
+            if (e == hipSuccess) e = nomad::launch_train_batch(shape, c->total_wg, c->d_descs, c->d_wg, cs);
+            prev = ne;
+            done += ne;
+        }
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        c->graph = nullptr;
+        return hip_fail(c, e, "nomad_batch_graph: capture");
+    }
+    c->graph_epochs = epochs;
+    return NOMAD_OK;
+}
+
+nomad_status nomad_tune_batched(int32_t nprob, const nomad_problem_desc *descs, const nomad_config *common,
+                                void *hip_stream, nomad_config *best, double *best_seconds) {
+    if (!common || !best) return fail(nullptr, NOMAD_EINVAL, "nomad_tune_batched: NULL config");
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return fail(nullptr, NOMAD_EDEVICE, "nomad_tune_batched: no usable HIP device");
+    // Candidates: one or two workers per CU, four or eight compute waves, row windows of 8
+    // or 16; a field the caller set stays as set.
+    std::vector<int32_t> ws, nws, wins;
+    if (common->workers > 0) ws = {common->workers}; else ws = {cus, 2 * cus};
+    if (common->waves_per_worker > 0) nws = {common->waves_per_worker}; else nws = {4, 8};
+    if (common->window > 0) wins = {common->window}; else wins = {8, 16};
+    double tbest = 0.0;
+    bool found = false;
+    std::string last;
+    for (int32_t w : ws)
+        for (int32_t nw : nws)
+            for (int32_t win : wins) {
+                nomad_config cfg = *common;
+                cfg.workers = w;
+                cfg.waves_per_worker = nw;
+                cfg.window = win;
+                nomad_ctx *c = nullptr;
+                if (nomad_init_batched(&c, nprob, descs, &cfg, hip_stream) != NOMAD_OK) {
+                    last = g_last_error;  // the shape does not fit (LDS, residency): next one
+                    continue;
+                }
+                // the faster of two epochs (the first also loads the kernel's code)
+                double t = 0.0;
+                bool ok = true;
+                for (int r = 0; r < 2 && ok; ++r) {
+                    nomad_stats stt{};
+                    ok = nomad_train_epochs(c, 1, &stt) == NOMAD_OK;
+                    if (ok) t = r == 0 ? stt.seconds : std::min(t, stt.seconds);
+                }
+                if (!ok) last = c->err;
+                nomad_destroy(c);
+                if (ok && (!found || t < tbest)) {
+                    found = true;
+                    tbest = t;
+                    *best = cfg;
+                }
+            }
+    if (!found) return fail(nullptr, NOMAD_EDEVICE, "nomad_tune_batched: no launch shape worked (%s)", last.c_str());
+    if (best_seconds) *best_seconds = tbest;
     return NOMAD_OK;
 }
 

@@ -200,6 +200,12 @@ size_t async_scratch_bytes(int64_t n, int32_t p);
 // shared by all (kp, storage type, nw, slots, window).
 hipError_t launch_train_batch(const TrainArgs &shape, int32_t workgroups, const TrainArgs *d_descs,
                               const int32_t *d_wg_prob, hipStream_t stream);
+// Kernels a captured batch launch uses in place of memsets (a HIP graph records no memset
+// nodes here): clear every problem's abort word, diagnostics and worker statistics; set
+// every problem's launch epoch count to `epochs` after advancing its epoch0 by `advance`.
+hipError_t launch_batch_reset(const TrainArgs *d_descs, int32_t nprob, hipStream_t stream);
+hipError_t launch_batch_epochs(TrainArgs *d_descs, int32_t nprob, int32_t epochs, int32_t advance,
+                               hipStream_t stream);
 // Workers of `nw` compute waves that can be resident at once on the device.
 hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
                              int32_t *max_workers);

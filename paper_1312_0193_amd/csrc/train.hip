@@ -1564,6 +1564,39 @@ hipError_t launch_train_async(const TrainArgs &a, const int64_t *vbase, void *sc
     return launch_async_b(a, st);
 }
 
+namespace {
+// Per-launch resets of a batch's problems: block b clears problem b's abort word, its
+// eight diagnostic words and its workers' statistics.
+__global__ void k_batch_reset(const TrainArgs *descs, int nprob) {
+    const int b = blockIdx.x;
+    if (b >= nprob) return;
+    const TrainArgs a = descs[b];
+    if (threadIdx.x == 0) *a.abort_flag = 0u;
+    if (threadIdx.x < 8) a.diag[threadIdx.x] = 0;
+    const int64_t nst = (int64_t)kWStatCount * a.p;
+    for (int64_t i = threadIdx.x; i < nst; i += blockDim.x) a.wstats[i] = 0;
+}
+
+__global__ void k_batch_epochs(TrainArgs *descs, int nprob, int32_t epochs, int32_t advance) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nprob) return;
+    descs[b].epoch0 += advance;
+    descs[b].epochs = epochs;
+}
+}  // namespace
+
+hipError_t launch_batch_reset(const TrainArgs *d_descs, int32_t nprob, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_reset, dim3(nprob), dim3(64), 0, st, d_descs, (int)nprob);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_epochs(TrainArgs *d_descs, int32_t nprob, int32_t epochs, int32_t advance, hipStream_t st) {
+    if (nprob <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_batch_epochs, dim3((nprob + 63) / 64), dim3(64), 0, st, d_descs, (int)nprob, epochs, advance);
+    return hipGetLastError();
+}
+
 hipError_t launch_train_batch(const TrainArgs &shape, int32_t workgroups, const TrainArgs *d_descs,
                               const int32_t *d_wg_prob, hipStream_t st) {
     TrainArgs a = shape;

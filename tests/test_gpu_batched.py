@@ -135,3 +135,79 @@ def test_batch_errors():
     assert lib.nomad_get_factors(batch.ctx, W.data_ptr(), H.data_ptr()) == nm.NOMAD_ESTATE
     assert lib.nomad_train_epochs(batch.problems[0].ctx, 1, None) == nm.NOMAD_ESTATE
     batch.close()
+
+
+def _factors_equal(a, b):
+    return all(torch.equal(x, y) for va, vb in zip(a.problems, b.problems)
+               for x, y in zip(va.factors(), vb.factors()))
+
+
+def test_batch_graph_replays_match_direct_launches():
+    """A captured batch launch (nomad_batch_graph) gives the direct launches' factors
+    bitwise, on every replay, with other GPU work between replays, after a direct call of a
+    different length, and for a graph of two launches (66 epochs)."""
+    probs = problems(SPECS[:4], seed0=500)
+    for kw in (dict(), dict(dtype="bf16", rounding="stochastic")):
+        print(f"[case] batch graph, 4 problems, {kw}", flush=True)
+        g = nm.NomadBatch(probs, workers=24, seed=5, **kw)
+        d = nm.NomadBatch(probs, workers=24, seed=5, **kw)
+        g.graph(2)
+        for r in range(3):
+            g.train(2)
+            d.train(2)
+            # eager work and a synchronisation between replays
+            pr = probs[0]["prob"]
+            g.problems[0].evaluate(pr.test_row, pr.test_col, pr.test_val)
+            torch.cuda.synchronize()
+            assert _factors_equal(g, d), (kw, r)
+        g.train(1)  # a direct launch between replays
+        d.train(1)
+        g.train(2)
+        d.train(2)
+        assert _factors_equal(g, d), kw
+        g.close()
+        d.close()
+    print("[case] batch graph of 66 epochs (two launches)", flush=True)
+    g = nm.NomadBatch(probs[:2], workers=8, seed=6)
+    d = nm.NomadBatch(probs[:2], workers=8, seed=6)
+    g.graph(66)
+    g.train(66)
+    d.train(66)
+    assert _factors_equal(g, d)
+    g.graph(0)  # dropped: direct launches again
+    g.train(66)
+    d.train(66)
+    assert _factors_equal(g, d)
+    g.close()
+    d.close()
+    with pytest.raises(nm.NomadError, match="ESTATE"):
+        alone = nm.Nomad(probs[0]["m"], probs[0]["n"], probs[0]["row"], probs[0]["col"], probs[0]["val"],
+                         probs[0]["W0"], probs[0]["H0"], k=probs[0]["k"], lam=0.05, alpha=0.01, beta=1e-4,
+                         gamma=1.0, workers=4)
+        try:
+            nm._check(nm.load().nomad_batch_graph(alone.ctx, 2), alone.ctx)
+        finally:
+            alone.close()
+
+
+def test_tune_batched_picks_a_working_shape():
+    probs = problems(SPECS, seed0=600)
+    print("[case] autotuner over the 6-problem batch", flush=True)
+    shape, sec = nm.tune_batched(probs, seed=3)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert shape["workers"] in (cus, 2 * cus) and shape["waves_per_worker"] in (4, 8)
+    assert shape["window"] in (8, 16) and sec > 0.0
+    # a field that is set stays fixed
+    shape2, _ = nm.tune_batched(probs, seed=3, waves_per_worker=6, window=8)
+    assert shape2["waves_per_worker"] == 6 and shape2["window"] == 8
+    batch = nm.NomadBatch(probs, autotune=True, seed=3)
+    assert batch.tuned is not None and batch.tuned["workers"] == sum(v.workers for v in batch.problems)
+    batch.train(1)
+    b = int(np.argmax([v.workers for v in batch.problems]))
+    p = probs[b]
+    alone = nm.Nomad(p["m"], p["n"], p["row"], p["col"], p["val"], p["W0"], p["H0"], k=p["k"], lam=p["lam"],
+                     alpha=p["alpha"], beta=p["beta"], gamma=p["gamma"], workers=batch.problems[b].workers, seed=3)
+    alone.train(1)
+    assert all(torch.equal(x, y) for x, y in zip(alone.factors(), batch.problems[b].factors()))
+    alone.close()
+    batch.close()
