@@ -212,14 +212,22 @@ nomad_status nomad_batch_problem(nomad_ctx *batch, int32_t b, nomad_ctx **proble
  * not a batch; EINVAL if epochs < 0; EDEVICE if the capture fails. */
 nomad_status nomad_batch_graph(nomad_ctx *batch, int32_t epochs);
 
+/* Called by nomad_tune_batched after each candidate: its config, NOMAD_OK and the
+ * seconds of its faster epoch, or the status that ruled it out (seconds 0). */
+typedef void (*nomad_tune_progress)(const nomad_config *candidate, nomad_status status, double seconds,
+                                    void *user);
+
 /* Launch-shape autotuner for a batch: builds the batch (nomad_init_batched) with each
- * candidate shape — workers = 1 or 2 per CU, 4 or 8 compute waves, a row window of 8 or 16;
- * a field of `common` that is set (> 0) stays fixed — trains each for two epochs from the
- * problems' initial factors (the caller's arrays are only read) and writes the config of
- * the fastest epoch into *best (and its seconds into *best_seconds if not NULL).  Shapes
- * that do not fit the device are skipped; EDEVICE if none fits, with the last reason. */
+ * candidate shape — workers = 1 or 2 per CU times 4 or 8 compute waves; a field of
+ * `common` that is set (> 0) stays fixed, the row window is common's — trains each for two
+ * epochs from the problems' initial factors (the caller's arrays are only read), reports
+ * each to `progress` if not NULL, and writes the config of the fastest epoch into *best
+ * (and its seconds into *best_seconds if not NULL).  Every candidate costs a layout of the
+ * whole batch.  Shapes that do not fit the device are skipped; EDEVICE if none fits, with
+ * the last reason. */
 nomad_status nomad_tune_batched(int32_t nprob, const nomad_problem_desc *descs, const nomad_config *common,
-                                void *hip_stream, nomad_config *best, double *best_seconds);
+                                void *hip_stream, nomad_tune_progress progress, void *user, nomad_config *best,
+                                double *best_seconds);
 
 /* Free every resource of the context (of a batch: of all its problems).  NULL, and a
  * problem of a batch, are ignored. */

@@ -43,6 +43,10 @@ class NomadStats(C.Structure):
                 ("layout_seconds", C.c_double)]
 
 
+# nomad_tune_progress(const nomad_config *candidate, nomad_status status, double seconds, void *user)
+TUNE_PROGRESS = C.CFUNCTYPE(None, C.POINTER(NomadConfig), C.c_int, C.c_double, C.c_void_p)
+
+
 class NomadError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
@@ -89,7 +93,7 @@ def load() -> C.CDLL:
     lib.nomad_batch_graph.argtypes = [P, i32]
     lib.nomad_tune_batched.restype = C.c_int
     lib.nomad_tune_batched.argtypes = [i32, C.POINTER(NomadProblemDesc), C.POINTER(NomadConfig), P,
-                                       C.POINTER(NomadConfig), C.POINTER(C.c_double)]
+                                       TUNE_PROGRESS, P, C.POINTER(NomadConfig), C.POINTER(C.c_double)]
     lib.nomad_destroy.restype = None
     lib.nomad_destroy.argtypes = [P]
     lib.nomad_last_error.restype = C.c_char_p
@@ -273,15 +277,24 @@ def _problem_descs(problems):
     return descs, keep
 
 
-def tune_batched(problems, **kw):
+def tune_batched(problems, progress=None, **kw):
     """nomad_tune_batched: the fastest launch shape for a batch of `problems`.  Returns
-    (dict(workers=, waves_per_worker=, window=), seconds of its epoch)."""
+    (dict(workers=, waves_per_worker=, window=), seconds of its epoch).  `progress`, if
+    given, is called as progress(shape dict, status, seconds) after each candidate."""
     lib = load()
     cfg = make_config(1, 0.0, 0.0, 0.0, 0.0, **kw)
     descs, keep = _problem_descs(problems)
     best = NomadConfig()
     sec = C.c_double()
-    _check(lib.nomad_tune_batched(len(problems), descs, C.byref(cfg), _stream_handle(), C.byref(best),
+
+    def report(c, status, seconds, user):
+        if progress is not None:
+            c = c.contents
+            progress(dict(workers=c.workers, waves_per_worker=c.waves_per_worker, window=c.window), status,
+                     seconds)
+
+    cb = TUNE_PROGRESS(report)
+    _check(lib.nomad_tune_batched(len(problems), descs, C.byref(cfg), _stream_handle(), cb, None, C.byref(best),
                                   C.byref(sec)))
     del keep
     return dict(workers=best.workers, waves_per_worker=best.waves_per_worker, window=best.window), sec.value
@@ -294,11 +307,11 @@ class NomadBatch:
     autotune=True the launch shape (workers, compute waves, row window) left unset in the
     keywords is picked by nomad_tune_batched first (kept in .tuned)."""
 
-    def __init__(self, problems, autotune=False, **kw):
+    def __init__(self, problems, autotune=False, progress=None, **kw):
         lib = load()
         self.tuned = None
         if autotune:
-            shape, sec = tune_batched(problems, **kw)
+            shape, sec = tune_batched(problems, progress=progress, **kw)
             self.tuned = dict(shape, seconds=sec)
             kw = dict(kw, **shape)
         self.cfg = make_config(1, 0.0, 0.0, 0.0, 0.0, **kw)

@@ -847,18 +847,19 @@ nomad_status nomad_batch_graph(nomad_ctx *c, int32_t epochs) {
 }
 
 nomad_status nomad_tune_batched(int32_t nprob, const nomad_problem_desc *descs, const nomad_config *common,
-                                void *hip_stream, nomad_config *best, double *best_seconds) {
+                                void *hip_stream, nomad_tune_progress progress, void *user, nomad_config *best,
+                                double *best_seconds) {
     if (!common || !best) return fail(nullptr, NOMAD_EINVAL, "nomad_tune_batched: NULL config");
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return fail(nullptr, NOMAD_EDEVICE, "nomad_tune_batched: no usable HIP device");
-    // Candidates: one or two workers per CU, four or eight compute waves, row windows of 8
-    // or 16; a field the caller set stays as set.
+    // Candidates: one or two workers per CU, four or eight compute waves (the row window
+    // stays the batch's default unless set); a field the caller set stays as set.
     std::vector<int32_t> ws, nws, wins;
     if (common->workers > 0) ws = {common->workers}; else ws = {cus, 2 * cus};
     if (common->waves_per_worker > 0) nws = {common->waves_per_worker}; else nws = {4, 8};
-    if (common->window > 0) wins = {common->window}; else wins = {8, 16};
+    wins = {common->window};
     double tbest = 0.0;
     bool found = false;
     std::string last;
@@ -870,8 +871,10 @@ nomad_status nomad_tune_batched(int32_t nprob, const nomad_problem_desc *descs, 
                 cfg.waves_per_worker = nw;
                 cfg.window = win;
                 nomad_ctx *c = nullptr;
-                if (nomad_init_batched(&c, nprob, descs, &cfg, hip_stream) != NOMAD_OK) {
+                const nomad_status si = nomad_init_batched(&c, nprob, descs, &cfg, hip_stream);
+                if (si != NOMAD_OK) {
                     last = g_last_error;  // the shape does not fit (LDS, residency): next one
+                    if (progress) progress(&cfg, si, 0.0, user);
                     continue;
                 }
                 // the faster of two epochs (the first also loads the kernel's code)
@@ -884,6 +887,7 @@ nomad_status nomad_tune_batched(int32_t nprob, const nomad_problem_desc *descs, 
                 }
                 if (!ok) last = c->err;
                 nomad_destroy(c);
+                if (progress) progress(&cfg, ok ? NOMAD_OK : NOMAD_EDEVICE, t, user);
                 if (ok && (!found || t < tbest)) {
                     found = true;
                     tbest = t;

@@ -193,13 +193,18 @@ def test_batch_graph_replays_match_direct_launches():
 def test_tune_batched_picks_a_working_shape():
     probs = problems(SPECS, seed0=600)
     print("[case] autotuner over the 6-problem batch", flush=True)
-    shape, sec = nm.tune_batched(probs, seed=3)
+    seen = []
+    shape, sec = nm.tune_batched(probs, progress=lambda c, st, t: seen.append((c, st, t)), seed=3)
+    print(f"[case] candidates {seen}", flush=True)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    assert shape["workers"] in (cus, 2 * cus) and shape["waves_per_worker"] in (4, 8)
-    assert shape["window"] in (8, 16) and sec > 0.0
+    assert len(seen) == 4
+    assert {(c["workers"], c["waves_per_worker"]) for c, _, _ in seen} == {(w, nw) for w in (cus, 2 * cus)
+                                                                           for nw in (4, 8)}
+    ok = [(t, c) for c, st, t in seen if st == nm.NOMAD_OK]
+    assert ok and sec == min(t for t, _ in ok) and shape == min(ok, key=lambda x: x[0])[1]
     # a field that is set stays fixed
-    shape2, _ = nm.tune_batched(probs, seed=3, waves_per_worker=6, window=8)
-    assert shape2["waves_per_worker"] == 6 and shape2["window"] == 8
+    shape2, _ = nm.tune_batched(probs, seed=3, waves_per_worker=6, window=16)
+    assert shape2["waves_per_worker"] == 6 and shape2["window"] == 16
     batch = nm.NomadBatch(probs, autotune=True, seed=3)
     assert batch.tuned is not None and batch.tuned["workers"] == sum(v.workers for v in batch.problems)
     batch.train(1)
