@@ -80,3 +80,18 @@ def test_null_arguments_are_rejected_without_a_device():
     assert b"k=0" in lib.nomad_last_error(None)
     assert lib.nomad_train_epochs(None, 1, None) == nm.NOMAD_ESTATE
     lib.nomad_destroy(None)
+
+
+def test_batch_entry_points_reject_bad_arguments_without_a_device():
+    if not os.path.exists(nm.library_path()):
+        pytest.skip("libnomad.so not built")
+    lib = nm.load()
+    assert lib.nomad_batch_graph(None, 2) == nm.NOMAD_ESTATE
+    assert b"not a batch" in lib.nomad_last_error(None)
+    best = nm.NomadConfig()
+    assert lib.nomad_tune_batched(1, None, None, None, nm.TUNE_PROGRESS(0), None, C.byref(best), None) == \
+        nm.NOMAD_EINVAL
+    assert b"NULL config" in lib.nomad_last_error(None)
+    sub = C.c_void_p()
+    assert lib.nomad_batch_problem(None, 0, C.byref(sub)) == nm.NOMAD_ESTATE
+    assert lib.nomad_init_batched(C.byref(sub), 0, None, None, None) != nm.NOMAD_OK
