@@ -143,7 +143,8 @@ nomad_status choose_shape(const nomad_config *cfg, int32_t kp, int32_t wbytes, n
     // come first, then item slots.
     int32_t slots = cfg->item_slots;
     int32_t window = cfg->window <= 0 ? nomad::kMaxWindow : (cfg->window <= 8 ? 8 : (cfg->window <= 16 ? 16 : 32));
-    const bool auto_window = cfg->window <= 0;
+    if (async) window = nomad::kAsyncWindow;  // the asynchronous kernel keeps its rows in registers
+    const bool auto_window = cfg->window <= 0 && !async;
     auto fits = [&](int32_t s_, int32_t w_) {
         return nomad::train_lds_bytes(kp, nw, s_, w_, wbytes) <= (size_t)max_lds;
     };
@@ -168,7 +169,7 @@ nomad_status choose_shape(const nomad_config *cfg, int32_t kp, int32_t wbytes, n
         return fail(ec, NOMAD_EINVAL, "nomad_init: %d compute waves, %d item slots and a window of %d rows need "
                     "%zu bytes of LDS for padded k=%d, device allows %d", nw, slots, window, lds, kp, max_lds);
     int32_t maxw = 0;
-    hipError_t he = nomad::train_max_workers(kp, nw, slots, window, wbytes, &maxw);
+    hipError_t he = nomad::train_max_workers(kp, nw, slots, window, wbytes, &maxw, async);
     if (he != hipSuccess) return hip_fail(ec, he, "nomad_init: occupancy query");
     out->kp = kp;
     out->nw = nw;

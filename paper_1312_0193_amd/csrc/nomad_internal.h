@@ -208,7 +208,10 @@ hipError_t launch_batch_epochs(TrainArgs *d_descs, int32_t nprob, int32_t epochs
                                hipStream_t stream);
 // Workers of `nw` compute waves that can be resident at once on the device.
 hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
-                             int32_t *max_workers);
+                             int32_t *max_workers, bool async = false);
+// The row window the asynchronous kernel's LDS layout is built for (its rows are in
+// registers; the layout keeps the ring kernel's shape).
+constexpr int kAsyncWindow = 8;
 // Row stride of the factors for k: a whole number of 16-byte pieces per lane of a wave.
 inline int32_t padded_k(int32_t k) { return k <= 64 ? 64 : (k <= 128 ? 128 : 256); }
 

@@ -1490,20 +1490,30 @@ hipError_t launch_b(const TrainArgs &a, const TrainArgs *d, const int32_t *g, hi
 
 }  // namespace
 
+namespace {
+template <bool BF>
+const void *pick_async(int kp) {
+    if (kp <= 64) return (const void *)k_worker_async<1, kAsyncWindow, BF>;
+    if (kp <= 128) return (const void *)k_worker_async<2, kAsyncWindow, BF>;
+    return (const void *)k_worker_async<4, kAsyncWindow, BF>;
+}
+}  // namespace
+
 size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes) {
     return lds_bytes(kp, nw, slots, window, wbytes);
 }
 
 hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
-                             int32_t *max_workers) {
+                             int32_t *max_workers, bool async) {
     int dev = 0, cus = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &nb, wbytes == 2 ? pick_kernel<true>(kp, window) : pick_kernel<false>(kp, window), 64 * (nw + 1),
-        lds_bytes(kp, nw, slots, window, wbytes));
+    if (async) window = kAsyncWindow;
+    const void *kern = async ? (wbytes == 2 ? pick_async<true>(kp) : pick_async<false>(kp))
+                             : (wbytes == 2 ? pick_kernel<true>(kp, window) : pick_kernel<false>(kp, window));
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 64 * (nw + 1), lds_bytes(kp, nw, slots, window, wbytes));
     if (e != hipSuccess) return e;
     *max_workers = nb * cus;
     return hipSuccess;
@@ -1522,7 +1532,7 @@ hipError_t launch_async_t(const TrainArgs &a, hipStream_t st) {
 }
 template <int VEC, bool BF>
 hipError_t launch_async_v(const TrainArgs &a, hipStream_t st) {
-    return launch_async_t<VEC, 8, BF>(a, st);  // the row window of the LDS layout is not used here
+    return launch_async_t<VEC, kAsyncWindow, BF>(a, st);  // the row window of the LDS layout is not used here
 }
 template <bool BF>
 hipError_t launch_async_k(const TrainArgs &a, hipStream_t st) {

@@ -57,6 +57,7 @@ def holders(prob, P):
     (600, 300, 12_000, 16, 6, "uniform", 3, 4),
     (2_000, 1_000, 60_000, 100, 32, "zipf", 0, 0),
     (400, 250, 15_000, 64, 64, "uniform", 8, 2),
+    (300, 200, 9_000, 200, 16, "zipf", 0, 0),       # k > 128: four elements per lane
 ])
 def test_perm_trace_covers_every_visit_once_per_epoch_and_replays(case):
     m, n, nnz, k, P, degrees, nw, slots = case
@@ -104,9 +105,11 @@ def test_perm_visiting_orders_differ_between_epochs():
     assert differ >= len(np.unique(tr[:, 1])) // 2
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(waves_per_worker=3, item_slots=2), dict(dtype="bf16")])
-def test_perm_one_worker_is_the_ring_order(kw):
-    prob, W0, H0, hp = make(500, 200, 10_000, k=32, seed=8)
+@pytest.mark.parametrize("kw,k", [(dict(), 32), (dict(waves_per_worker=3, item_slots=2), 32), (dict(dtype="bf16"), 32),
+                                  (dict(), 256), (dict(dtype="bf16", rounding="stochastic"), 256),
+                                  (dict(dtype="bf16", rounding="stochastic"), 8)])
+def test_perm_one_worker_is_the_ring_order(kw, k):
+    prob, W0, H0, hp = make(500, 200, 10_000, k=k, seed=8)
     _, Wp, Hp = run(prob, W0, H0, hp, 1, 2, [2, 1], **kw)
     ring = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
                     beta=hp.beta, gamma=hp.gamma, workers=1, seed=2, **kw)
