@@ -975,17 +975,13 @@ struct AsyncComputeWave {
     const Lds &L;
     const int q, w, lane, kp, loff, rb;
     const RatingRec *rs;  // the wave's records, grouped by local item
-    const int64_t cnt;
-    const int64_t vb;     // first visit record of the worker (local item 0)
-    const int nv;         // local items
     lds_float *const items;
     char *const W;
     const uint32_t lb;    // the lane's byte offset inside a row
     uint64_t nrat = 0, t_wait = 0;
 
-    __device__ AsyncComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0, int64_t cnt_)
+    __device__ AsyncComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0)
         : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC), rb(a_.kp * ES), rs(a_.recs + r0),
-          cnt(cnt_), vb(a_.vbase[q_]), nv((int)(a_.vbase[q_ + 1] - a_.vbase[q_])),
           items(to_lds(L_.items) + lane_ * VEC), W((char *)a_.W), lb((uint32_t)(lane_ * VEC * ES)) {}
 
     // The lane's part of row `row` (uniform).
@@ -1032,8 +1028,6 @@ struct AsyncComputeWave {
 
     __device__ void run() {
         const int32_t *word = w == 0 ? &L.ctl[0] : &L.flag[w - 1];
-        typedef const __attribute__((address_space(4))) int32_t *cint;
-        const cint xo = (cint)a.xoff;
         for (int X = 0;; ++X) {
             const uint64_t t0 = tick(a.timing);
             if (!wait_visit(word, X)) break;
@@ -1043,9 +1037,10 @@ struct AsyncComputeWave {
             const int x = __builtin_amdgcn_readfirstlane(L.sx[sl]);  // -1: the worker holds no rating of the item
             int64_t b = 0, e = 0;
             if (x >= 0) {
-                const int64_t v = vb + x;
-                b = xo[v * a.nw + w];
-                e = x + 1 < nv ? (int64_t)xo[(v + 1) * a.nw + w] : cnt;
+                // the wave's record range of the visit, left in LDS by the memory wave
+                const int32_t *rng = (const int32_t *)L.recs;
+                b = __builtin_amdgcn_readfirstlane(rng[w * kMaxItemSlots + sl]);
+                e = __builtin_amdgcn_readfirstlane(rng[(a.nw + w) * kMaxItemSlots + sl]);
             }
             if (b < e) {
                 const int t = __builtin_amdgcn_readfirstlane(L.se[sl]);
@@ -1144,6 +1139,8 @@ struct AsyncMemoryWave {
     const bool uni;       // uniform routing
     const int64_t qb;     // inbound queue: [qb, qb + cap)
     const int64_t cap;
+    const int64_t vbq;    // the worker's first visit record
+    const int nvq;        // the worker's local items
     int Xl = 0, Xr = 0;   // visits taken / passed on
     int64_t head = 0;     // next queue position to take
     // lane s < S: the visit in slot s: item, holder entry (-1 if none), step counter t, visit
@@ -1154,7 +1151,8 @@ struct AsyncMemoryWave {
     __device__ AsyncMemoryWave(const TrainArgs &a_, const Lds &L_, int q_, int lane_)
         : a(a_), L(L_), io(a_, L_, q_, lane_), q(q_), lane(lane_), S(a_.slots), uni(a_.sched == 2),
           qb(a_.sched == 2 ? (int64_t)q_ * a_.n : a_.vbase[q_]),
-          cap(a_.sched == 2 ? a_.n : a_.vbase[q_ + 1] - a_.vbase[q_]) {}
+          cap(a_.sched == 2 ? a_.n : a_.vbase[q_ + 1] - a_.vbase[q_]), vbq(a_.vbase[q_]),
+          nvq((int)(a_.vbase[q_ + 1] - a_.vbase[q_])) {}
 
     // Push item j (payload `pay`) to worker q2's queue.
     __device__ __forceinline__ void push(int q2, uint32_t pay) {
@@ -1266,6 +1264,28 @@ struct AsyncMemoryWave {
                             cv = (float)((double)sv * (double)a.lambda);
                         }
                         for (int k = 0; k < nt; ++k) io.load_item(__shfl(j, k), (Xl + k) & Smask);
+                        {
+                            // Every compute wave's record range of the new visits, into LDS
+                            // (the record ring of the ring kernel's layout, unused here): one
+                            // batched load here instead of a dependent load at the start of
+                            // every visit in every compute wave.
+                            int32_t *rng = (int32_t *)L.recs;
+                            const int sl = (Xl + lane) & Smask;
+                            for (int w2 = 0; w2 < a.nw; ++w2) {
+                                int bw = 0, ew = 0;
+                                if (lane < nt && x >= 0) {
+                                    const int64_t v = vbq + x;
+                                    bw = a.xoff[v * a.nw + w2];
+                                    ew = x + 1 < nvq ? a.xoff[(v + 1) * a.nw + w2]
+                                                     : (int)(a.rbase[(int64_t)q * a.nw + w2 + 1] -
+                                                             a.rbase[(int64_t)q * a.nw + w2]);
+                                }
+                                if (lane < nt) {
+                                    rng[w2 * kMaxItemSlots + sl] = bw;
+                                    rng[(a.nw + w2) * kMaxItemSlots + sl] = ew;
+                                }
+                            }
+                        }
                         if (lane < nt) {
                             const int sl = (Xl + lane) & Smask;
                             L.sx[sl] = x;
@@ -1358,8 +1378,7 @@ __global__ __launch_bounds__(1024) void k_worker_async(TrainArgs a) {
     __syncthreads();
     if (q >= a.p || a.epochs <= 0) return;
     if (wave < a.nw) {
-        const int64_t i0 = a.rbase[(int64_t)q * a.nw + wave], i1 = a.rbase[(int64_t)q * a.nw + wave + 1];
-        AsyncComputeWave<VEC, BF> cw(a, L, q, wave, lane, i0, i1 - i0);
+        AsyncComputeWave<VEC, BF> cw(a, L, q, wave, lane, a.rbase[(int64_t)q * a.nw + wave]);
         cw.run();
     } else if (wave == a.nw) {
         AsyncMemoryWave mw(a, L, q, lane);
