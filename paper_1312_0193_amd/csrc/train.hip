@@ -1026,22 +1026,33 @@ struct AsyncComputeWave {
         row_gstore<VEC, BF>(lane_row(row), nw);
     }
 
+    // The wave's record range of visit X, left in LDS by the memory wave ([b, e); b = e when
+    // the worker holds no rating of the item or the wave none of its ratings).
+    __device__ __forceinline__ void range(int X, int64_t &b, int64_t &e) const {
+        const int sl = X & (a.slots - 1);
+        const int x = __builtin_amdgcn_readfirstlane(L.sx[sl]);  // -1: the worker holds no rating of the item
+        b = e = 0;
+        if (x >= 0) {
+            const int32_t *rng = (const int32_t *)L.recs;
+            b = __builtin_amdgcn_readfirstlane(rng[w * kMaxItemSlots + sl]);
+            e = __builtin_amdgcn_readfirstlane(rng[(a.nw + w) * kMaxItemSlots + sl]);
+        }
+    }
+
     __device__ void run() {
         const int32_t *word = w == 0 ? &L.ctl[0] : &L.flag[w - 1];
+        // The first records of a later visit, loaded while this one is updated: `pre` holds
+        // them (lane l: record l) for visit pre_X.
+        int pre_X = -1;
+        u32x2v pre = {0u, 0u};
         for (int X = 0;; ++X) {
             const uint64_t t0 = tick(a.timing);
             if (!wait_visit(word, X)) break;
             compiler_fence();
             t_wait += tick(a.timing) - t0;
             const int sl = X & (a.slots - 1);
-            const int x = __builtin_amdgcn_readfirstlane(L.sx[sl]);  // -1: the worker holds no rating of the item
-            int64_t b = 0, e = 0;
-            if (x >= 0) {
-                // the wave's record range of the visit, left in LDS by the memory wave
-                const int32_t *rng = (const int32_t *)L.recs;
-                b = __builtin_amdgcn_readfirstlane(rng[w * kMaxItemSlots + sl]);
-                e = __builtin_amdgcn_readfirstlane(rng[(a.nw + w) * kMaxItemSlots + sl]);
-            }
+            int64_t b, e;
+            range(X, b, e);
             if (b < e) {
                 const int t = __builtin_amdgcn_readfirstlane(L.se[sl]);
                 const int item = __builtin_amdgcn_readfirstlane(L.item[sl]);
@@ -1054,10 +1065,38 @@ struct AsyncComputeWave {
                     // lane l: record r0 + l (row, rating)
                     int crow = 0;
                     float crat = 0.0f;
-                    if (lane < nb) {
-                        const u32x2v rv = *(const u32x2v *)(rs + r0 + lane);
-                        crow = (int)rv.x;
-                        crat = __uint_as_float(rv.y);
+                    if (r0 == b && pre_X == X) {
+                        const uint32_t p0 = pre.x, p1 = pre.y;
+                        crow = (int)p0;
+                        crat = __uint_as_float(p1);
+                    } else {
+                        if (lane < nb) {
+                            const u32x2v rv = *(const u32x2v *)(rs + r0 + lane);
+                            const uint32_t v0 = rv.x, v1 = rv.y;
+                            crow = (int)v0;
+                            crat = __uint_as_float(v1);
+                        }
+                        // the records are in place here, so that no path into what follows
+                        // leaves a load of them pending
+                        asm volatile("" : "+v"(crow), "+v"(crat));
+                    }
+                    if (r0 == b) {
+                        // The next visit's first records, if it is announced and has ratings
+                        // of this wave (else this visit's again: no branch around the load).
+                        int64_t pb = b, pe = e;
+                        int px = -1;
+                        if (sync_load(&L.ctl[0]) > X + 1) {
+                            int64_t b1, e1;
+                            range(X + 1, b1, e1);
+                            if (b1 < e1) {
+                                pb = b1;
+                                pe = e1;
+                                px = X + 1;
+                            }
+                        }
+                        const int pn = (int)(pe - pb < 64 ? pe - pb : 64);
+                        if (lane < pn) pre = *(const u32x2v *)(rs + pb + lane);
+                        pre_X = px;
                     }
                     // Sixteen row buffers: the row of rating l + 16 is loaded while rating l is
                     // updated.  Groups of four updates run in a branch-free body with
