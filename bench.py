@@ -47,15 +47,18 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def counters_path(kernel: str) -> str:
-    return os.path.join(ROOT, "profiles", f"{kernel}_medium_counters.txt")
+def counters_path(kernel: str, sched: str) -> str:
+    """The counter summary of `kernel` on the medium workload under schedule `sched`
+    (uniform routing has its own: the same kernel moves different bytes there)."""
+    tag = "_uniform" if sched == "uniform" else ""
+    return os.path.join(ROOT, "profiles", f"{kernel}_medium{tag}_counters.txt")
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, sched: str):
     """HBM bytes per training launch from the committed rocprofv3 counter summary, each
     counter scaled by what it reads for a plain copy of known size; None when the
     summary is missing or was taken on a different kernel source."""
-    path = counters_path(kernel)
+    path = counters_path(kernel, sched)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -183,7 +186,7 @@ def main():
     avg_kernel = sum(ksec) / len(ksec)
     achieved = B * (updates / args.steps) / avg_kernel
     kernel = KERNELS[args.sched]
-    traffic = measured_traffic(kernel)
+    traffic = measured_traffic(kernel, args.sched)
     out = {
         "metric": METRIC,
         "value": value,
