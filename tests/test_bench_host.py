@@ -1,0 +1,43 @@
+"""Host logic of bench.py (no GPU): algorithmic bytes, the counter summaries it reads,
+and the one-GPU guard."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_bytes_per_update_of_the_medium_workload():
+    # 12-byte entry + 2 x 400 B for w_i + 2 x 400 B x 17,770 columns x 256 workers / 98.6 M
+    assert bench.bytes_per_update(100, 4, 4, 17_770, 98_600_000) == pytest.approx(848.91, abs=0.01)
+    # BF16 w_i halves the row term only
+    assert bench.bytes_per_update(100, 2, 4, 17_770, 98_600_000) == pytest.approx(448.91, abs=0.01)
+
+
+@pytest.mark.parametrize("sched", ["perm", "uniform", "ring"])
+def test_counter_summaries_match_the_kernel_source(sched):
+    kernel = bench.KERNELS[sched]
+    path = bench.counters_path(kernel, sched)
+    assert os.path.exists(path), path
+    kv = dict(line.split(":", 1) for line in open(path) if ":" in line and not line.startswith("#"))
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    assert kv["kernel_source_sha256"] == bench.kernel_source_hash()
+    traffic = bench.measured_traffic(kernel, sched)
+    assert traffic is not None
+    # the summary's per-update figure is the same bytes over the workload's ratings
+    assert traffic / 98_600_000 == pytest.approx(float(kv["hbm_bytes_per_update"]), rel=2e-3)
+
+
+def test_stale_counter_summary_is_not_used(monkeypatch):
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic("k_worker_async", "perm") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
