@@ -54,14 +54,19 @@ typedef enum {
  *     updates, independent of timing.
  *   PERM: asynchronous (Algorithm 1 with the random-permutation circulation of section
  *     3.4).  Every worker has a lock-free inbound queue of items and takes them in arrival
- *     order.  In epoch e item j visits the workers holding its ratings in the order of
- *     key(q) = lowbias32(lowbias32(r ^ j) ^ e*0x9E3779B9 ^ q*0x85EBCA77) (ties by the
- *     worker's rank among the holders), r = 0x6a09e667 ^ the two 32-bit halves of
- *     nomad_config.seed: a fresh pseudo-random permutation every epoch, so every rating is
- *     updated once per epoch and t = epochs done.  At the start of a call every item is
- *     queued at its first worker (each queue in ascending item order).  The serial order
- *     depends on timing (record_trace gives it); with one worker it is the ring order.
- *     Not available in batches.
+ *     order.  In epoch e item j visits its nh holders (the workers holding its ratings,
+ *     ranked 0..nh-1 in ascending worker order) in the order rank = pi(0), pi(1), ...,
+ *     pi(nh-1) of a keyed bijection pi of [0, nh): with b the bits of nh - 1, lo = b/2,
+ *     key = lowbias32(lowbias32(r ^ j) ^ e*0x9E3779B9), x split into L = x >> lo and
+ *     R = x mod 2^lo, four steps L ^= H(R, key), R ^= H(L, key + 0x632BE5AB),
+ *     L ^= H(R, key + 0xC6579D56), R ^= H(L, key + 0x2983B501) (H(v, k) = lowbias32(v ^ k)
+ *     reduced to the half's bits) map x to (L << lo) | R, repeated until the value is below
+ *     nh; r = 0x6a09e667 ^ the two 32-bit halves of nomad_config.seed.  A fresh
+ *     pseudo-random permutation every epoch, so every rating is updated once per epoch and
+ *     t = epochs done.  At the start of a call every item is queued at its first worker
+ *     (each queue in ascending item order).  The serial order depends on timing
+ *     (record_trace gives it); with one worker it is the ring order.  Not available in
+ *     batches.
  *   UNIFORM: asynchronous, Algorithm 1 as printed: after a visit an item goes to a worker
  *     drawn uniformly from all p (move v of item j: lowbias32(lowbias32(r ^ 0x2545F491 ^ j)
  *     + v*0x9E3779B9) scaled to [0, p)), also to workers holding none of its ratings,
@@ -104,6 +109,17 @@ typedef struct {
     int32_t record_trace;    /* 1 = record every (worker, item) visit for replay */
     int32_t collect_stats;   /* 1 = time the phases of every worker (nomad_get_worker_stats);
                                 counts are always collected */
+    int32_t debug_ownership; /* 1 = check the ownership invariant of section 3.1 while training
+                                (nomad_stats.violations): every item has one holder word, which
+                                a worker claims when it takes the item over (it must find the
+                                item free) and frees when it passes the item on (it must find
+                                its own claim), and every rating a compute wave updates must be
+                                of a row the wave owns.  Costs two atomics per visit. */
+    int32_t t_source;        /* what t counts in s_t: 0 = earlier updates of the same (i,j) pair
+                                (section 5.1; the default), 1 = all updates applied before the
+                                visit since nomad_init, in the run's serial order (the global
+                                count; every rating of a visit uses the count at the visit's
+                                start).  Not available in batches. */
     uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing,
                            stochastic rounding */
 } nomad_config;
@@ -113,6 +129,12 @@ typedef struct {
     uint64_t updates;      /* SGD updates applied by the call */
     uint64_t epochs_done;  /* epochs completed since nomad_init */
     double layout_seconds; /* device time spent by nomad_init building the layout */
+    uint64_t hops;         /* hand-offs of an item from one worker to the next during the call:
+                              queue pushes under the asynchronous schedules (pass-through
+                              visits of uniform routing included); under the ring order,
+                              passes to a later visit of the same call */
+    uint64_t violations;   /* ownership violations seen by debug_ownership (always 0 when
+                              the invariant holds; 0 when the checks are off) */
 } nomad_stats;
 
 /* Default values of nomad_config (k = 0 means "caller must set"). */

@@ -32,7 +32,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no fast-math: IEEE semantics are part of the contract)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -68,12 +68,18 @@ def _load():
         lib.orc_train_ring_bf16.argtypes = common + [i32, i32, i32, C.c_uint32, P, P, P]
         lib.orc_train_ring_interleaved.restype = C.c_int
         lib.orc_train_ring_interleaved.argtypes = common + [i32, i32, u64, P, P, P]
+        lib.orc_train_ring_gcount.restype = C.c_int
+        lib.orc_train_ring_gcount.argtypes = common + [i64, i32, P, P, P]
         lib.orc_train_perm.restype = C.c_int
-        lib.orc_train_perm.argtypes = common + [i32, i32, u64, P, P, P]
+        lib.orc_train_perm.argtypes = common + [i32, i32, u64, P, P, P, P, i64, P]
         lib.orc_train_uniform.restype = C.c_int
-        lib.orc_train_uniform.argtypes = common + [i64, u64, P, P, P, P]
+        lib.orc_train_uniform.argtypes = common + [i64, u64, P, P, P, P, P, i64, P]
+        lib.orc_train_threaded.restype = C.c_int
+        lib.orc_train_threaded.argtypes = common + [i64, u64, P, P, P, P]
         lib.orc_replay.restype = C.c_int
         lib.orc_replay.argtypes = common + [i64, P, P, P, P, P, P, P]
+        lib.orc_set_progress.restype = None
+        lib.orc_set_progress.argtypes = [i64]
         lib.orc_rmse.restype = C.c_int
         lib.orc_rmse.argtypes = [i64, i64, i64, P, P, P, i32, P, P, P]
         lib.orc_objective.restype = C.c_int
@@ -189,19 +195,43 @@ def train_ring_bf16(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, rou
     return W, H, st
 
 
-def train_perm(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, sched_seed, epoch0=0):
+def train_ring_gcount(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, t0=0):
+    """Ring order with t = the global count of updates before each visit (from t0)."""
     row, col, val = _coo(row, col, val)
     W = _factors(W0, m, hp.k)
     H = _factors(H0, n, hp.k)
     st = Stats()
+    _check(_load().orc_train_ring_gcount(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha,
+                                         hp.beta, hp.gamma, p, seed, int(t0), epochs, _p(W), _p(H), C.byref(st)))
+    return W, H, st
+
+
+def _trace_buf(cap):
+    return np.zeros((max(int(cap), 1), 4), dtype=np.int32), C.c_int64()
+
+
+def train_perm(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, sched_seed, epoch0=0, trace=False):
+    """Random-permutation circulation (discrete-event emulation).  Returns (W, H, stats),
+    plus the visit trace (rows: worker, item, t, visit number of the item) with trace=True."""
+    row, col, val = _coo(row, col, val)
+    W = _factors(W0, m, hp.k)
+    H = _factors(H0, n, hp.k)
+    st = Stats()
+    cap = epochs * min(row.size, n * p) if trace else 0
+    buf, tlen = _trace_buf(cap)
     _check(_load().orc_train_perm(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha,
                                   hp.beta, hp.gamma, p, seed, epoch0, epochs, sched_seed, _p(W), _p(H),
-                                  C.byref(st)))
+                                  C.byref(st), _p(buf) if trace else None, cap, C.byref(tlen)))
+    if trace:
+        assert tlen.value <= cap
+        return W, H, st, buf[:tlen.value].copy()
     return W, H, st
 
 
 def train_uniform(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, max_updates, sched_seed,
-                  visit_count=None):
+                  visit_count=None, trace=False, trace_cap=None):
+    """Algorithm 1 with uniform recipients (discrete-event emulation).  Returns (W, H,
+    stats), plus the trace of the visits that update something with trace=True."""
     row, col, val = _coo(row, col, val)
     W = _factors(W0, m, hp.k)
     H = _factors(H0, n, hp.k)
@@ -209,10 +239,30 @@ def train_uniform(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, max_updates, 
         visit_count = np.zeros(p * n, dtype=np.int32)
     assert visit_count.dtype == np.int32 and visit_count.size == p * n
     st = Stats()
+    cap = (trace_cap if trace_cap is not None else int(max_updates) + 1) if trace else 0
+    buf, tlen = _trace_buf(cap)
     _check(_load().orc_train_uniform(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha,
                                      hp.beta, hp.gamma, p, seed, int(max_updates), sched_seed,
-                                     _p(visit_count), _p(W), _p(H), C.byref(st)))
+                                     _p(visit_count), _p(W), _p(H), C.byref(st),
+                                     _p(buf) if trace else None, cap, C.byref(tlen)))
+    if trace:
+        assert tlen.value <= cap
+        return W, H, st, buf[:tlen.value].copy()
     return W, H, st
+
+
+def train_threaded(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, max_updates, sched_seed):
+    """Algorithm 1 on p POSIX threads (CPU throughput baseline).  Returns (W, H, stats,
+    seconds of the threaded run, layout excluded)."""
+    row, col, val = _coo(row, col, val)
+    W = _factors(W0, m, hp.k)
+    H = _factors(H0, n, hp.k)
+    st = Stats()
+    sec = C.c_double()
+    _check(_load().orc_train_threaded(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha,
+                                      hp.beta, hp.gamma, p, seed, int(max_updates), sched_seed, _p(W), _p(H),
+                                      C.byref(st), C.byref(sec)))
+    return W, H, st, sec.value
 
 
 def replay(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, tq, tj, tt, tseq):
@@ -225,6 +275,11 @@ def replay(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, tq, tj, tt, tseq):
                               hp.gamma, p, seed, tq.size, _p(tq), _p(tj), _p(tt), _p(tseq), _p(W), _p(H),
                               C.byref(st)))
     return W, H, st
+
+
+def set_progress(every: int) -> None:
+    """Report progress on stderr every `every` updates (0 = off)."""
+    _load().orc_set_progress(int(every))
 
 
 def rmse(m, n, row, col, val, W, H) -> float:

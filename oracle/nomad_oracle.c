@@ -35,6 +35,12 @@
  *                       uniformly random order, workers take turns at random.
  *   orc_train_uniform -- Algorithm 1 literally: recipient uniform over all p workers, t is
  *                       the per-(worker,item) visit count, stop after a number of updates.
+ *   orc_train_ring_gcount -- the ring order with t read as the global count of updates
+ *                       applied before the visit (the alternative reading of t in the step
+ *                       size of section 5.1).
+ *   orc_train_threaded -- Algorithm 1 run literally by one POSIX thread per worker, each
+ *                       with a mutex-protected FIFO queue and uniformly random recipients
+ *                       (the CPU throughput baseline; its interleaving depends on timing).
  *   orc_replay       -- re-execute a recorded sequence of (worker, item, t, seq) visits.
  *   orc_train_ring_bf16 -- the ring order with the rows w_i stored in bfloat16 (the
  *                       storage form of the benchmark's BF16 configuration; the paper
@@ -47,9 +53,14 @@
  *                       with FP64 dot products and Neumaier-compensated sums.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <sched.h>
+#include <time.h>
+
+#include <stdio.h>
 
 #define ORC_OK 0
 #define ORC_EINVAL (-1)
@@ -259,6 +270,27 @@ static int layout_build(layout *L, int64_t m, int64_t n, int64_t nnz, const int3
     return ORC_OK;
 }
 
+/* Progress report of long runs (off by default): a line on stderr every `every` updates. */
+static int64_t g_progress_every = 0, g_progress_next = 0, g_progress_done = 0;
+
+void orc_set_progress(int64_t every)
+{
+    g_progress_every = every;
+    g_progress_next = every;
+    g_progress_done = 0;
+}
+
+static void progress_add(int64_t updates)
+{
+    if (g_progress_every <= 0) return;
+    g_progress_done += updates;
+    if (g_progress_done >= g_progress_next) {
+        fprintf(stderr, "[oracle] %lld updates applied\n", (long long)g_progress_done);
+        fflush(stderr);
+        g_progress_next = g_progress_done + g_progress_every;
+    }
+}
+
 /* Apply one visit: worker q holding item j runs SGD over its ratings of j. */
 static void apply_visit(const layout *L, const visit *V, int32_t k, double *W, double *H,
                         double lambda, double s, int32_t holder_ok, orc_stats *st)
@@ -272,6 +304,7 @@ static void apply_visit(const layout *L, const visit *V, int32_t k, double *W, d
         if (st) st->updates++;
     }
     if (st && V->end > V->begin) st->visits++;
+    if (st) progress_add(V->end - V->begin);  /* (the threaded run passes no stats) */
 }
 
 static int check_common(int32_t k, int32_t p, int32_t epochs)
@@ -304,6 +337,41 @@ int orc_train_ring(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const 
                 while (cursor[q] < L.wvis[q + 1] &&
                        L.ratings[L.visits[cursor[q]].begin].s == sub) {
                     apply_visit(&L, &L.visits[cursor[q]], k, W, H, lambda, s_t, 1, st);
+                    cursor[q]++;
+                }
+            }
+        }
+    }
+    free(cursor);
+    layout_free(&L);
+    return ORC_OK;
+}
+
+/* The ring order with t = the number of updates applied before the visit (globally,
+ * starting from t0): every rating of a visit uses the count at the visit's start. */
+int orc_train_ring_gcount(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                          const float *val, int32_t k, double lambda, double alpha, double beta,
+                          double gamma, int32_t p, uint64_t seed, int64_t t0, int32_t epochs,
+                          double *W, double *H, orc_stats *st)
+{
+    int rc = check_common(k, p, epochs);
+    if (rc) return rc;
+    layout L;
+    rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
+    if (rc) return rc;
+    if (st) memset(st, 0, sizeof(*st));
+    int64_t *cursor = (int64_t *)malloc(sizeof(int64_t) * ((size_t)p + 1));
+    if (!cursor) { layout_free(&L); return ORC_ENOMEM; }
+    int64_t t = t0;
+    for (int32_t e = 0; e < epochs; ++e) {
+        for (int32_t q = 0; q < p; ++q) cursor[q] = L.wvis[q];
+        for (int32_t sub = 0; sub < p; ++sub) {
+            for (int32_t q = 0; q < p; ++q) {
+                while (cursor[q] < L.wvis[q + 1] &&
+                       L.ratings[L.visits[cursor[q]].begin].s == sub) {
+                    const visit *V = &L.visits[cursor[q]];
+                    apply_visit(&L, V, k, W, H, lambda, orc_step(alpha, beta, gamma, (double)t), 1, st);
+                    t += V->end - V->begin;
                     cursor[q]++;
                 }
             }
@@ -531,10 +599,23 @@ static int64_t find_visit(const layout *L, int32_t j, int32_t q)
  * uniformly random holder of the item's ratings that it has not visited in its current
  * epoch; when every holder has been visited, the item's epoch advances (t = epoch0 +
  * item epoch) and all holders become eligible again.  Items retire after `epochs`. */
+/* trace (nullable): 4 ints per visit that applies updates, in execution order: worker,
+ * item, t, visit number of the item (as orc_replay reads them), at most trace_cap visits;
+ * *trace_len receives the count. */
+static void trace_put(int32_t *trace, int64_t cap, int64_t *len, int32_t q, int32_t j, int64_t t, int64_t seq)
+{
+    if (trace && *len < cap) {
+        int32_t *r = trace + 4 * *len;
+        r[0] = q; r[1] = j; r[2] = (int32_t)t; r[3] = (int32_t)seq;
+    }
+    ++*len;
+}
+
 int orc_train_perm(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
                    const float *val, int32_t k, double lambda, double alpha, double beta,
                    double gamma, int32_t p, uint64_t seed, int32_t epoch0, int32_t epochs,
-                   uint64_t sched_seed, double *W, double *H, orc_stats *st)
+                   uint64_t sched_seed, double *W, double *H, orc_stats *st,
+                   int32_t *trace, int64_t trace_cap, int64_t *trace_len)
 {
     int rc = check_common(k, p, epochs);
     if (rc) return rc;
@@ -548,10 +629,12 @@ int orc_train_perm(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const 
     uint8_t *seen = (uint8_t *)calloc((size_t)L.nvisit + 1, 1);          /* per visit: done this epoch */
     int32_t *holder = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
     int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * ((size_t)p + 1));
-    if (queues_init(&Q, p, n) || !ep || !left || !seen || !holder || !cand) {
-        queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand);
+    int64_t *nvisits = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (queues_init(&Q, p, n) || !ep || !left || !seen || !holder || !cand || !nvisits) {
+        queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand); free(nvisits);
         layout_free(&L); return ORC_ENOMEM;
     }
+    int64_t tlen = 0;
     uint64_t ctr = 0;
     for (int64_t j = 0; j < n; ++j) {
         left[j] = L.nhold[j];
@@ -568,6 +651,7 @@ int orc_train_perm(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const 
         if (vi >= 0 && !seen[vi]) {
             apply_visit(&L, &L.visits[vi], k, W, H, lambda,
                         orc_step(alpha, beta, gamma, (double)(epoch0 + ep[j])), holder[j] == q, st);
+            trace_put(trace, trace_cap, &tlen, q, j, epoch0 + ep[j], nvisits[j]++);
             seen[vi] = 1;
             left[j]--;
         }
@@ -585,8 +669,9 @@ int orc_train_perm(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const 
         if (st) st->hops++;
         q_push(&Q, dst, j);
     }
-    queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand);
+    queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand); free(nvisits);
     layout_free(&L);
+    if (trace_len) *trace_len = tlen;
     return ORC_OK;
 }
 
@@ -598,7 +683,7 @@ int orc_train_uniform(int64_t m, int64_t n, int64_t nnz, const int32_t *row, con
                       const float *val, int32_t k, double lambda, double alpha, double beta,
                       double gamma, int32_t p, uint64_t seed, int64_t max_updates,
                       uint64_t sched_seed, int32_t *visit_count, double *W, double *H,
-                      orc_stats *st)
+                      orc_stats *st, int32_t *trace, int64_t trace_cap, int64_t *trace_len)
 {
     int rc = check_common(k, p, 0);
     if (rc) return rc;
@@ -607,7 +692,9 @@ int orc_train_uniform(int64_t m, int64_t n, int64_t nnz, const int32_t *row, con
     if (rc) return rc;
     if (st) memset(st, 0, sizeof(*st));
     queues Q;
-    if (queues_init(&Q, p, n)) { queues_free(&Q); layout_free(&L); return ORC_ENOMEM; }
+    int64_t *nvisits = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    if (queues_init(&Q, p, n) || !nvisits) { queues_free(&Q); free(nvisits); layout_free(&L); return ORC_ENOMEM; }
+    int64_t tlen = 0;
     uint64_t ctr = 0;
     int64_t applied = 0;
     if (max_updates > 0 && nnz > 0)
@@ -619,6 +706,7 @@ int orc_train_uniform(int64_t m, int64_t n, int64_t nnz, const int32_t *row, con
         if (vi >= 0) {
             int32_t *t = &visit_count[(int64_t)q * n + j];
             apply_visit(&L, &L.visits[vi], k, W, H, lambda, orc_step(alpha, beta, gamma, (double)*t), 1, st);
+            trace_put(trace, trace_cap, &tlen, q, j, *t, nvisits[j]++);
             applied += L.visits[vi].end - L.visits[vi].begin;
             (*t)++;
         }
@@ -627,8 +715,158 @@ int orc_train_uniform(int64_t m, int64_t n, int64_t nnz, const int32_t *row, con
         q_push(&Q, dst, j);
     }
     queues_free(&Q);
+    free(nvisits);
     layout_free(&L);
+    if (trace_len) *trace_len = tlen;
     return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------------- */
+/* Algorithm 1 on POSIX threads: the CPU throughput baseline.                        */
+/* ------------------------------------------------------------------------------- */
+/* One thread per worker.  Each worker's queue is a mutex-protected FIFO ring with room
+ * for every item.  A worker pops an item (waiting while its queue is empty), applies its
+ * ratings of the item in ascending row order with t = its earlier visits of the item,
+ * and pushes the item to a worker drawn uniformly from all p (splitmix64 of a per-worker
+ * counter).  Every item starts in the queue of owner0(j).  The run stops once at least
+ * max_updates updates were applied (checked after each visit); items still queued stay
+ * there.  Ownership holds by construction: an item is in one queue or held by one
+ * worker, and a worker touches only its own rows.  With one worker the order is the ring
+ * order, so the result is that of orc_train_ring bit for bit. */
+typedef struct {
+    pthread_mutex_t mu;
+    int32_t *buf;
+    int64_t head, size, cap;
+} tqueue;
+
+typedef struct {
+    const layout *L;
+    int32_t k, p;
+    double lambda, alpha, beta, gamma;
+    double *W, *H;
+    tqueue *Q;
+    int64_t *vmap;           /* p x n: visit index of (q, j), or -1 */
+    int32_t *visit_count;    /* p x n: earlier visits of (q, j) */
+    int64_t max_updates;
+    uint64_t sched_seed;
+    int64_t applied;         /* updates applied (atomic) */
+    int32_t stop;            /* atomic */
+    int64_t *hops;           /* per worker */
+} tshared;
+
+typedef struct {
+    tshared *S;
+    int32_t q;
+} targ;
+
+static void *worker_main(void *vp)
+{
+    targ *A = (targ *)vp;
+    tshared *S = A->S;
+    const int32_t q = A->q;
+    const int64_t n = S->L->n;
+    uint64_t ctr = 0;
+    while (!__atomic_load_n(&S->stop, __ATOMIC_ACQUIRE)) {
+        tqueue *mine = &S->Q[q];
+        int32_t j = -1;
+        pthread_mutex_lock(&mine->mu);
+        if (mine->size > 0) {
+            j = mine->buf[mine->head];
+            mine->head = (mine->head + 1) % mine->cap;
+            mine->size--;
+        }
+        pthread_mutex_unlock(&mine->mu);
+        if (j < 0) { sched_yield(); continue; }
+        int64_t vi = S->vmap[(int64_t)q * n + j];
+        if (vi >= 0) {
+            int32_t *t = &S->visit_count[(int64_t)q * n + j];
+            const visit *V = &S->L->visits[vi];
+            apply_visit(S->L, V, S->k, S->W, S->H, S->lambda, orc_step(S->alpha, S->beta, S->gamma, (double)*t),
+                        1, NULL);
+            (*t)++;
+            int64_t done = __atomic_add_fetch(&S->applied, V->end - V->begin, __ATOMIC_ACQ_REL);
+            if (done >= S->max_updates) __atomic_store_n(&S->stop, 1, __ATOMIC_RELEASE);
+        }
+        int32_t dst = (int32_t)(orc_splitmix64(S->sched_seed ^ ((uint64_t)q << 40) ^ ctr++) % (uint64_t)S->p);
+        tqueue *to = &S->Q[dst];
+        pthread_mutex_lock(&to->mu);
+        to->buf[(to->head + to->size) % to->cap] = j;
+        to->size++;
+        pthread_mutex_unlock(&to->mu);
+        S->hops[q]++;
+    }
+    return NULL;
+}
+
+int orc_train_threaded(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                       const float *val, int32_t k, double lambda, double alpha, double beta,
+                       double gamma, int32_t p, uint64_t seed, int64_t max_updates, uint64_t sched_seed,
+                       double *W, double *H, orc_stats *st, double *seconds)
+{
+    int rc = check_common(k, p, 0);
+    if (rc) return rc;
+    layout L;
+    rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
+    if (rc) return rc;
+    if (st) memset(st, 0, sizeof(*st));
+    tshared S;
+    memset(&S, 0, sizeof(S));
+    S.L = &L; S.k = k; S.p = p; S.lambda = lambda; S.alpha = alpha; S.beta = beta; S.gamma = gamma;
+    S.W = W; S.H = H; S.max_updates = max_updates; S.sched_seed = sched_seed;
+    S.Q = (tqueue *)calloc((size_t)p, sizeof(tqueue));
+    S.vmap = (int64_t *)malloc(sizeof(int64_t) * (size_t)p * (size_t)(n > 0 ? n : 1));
+    S.visit_count = (int32_t *)calloc((size_t)p * (size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    S.hops = (int64_t *)calloc((size_t)p, sizeof(int64_t));
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)p);
+    targ *args = (targ *)malloc(sizeof(targ) * (size_t)p);
+    int ok = S.Q && S.vmap && S.visit_count && S.hops && th && args;
+    for (int32_t q = 0; ok && q < p; ++q) {
+        S.Q[q].buf = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+        S.Q[q].cap = n > 0 ? n : 1;
+        if (!S.Q[q].buf) ok = 0;
+        else pthread_mutex_init(&S.Q[q].mu, NULL);
+    }
+    if (!ok) {
+        rc = ORC_ENOMEM;
+        goto out;
+    }
+    for (int64_t x = 0; x < (int64_t)p * n; ++x) S.vmap[x] = -1;
+    for (int64_t v = 0; v < L.nvisit; ++v) S.vmap[(int64_t)L.visits[v].q * n + L.visits[v].j] = v;
+    if (max_updates > 0 && nnz > 0)
+        for (int64_t j = 0; j < n; ++j) {
+            tqueue *to = &S.Q[orc_owner0(seed, j, p)];
+            to->buf[(to->head + to->size) % to->cap] = (int32_t)j;
+            to->size++;
+        }
+    struct timespec t0, t1;
+    clock_gettime(CLOCK_MONOTONIC, &t0);
+    if (max_updates > 0 && nnz > 0) {
+        int32_t started = 0;
+        for (int32_t q = 0; q < p; ++q) {
+            args[q].S = &S;
+            args[q].q = q;
+            if (pthread_create(&th[q], NULL, worker_main, &args[q]) != 0) {
+                __atomic_store_n(&S.stop, 1, __ATOMIC_RELEASE);
+                rc = ORC_ENOMEM;
+                break;
+            }
+            started++;
+        }
+        for (int32_t q = 0; q < started; ++q) pthread_join(th[q], NULL);
+    }
+    clock_gettime(CLOCK_MONOTONIC, &t1);
+    if (seconds) *seconds = (double)(t1.tv_sec - t0.tv_sec) + 1e-9 * (double)(t1.tv_nsec - t0.tv_nsec);
+    if (st) {
+        st->updates = S.applied;
+        for (int32_t q = 0; q < p; ++q) st->hops += S.hops[q];
+    }
+out:
+    if (S.Q)
+        for (int32_t q = 0; q < p; ++q)
+            if (S.Q[q].buf) { free(S.Q[q].buf); pthread_mutex_destroy(&S.Q[q].mu); }
+    free(S.Q); free(S.vmap); free(S.visit_count); free(S.hops); free(th); free(args);
+    layout_free(&L);
+    return rc;
 }
 
 /* Re-execute recorded visits.  Record x says: worker tq[x] applied its ratings of item

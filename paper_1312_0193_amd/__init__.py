@@ -20,6 +20,7 @@ NOMAD_OK, NOMAD_EINVAL, NOMAD_ENOMEM, NOMAD_EDEVICE, NOMAD_ESTATE, NOMAD_ENOTIMP
 SCHED = {"ring": 0, "perm": 1, "uniform": 2}
 DTYPE = {"fp32": 0, "bf16": 1}
 ROUND = {"rne": 0, "stochastic": 1}
+T_SOURCE = {"pair": 0, "global": 1}
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENOTIMPL"}
 
 
@@ -28,7 +29,8 @@ class NomadConfig(C.Structure):
                 ("gamma", C.c_float), ("sched", C.c_int32), ("dtype", C.c_int32), ("rounding", C.c_int32),
                 ("workers", C.c_int32), ("waves_per_worker", C.c_int32), ("item_slots", C.c_int32),
                 ("window", C.c_int32),
-                ("record_trace", C.c_int32), ("collect_stats", C.c_int32), ("seed", C.c_uint64)]
+                ("record_trace", C.c_int32), ("collect_stats", C.c_int32), ("debug_ownership", C.c_int32),
+                ("t_source", C.c_int32), ("seed", C.c_uint64)]
 
 
 class NomadProblemDesc(C.Structure):
@@ -40,7 +42,7 @@ class NomadProblemDesc(C.Structure):
 
 class NomadStats(C.Structure):
     _fields_ = [("seconds", C.c_double), ("updates", C.c_uint64), ("epochs_done", C.c_uint64),
-                ("layout_seconds", C.c_double)]
+                ("layout_seconds", C.c_double), ("hops", C.c_uint64), ("violations", C.c_uint64)]
 
 
 # nomad_tune_progress(const nomad_config *candidate, nomad_status status, double seconds, void *user)
@@ -140,6 +142,8 @@ class Stats:
     updates: int
     epochs_done: int
     layout_seconds: float
+    hops: int = 0
+    violations: int = 0
 
     @property
     def updates_per_s(self) -> float:
@@ -148,7 +152,7 @@ class Stats:
 
 def make_config(k: int, lam: float, alpha: float, beta: float, gamma: float, *, sched="ring", dtype="fp32",
                 rounding="rne", workers=0, waves_per_worker=0, item_slots=0, window=0, record_trace=False,
-                collect_stats=False, seed=0) -> NomadConfig:
+                collect_stats=False, debug_ownership=False, t_source="pair", seed=0) -> NomadConfig:
     cfg = NomadConfig()
     load().nomad_config_default(C.byref(cfg))
     cfg.k, cfg.lambda_, cfg.alpha, cfg.beta, cfg.gamma = k, lam, alpha, beta, gamma
@@ -157,6 +161,8 @@ def make_config(k: int, lam: float, alpha: float, beta: float, gamma: float, *, 
     cfg.window = window
     cfg.record_trace = int(bool(record_trace))
     cfg.collect_stats = int(bool(collect_stats))
+    cfg.debug_ownership = int(bool(debug_ownership))
+    cfg.t_source = T_SOURCE[t_source]
     cfg.seed = seed
     return cfg
 
@@ -191,7 +197,7 @@ class Nomad:
     def train(self, epochs: int) -> Stats:
         st = NomadStats()
         _check(load().nomad_train_epochs(self._c(), int(epochs), C.byref(st)), self.ctx)
-        return Stats(st.seconds, st.updates, st.epochs_done, st.layout_seconds)
+        return Stats(st.seconds, st.updates, st.epochs_done, st.layout_seconds, st.hops, st.violations)
 
     def evaluate(self, row, col, val) -> tuple[float, float]:
         """(RMSE, objective J) over the given ratings, FP64."""
@@ -340,7 +346,7 @@ class NomadBatch:
             raise NomadError(NOMAD_ESTATE, "batch destroyed")
         st = NomadStats()
         _check(load().nomad_train_epochs(self.ctx, int(epochs), C.byref(st)), self.ctx)
-        return Stats(st.seconds, st.updates, st.epochs_done, st.layout_seconds)
+        return Stats(st.seconds, st.updates, st.epochs_done, st.layout_seconds, st.hops, st.violations)
 
     def close(self):
         if getattr(self, "ctx", None) is not None:

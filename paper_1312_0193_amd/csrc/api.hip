@@ -20,6 +20,7 @@ struct nomad_ctx {
     int32_t window = 0;                // rows a compute wave keeps in flight
     int32_t cus = 0, max_lds = 0;
     hipStream_t stream = nullptr;
+    int device = 0;                    // the device current at nomad_init
     Plan plan;
     void *W = nullptr;                 // m x kp, FP32 or bfloat16 (row stride kp, padding kept at 0)
     float *H = nullptr;                // n x kp FP32
@@ -42,11 +43,18 @@ struct nomad_ctx {
     // Asynchronous schedule: inbound queues, item state, seeding scratch.
     uint64_t *queue = nullptr;
     uint32_t *qtail = nullptr, *parked = nullptr;
-    int32_t *itep = nullptr, *ihop = nullptr, *tvis = nullptr;
+    int32_t *istate = nullptr, *tvis = nullptr;   // per item state words (n x 4), per holder visits
     unsigned long long *upd = nullptr;
     int64_t queue_len = 0;
     void *async_scratch = nullptr;
     size_t async_scratch_bytes = 0;
+    // Ownership checks and counters: [0] violations, [1] hops (both per call), [2] global
+    // update count (since nomad_init).
+    uint32_t *holder = nullptr;
+    unsigned long long *counters = nullptr;
+    // A launch that ran out of time or found a malformed layout leaves the factors and the
+    // items' state undefined: every later call that needs them is refused.
+    bool failed = false;
     // A batch (nomad_init_batched): its problems, each a full context of its own, trained
     // together by one launch.
     std::vector<nomad_ctx *> members;
@@ -102,9 +110,10 @@ void release(nomad_ctx *c) {
     (void)hipFree(c->queue);
     (void)hipFree(c->qtail);
     (void)hipFree(c->parked);
-    (void)hipFree(c->itep);
-    (void)hipFree(c->ihop);
+    (void)hipFree(c->istate);
     (void)hipFree(c->tvis);
+    (void)hipFree(c->holder);
+    (void)hipFree(c->counters);
     (void)hipFree(c->upd);
     (void)hipFree(c->async_scratch);
     nomad::free_plan(&c->plan);
@@ -202,6 +211,8 @@ void nomad_config_default(nomad_config *cfg) {
     cfg->window = 0;
     cfg->record_trace = 0;
     cfg->collect_stats = 0;
+    cfg->debug_ownership = 0;
+    cfg->t_source = 0;
     cfg->seed = 0;
 }
 
@@ -236,6 +247,12 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
     if (cfg->rounding != NOMAD_ROUND_RNE && cfg->rounding != NOMAD_ROUND_STOCHASTIC)
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: rounding %d is not one of NOMAD_ROUND_RNE, "
                     "NOMAD_ROUND_STOCHASTIC", cfg->rounding);
+    if (cfg->debug_ownership != 0 && cfg->debug_ownership != 1)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: debug_ownership=%d is not 0 or 1", cfg->debug_ownership);
+    if (cfg->t_source != 0 && cfg->t_source != 1)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: t_source=%d is not 0 or 1", cfg->t_source);
+    if (cfg->t_source == 1 && forced)
+        return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init_batched: t_source=1 (global update count) is per problem only");
 
     nomad_ctx *c = new (std::nothrow) nomad_ctx();
     if (!c) return fail(nullptr, NOMAD_ENOMEM, "nomad_init: host allocation failed");
@@ -282,6 +299,7 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
     c->cfg.item_slots = slots;
 
     hipError_t e;
+    if ((e = hipGetDevice(&c->device)) != hipSuccess) return bail(hip_fail(c, e, "nomad_init: device"));
     if ((e = hipMalloc(&c->W, (size_t)c->wbytes * (size_t)m * c->kp)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: W"));
     if ((e = hipMalloc(&c->H, sizeof(float) * (size_t)n * c->kp)) != hipSuccess)
@@ -294,6 +312,13 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
         return bail(hip_fail(c, e, "nomad_init: diagnostics"));
     if ((e = hipMalloc(&c->wstats, sizeof(int64_t) * nomad::kWStatCount * (size_t)p)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: worker counters"));
+    if ((e = hipMalloc(&c->counters, sizeof(unsigned long long) * 4)) != hipSuccess ||
+        (e = hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * 4, c->stream)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: counters"));
+    if (cfg->debug_ownership &&
+        ((e = hipMalloc(&c->holder, sizeof(uint32_t) * (size_t)n)) != hipSuccess ||
+         (e = hipMemsetAsync(c->holder, 0xFF, sizeof(uint32_t) * (size_t)n, c->stream)) != hipSuccess))
+        return bail(hip_fail(c, e, "nomad_init: holder words"));
     c->eval_scratch_bytes = nomad::eval_scratch_bytes();
     if ((e = hipMalloc(&c->eval_scratch, c->eval_scratch_bytes)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: scratch"));
@@ -319,9 +344,19 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
                           sizeof(msg));
     if (e != hipSuccess) return bail(hip_fail(c, e, "nomad_init: layout"));
     if (code != 0) return bail(fail(c, (nomad_status)code, "nomad_init: %s", msg));
+    if (cfg->sched == NOMAD_SCHED_RING && cfg->t_source == 1 &&
+        (e = nomad::build_visit_starts(&c->plan, cfg->seed, st)) != hipSuccess)
+        return bail(hip_fail(c, e, "nomad_init: visit positions"));
     if (cfg->sched == NOMAD_SCHED_PERM || cfg->sched == NOMAD_SCHED_UNIFORM) {
+        if (c->plan.nvisits >= (int64_t)INT32_MAX)
+            return bail(fail(c, NOMAD_EINVAL, "nomad_init: %lld (worker, item) visits per epoch are too many for the "
+                             "asynchronous schedules", (long long)c->plan.nvisits));
+        if (cfg->sched == NOMAD_SCHED_UNIFORM && (int64_t)p * n >= (int64_t)INT32_MAX)
+            return bail(fail(c, NOMAD_EINVAL, "nomad_init: uniform routing needs workers x items < 2^31"));
         if ((e = nomad::build_async_tables(&c->plan, st)) != hipSuccess)
             return bail(hip_fail(c, e, "nomad_init: asynchronous tables"));
+        if (cfg->sched == NOMAD_SCHED_UNIFORM && (e = nomad::build_holder_map(&c->plan, st)) != hipSuccess)
+            return bail(hip_fail(c, e, "nomad_init: holder map"));
         const int64_t nv = c->plan.nvisits > 0 ? c->plan.nvisits : 1;
         // permutation: a worker's queue holds its local items; uniform routing: any item
         c->queue_len = cfg->sched == NOMAD_SCHED_UNIFORM ? (int64_t)p * n : nv;
@@ -332,11 +367,9 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
             (e = hipMemsetAsync(c->tvis, 0, sizeof(int32_t) * (size_t)nv, st)) != hipSuccess ||
             (e = hipMalloc(&c->qtail, sizeof(uint32_t) * (size_t)p)) != hipSuccess ||
             (e = hipMalloc(&c->parked, sizeof(uint32_t))) != hipSuccess ||
-            (e = hipMalloc(&c->itep, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
-            (e = hipMalloc(&c->ihop, sizeof(int32_t) * (size_t)n)) != hipSuccess ||
+            (e = hipMalloc(&c->istate, sizeof(int32_t) * 4 * (size_t)n)) != hipSuccess ||
             (e = hipMalloc(&c->async_scratch, c->async_scratch_bytes)) != hipSuccess ||
-            (e = hipMemsetAsync(c->ihop, 0, sizeof(int32_t) * (size_t)n, st)) != hipSuccess ||
-            (e = hipMemsetAsync(c->itep, 0, sizeof(int32_t) * (size_t)n, st)) != hipSuccess)
+            (e = hipMemsetAsync(c->istate, 0, sizeof(int32_t) * 4 * (size_t)n, st)) != hipSuccess)
             return bail(hip_fail(c, e, "nomad_init: queues"));
     }
     if ((e = hipEventRecord(c->ev1, st)) != hipSuccess || (e = hipEventSynchronize(c->ev1)) != hipSuccess)
@@ -362,6 +395,12 @@ nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int
 static void fill_args(nomad_ctx *c, nomad::TrainArgs &a) {
     a.m = c->m;
     a.n = c->n;
+    a.nnz = c->nnz;
+    a.wave_start = c->plan.wave_start;
+    a.vstart = c->plan.vstart;
+    a.owner = c->holder;
+    a.counters = c->counters;
+    a.gstep = c->cfg.t_source == 1 ? 1 : 0;
     a.W = c->W;
     a.H = c->H;
     a.recs = c->plan.recs;
@@ -402,6 +441,7 @@ static nomad_status check_epochs(nomad_ctx *c, int32_t epochs, const char *who) 
 static nomad_status check_abort(nomad_ctx *c, const char *who) {
     uint32_t aborted = 0;
     HIPTRY(c, hipMemcpy(&aborted, c->tok_done + c->n, sizeof(uint32_t), hipMemcpyDeviceToHost), "train: flag");
+    if (aborted) c->failed = true;
     if (aborted == 2)
         return fail(c, NOMAD_EDEVICE, "%s: malformed layout detected; the factors are undefined", who);
     if (aborted) {
@@ -444,8 +484,10 @@ static nomad_status train_batch(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         seconds = ms * 1e-3;
         for (size_t b = 0; b < np; ++b) {
             const nomad_status ab = check_abort(c->members[b], "nomad_train_epochs");
-            if (ab != NOMAD_OK)
+            if (ab != NOMAD_OK) {
+                c->failed = true;
                 return fail(c, ab, "problem %zu of the batch: %s", b, c->members[b]->err.c_str());
+            }
         }
         for (nomad_ctx *m : c->members) m->epochs_done += epochs;
         c->epochs_done += epochs;
@@ -457,6 +499,7 @@ static nomad_status train_batch(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
             HIPTRY(c, hipMemsetAsync(m->diag, 0, sizeof(int32_t) * 8, st), "train: reset");
             HIPTRY(c, hipMemsetAsync(m->wstats, 0, sizeof(int64_t) * nomad::kWStatCount * (size_t)m->p, st),
                    "train: reset");
+            HIPTRY(c, hipMemsetAsync(m->counters, 0, sizeof(unsigned long long) * 2, st), "train: reset");
         }
         HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
         for (int32_t done = 0; done < epochs;) {
@@ -483,8 +526,10 @@ static nomad_status train_batch(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         seconds = ms * 1e-3;
         for (size_t b = 0; b < np; ++b) {
             const nomad_status ab = check_abort(c->members[b], "nomad_train_epochs");
-            if (ab != NOMAD_OK)
+            if (ab != NOMAD_OK) {
+                c->failed = true;
                 return fail(c, ab, "problem %zu of the batch: %s", b, c->members[b]->err.c_str());
+            }
         }
         for (nomad_ctx *m : c->members) m->epochs_done += epochs;
         c->epochs_done += epochs;
@@ -495,6 +540,13 @@ static nomad_status train_batch(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         out->updates = (uint64_t)c->nnz * (uint64_t)epochs;
         out->epochs_done = (uint64_t)c->epochs_done;
         out->layout_seconds = c->layout_seconds;
+        if (epochs > 0)
+            for (nomad_ctx *m : c->members) {
+                unsigned long long ctr[2] = {0, 0};
+                HIPTRY(c, hipMemcpy(ctr, m->counters, sizeof(ctr), hipMemcpyDeviceToHost), "train: counters");
+                out->violations += ctr[0];
+                out->hops += ctr[1];
+            }
     }
     return NOMAD_OK;
 }
@@ -503,6 +555,9 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
     if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_train_epochs: NULL context");
     if (c->owner) return fail(c, NOMAD_ESTATE, "nomad_train_epochs: this problem belongs to a batch; train the batch");
     if (epochs < 0) return fail(c, NOMAD_EINVAL, "nomad_train_epochs: epochs=%d < 0", epochs);
+    if (c->failed)
+        return fail(c, NOMAD_ESTATE, "nomad_train_epochs: an earlier launch failed; the factors are undefined "
+                    "(destroy the context and build a new one)");
     if (!c->members.empty()) return train_batch(c, epochs, out);
     {
         const nomad_status ce = check_epochs(c, epochs, "nomad_train_epochs");
@@ -539,6 +594,7 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         HIPTRY(c, hipMemsetAsync(c->tok_done + c->n, 0, sizeof(uint32_t), st), "train: reset");
         HIPTRY(c, hipMemsetAsync(c->diag, 0, sizeof(int32_t) * 8, st), "train: reset");
         HIPTRY(c, hipMemsetAsync(c->wstats, 0, sizeof(int64_t) * nomad::kWStatCount * (size_t)c->p, st), "train: reset");
+        HIPTRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * 2, st), "train: reset");
         HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
         const bool async = c->cfg.sched == NOMAD_SCHED_PERM || c->cfg.sched == NOMAD_SCHED_UNIFORM;
         const bool uniform = c->cfg.sched == NOMAD_SCHED_UNIFORM;
@@ -555,8 +611,8 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
             a.xoff = c->plan.xoff;
             a.queue = c->queue;
             a.qtail = c->qtail;
-            a.itep = c->itep;
-            a.ihop = c->ihop;
+            a.istate = c->istate;
+            a.hmap = c->plan.hmap;
             a.parked = c->parked;
             a.active = c->plan.active;
             a.route_seed = (uint32_t)(c->cfg.seed >> 32) ^ (uint32_t)c->cfg.seed ^ 0x6a09e667u;
@@ -578,6 +634,11 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
                 HIPTRY(c, nomad::launch_train(a, st), "train: launch");
             }
             done += ne;
+            if (done < epochs) {
+                // a launch that stopped early ends the call: the next one would wait again
+                const nomad_status ab = check_abort(c, "nomad_train_epochs");
+                if (ab != NOMAD_OK) return ab;
+            }
         }
         HIPTRY(c, hipEventRecord(c->ev1, st), "train: event");
         HIPTRY(c, hipEventSynchronize(c->ev1), "train: kernel");
@@ -597,6 +658,12 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
     if (out) {
         out->seconds = seconds;
         out->updates = (uint64_t)c->nnz * (uint64_t)epochs;
+        if (epochs > 0 && c->nnz > 0) {
+            unsigned long long ctr[2] = {0, 0};
+            HIPTRY(c, hipMemcpy(ctr, c->counters, sizeof(ctr), hipMemcpyDeviceToHost), "train: counters");
+            out->violations = ctr[0];
+            out->hops = ctr[1];
+        }
         if (c->cfg.sched == NOMAD_SCHED_UNIFORM && epochs > 0 && c->nnz > 0) {
             unsigned long long u = 0;
             HIPTRY(c, hipMemcpy(&u, c->upd, sizeof(u), hipMemcpyDeviceToHost), "train: update count");
@@ -614,6 +681,7 @@ nomad_status nomad_eval_rmse(nomad_ctx *c, int64_t nnz, const int32_t *d_row, co
     if (!c->members.empty())
         return fail(c, NOMAD_ESTATE, "nomad_eval_rmse: a batch; use nomad_batch_problem for one of its problems");
     if (!rmse_out) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: rmse_out is NULL");
+    if (c->failed) return fail(c, NOMAD_ESTATE, "nomad_eval_rmse: an earlier launch failed; the factors are undefined");
     if (nnz < 0) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: nnz < 0");
     if (nnz > 0 && (!d_row || !d_col || !d_val)) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: NULL arrays");
     double sq = 0.0, obj = 0.0;
@@ -634,6 +702,7 @@ nomad_status nomad_get_factors(nomad_ctx *c, float *d_W, float *d_H) {
     if (!c->members.empty())
         return fail(c, NOMAD_ESTATE, "nomad_get_factors: a batch; use nomad_batch_problem for one of its problems");
     if (!d_W || !d_H) return fail(c, NOMAD_EINVAL, "nomad_get_factors: NULL output");
+    if (c->failed) return fail(c, NOMAD_ESTATE, "nomad_get_factors: an earlier launch failed; the factors are undefined");
     if (c->wbytes == 2)
         HIPTRY(c, nomad::from_bf16((const uint16_t *)c->W, c->kp, d_W, c->k, c->m, c->stream), "get_factors");
     else

@@ -343,9 +343,37 @@ __global__ void k_xoff_fill(const int64_t *rbase, int64_t nwt, int32_t nw, const
     }
 }
 
+// Sort key of each visit in the ring order of an epoch: sub-step s = (g(j) - q) mod p, then
+// worker q (a worker's visits are already in (s, j) order, which a stable sort keeps).
+__global__ void k_visit_ring_key(const int64_t *vbase, int32_t p, const VisitRec *visits, int64_t nv, uint64_t seed,
+                                 uint32_t *key, uint32_t *vidx) {
+    GRID_LOOP(v, nv) {
+        const int32_t q = find_block(vbase, p, v);
+        const int32_t g = item_group(seed, visits[v].j, p);
+        const int32_t sub = g >= q ? g - q : g - q + p;
+        key[v] = (uint32_t)sub * (uint32_t)p + (uint32_t)q;
+        vidx[v] = (uint32_t)v;
+    }
+}
+
+__global__ void k_gather_counts(const uint32_t *vidx_sorted, const unsigned int *vcnt, int64_t nv, int64_t *out) {
+    GRID_LOOP(i, nv) out[i] = (int64_t)vcnt[vidx_sorted[i]];
+}
+
+__global__ void k_scatter_starts(const uint32_t *vidx_sorted, const int64_t *pos, int64_t nv, int64_t *vstart) {
+    GRID_LOOP(i, nv) vstart[vidx_sorted[i]] = pos[i];
+}
+
+// Holder map of uniform routing: hmap[q * n + j] = the holder entry of (q, j).
+__global__ void k_holder_map(const int32_t *hold, const int32_t *hitem, int64_t nv, int64_t n, int32_t *hmap) {
+    GRID_LOOP(g, nv) hmap[(int64_t)hold[g] * n + hitem[g]] = (int32_t)g;
+}
+
 }  // namespace
 
 void free_plan(Plan *pl) {
+    (void)hipFree(pl->vstart);
+    (void)hipFree(pl->hmap);
     (void)hipFree(pl->row_start);
     (void)hipFree(pl->wave_start);
     (void)hipFree(pl->rbase);
@@ -434,6 +462,61 @@ hipError_t build_async_tables(Plan *pl, hipStream_t st) {
 done:
     (void)hipFree(vq); (void)hipFree(vj); (void)hipFree(vj_s); (void)hipFree(vidx); (void)hipFree(vidx_s);
     (void)hipFree(cnt); (void)hipFree(act); (void)hipFree(vcnt);
+    return rc;
+}
+
+hipError_t build_visit_starts(Plan *pl, uint64_t seed, hipStream_t st) {
+    hipError_t rc = hipSuccess;
+    const int64_t nv = pl->nvisits, nwt = (int64_t)pl->p * pl->nw;
+    unsigned int *vcnt = nullptr;
+    uint32_t *key = nullptr, *key_s = nullptr, *vidx = nullptr, *vidx_s = nullptr;
+    int64_t *cnt = nullptr, *pos = nullptr;
+    Tmp tmp;
+    CK(dalloc(&pl->vstart, nv));
+    if (nv > 0) {
+        CK(dalloc(&vcnt, nv)); CK(dalloc(&key, nv)); CK(dalloc(&key_s, nv)); CK(dalloc(&vidx, nv));
+        CK(dalloc(&vidx_s, nv)); CK(dalloc(&cnt, nv)); CK(dalloc(&pos, nv));
+        CK(hipMemsetAsync(vcnt, 0, sizeof(unsigned int) * nv, st));
+        if (pl->nnz > 0) {
+            hipLaunchKernelGGL(k_visit_ratings, dim3(grid_for(pl->nnz)), dim3(kThreads), 0, st, pl->recs, pl->nnz,
+                               pl->rbase, nwt, pl->nw, pl->vbase, vcnt);
+            CK(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_visit_ring_key, dim3(grid_for(nv)), dim3(kThreads), 0, st, pl->vbase, pl->p, pl->visits,
+                           nv, seed, key, vidx);
+        CK(hipGetLastError());
+        const int kb = bits_for((uint64_t)pl->p * (uint64_t)pl->p);
+        size_t need = 0;
+        CK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, key, key_s, vidx, vidx_s, nv, 0, kb, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceRadixSort::SortPairs(tmp.p, need, key, key_s, vidx, vidx_s, nv, 0, kb, st));
+        hipLaunchKernelGGL(k_gather_counts, dim3(grid_for(nv)), dim3(kThreads), 0, st, vidx_s, vcnt, nv, cnt);
+        CK(hipGetLastError());
+        need = 0;
+        CK(hipcub::DeviceScan::ExclusiveSum(nullptr, need, (const int64_t *)cnt, pos, nv, st));
+        CK(tmp.need(need));
+        CK(hipcub::DeviceScan::ExclusiveSum(tmp.p, need, (const int64_t *)cnt, pos, nv, st));
+        hipLaunchKernelGGL(k_scatter_starts, dim3(grid_for(nv)), dim3(kThreads), 0, st, vidx_s, pos, nv, pl->vstart);
+        CK(hipGetLastError());
+        CK(hipStreamSynchronize(st));
+    }
+done:
+    (void)hipFree(vcnt); (void)hipFree(key); (void)hipFree(key_s); (void)hipFree(vidx); (void)hipFree(vidx_s);
+    (void)hipFree(cnt); (void)hipFree(pos);
+    return rc;
+}
+
+hipError_t build_holder_map(Plan *pl, hipStream_t st) {
+    hipError_t rc = hipSuccess;
+    const size_t cells = (size_t)pl->p * (size_t)pl->n;
+    CK(dalloc(&pl->hmap, cells));
+    CK(hipMemsetAsync(pl->hmap, 0xFF, sizeof(int32_t) * cells, st));
+    if (pl->nvisits > 0) {
+        hipLaunchKernelGGL(k_holder_map, dim3(grid_for(pl->nvisits)), dim3(kThreads), 0, st, pl->hold, pl->hitem,
+                           pl->nvisits, pl->n, pl->hmap);
+        CK(hipGetLastError());
+    }
+done:
     return rc;
 }
 

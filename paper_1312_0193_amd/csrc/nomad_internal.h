@@ -35,8 +35,8 @@ constexpr int kDefaultWaves = 8;
 constexpr int kDefaultWavesAsync = 4;
 constexpr int kMaxItemSlots = 64;   // items a worker holds in LDS at once
 constexpr int kMaxWorkers = 4096;
-constexpr int kMaxEpochsPerLaunch = 64;
-constexpr int kMaxWindow = 32;           // rows a compute wave keeps in flight  // a call runs longer epoch counts as several launches
+constexpr int kMaxEpochsPerLaunch = 64;  // a call runs longer epoch counts as several launches
+constexpr int kMaxWindow = 32;           // rows a compute wave keeps in flight
 
 // Visit information of a rating record.
 constexpr uint32_t kInfoXBits = 23;                       // visit index x within the epoch
@@ -117,6 +117,9 @@ struct Plan {
     int32_t *xoff = nullptr;   // nvisits * nw: first record of local item x in wave w's stream, relative to
                                //   the stream start (the end is the next local item's entry, or the stream end)
     int64_t active = 0;        // items with at least one rating
+    // Options (built on demand).
+    int64_t *vstart = nullptr;  // per visit: ratings before it in an epoch of the ring order
+    int32_t *hmap = nullptr;    // uniform routing: p x n, holder entry of (worker, item) or -1
 };
 
 // Arguments of the training kernel.
@@ -128,7 +131,7 @@ struct Shape {
 };
 
 struct TrainArgs {
-    int64_t m, n;
+    int64_t m, n, nnz;
     void *W;                    // m x kp, FP32 or bfloat16 (wbytes per element)
     float *H;                   // n x kp
     const RatingRec *recs;
@@ -166,11 +169,21 @@ struct TrainArgs {
     unsigned long long *upd;    // uniform routing: updates applied in the call
     unsigned long long budget;  // uniform routing: updates after which items stop moving
     uint32_t *qtail;            // p: pushes into each queue during the launch
-    int32_t *itep;              // n: permutation: epoch of each item's next visit; uniform: moves so far
-    int32_t *ihop;              // n: visits of each item since the call began
+    int32_t *istate;            // n x 4: state of each item, written by its holder before it moves on:
+                                //   [0] permutation: epoch of the next visit; uniform: moves so far
+                                //   [1] permutation: position of the next visit in the epoch's order
+                                //   [2] visits of the item (that updated something) since nomad_init
+                                //   [3] unused
+    const int32_t *hmap;        // uniform routing: p x n, holder entry of (worker, item) or -1
     uint32_t *parked;           // items that finished the launch's epochs
     int64_t active;             // items with at least one rating
     uint32_t route_seed;
+    const int64_t *wave_start;  // p * nw + 1 row boundaries of the compute waves
+    const int64_t *vstart;      // ring order, gstep: per visit, ratings before it in an epoch
+    uint32_t *owner;            // ownership checks (NULL = off): n words, the worker holding each
+                                // item or 0xFFFFFFFF
+    unsigned long long *counters;  // [0] ownership violations, [1] hops, [2] global update count
+    int32_t gstep;              // 1: t = global count of updates before the visit (step-size option)
     int32_t *trace;             // optional: 4 ints per visit
     int64_t *trace_len;         // optional counter
     int64_t trace_cap;
@@ -185,6 +198,11 @@ hipError_t build_plan(Plan *plan, int64_t m, int64_t n, int64_t nnz, const int32
 void free_plan(Plan *plan);
 // The tables of the asynchronous schedules, from a built plan.
 hipError_t build_async_tables(Plan *plan, hipStream_t stream);
+// Per visit, the number of ratings before it in one epoch of the ring order (the global
+// update count option of the step size).
+hipError_t build_visit_starts(Plan *plan, uint64_t seed, hipStream_t stream);
+// Uniform routing's holder map (after build_async_tables).
+hipError_t build_holder_map(Plan *plan, hipStream_t stream);
 
 // train.hip
 size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes);

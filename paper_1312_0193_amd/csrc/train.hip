@@ -341,6 +341,13 @@ __device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
     return x;
 }
 
+// Step size of eq. (stepsize_method), s_t = alpha / (1 + beta t^gamma), in double rounded
+// to float, and s_t lambda rounded from double.
+__device__ __forceinline__ void step_size(const TrainArgs &a, double t, float &s, float &c) {
+    s = (float)(a.alpha / (1.0 + a.beta * (t > 0.0 ? pow(t, a.gamma) : 0.0)));
+    c = (float)((double)s * (double)a.lambda);
+}
+
 // VEC elements of a row in W's storage type (FP32, or bfloat16 = the upper half of an
 // FP32) to and from FP32 registers, in LDS and in global memory.  The bfloat16 values
 // stored are exactly the registers' values (rounded before).
@@ -447,6 +454,9 @@ struct ComputeWave {
     int64_t bpos = 0;         // stream position of the next record batch
     int bent = 0;             // ring entry of the next record batch
     uint64_t forwarded = 0, t_wait = 0;
+    // ownership checks: a rating's row must lie in [own_lo, own_lo + own_span); a span of
+    // 2^32 - 1 admits every row (checks off)
+    uint32_t own_lo = 0, own_span = 0xFFFFFFFFu, viol = 0;
 
     __device__ ComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0, int64_t cnt_)
         : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC), rb(a_.kp * ES),
@@ -506,6 +516,10 @@ struct ComputeWave {
     __device__ void run() {
         if (total <= 0) return;
         const uint64_t t_start = tick(a.timing);
+        if (a.owner) {
+            own_lo = (uint32_t)a.wave_start[(int64_t)q * a.nw + w];
+            own_span = (uint32_t)(a.wave_start[(int64_t)q * a.nw + w + 1] - a.wave_start[(int64_t)q * a.nw + w]);
+        }
         load_batch();
         load_batch();
         wait_vm();
@@ -563,6 +577,7 @@ struct ComputeWave {
             const uint32_t ifwd = (uint32_t)__builtin_amdgcn_readfirstlane((int)vi.y);
             const int X = xbase + (int)(rc.info & kInfoXMask);
             const int slot = X & (a.slots - 1);
+            viol += (uint32_t)rc.row - own_lo >= own_span;
             if (rc.info & kInfoFirst) {
                 // This wave's part of visit X starts: wait for the item, from the memory
                 // wave (first wave of the visit) or from the wave before.
@@ -574,6 +589,11 @@ struct ComputeWave {
                 t_wait += tick(a.timing) - t0;
                 lload<VEC>(items + (size_t)slot * kp, h);
                 if constexpr (BF) item = __builtin_amdgcn_readfirstlane(L.item[slot]);
+                if (a.gstep) {
+                    // the visit's step size (t = the global update count before it)
+                    s = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(L.ss[slot])));
+                    sl = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(L.sc[slot])));
+                }
             }
             // Section 2.3: one residual, both vectors from their values before the update.
             float d = 0.0f;
@@ -633,6 +653,7 @@ struct ComputeWave {
             }
         }
         wait_vm();
+        if (viol && lane == 0) atomicAdd(a.counters + 0, (unsigned long long)viol);
         if (a.wstats && lane == 0) {
             unsigned long long *ws = (unsigned long long *)(a.wstats + (int64_t)q * kWStatCount);
             const uint64_t tot = tick(a.timing) - t_start;
@@ -689,16 +710,19 @@ struct MemoryWave {
     int Xl = 0, Xr = 0; // visits taken over / passed on
     // visits held (loaded, not yet passed on): lane (X mod S)
     int f_j = 0, f_lw = 0;
-    uint32_t f_tk = 0;
-    // candidates: lane l = visit Xl + l
+    uint32_t f_tk = 0, f_nv = 0;
+    // candidates: lane l = visit Xl + l; c_s, c_c: the visit's step size and step size
+    // times lambda when t is the global update count
     int c_j = 0, c_lw = 0;
     uint32_t c_tk = 0, c_pv = 0, c_v = 0, c_nvis = 0;
+    int64_t c_vs = 0;
+    float c_s = 0.0f, c_c = 0.0f;
     int c_state = 0;    // 0 none, 1 record requested, 2 record known, 3 polled
     // items passed on this round: published once their stores are complete
     int pub_j = 0;
     uint32_t pub_tk = 0;
     int npub = 0;
-    uint64_t iters = 0, misses = 0, t_mem = 0;
+    uint64_t iters = 0, misses = 0, t_mem = 0, hops = 0, viol = 0;
     const uint64_t row_mask;  // lanes that load a vector (16 bytes each)
 
     __device__ MemoryWave(const TrainArgs &a_, const Lds &L_, int q_, int lane_)
@@ -767,13 +791,21 @@ struct MemoryWave {
                 const int X = Xr + lane;
                 const int sl = X & Smask;
                 const int j = __shfl(f_j, sl), lw = __shfl(f_lw, sl);
-                const uint32_t tk = (uint32_t)__shfl((int)f_tk, sl);
+                const uint32_t tk = (uint32_t)__shfl((int)f_tk, sl), nvj = (uint32_t)__shfl((int)f_nv, sl);
                 bool done = false;
                 if (lane < inflight) done = lds_read_i32_now(&L.flag[lw]) > X;
                 const uint64_t dm = __builtin_amdgcn_ballot_w64(done);
                 const int nr = leading_run(dm);
                 if (nr > 0) {
                     write_back(j, sl, nr);
+                    if (a.owner && lane < nr) {
+                        // the item leaves this worker: its holder word must name it
+                        const uint32_t was = atomicExch(a.owner + j, 0xFFFFFFFFu);
+                        viol += was != (uint32_t)q;
+                    }
+                    // hand-offs to a later visit of the same call
+                    hops += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(
+                        lane < nr && tk + 1u < (uint32_t)(a.epoch0 + a.epochs) * nvj));
                     pub_j = j;
                     pub_tk = tk + 1u;
                     npub = nr;
@@ -797,16 +829,25 @@ struct MemoryWave {
                     const int j = __shfl(c_j, t);
                     load_item(j, (Xl + t) & Smask);
                 }
+                if (a.owner && lane < nl) {
+                    // the item arrives: no other worker may hold it
+                    const uint32_t was = atomicCAS(a.owner + c_j, 0xFFFFFFFFu, (uint32_t)q);
+                    viol += was != 0xFFFFFFFFu;
+                }
                 if (nl > 0) {
                     // holder lanes: slot s takes candidate t = (s - Xl) mod S when t < nl
                     const int t = (lane - Xl) & Smask;
                     const int j = __shfl(c_j, t), lw = __shfl(c_lw, t);
-                    const uint32_t tk = (uint32_t)__shfl((int)c_tk, t);
+                    const uint32_t tk = (uint32_t)__shfl((int)c_tk, t), nvj = (uint32_t)__shfl((int)c_nvis, t);
+                    const float ts = __shfl(c_s, t), tc = __shfl(c_c, t);
                     if (lane < S && t < nl) {
                         f_j = j;
                         f_lw = lw;
                         f_tk = tk;
+                        f_nv = nvj;
                         L.item[lane] = j;
+                        L.ss[lane] = ts;
+                        L.sc[lane] = tc;
                     }
                     if (a.trace) {
                         int64_t base = 0;
@@ -828,12 +869,17 @@ struct MemoryWave {
                     const int sj = __shfl(c_j, src & 63), slw = __shfl(c_lw, src & 63),
                               sst = __shfl(c_state, src & 63);
                     const uint32_t stk = (uint32_t)__shfl((int)c_tk, src & 63),
-                                   spv = (uint32_t)__shfl((int)c_pv, src & 63);
+                                   spv = (uint32_t)__shfl((int)c_pv, src & 63),
+                                   snv = (uint32_t)__shfl((int)c_nvis, src & 63);
+                    const float ss = __shfl(c_s, src & 63), sc = __shfl(c_c, src & 63);
                     const bool in = src < 64;
                     c_j = sj;
                     c_lw = slw;
                     c_tk = stk;
                     c_pv = spv;
+                    c_nvis = snv;
+                    c_s = ss;
+                    c_c = sc;
                     c_state = in ? sst : 0;
                     progress = true;
                 }
@@ -854,6 +900,7 @@ struct MemoryWave {
                     c_v = (uint32_t)r.y;
                     c_nvis = (uint32_t)r.z;
                     c_lw = r.w;
+                    if (a.gstep) c_vs = a.vstart[vb + x];
                     req = true;
                 }
             }
@@ -870,6 +917,8 @@ struct MemoryWave {
                     return;
                 }
                 c_tk = ((uint32_t)a.epoch0 + e_rel) * c_nvis + c_v;
+                // t = the global count of updates before the visit, in the ring order
+                if (a.gstep) step_size(a, (double)((int64_t)(a.epoch0 + (int)e_rel) * a.nnz + c_vs), c_s, c_c);
                 c_state = 2;
             }
             if (npub > 0) {
@@ -900,6 +949,12 @@ struct MemoryWave {
             }
         }
         wait_vm();
+        unsigned long long vsum = viol;
+        for (int o = 32; o > 0; o >>= 1) vsum += __shfl_xor(vsum, o);
+        if (lane == 0) {
+            if (vsum) atomicAdd(a.counters + 0, vsum);
+            if (hops) atomicAdd(a.counters + 1, (unsigned long long)hops);
+        }
         if (a.wstats && lane == 0) {
             unsigned long long *ws = (unsigned long long *)(a.wstats + (int64_t)q * kWStatCount);
             atomicAdd(&ws[kWStatMemTotal], (unsigned long long)(tick(a.timing) - t_start));
@@ -920,26 +975,46 @@ struct MemoryWave {
 // in arrival order; after its last compute wave is done with an item it writes h_j back
 // (device-coherent), passes it to the next worker of the item's visiting order for the
 // epoch, or parks it after the launch's last epoch.  The visiting order of item j in epoch
-// e is its holders sorted by a hash of (seed, j, e, worker): a fresh pseudo-random
-// permutation every epoch, so every rating is updated once per epoch and t = e.
+// e is a keyed pseudo-random permutation of its holders (a fresh one every epoch), so every
+// rating is updated once per epoch and t = e.
 
-// Position of holder `q` (entry `rank` of the item's holder list) in the visiting order of
-// item j for epoch e: larger keys come later.
-__device__ __forceinline__ uint64_t route_key(uint32_t seed, int j, int e, int q, int rank) {
-    const uint32_t k = lowbias32(lowbias32(seed ^ (uint32_t)j) ^ ((uint32_t)e * 0x9E3779B9u) ^ ((uint32_t)q * 0x85EBCA77u));
-    return ((uint64_t)k << 32) | (uint32_t)rank;
+// Position -> holder rank of item j's visiting order in epoch e: a keyed bijection of
+// [0, nh).  Four alternating half-steps of a Feistel network (each xors one half of the
+// bits with a hash of the other half, so each is invertible) permute [0, 2^b), 2^b >= nh
+// the smallest such power of two; values outside [0, nh) are mapped again until one falls
+// inside (cycle walking), which keeps the map a bijection of [0, nh).  Fewer than two
+// passes are needed on average, and the cost does not grow with nh.
+__device__ __forceinline__ uint32_t visit_rank(uint32_t seed, int j, int e, uint32_t nh, uint32_t x) {
+    if (nh <= 1u) return 0u;
+    const int b = 32 - __builtin_clz(nh - 1u);
+    const int lo = b >> 1;
+    const uint32_t mlo = (1u << lo) - 1u, mhi = (1u << (b - lo)) - 1u;
+    const uint32_t key = lowbias32(lowbias32(seed ^ (uint32_t)j) ^ ((uint32_t)e * 0x9E3779B9u));
+    do {
+        uint32_t L = x >> lo, R = x & mlo;
+        L ^= lowbias32(R ^ key) & mhi;
+        R ^= lowbias32(L ^ (key + 0x632BE5ABu)) & mlo;
+        L ^= lowbias32(R ^ (key + 0xC6579D56u)) & mhi;
+        R ^= lowbias32(L ^ (key + 0x2983B501u)) & mlo;
+        x = (L << lo) | R;
+    } while (x >= nh);
+    return x;
 }
 
-// The holder entry that comes first in item j's visiting order for epoch e (after `after`
-// if given), or -1 if none does.
-__device__ __forceinline__ int64_t route_next(const TrainArgs &a, int j, int e, uint64_t after, bool use_after) {
-    const int64_t hb = a.hoff[j], nh = a.hoff[j + 1] - hb;
-    uint64_t best = ~0ull;
-    for (int64_t r = 0; r < nh; ++r) {
-        const uint64_t k = route_key(a.route_seed, j, e, a.hold[hb + r], (int)r);
-        if ((!use_after || k > after) && k < best) best = k;
-    }
-    return best == ~0ull ? -1 : hb + (int64_t)(uint32_t)best;
+// Per-item state words (TrainArgs::istate), read and written device-coherently: the item's
+// holder writes them before the item moves on, the next holder reads them after taking it.
+__device__ __forceinline__ int4 istate_load(const TrainArgs &a, int j) {
+    const uint64_t *p = (const uint64_t *)(a.istate + 4 * (int64_t)j);
+    const uint64_t u0 = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t u1 = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_int4((int)(uint32_t)u0, (int)(uint32_t)(u0 >> 32), (int)(uint32_t)u1, (int)(uint32_t)(u1 >> 32));
+}
+__device__ __forceinline__ void istate_store(const TrainArgs &a, int j, int4 v) {
+    uint64_t *p = (uint64_t *)(a.istate + 4 * (int64_t)j);
+    __hip_atomic_store(p, (uint64_t)(uint32_t)v.x | ((uint64_t)(uint32_t)v.y << 32), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + 1, (uint64_t)(uint32_t)v.z | ((uint64_t)(uint32_t)v.w << 32), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // W's stored row elements of the lane to FP32 registers (global memory).
@@ -979,6 +1054,7 @@ struct AsyncComputeWave {
     char *const W;
     const uint32_t lb;    // the lane's byte offset inside a row
     uint64_t nrat = 0, t_wait = 0;
+    uint32_t viol = 0;    // ownership checks: ratings of rows the wave does not own
 
     __device__ AsyncComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0)
         : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC), rb(a_.kp * ES), rs(a_.recs + r0),
@@ -1080,6 +1156,11 @@ struct AsyncComputeWave {
                         // leaves a load of them pending
                         asm volatile("" : "+v"(crow), "+v"(crat));
                     }
+                    if (a.owner) {
+                        // every rating of the batch is of a row this wave owns
+                        const int64_t lo = a.wave_start[(int64_t)q * a.nw + w], hi = a.wave_start[(int64_t)q * a.nw + w + 1];
+                        viol += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(lane < nb && (crow < lo || crow >= hi)));
+                    }
                     if (r0 == b) {
                         // The next visit's first records, if it is announced and has ratings
                         // of this wave (else this visit's again: no branch around the load).
@@ -1139,6 +1220,7 @@ struct AsyncComputeWave {
             if (lane == 0) sync_store(&L.flag[w], X + 1);
         }
         wait_vm();
+        if (viol && lane == 0) atomicAdd(a.counters + 0, (unsigned long long)viol);
         if (a.wstats && lane == 0) {
             unsigned long long *ws = (unsigned long long *)(a.wstats + (int64_t)q * kWStatCount);
             atomicAdd(&ws[kWStatItemWait], (unsigned long long)t_wait);
@@ -1147,29 +1229,25 @@ struct AsyncComputeWave {
     }
 };
 
-// Holder entry of worker q in item j's holder list, or -1 (binary search: the list is in
-// ascending worker order).
-__device__ __forceinline__ int64_t holder_entry(const TrainArgs &a, int j, int q) {
-    int64_t lo = a.hoff[j], hi = a.hoff[j + 1];
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (a.hold[mid] < q) lo = mid + 1; else hi = mid;
-    }
-    return (lo < a.hoff[j + 1] && a.hold[lo] == q) ? lo : -1;
-}
-
 // Uniform routing (Algorithm 1 as printed): the next worker of item j after its v-th move.
 __device__ __forceinline__ int route_uniform(uint32_t seed, int j, int v, int p) {
     const uint32_t k = lowbias32(lowbias32(seed ^ 0x2545F491u ^ (uint32_t)j) + (uint32_t)v * 0x9E3779B9u);
     return (int)(((uint64_t)k * (uint64_t)(uint32_t)p) >> 32);
 }
 
+// Payload of a queue entry: the holder entry of the visit, or (uniform routing, for a
+// worker holding no rating of the item) kPassBit | item.
+constexpr uint32_t kPassBit = 0x80000000u;
+
 // Memory wave of the asynchronous schedules.
-//   Queue entries: (position + 1) << 32 | payload, the payload being a holder entry (random
-//   permutation: items only go to workers holding their ratings; worker q's queue has room
-//   for its local items) or an item (uniform routing: any item may come; room for n).
-//   Per visit the wave works out t (epoch, or the number of earlier visits of the item to
-//   this worker) and the step size, for the compute waves.
+//   Queue entries: (position + 1) << 32 | payload (see kPassBit).  Random permutation:
+//   items only go to workers holding their ratings, and worker q's queue has room for its
+//   local items; uniform routing: any item may come, room for n.
+//   Per visit the wave works out t (the epoch, or the number of earlier visits of the item
+//   to this worker, or the global update count) and the step size, for the compute waves.
+//   Taking an item over costs two rounds of dependent loads after its queue entry: the
+//   holder tables of the entry, then the item's state words, its vector (LDS-DMA) and the
+//   compute waves' record ranges.
 struct AsyncMemoryWave {
     const TrainArgs &a;
     const Lds &L;
@@ -1182,18 +1260,27 @@ struct AsyncMemoryWave {
     const int nvq;        // the worker's local items
     int Xl = 0, Xr = 0;   // visits taken / passed on
     int64_t head = 0;     // next queue position to take
-    // lane s < S: the visit in slot s: item, holder entry (-1 if none), step counter t, visit
-    // number of the item, moves of the item
-    int f_j = 0, f_g = 0, f_t = 0, f_seq = 0;
-    uint64_t iters = 0, misses = 0;
+    // lane s < S: the visit in slot s: item, holder entry (-1 if none), step counter t, the
+    // item's state words (epoch or moves, position, visits), its first holder entry and
+    // number of holders
+    int f_j = 0, f_g = -1, f_t = 0, f_e = 0, f_pos = 0, f_seq = 0, f_hb = 0, f_nh = 0;
+    // step sizes of t = tbase + lane
+    int tbase = 0;
+    float s_tab = 0.0f, c_tab = 0.0f;
+    uint64_t iters = 0, misses = 0, hops = 0, viol = 0;
 
     __device__ AsyncMemoryWave(const TrainArgs &a_, const Lds &L_, int q_, int lane_)
         : a(a_), L(L_), io(a_, L_, q_, lane_), q(q_), lane(lane_), S(a_.slots), uni(a_.sched == 2),
           qb(a_.sched == 2 ? (int64_t)q_ * a_.n : a_.vbase[q_]),
           cap(a_.sched == 2 ? a_.n : a_.vbase[q_ + 1] - a_.vbase[q_]), vbq(a_.vbase[q_]),
-          nvq((int)(a_.vbase[q_ + 1] - a_.vbase[q_])) {}
+          nvq((int)(a_.vbase[q_ + 1] - a_.vbase[q_])) {
+        // the permutation's t is the epoch, within [epoch0, epoch0 + epochs); uniform
+        // routing's per-pair counts stay near the epochs done
+        tbase = uni ? (a.epoch0 > 32 ? a.epoch0 - 32 : 0) : a.epoch0;
+        step_size(a, (double)(tbase + lane), s_tab, c_tab);
+    }
 
-    // Push item j (payload `pay`) to worker q2's queue.
+    // Push the item to worker q2's queue with payload `pay`.
     __device__ __forceinline__ void push(int q2, uint32_t pay) {
         const int64_t b2 = uni ? (int64_t)q2 * a.n : a.vbase[q2];
         const int64_t cap2 = uni ? a.n : a.vbase[q2 + 1] - b2;
@@ -1203,176 +1290,215 @@ struct AsyncMemoryWave {
                            __HIP_MEMORY_SCOPE_AGENT);
     }
 
+    // 1. Pass on the visits the last compute wave has finished (in order): write h_j back,
+    //    work out the next worker, write the item's state words, then push.
+    __device__ __forceinline__ bool pass_on() {
+        int nr = sync_load(&L.flag[a.nw - 1]) - Xr;
+        if (nr > 64) nr = 64;
+        if (nr <= 0) return false;
+        const int Smask = S - 1;
+        const int X = Xr + lane;
+        const int sl = X & Smask;
+        const int j = __shfl(f_j, sl), g = __shfl(f_g, sl), t = __shfl(f_t, sl), e = __shfl(f_e, sl),
+                  pos = __shfl(f_pos, sl), seq = __shfl(f_seq, sl), hb = __shfl(f_hb, sl), nh = __shfl(f_nh, sl);
+        io.write_back(j, sl, nr);
+        const bool mine = lane < nr;
+        int dest = -1;  // next worker, -1: the item is parked
+        uint32_t pay = 0;
+        int4 nst = make_int4(0, 0, g >= 0 ? seq + 1 : seq, 0);
+        unsigned long long done_upd = 0;
+        if (mine) {
+            if (uni) {
+                if (g >= 0) {
+                    if (!a.gstep) a.tvis[g] = t + 1;
+                    done_upd = (unsigned long long)a.hcnt[g];
+                }
+            } else {
+                // the next position of the epoch's visiting order, or the first of the next epoch
+                int np = pos + 1, ne = e;
+                if (np >= nh) {
+                    np = 0;
+                    ++ne;
+                }
+                if (ne < a.epoch0 + a.epochs) {
+                    const int ng = hb + (int)visit_rank(a.route_seed, j, ne, (uint32_t)nh, (uint32_t)np);
+                    dest = a.hold[ng];
+                    pay = (uint32_t)ng;
+                }
+                nst.x = ne;
+                nst.y = np;
+            }
+        }
+        if (uni) {
+            // updates of these visits, then: keep the items moving until the budget is met
+            unsigned long long sum = done_upd;
+            for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+            unsigned long long before = 0;
+            if (lane == 0) before = atomicAdd(a.upd, sum);
+            before = __shfl(before, 0);
+            if (mine) {
+                nst.x = e;  // moves so far
+                if (before + sum < a.budget) {
+                    dest = route_uniform(a.route_seed, j, e, a.p);
+                    nst.x = e + 1;
+                    const int g2 = a.hmap[(int64_t)dest * a.n + j];
+                    pay = g2 >= 0 ? (uint32_t)g2 : (kPassBit | (uint32_t)j);
+                }
+            }
+        }
+        if (mine) istate_store(a, j, nst);
+        if (a.owner && mine) {
+            // the item leaves this worker: its holder word must name it
+            const uint32_t was = atomicExch(a.owner + j, 0xFFFFFFFFu);
+            viol += was != (uint32_t)q;
+        }
+        wait_vm();  // the item vectors and state words are in place before the items move on
+        if (mine && dest >= 0) push(dest, pay);
+        hops += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(mine && dest >= 0));
+        const int np = __popcll(__builtin_amdgcn_ballot_w64(mine && dest < 0));
+        if (np > 0 && lane == 0) atomicAdd(a.parked, (uint32_t)np);
+        Xr += nr;
+        return true;
+    }
+
+    // 2. Take over arrived items, in arrival order, as far as slots allow.
+    __device__ __forceinline__ bool take_over() {
+        int room = Xr + S - Xl;
+        if (room > 64) room = 64;
+        if (room <= 0 || cap <= 0) return false;
+        const int Smask = S - 1;
+        uint64_t ent = 0;
+        bool valid = false;
+        if (lane < room) {
+            ent = __hip_atomic_load(a.queue + qb + (head + lane) % cap, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            valid = (uint32_t)(ent >> 32) == (uint32_t)(head + lane + 1);
+        }
+        const int nt = leading_run(__builtin_amdgcn_ballot_w64(valid));
+        if (nt <= 0) {
+            ++misses;
+            return false;
+        }
+        const bool mine = lane < nt;
+        // the holder tables of the entry
+        int j = 0, g = -1, x = -1, t = 0, cnt = 0;
+        if (mine) {
+            const uint32_t pay = (uint32_t)ent;
+            if (pay & kPassBit) {
+                j = (int)(pay & ~kPassBit);
+            } else {
+                g = (int)pay;
+                j = a.hitem[g];
+                x = a.hx[g];
+                cnt = a.hcnt[g];
+                if (uni) t = a.tvis[g];
+            }
+        }
+        // the item's vector and state words
+        for (int k = 0; k < nt; ++k) io.load_item(__shfl(j, k), (Xl + k) & Smask);
+        int4 st = make_int4(0, 0, 0, 0);
+        int hb = 0, nh = 0;
+        if (mine) {
+            st = istate_load(a, j);
+            if (!uni) {
+                const int64_t h0 = a.hoff[j];
+                hb = (int)h0;
+                nh = (int)(a.hoff[j + 1] - h0);
+                t = st.x;  // the epoch
+            }
+        }
+        {
+            // Every compute wave's record range of the new visits, into LDS (the record ring
+            // of the ring kernel's layout, unused here): one batched load here instead of a
+            // dependent load at the start of every visit in every compute wave.
+            int32_t *rng = (int32_t *)L.recs;
+            const int sl = (Xl + lane) & Smask;
+            for (int w2 = 0; w2 < a.nw; ++w2) {
+                int bw = 0, ew = 0;
+                if (mine && x >= 0) {
+                    const int64_t v = vbq + x;
+                    bw = a.xoff[v * a.nw + w2];
+                    ew = x + 1 < nvq ? a.xoff[(v + 1) * a.nw + w2]
+                                     : (int)(a.rbase[(int64_t)q * a.nw + w2 + 1] - a.rbase[(int64_t)q * a.nw + w2]);
+                }
+                if (mine) {
+                    rng[w2 * kMaxItemSlots + sl] = bw;
+                    rng[(a.nw + w2) * kMaxItemSlots + sl] = ew;
+                }
+            }
+        }
+        if (a.owner && mine) {
+            // the item arrives: no other worker may hold it
+            const uint32_t was = atomicCAS(a.owner + j, 0xFFFFFFFFu, (uint32_t)q);
+            viol += was != 0xFFFFFFFFu;
+        }
+        // step size of the visit: from the table, else computed
+        double tg = (double)t;
+        if (a.gstep && mine && g >= 0) {
+            // the global count of updates before the visit (visits are counted in the order
+            // they are taken, which is an order that every row and item sees)
+            tg = (double)atomicAdd(a.counters + 2, (unsigned long long)cnt);
+            t = (int)(uint32_t)(unsigned long long)tg;
+        }
+        const int ti = t - tbase;
+        float sv = __shfl(s_tab, ti & 63), cv = __shfl(c_tab, ti & 63);
+        if (mine && (a.gstep || ti < 0 || ti >= 64)) step_size(a, tg, sv, cv);
+        if (mine) {
+            const int sl = (Xl + lane) & Smask;
+            L.sx[sl] = x;
+            L.se[sl] = t;
+            L.ss[sl] = sv;
+            L.sc[sl] = cv;
+            L.item[sl] = j;
+        }
+        {
+            const int k = (lane - Xl) & Smask;
+            const int tj = __shfl(j, k), tg2 = __shfl(g, k), tt = __shfl(t, k), te = __shfl(st.x, k),
+                      tp = __shfl(st.y, k), ts = __shfl(st.z, k), thb = __shfl(hb, k), tnh = __shfl(nh, k);
+            if (lane < S && k < nt) {
+                f_j = tj;
+                f_g = tg2;
+                f_t = tt;
+                f_e = te;
+                f_pos = tp;
+                f_seq = ts;
+                f_hb = thb;
+                f_nh = tnh;
+            }
+        }
+        if (a.trace) {
+            // the visits that update something (uniform routing also visits workers holding
+            // no rating of the item)
+            const uint64_t rec = __builtin_amdgcn_ballot_w64(mine && g >= 0);
+            const int nrec = __popcll(rec);
+            int64_t base = 0;
+            if (lane == 0 && nrec > 0)
+                base = (int64_t)atomicAdd((unsigned long long *)a.trace_len, (unsigned long long)nrec);
+            base = __shfl(base, 0);
+            const int rank = __popcll(rec & ((1ull << lane) - 1ull));
+            if (mine && g >= 0 && base + rank < a.trace_cap) {
+                int32_t *tr = a.trace + 4 * (base + rank);
+                tr[0] = q;
+                tr[1] = j;
+                tr[2] = t;
+                tr[3] = st.z;
+            }
+        }
+        head += nt;
+        Xl += nt;
+        wait_vm();    // the item vectors are in LDS
+        wait_lgkm();  // and so are the slots' descriptions
+        if (lane == 0) sync_store(&L.ctl[0], Xl);
+        return true;
+    }
+
     __device__ void run() {
         const uint64_t t_start = tick(a.timing);
-        const int Smask = S - 1;
         uint64_t t_prog = wall_clock64();
         while (true) {
             ++iters;
-            bool progress = false;
-            // 1. Pass on the visits the last compute wave has finished (in order).
-            {
-                int nr = sync_load(&L.flag[a.nw - 1]) - Xr;
-                if (nr > 64) nr = 64;
-                if (nr > 0) {
-                    const int X = Xr + lane;
-                    const int sl = X & Smask;
-                    const int j = __shfl(f_j, sl), g = __shfl(f_g, sl), t = __shfl(f_t, sl), seq = __shfl(f_seq, sl);
-                    io.write_back(j, sl, nr);
-                    int dest = -1;      // next worker, -1: the item is parked
-                    uint32_t pay = 0;
-                    int ne = t;
-                    unsigned long long done_upd = 0;
-                    if (lane < nr) {
-                        if (uni) {
-                            if (g >= 0) {
-                                a.tvis[g] = t + 1;
-                                done_upd = (unsigned long long)a.hcnt[g];
-                            }
-                        } else {
-                            const int64_t hb = a.hoff[j];
-                            const uint64_t cur = route_key(a.route_seed, j, t, q, (int)(g - hb));
-                            int64_t ng = route_next(a, j, t, cur, true);
-                            if (ng < 0 && t + 1 < a.epoch0 + a.epochs) {
-                                ne = t + 1;
-                                ng = route_next(a, j, ne, 0, false);
-                            }
-                            if (ng >= 0) {
-                                dest = a.hold[ng];
-                                pay = (uint32_t)ng;
-                                __hip_atomic_store(a.itep + j, ne, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            }
-                        }
-                        if (g >= 0) __hip_atomic_store(a.ihop + j, seq + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    if (uni) {
-                        // updates of these visits, then: keep the items moving until the budget is met
-                        unsigned long long sum = done_upd;
-                        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-                        unsigned long long before = 0;
-                        if (lane == 0) before = atomicAdd(a.upd, sum);
-                        before = __shfl(before, 0);
-                        if (lane < nr && before + sum < a.budget) {
-                            const int moves = __hip_atomic_load(a.itep + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            dest = route_uniform(a.route_seed, j, moves, a.p);
-                            pay = (uint32_t)j;
-                            __hip_atomic_store(a.itep + j, moves + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        }
-                    }
-                    wait_vm();  // the items and their state are in place before they move on
-                    if (lane < nr && dest >= 0) push(dest, pay);
-                    const int np = __popcll(__builtin_amdgcn_ballot_w64(lane < nr && dest < 0));
-                    if (np > 0 && lane == 0) atomicAdd(a.parked, (uint32_t)np);
-                    Xr += nr;
-                    progress = true;
-                }
-            }
-            // 2. Take over arrived items, in arrival order, as far as slots allow.
-            {
-                int room = Xr + S - Xl;
-                if (room > 64) room = 64;
-                if (room > 0 && cap > 0) {
-                    uint64_t ent = 0;
-                    bool valid = false;
-                    if (lane < room) {
-                        ent = __hip_atomic_load(a.queue + qb + (head + lane) % cap, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-                        valid = (uint32_t)(ent >> 32) == (uint32_t)(head + lane + 1);
-                    }
-                    const int nt = leading_run(__builtin_amdgcn_ballot_w64(valid));
-                    if (nt > 0) {
-                        int j = 0, x = -1, t = 0, seq = 0, g = -1;
-                        float sv = 0.0f, cv = 0.0f;
-                        if (lane < nt) {
-                            const uint32_t pay = (uint32_t)ent;
-                            if (uni) {
-                                j = (int)pay;
-                                g = (int)holder_entry(a, j, q);
-                                if (g >= 0) t = a.tvis[g];
-                            } else {
-                                g = (int)pay;
-                                j = a.hitem[g];
-                                t = __hip_atomic_load(a.itep + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            }
-                            if (g >= 0) x = a.hx[g];
-                            seq = __hip_atomic_load(a.ihop + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            // s_t = alpha / (1 + beta t^gamma) (eq. stepsize_method) in double,
-                            // rounded to float; and s_t lambda, rounded from double
-                            const double td = (double)t;
-                            sv = (float)(a.alpha / (1.0 + a.beta * (td > 0.0 ? pow(td, a.gamma) : 0.0)));
-                            cv = (float)((double)sv * (double)a.lambda);
-                        }
-                        for (int k = 0; k < nt; ++k) io.load_item(__shfl(j, k), (Xl + k) & Smask);
-                        {
-                            // Every compute wave's record range of the new visits, into LDS
-                            // (the record ring of the ring kernel's layout, unused here): one
-                            // batched load here instead of a dependent load at the start of
-                            // every visit in every compute wave.
-                            int32_t *rng = (int32_t *)L.recs;
-                            const int sl = (Xl + lane) & Smask;
-                            for (int w2 = 0; w2 < a.nw; ++w2) {
-                                int bw = 0, ew = 0;
-                                if (lane < nt && x >= 0) {
-                                    const int64_t v = vbq + x;
-                                    bw = a.xoff[v * a.nw + w2];
-                                    ew = x + 1 < nvq ? a.xoff[(v + 1) * a.nw + w2]
-                                                     : (int)(a.rbase[(int64_t)q * a.nw + w2 + 1] -
-                                                             a.rbase[(int64_t)q * a.nw + w2]);
-                                }
-                                if (lane < nt) {
-                                    rng[w2 * kMaxItemSlots + sl] = bw;
-                                    rng[(a.nw + w2) * kMaxItemSlots + sl] = ew;
-                                }
-                            }
-                        }
-                        if (lane < nt) {
-                            const int sl = (Xl + lane) & Smask;
-                            L.sx[sl] = x;
-                            L.se[sl] = t;
-                            L.ss[sl] = sv;
-                            L.sc[sl] = cv;
-                            L.item[sl] = j;
-                        }
-                        {
-                            const int k = (lane - Xl) & Smask;
-                            const int tj = __shfl(j, k), tg = __shfl(g, k), tt = __shfl(t, k), ts = __shfl(seq, k);
-                            if (lane < S && k < nt) {
-                                f_j = tj;
-                                f_g = tg;
-                                f_t = tt;
-                                f_seq = ts;
-                            }
-                        }
-                        if (a.trace) {
-                            // the visits that update something (uniform routing also visits
-                            // workers holding no rating of the item)
-                            const uint64_t rec = __builtin_amdgcn_ballot_w64(lane < nt && g >= 0);
-                            const int nrec = __popcll(rec);
-                            int64_t base = 0;
-                            if (lane == 0 && nrec > 0)
-                                base = (int64_t)atomicAdd((unsigned long long *)a.trace_len, (unsigned long long)nrec);
-                            base = __shfl(base, 0);
-                            const int rank = __popcll(rec & ((1ull << lane) - 1ull));
-                            if (lane < nt && g >= 0 && base + rank < a.trace_cap) {
-                                int32_t *tr = a.trace + 4 * (base + rank);
-                                tr[0] = q;
-                                tr[1] = j;
-                                tr[2] = t;
-                                tr[3] = seq;
-                            }
-                        }
-                        head += nt;
-                        Xl += nt;
-                        wait_vm();    // the item vectors are in LDS
-                        wait_lgkm();  // and so are the slots' descriptions
-                        if (lane == 0) sync_store(&L.ctl[0], Xl);
-                        progress = true;
-                    } else if (room > 0) {
-                        ++misses;
-                    }
-                }
-            }
-            // 3. Done when every item has stopped moving and nothing is held.
+            bool progress = pass_on();
+            progress = take_over() || progress;
+            // Done when every item has stopped moving and nothing is held.
             if (Xr == Xl &&
                 (int64_t)__hip_atomic_load(a.parked, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.active)
                 break;
@@ -1395,6 +1521,13 @@ struct AsyncMemoryWave {
         }
         wait_vm();
         if (lane == 0) sync_store(&L.ctl[1], 1);  // compute waves: no more visits
+        // per-lane counts (violations) summed over the wave
+        unsigned long long vsum = viol;
+        for (int o = 32; o > 0; o >>= 1) vsum += __shfl_xor(vsum, o);
+        if (lane == 0) {
+            if (vsum) atomicAdd(a.counters + 0, vsum);
+            if (hops) atomicAdd(a.counters + 1, (unsigned long long)hops);
+        }
         if (a.wstats && lane == 0) {
             unsigned long long *ws = (unsigned long long *)(a.wstats + (int64_t)q * kWStatCount);
             atomicAdd(&ws[kWStatMemTotal], (unsigned long long)(tick(a.timing) - t_start));
@@ -1426,34 +1559,40 @@ __global__ __launch_bounds__(1024) void k_worker_async(TrainArgs a) {
 }
 
 // Seeding: the first worker of every item (sort key; p for an item without ratings) and the
-// payload of its queue entry.  Random permutation: the first holder of the item's visiting
-// order for epoch a.epoch0 (payload: that holder entry).  Uniform routing: a uniformly
-// random worker, the item's next move (payload: the item).
-__global__ void k_seed_first(TrainArgs a, int64_t n, uint32_t *key, uint32_t *val, int32_t *first) {
+// payload of its queue entry.  Random permutation: the holder at position 0 of the item's
+// visiting order for epoch a.epoch0 (payload: that holder entry).  Uniform routing: a
+// uniformly random worker, the item's next move (payload: the holder entry there, or the
+// item with kPassBit).
+__global__ void k_seed_first(TrainArgs a, int64_t n, uint32_t *key, uint32_t *val, uint32_t *first) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += stride) {
         val[j] = (uint32_t)j;
-        if (a.sched == 2) {
-            if (a.hoff[j + 1] > a.hoff[j]) {
-                const int mv = a.itep[j];
-                key[j] = (uint32_t)route_uniform(a.route_seed, (int)j, mv, a.p);
-                first[j] = (int32_t)j;
-                a.itep[j] = mv + 1;
-            } else {
-                key[j] = (uint32_t)a.p;
-                first[j] = -1;
-            }
-        } else {
-            const int64_t g = route_next(a, (int)j, a.epoch0, 0, false);
-            first[j] = (int32_t)g;
-            key[j] = g >= 0 ? (uint32_t)a.hold[g] : (uint32_t)a.p;
-            a.itep[j] = a.epoch0;
+        int4 st = *(const int4 *)(a.istate + 4 * j);
+        const int64_t hb = a.hoff[j], nh = a.hoff[j + 1] - hb;
+        if (nh <= 0) {
+            key[j] = (uint32_t)a.p;
+            first[j] = 0;
+            continue;
         }
+        if (a.sched == 2) {
+            const int dest = route_uniform(a.route_seed, (int)j, st.x, a.p);
+            const int g = a.hmap[(int64_t)dest * n + j];
+            key[j] = (uint32_t)dest;
+            first[j] = g >= 0 ? (uint32_t)g : (kPassBit | (uint32_t)j);
+            st.x += 1;
+        } else {
+            const int64_t g = hb + visit_rank(a.route_seed, (int)j, a.epoch0, (uint32_t)nh, 0u);
+            key[j] = (uint32_t)a.hold[g];
+            first[j] = (uint32_t)g;
+            st.x = a.epoch0;
+            st.y = 0;
+        }
+        *(int4 *)(a.istate + 4 * j) = st;
     }
 }
 
 __global__ void k_seed_write(TrainArgs a, int64_t n, const uint32_t *key_s, const uint32_t *val_s,
-                             const int32_t *first) {
+                             const uint32_t *first) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += stride) {
         const uint32_t q = key_s[i];
@@ -1465,7 +1604,7 @@ __global__ void k_seed_write(TrainArgs a, int64_t n, const uint32_t *key_s, cons
         }
         const uint32_t pos = (uint32_t)(i - lo);
         const int64_t qb = a.sched == 2 ? (int64_t)q * a.n : a.vbase[q];
-        a.queue[qb + pos] = ((uint64_t)(pos + 1u) << 32) | (uint32_t)first[val_s[i]];
+        a.queue[qb + pos] = ((uint64_t)(pos + 1u) << 32) | first[val_s[i]];
         atomicAdd(a.qtail + q, 1u);
     }
 }
@@ -1617,7 +1756,7 @@ hipError_t launch_train_async(const TrainArgs &a, const int64_t *vbase, void *sc
     const int64_t n = a.n;
     if (scratch_bytes < async_scratch_bytes(n, a.p)) return hipErrorInvalidValue;
     uint32_t *key = (uint32_t *)scratch, *val = key + n, *key_s = val + n, *val_s = key_s + n;
-    int32_t *first = (int32_t *)(val_s + n);
+    uint32_t *first = val_s + n;
     void *tmp = (void *)(((uintptr_t)(first + n) + 255) & ~(uintptr_t)255);
     size_t tmp_bytes = scratch_bytes - ((char *)tmp - (char *)scratch);
     hipError_t e;
@@ -1641,6 +1780,7 @@ __global__ void k_batch_reset(const TrainArgs *descs, int nprob) {
     const TrainArgs a = descs[b];
     if (threadIdx.x == 0) *a.abort_flag = 0u;
     if (threadIdx.x < 8) a.diag[threadIdx.x] = 0;
+    if (threadIdx.x < 2) a.counters[threadIdx.x] = 0ull;
     const int64_t nst = (int64_t)kWStatCount * a.p;
     for (int64_t i = threadIdx.x; i < nst; i += blockDim.x) a.wstats[i] = 0;
 }
