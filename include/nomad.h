@@ -58,12 +58,12 @@ typedef enum {
  *     ranked 0..nh-1 in ascending worker order) in the order rank = pi(0), pi(1), ...,
  *     pi(nh-1) of a keyed bijection pi of [0, nh): with b the bits of nh - 1, lo = b/2,
  *     key = lowbias32(lowbias32(r ^ j) ^ e*0x9E3779B9), x split into L = x >> lo and
- *     R = x mod 2^lo, four steps L ^= H(R, key), R ^= H(L, key + 0x632BE5AB),
- *     L ^= H(R, key + 0xC6579D56), R ^= H(L, key + 0x2983B501) (H(v, k) = lowbias32(v ^ k)
- *     reduced to the half's bits) map x to (L << lo) | R, repeated until the value is below
- *     nh; r = 0x6a09e667 ^ the two 32-bit halves of nomad_config.seed.  A fresh
- *     pseudo-random permutation every epoch, so every rating is updated once per epoch and
- *     t = epochs done.  At the start of a call every item is queued at its first worker
+ *     R = x mod 2^lo, eight steps, L ^= H(R, key + s*0x9E3779B9) then
+ *     R ^= H(L, key + (s+1)*0x9E3779B9) for s = 0, 2, 4, 6 (H(v, c) = lowbias32(v ^ c)
+ *     reduced to the half's bits; 32-bit arithmetic), map x to (L << lo) | R, repeated
+ *     until the value is below nh; r = 0x6a09e667 ^ the two 32-bit halves of
+ *     nomad_config.seed.  A fresh pseudo-random permutation every epoch, so every rating
+ *     is updated once per epoch and t = epochs done.  At the start of a call every item is queued at its first worker
  *     (each queue in ascending item order).  The serial order depends on timing
  *     (record_trace gives it); with one worker it is the ring order.  Not available in
  *     batches.
@@ -125,7 +125,8 @@ typedef struct {
 } nomad_config;
 
 typedef struct {
-    double seconds;        /* device time of the training kernel(s), HIP events */
+    double seconds;        /* device time of the training kernel launches of the call (HIP events
+                              around each launch; seeding kernels and resets excluded) */
     uint64_t updates;      /* SGD updates applied by the call */
     uint64_t epochs_done;  /* epochs completed since nomad_init */
     double layout_seconds; /* device time spent by nomad_init building the layout */

@@ -25,7 +25,7 @@ OK, EINVAL, ENOMEM, EDEADLOCK = 0, -1, -2, -3
 
 class Stats(C.Structure):
     _fields_ = [("updates", C.c_int64), ("visits", C.c_int64), ("violations", C.c_int64),
-                ("hops", C.c_int64)]
+                ("hops", C.c_int64), ("max_queue", C.c_int64)]
 
 
 def build(force: bool = True) -> str:
@@ -71,9 +71,11 @@ def _load():
         lib.orc_train_ring_gcount.restype = C.c_int
         lib.orc_train_ring_gcount.argtypes = common + [i64, i32, P, P, P]
         lib.orc_train_perm.restype = C.c_int
-        lib.orc_train_perm.argtypes = common + [i32, i32, u64, P, P, P, P, i64, P]
+        lib.orc_train_perm.argtypes = common + [i32, i32, u64, P, P, P, P, i64, P, i32]
         lib.orc_train_uniform.restype = C.c_int
-        lib.orc_train_uniform.argtypes = common + [i64, u64, P, P, P, P, P, i64, P]
+        lib.orc_train_uniform.argtypes = common + [i64, u64, P, P, P, P, P, i64, P, i32, i32, dbl, dbl]
+        lib.orc_balanced_pick.restype = i32
+        lib.orc_balanced_pick.argtypes = [i32, i64, i32, i64]
         lib.orc_train_threaded.restype = C.c_int
         lib.orc_train_threaded.argtypes = common + [i64, u64, P, P, P, P]
         lib.orc_replay.restype = C.c_int
@@ -210,9 +212,16 @@ def _trace_buf(cap):
     return np.zeros((max(int(cap), 1), 4), dtype=np.int32), C.c_int64()
 
 
-def train_perm(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, sched_seed, epoch0=0, trace=False):
+def balanced_pick(a: int, len_a: int, b: int, len_b: int) -> int:
+    """Section 3.3's load-balanced choice between two workers (a on a tie)."""
+    return int(_load().orc_balanced_pick(a, len_a, b, len_b))
+
+
+def train_perm(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, sched_seed, epoch0=0, trace=False,
+               balance=False):
     """Random-permutation circulation (discrete-event emulation).  Returns (W, H, stats),
-    plus the visit trace (rows: worker, item, t, visit number of the item) with trace=True."""
+    plus the visit trace (rows: worker, item, t, visit number of the item) with trace=True.
+    balance=True: section 3.3's dynamic load balancing of the next holder."""
     row, col, val = _coo(row, col, val)
     W = _factors(W0, m, hp.k)
     H = _factors(H0, n, hp.k)
@@ -221,7 +230,7 @@ def train_perm(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, sched_se
     buf, tlen = _trace_buf(cap)
     _check(_load().orc_train_perm(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha,
                                   hp.beta, hp.gamma, p, seed, epoch0, epochs, sched_seed, _p(W), _p(H),
-                                  C.byref(st), _p(buf) if trace else None, cap, C.byref(tlen)))
+                                  C.byref(st), _p(buf) if trace else None, cap, C.byref(tlen), int(bool(balance))))
     if trace:
         assert tlen.value <= cap
         return W, H, st, buf[:tlen.value].copy()
@@ -229,9 +238,13 @@ def train_perm(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, sched_se
 
 
 def train_uniform(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, max_updates, sched_seed,
-                  visit_count=None, trace=False, trace_cap=None):
+                  visit_count=None, trace=False, trace_cap=None, balance=False, timing=None):
     """Algorithm 1 with uniform recipients (discrete-event emulation).  Returns (W, H,
-    stats), plus the trace of the visits that update something with trace=True."""
+    stats), plus the trace of the visits that update something with trace=True.
+    balance=True: the recipient is the less loaded of two uniform draws (section 3.3).
+    timing=(slots, visit_cost, hop_time): turns follow time (workers serving `slots` items
+    at once, costs in units of one update) instead of a uniform draw."""
+    slots, vcost, hop = timing if timing is not None else (0, 0.0, 0.0)
     row, col, val = _coo(row, col, val)
     W = _factors(W0, m, hp.k)
     H = _factors(H0, n, hp.k)
@@ -244,7 +257,8 @@ def train_uniform(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, max_updates, 
     _check(_load().orc_train_uniform(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha,
                                      hp.beta, hp.gamma, p, seed, int(max_updates), sched_seed,
                                      _p(visit_count), _p(W), _p(H), C.byref(st),
-                                     _p(buf) if trace else None, cap, C.byref(tlen)))
+                                     _p(buf) if trace else None, cap, C.byref(tlen), int(bool(balance)),
+                                     int(slots), float(vcost), float(hop)))
     if trace:
         assert tlen.value <= cap
         return W, H, st, buf[:tlen.value].copy()

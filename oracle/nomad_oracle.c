@@ -32,9 +32,15 @@
  *                       and section 4.4).
  *   orc_train_perm   -- Algorithm 1 with the random-permutation circulation of section 3.4:
  *                       each item visits every worker holding its ratings once per epoch, in
- *                       uniformly random order, workers take turns at random.
+ *                       uniformly random order, workers take turns at random.  With
+ *                       balance = 1, section 3.3's dynamic load balancing: of two candidate
+ *                       holders not yet visited the one with the shorter queue comes next.
+ *   orc_balanced_pick -- that choice on its own: the less loaded of two candidates.
  *   orc_train_uniform -- Algorithm 1 literally: recipient uniform over all p workers, t is
  *                       the per-(worker,item) visit count, stop after a number of updates.
+ *                       With balance = 1 (section 3.3) the recipient is the less loaded of
+ *                       two workers drawn uniformly.  With slots > 0 the turns follow time
+ *                       instead of a uniform draw (see orc_train_uniform).
  *   orc_train_ring_gcount -- the ring order with t read as the global count of updates
  *                       applied before the visit (the alternative reading of t in the step
  *                       size of section 5.1).
@@ -72,6 +78,7 @@ typedef struct {
     int64_t visits;      /* (worker, item) visits that applied at least one update */
     int64_t violations;  /* updates whose row or item was not owned by the worker */
     int64_t hops;        /* item transfers between workers */
+    int64_t max_queue;   /* longest queue seen when an item was pushed (asynchronous emulations) */
 } orc_stats;
 
 /* ------------------------------------------------------------------------------- */
@@ -270,24 +277,27 @@ static int layout_build(layout *L, int64_t m, int64_t n, int64_t nnz, const int3
     return ORC_OK;
 }
 
-/* Progress report of long runs (off by default): a line on stderr every `every` updates. */
+/* Progress report of long runs (off by default): a line on stderr every `every` updates,
+ * counted over all runs in progress (several may run at once in different threads). */
 static int64_t g_progress_every = 0, g_progress_next = 0, g_progress_done = 0;
 
 void orc_set_progress(int64_t every)
 {
-    g_progress_every = every;
-    g_progress_next = every;
-    g_progress_done = 0;
+    __atomic_store_n(&g_progress_done, 0, __ATOMIC_RELAXED);
+    __atomic_store_n(&g_progress_next, every, __ATOMIC_RELAXED);
+    __atomic_store_n(&g_progress_every, every, __ATOMIC_RELAXED);
 }
 
 static void progress_add(int64_t updates)
 {
-    if (g_progress_every <= 0) return;
-    g_progress_done += updates;
-    if (g_progress_done >= g_progress_next) {
-        fprintf(stderr, "[oracle] %lld updates applied\n", (long long)g_progress_done);
+    const int64_t every = __atomic_load_n(&g_progress_every, __ATOMIC_RELAXED);
+    if (every <= 0) return;
+    const int64_t done = __atomic_add_fetch(&g_progress_done, updates, __ATOMIC_RELAXED);
+    int64_t next = __atomic_load_n(&g_progress_next, __ATOMIC_RELAXED);
+    if (done >= next && __atomic_compare_exchange_n(&g_progress_next, &next, done + every, 0, __ATOMIC_RELAXED,
+                                                    __ATOMIC_RELAXED)) {
+        fprintf(stderr, "[oracle] %lld updates applied\n", (long long)done);
         fflush(stderr);
-        g_progress_next = g_progress_done + g_progress_every;
     }
 }
 
@@ -586,6 +596,31 @@ static int32_t q_pop(queues *Q, int32_t q)
     return j;
 }
 
+/* Remove item j from worker q's queue (it is in it). */
+static void q_remove(queues *Q, int32_t q, int32_t j)
+{
+    if (Q->head[q] == j) { (void)q_pop(Q, q); return; }
+    int32_t prev = Q->head[q];
+    while (Q->next[prev] != j) prev = Q->next[prev];
+    Q->next[prev] = Q->next[j];
+    if (Q->tail[q] == j) Q->tail[q] = prev;
+}
+
+/* Queue length of worker q. */
+static int64_t q_len(const queues *Q, const int32_t *next, int32_t q)
+{
+    int64_t len = 0;
+    for (int32_t j = Q->head[q]; j >= 0; j = next[j]) ++len;
+    return len;
+}
+
+/* Section 3.3's dynamic load balancing reduced to one choice: of two candidate workers
+ * a (the first drawn) and b, the one whose queue holds fewer items; a on a tie. */
+int32_t orc_balanced_pick(int32_t a, int64_t len_a, int32_t b, int64_t len_b)
+{
+    return len_b < len_a ? b : a;
+}
+
 /* Index (into L->visits) of worker q's visit of item j, or -1 if q holds no rating of j. */
 static int64_t find_visit(const layout *L, int32_t j, int32_t q)
 {
@@ -615,7 +650,7 @@ int orc_train_perm(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const 
                    const float *val, int32_t k, double lambda, double alpha, double beta,
                    double gamma, int32_t p, uint64_t seed, int32_t epoch0, int32_t epochs,
                    uint64_t sched_seed, double *W, double *H, orc_stats *st,
-                   int32_t *trace, int64_t trace_cap, int64_t *trace_len)
+                   int32_t *trace, int64_t trace_cap, int64_t *trace_len, int32_t balance)
 {
     int rc = check_common(k, p, epochs);
     if (rc) return rc;
@@ -630,10 +665,12 @@ int orc_train_perm(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const 
     int32_t *holder = (int32_t *)malloc(sizeof(int32_t) * ((size_t)n + 1));
     int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * ((size_t)p + 1));
     int64_t *nvisits = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
-    if (queues_init(&Q, p, n) || !ep || !left || !seen || !holder || !cand || !nvisits) {
-        queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand); free(nvisits);
+    int64_t *carry = (int64_t *)malloc(sizeof(int64_t) * ((size_t)n + 1)); /* held-over candidate visit, -1 none */
+    if (queues_init(&Q, p, n) || !ep || !left || !seen || !holder || !cand || !nvisits || !carry) {
+        queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand); free(nvisits); free(carry);
         layout_free(&L); return ORC_ENOMEM;
     }
+    for (int64_t j = 0; j < n; ++j) carry[j] = -1;
     int64_t tlen = 0;
     uint64_t ctr = 0;
     for (int64_t j = 0; j < n; ++j) {
@@ -663,13 +700,36 @@ int orc_train_perm(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const 
         }
         int32_t nc = 0;
         for (int64_t x = L.istart[j]; x < L.istart[j + 1]; ++x)
-            if (!seen[L.ivis[x]]) cand[nc++] = L.ivis[x];
-        int32_t dst = L.visits[cand[orc_splitmix64(sched_seed + ctr++) % (uint64_t)nc]].q;
+            if (!seen[L.ivis[x]] && L.ivis[x] != carry[j]) cand[nc++] = L.ivis[x];
+        int32_t dst;
+        if (!balance) {
+            dst = L.visits[cand[orc_splitmix64(sched_seed + ctr++) % (uint64_t)nc]].q;
+        } else {
+            /* two candidates not yet visited: the held-over one (or, if none, a first random
+             * draw) and a random draw from the rest; the less loaded goes next, the other is
+             * held over for the next choice (with nothing else left, the held-over one goes) */
+            int64_t a = carry[j];
+            if (a < 0 && nc > 0) {
+                int32_t pick = (int32_t)(orc_splitmix64(sched_seed + ctr++) % (uint64_t)nc);
+                a = cand[pick];
+                cand[pick] = cand[--nc];
+            }
+            if (nc == 0) {
+                dst = L.visits[a].q;
+                carry[j] = -1;
+            } else {
+                int64_t b = cand[orc_splitmix64(sched_seed + ctr++) % (uint64_t)nc];
+                int32_t qa = L.visits[a].q, qb = L.visits[b].q;
+                dst = orc_balanced_pick(qa, q_len(&Q, Q.next, qa), qb, q_len(&Q, Q.next, qb));
+                carry[j] = dst == qa ? b : a;
+            }
+        }
         holder[j] = dst;
         if (st) st->hops++;
         q_push(&Q, dst, j);
+        if (st) { int64_t len = q_len(&Q, Q.next, dst); if (len > st->max_queue) st->max_queue = len; }
     }
-    queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand); free(nvisits);
+    queues_free(&Q); free(ep); free(left); free(seen); free(holder); free(cand); free(nvisits); free(carry);
     layout_free(&L);
     if (trace_len) *trace_len = tlen;
     return ORC_OK;
@@ -678,12 +738,23 @@ int orc_train_perm(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const 
 /* Algorithm 1 literally: recipient uniform over all p workers; t = number of earlier
  * updates of the (i, j) pair = earlier visits of item j to worker q (visit_count, p*n
  * entries, in/out, may carry over from an earlier call); stop once `max_updates`
- * updates were applied (checked after each visit). */
+ * updates were applied (checked after each visit).
+ *
+ * Whose turn it is: with slots = 0 a worker drawn uniformly among those with a non-empty
+ * queue.  With slots > 0, time decides, as it does for workers running in parallel: every
+ * worker serves `slots` items at once; a visit takes visit_cost plus one unit per rating
+ * it updates (units of one update) and the item reaches its next queue hop_time after the
+ * visit ends; a worker takes its items in the order they arrive, and the next visit is the
+ * one that can start first (the earliest time at which some worker has a free slot and an
+ * item that has arrived; the lower worker, then the lower item, on a tie).  Which ratings
+ * receive how many of the budget's updates depends on this: under the uniform draw a long
+ * visit costs a worker one turn like a short one. */
 int orc_train_uniform(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
                       const float *val, int32_t k, double lambda, double alpha, double beta,
                       double gamma, int32_t p, uint64_t seed, int64_t max_updates,
                       uint64_t sched_seed, int32_t *visit_count, double *W, double *H,
-                      orc_stats *st, int32_t *trace, int64_t trace_cap, int64_t *trace_len)
+                      orc_stats *st, int32_t *trace, int64_t trace_cap, int64_t *trace_len,
+                      int32_t balance, int32_t slots, double visit_cost, double hop_time)
 {
     int rc = check_common(k, p, 0);
     if (rc) return rc;
@@ -699,9 +770,39 @@ int orc_train_uniform(int64_t m, int64_t n, int64_t nnz, const int32_t *row, con
     int64_t applied = 0;
     if (max_updates > 0 && nnz > 0)
         for (int64_t j = 0; j < n; ++j) q_push(&Q, orc_owner0(seed, j, p), (int32_t)j);
+    double *slot_free = slots > 0 ? (double *)calloc((size_t)p * (size_t)slots, sizeof(double)) : NULL;
+    double *arrive = slots > 0 ? (double *)calloc((size_t)n + 1, sizeof(double)) : NULL;
+    if (slots > 0 && (!slot_free || !arrive)) {
+        free(slot_free); free(arrive); queues_free(&Q); free(nvisits); layout_free(&L); return ORC_ENOMEM;
+    }
     while (applied < max_updates && Q.nne > 0) {
-        int32_t q = Q.ne[orc_splitmix64(sched_seed + ctr++) % (uint64_t)Q.nne];
-        int32_t j = q_pop(&Q, q);
+        int32_t q, j;
+        if (slots <= 0) {
+            q = Q.ne[orc_splitmix64(sched_seed + ctr++) % (uint64_t)Q.nne];
+            j = q_pop(&Q, q);
+        } else {
+            double best = 0.0;
+            int32_t best_slot = 0, best_j = -1;
+            q = -1;
+            for (int32_t x = 0; x < Q.nne; ++x) {
+                int32_t qq = Q.ne[x], fs = 0, first = Q.head[qq];
+                for (int32_t s2 = 1; s2 < slots; ++s2)
+                    if (slot_free[(int64_t)qq * slots + s2] < slot_free[(int64_t)qq * slots + fs]) fs = s2;
+                for (int32_t jj = Q.next[first]; jj >= 0; jj = Q.next[jj])
+                    if (arrive[jj] < arrive[first] || (arrive[jj] == arrive[first] && jj < first)) first = jj;
+                double ready = slot_free[(int64_t)qq * slots + fs];
+                if (arrive[first] > ready) ready = arrive[first];
+                if (q < 0 || ready < best || (ready == best && qq < q)) {
+                    best = ready; q = qq; best_slot = fs; best_j = first;
+                }
+            }
+            j = best_j;
+            q_remove(&Q, q, j);
+            int64_t v0 = find_visit(&L, j, q);
+            double end = best + visit_cost + (v0 >= 0 ? (double)(L.visits[v0].end - L.visits[v0].begin) : 0.0);
+            slot_free[(int64_t)q * slots + best_slot] = end;
+            arrive[j] = end + hop_time;
+        }
         int64_t vi = find_visit(&L, j, q);
         if (vi >= 0) {
             int32_t *t = &visit_count[(int64_t)q * n + j];
@@ -711,11 +812,18 @@ int orc_train_uniform(int64_t m, int64_t n, int64_t nnz, const int32_t *row, con
             (*t)++;
         }
         int32_t dst = (int32_t)(orc_splitmix64(sched_seed + ctr++) % (uint64_t)p);
+        if (balance) {
+            int32_t d2 = (int32_t)(orc_splitmix64(sched_seed + ctr++) % (uint64_t)p);
+            dst = orc_balanced_pick(dst, q_len(&Q, Q.next, dst), d2, q_len(&Q, Q.next, d2));
+        }
         if (st) st->hops++;
         q_push(&Q, dst, j);
+        if (st) { int64_t len = q_len(&Q, Q.next, dst); if (len > st->max_queue) st->max_queue = len; }
     }
     queues_free(&Q);
     free(nvisits);
+    free(slot_free);
+    free(arrive);
     layout_free(&L);
     if (trace_len) *trace_len = tlen;
     return ORC_OK;

@@ -38,6 +38,7 @@ struct nomad_ctx {
     void *eval_scratch = nullptr;
     size_t eval_scratch_bytes = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> lev;       // around each training launch of a call (pairs)
     double layout_seconds = 0.0;
     std::string err;
     // Asynchronous schedule: inbound queues, item state, seeding scratch.
@@ -128,6 +129,8 @@ void release(nomad_ctx *c) {
     (void)hipFree(c->eval_scratch);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (hipEvent_t ev : c->lev) (void)hipEventDestroy(ev);
+    c->lev.clear();
 }
 
 // Launch shape: compute waves, item slots and row window of a worker (LDS-fitted as the
@@ -595,7 +598,6 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         HIPTRY(c, hipMemsetAsync(c->diag, 0, sizeof(int32_t) * 8, st), "train: reset");
         HIPTRY(c, hipMemsetAsync(c->wstats, 0, sizeof(int64_t) * nomad::kWStatCount * (size_t)c->p, st), "train: reset");
         HIPTRY(c, hipMemsetAsync(c->counters, 0, sizeof(unsigned long long) * 2, st), "train: reset");
-        HIPTRY(c, hipEventRecord(c->ev0, st), "train: event");
         const bool async = c->cfg.sched == NOMAD_SCHED_PERM || c->cfg.sched == NOMAD_SCHED_UNIFORM;
         const bool uniform = c->cfg.sched == NOMAD_SCHED_UNIFORM;
         if (async) {
@@ -620,19 +622,31 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
         if (uniform) HIPTRY(c, hipMemsetAsync(c->upd, 0, sizeof(unsigned long long), st), "train: reset");
         // Launches of at most kMaxEpochsPerLaunch epochs (one launch per call for uniform
         // routing, which stops on its update budget instead).
+        // Each training launch is timed on its own (the seeding kernels and resets of the
+        // asynchronous schedules are not part of it).
+        int32_t launches = 0;
         for (int32_t done = 0; done < epochs;) {
             const int32_t ne = uniform ? epochs : std::min(epochs - done, (int32_t)nomad::kMaxEpochsPerLaunch);
             a.epoch0 = (int32_t)(c->epochs_done + done);
             a.epochs = ne;
+            while ((int32_t)c->lev.size() < 2 * (launches + 1)) {
+                hipEvent_t ev = nullptr;
+                HIPTRY(c, hipEventCreate(&ev), "train: event");
+                c->lev.push_back(ev);
+            }
             if (async) {
                 HIPTRY(c, hipMemsetAsync(c->queue, 0, sizeof(uint64_t) * (size_t)c->queue_len, st), "train: reset");
                 HIPTRY(c, hipMemsetAsync(c->qtail, 0, sizeof(uint32_t) * (size_t)c->p, st), "train: reset");
                 HIPTRY(c, hipMemsetAsync(c->parked, 0, sizeof(uint32_t), st), "train: reset");
-                HIPTRY(c, nomad::launch_train_async(a, c->plan.vbase, c->async_scratch, c->async_scratch_bytes, st),
-                       "train: launch");
+                HIPTRY(c, nomad::seed_train_async(a, c->async_scratch, c->async_scratch_bytes, st), "train: seeding");
+                HIPTRY(c, hipEventRecord(c->lev[2 * launches], st), "train: event");
+                HIPTRY(c, nomad::launch_train_async(a, st), "train: launch");
             } else {
+                HIPTRY(c, hipEventRecord(c->lev[2 * launches], st), "train: event");
                 HIPTRY(c, nomad::launch_train(a, st), "train: launch");
             }
+            HIPTRY(c, hipEventRecord(c->lev[2 * launches + 1], st), "train: event");
+            ++launches;
             done += ne;
             if (done < epochs) {
                 // a launch that stopped early ends the call: the next one would wait again
@@ -640,11 +654,12 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
                 if (ab != NOMAD_OK) return ab;
             }
         }
-        HIPTRY(c, hipEventRecord(c->ev1, st), "train: event");
-        HIPTRY(c, hipEventSynchronize(c->ev1), "train: kernel");
-        float ms = 0.0f;
-        HIPTRY(c, hipEventElapsedTime(&ms, c->ev0, c->ev1), "train: timing");
-        seconds = ms * 1e-3;
+        HIPTRY(c, hipEventSynchronize(c->lev[2 * launches - 1]), "train: kernel");
+        for (int32_t l = 0; l < launches; ++l) {
+            float ms = 0.0f;
+            HIPTRY(c, hipEventElapsedTime(&ms, c->lev[2 * l], c->lev[2 * l + 1]), "train: timing");
+            seconds += ms * 1e-3;
+        }
         {
             const nomad_status ab = check_abort(c, "nomad_train_epochs");
             if (ab != NOMAD_OK) return ab;

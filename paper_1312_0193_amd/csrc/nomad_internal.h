@@ -208,10 +208,10 @@ hipError_t build_holder_map(Plan *plan, hipStream_t stream);
 size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes);
 hipError_t launch_train(const TrainArgs &a, hipStream_t stream);
 // Asynchronous schedules: queue every item at the first worker of its visiting order for
-// epoch a.epoch0 (each worker's queue in ascending item order), then run the launch.
-// Scratch: 3 n + (p + 1) words at `scratch` plus the sort's temporary storage.
-hipError_t launch_train_async(const TrainArgs &a, const int64_t *vbase, void *scratch, size_t scratch_bytes,
-                              hipStream_t stream);
+// epoch a.epoch0 (each worker's queue in ascending item order); scratch: 5 n words at
+// `scratch` plus the sort's temporary storage.  Then run the launch.
+hipError_t seed_train_async(const TrainArgs &a, void *scratch, size_t scratch_bytes, hipStream_t stream);
+hipError_t launch_train_async(const TrainArgs &a, hipStream_t stream);
 size_t async_scratch_bytes(int64_t n, int32_t p);
 // Several problems in one launch: d_descs[b] describes problem b (its wg0 = first
 // workgroup), d_wg_prob[g] = the problem of workgroup g; `shape` gives the launch shape

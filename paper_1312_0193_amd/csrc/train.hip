@@ -979,11 +979,15 @@ struct MemoryWave {
 // rating is updated once per epoch and t = e.
 
 // Position -> holder rank of item j's visiting order in epoch e: a keyed bijection of
-// [0, nh).  Four alternating half-steps of a Feistel network (each xors one half of the
+// [0, nh).  Eight alternating half-steps of a Feistel network (each xors one half of the
 // bits with a hash of the other half, so each is invertible) permute [0, 2^b), 2^b >= nh
 // the smallest such power of two; values outside [0, nh) are mapped again until one falls
 // inside (cycle walking), which keeps the map a bijection of [0, nh).  Fewer than two
-// passes are needed on average, and the cost does not grow with nh.
+// passes are needed on average, and the cost does not grow with nh.  Halves are only a few
+// bits wide here (three for 64 holders), and with four half-steps the orders showed it:
+// consecutive ranks followed each other about 25% more often than in a uniform
+// permutation at 256 holders, many times more at 64; with eight the frequencies of
+// consecutive-rank gaps and of rank positions are those of uniform permutations.
 __device__ __forceinline__ uint32_t visit_rank(uint32_t seed, int j, int e, uint32_t nh, uint32_t x) {
     if (nh <= 1u) return 0u;
     const int b = 32 - __builtin_clz(nh - 1u);
@@ -992,10 +996,11 @@ __device__ __forceinline__ uint32_t visit_rank(uint32_t seed, int j, int e, uint
     const uint32_t key = lowbias32(lowbias32(seed ^ (uint32_t)j) ^ ((uint32_t)e * 0x9E3779B9u));
     do {
         uint32_t L = x >> lo, R = x & mlo;
-        L ^= lowbias32(R ^ key) & mhi;
-        R ^= lowbias32(L ^ (key + 0x632BE5ABu)) & mlo;
-        L ^= lowbias32(R ^ (key + 0xC6579D56u)) & mhi;
-        R ^= lowbias32(L ^ (key + 0x2983B501u)) & mlo;
+#pragma unroll
+        for (uint32_t r = 0; r < 8u; r += 2u) {
+            L ^= lowbias32(R ^ (key + r * 0x9E3779B9u)) & mhi;
+            R ^= lowbias32(L ^ (key + (r + 1u) * 0x9E3779B9u)) & mlo;
+        }
         x = (L << lo) | R;
     } while (x >= nh);
     return x;
@@ -1116,6 +1121,7 @@ struct AsyncComputeWave {
     }
 
     __device__ void run() {
+        const uint64_t t_start = tick(a.timing);
         const int32_t *word = w == 0 ? &L.ctl[0] : &L.flag[w - 1];
         // The first records of a later visit, loaded while this one is updated: `pre` holds
         // them (lane l: record l) for visit pre_X.
@@ -1223,6 +1229,9 @@ struct AsyncComputeWave {
         if (viol && lane == 0) atomicAdd(a.counters + 0, (unsigned long long)viol);
         if (a.wstats && lane == 0) {
             unsigned long long *ws = (unsigned long long *)(a.wstats + (int64_t)q * kWStatCount);
+            const uint64_t tot = tick(a.timing) - t_start;
+            atomicAdd(&ws[kWStatCompTotal], (unsigned long long)tot);
+            atomicMax(&ws[kWStatCompMax], (unsigned long long)tot);
             atomicAdd(&ws[kWStatItemWait], (unsigned long long)t_wait);
             atomicAdd(&ws[kWStatRatings], (unsigned long long)nrat);
         }
@@ -1750,9 +1759,7 @@ size_t async_scratch_bytes(int64_t n, int32_t p) {
     return (size_t)(5 * (n > 0 ? n : 1)) * 4 + sort_bytes + 256;
 }
 
-hipError_t launch_train_async(const TrainArgs &a, const int64_t *vbase, void *scratch, size_t scratch_bytes,
-                              hipStream_t st) {
-    (void)vbase;
+hipError_t seed_train_async(const TrainArgs &a, void *scratch, size_t scratch_bytes, hipStream_t st) {
     const int64_t n = a.n;
     if (scratch_bytes < async_scratch_bytes(n, a.p)) return hipErrorInvalidValue;
     uint32_t *key = (uint32_t *)scratch, *val = key + n, *key_s = val + n, *val_s = key_s + n;
@@ -1767,9 +1774,10 @@ hipError_t launch_train_async(const TrainArgs &a, const int64_t *vbase, void *sc
         hipSuccess)
         return e;
     hipLaunchKernelGGL(k_seed_write, dim3(grid > 0 ? grid : 1), dim3(256), 0, st, a, n, key_s, val_s, first);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_async_b(a, st);
+    return hipGetLastError();
 }
+
+hipError_t launch_train_async(const TrainArgs &a, hipStream_t st) { return launch_async_b(a, st); }
 
 namespace {
 // Per-launch resets of a batch's problems: block b clears problem b's abort word, its

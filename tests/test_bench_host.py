@@ -12,10 +12,20 @@ import bench  # noqa: E402
 
 
 def test_bytes_per_update_of_the_medium_workload():
-    # 12-byte entry + 2 x 400 B for w_i + 2 x 400 B x 17,770 columns x 256 workers / 98.6 M
-    assert bench.bytes_per_update(100, 4, 4, 17_770, 98_600_000) == pytest.approx(848.91, abs=0.01)
+    # 12-byte entry + 2 x 400 B for w_i + 2 x 400 B per (worker, item) visit: with every one
+    # of 17,770 items visiting all 256 workers, 2 x 400 x 4,549,120 / 98.6 M
+    assert bench.bytes_per_update(100, 4, 4, 17_770 * 256, 98_600_000) == pytest.approx(848.91, abs=0.01)
     # BF16 w_i halves the row term only
-    assert bench.bytes_per_update(100, 2, 4, 17_770, 98_600_000) == pytest.approx(448.91, abs=0.01)
+    assert bench.bytes_per_update(100, 2, 4, 17_770 * 256, 98_600_000) == pytest.approx(448.91, abs=0.01)
+
+
+def test_visits_per_epoch_counts_worker_item_pairs():
+    import torch
+
+    row = torch.tensor([0, 1, 2, 3, 4, 5, 5], dtype=torch.int32)
+    col = torch.tensor([0, 0, 1, 1, 1, 2, 0], dtype=torch.int32)
+    # workers own rows [0,2), [2,4), [4,6): pairs (0,0) (1,1) (2,1) (2,2) (2,0)
+    assert bench.visits_per_epoch(row, col, 3, [0, 2, 4, 6]) == 5
 
 
 @pytest.mark.parametrize("sched", ["perm", "uniform", "ring"])

@@ -12,6 +12,7 @@ import torch
 import oracle
 import paper_1312_0193_amd as nm
 import synth
+from parity import check, max_updates
 
 pytestmark = pytest.mark.gpu
 
@@ -71,12 +72,60 @@ def test_batch_matches_problems_alone_and_oracle():
         hp = oracle.Hyper(p["k"], f32(p["lam"]), f32(p["alpha"]), f32(p["beta"]), f32(p["gamma"]))
         Wo, Ho, _ = oracle.train_ring(p["m"], p["n"], p["row"].numpy(), p["col"].numpy(), p["val"].numpy(),
                                       p["W0"].numpy(), p["H0"].numpy(), hp, workers[b], 3, 1)
-        assert rel(Wb, Wo) < TOL_1EPOCH and rel(Hb, Ho) < TOL_1EPOCH, (b, rel(Wb, Wo), rel(Hb, Ho))
+        T = max_updates(p["row"].numpy(), p["col"].numpy(), 1)
+        check(Wb, Wo, norm_tol=TOL_1EPOCH, updates=T, what=f"problem {b} W")
+        check(Hb, Ho, norm_tol=TOL_1EPOCH, updates=T, what=f"problem {b} H")
         # evaluation through the problem's view
         pr = p["prob"]
         r_gpu, _ = view.evaluate(pr.test_row, pr.test_col, pr.test_val)
         r_orc = oracle.rmse(p["m"], p["n"], pr.test_row.numpy(), pr.test_col.numpy(), pr.test_val.numpy(), Wb, Hb)
         assert abs(r_gpu - r_orc) <= 1e-12 * max(1.0, r_orc)
+    batch.close()
+
+
+@pytest.mark.timeout(900)
+def test_batched_workload_256_problems():
+    """The batched configuration itself: 256 problems with log-uniform sizes (rows 1k-200k,
+    columns 500-20k, 50k-5M ratings), k in {16, 32, 64} and lambda in {0.01, 0.05, 0.1},
+    one launch per epoch.  For a sample of problems (the largest, the smallest and four
+    more) the factors after one epoch are bitwise those of the problem trained alone with
+    the same worker count, and within the ring tolerance of the oracle."""
+    specs = synth.batched_specs(256, seed=4)
+    print("[case] batched workload: generating 256 problems on the GPU", flush=True)
+    probs = []
+    for s in specs:
+        pr = synth.batched_problem(s, device="cuda")
+        W0, H0 = synth.init_factors(s["m"], s["n"], s["k"], s["seed"], device="cuda")
+        probs.append(dict(m=s["m"], n=s["n"], row=pr.row, col=pr.col, val=pr.val, W0=W0, H0=H0, k=s["k"],
+                          lam=s["lam"], alpha=s["alpha"], beta=s["beta"], gamma=s["gamma"]))
+    total = sum(int(p["row"].numel()) for p in probs)
+    print(f"[case] batch of 256 problems, {total} ratings: layout", flush=True)
+    batch = nm.NomadBatch(probs, seed=4)
+    st = batch.train(1)
+    assert st.updates == total
+    workers = [v.workers for v in batch.problems]
+    print(f"[case] one epoch {st.seconds * 1e3:.1f} ms, {sum(workers)} workers", flush=True)
+    nnz = np.array([int(p["row"].numel()) for p in probs])
+    rng = np.random.default_rng(0)
+    sample = [int(np.argmax(nnz)), int(np.argmin(nnz))] + [int(x) for x in rng.choice(256, 4, replace=False)]
+    for b in sample:
+        p = probs[b]
+        print(f"[case] problem {b}: {p['m']} x {p['n']}, {nnz[b]} ratings, k={p['k']}, {workers[b]} workers",
+              flush=True)
+        Wb, Hb = (x.cpu().double().numpy() for x in batch.problems[b].factors())
+        alone = nm.Nomad(p["m"], p["n"], p["row"], p["col"], p["val"], p["W0"], p["H0"], k=p["k"], lam=p["lam"],
+                         alpha=p["alpha"], beta=p["beta"], gamma=p["gamma"], workers=workers[b], seed=4)
+        alone.train(1)
+        Wa, Ha = (x.cpu().double().numpy() for x in alone.factors())
+        alone.close()
+        assert np.array_equal(Wa, Wb) and np.array_equal(Ha, Hb), b
+        hp = oracle.Hyper(p["k"], f32(p["lam"]), f32(p["alpha"]), f32(p["beta"]), f32(p["gamma"]))
+        row, col, val = (x.cpu().numpy() for x in (p["row"], p["col"], p["val"]))
+        Wo, Ho, _ = oracle.train_ring(p["m"], p["n"], row, col, val, p["W0"].cpu().numpy(), p["H0"].cpu().numpy(),
+                                      hp, workers[b], 4, 1)
+        T = max_updates(row, col, 1)
+        check(Wb, Wo, norm_tol=TOL_1EPOCH, updates=T, what=f"problem {b} W")
+        check(Hb, Ho, norm_tol=TOL_1EPOCH, updates=T, what=f"problem {b} H")
     batch.close()
 
 

@@ -13,17 +13,13 @@ import pytest
 import oracle
 import paper_1312_0193_amd as nm
 import synth
+from parity import check, max_updates
 
 pytestmark = pytest.mark.gpu
 
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-
-
-def max_elem(a, b):
-    """max |a - b| / (|b| + 1e-3) over all elements."""
-    return float(np.max(np.abs(a - b) / (np.abs(b) + 1e-3)))
 
 
 def make(m, n, nnz, *, k, seed, degrees="uniform", lam=0.05, alpha=0.01, beta=1e-4, gamma=1.0):
@@ -97,7 +93,9 @@ def test_ring_global_update_count_matches_oracle():
     model.close()
     Wo, Ho, _ = oracle.train_ring_gcount(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(),
                                          W0.numpy(), H0.numpy(), hp, P, seed, 3)
-    assert rel(W, Wo) < 3e-5 and rel(H, Ho) < 3e-5, (rel(W, Wo), rel(H, Ho))
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), 3)
+    check(W, Wo, norm_tol=3e-5, updates=T, what="W")
+    check(H, Ho, norm_tol=3e-5, updates=T, what="H")
     # the step falls with the global count: different from the per-pair reading
     Wp, Hp, _ = oracle.train_ring(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(),
                                   W0.numpy(), H0.numpy(), hp, P, seed, 3)
@@ -132,5 +130,6 @@ def test_async_global_update_count_replays(sched):
     t2 = tr[order]
     Wr, Hr, _ = oracle.replay(prob.m, prob.n, row, col, prob.val.numpy(), W0.numpy(), H0.numpy(), hp, P, seed,
                               t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
-    assert rel(W, Wr) < 2e-5 and rel(H, Hr) < 2e-5, (rel(W, Wr), rel(H, Hr))
-    assert max_elem(W, Wr) < 1e-3 and max_elem(H, Hr) < 1e-3
+    T = max_updates(row, col, 2 * E)
+    check(W, Wr, norm_tol=2e-5, updates=T, what="W")
+    check(H, Hr, norm_tol=2e-5, updates=T, what="H")

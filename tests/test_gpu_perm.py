@@ -7,8 +7,20 @@ Its serial order depends on timing, so parity is checked three ways:
     the FP32 tolerance, and the trace shows every item visiting every worker that holds
     its ratings exactly once per epoch;
   * exactly, with one worker, where the schedule is the ring order;
-  * statistically, against the oracle's own asynchronous emulation: test RMSE after
-    several epochs agrees within 1e-3 relative.
+  * statistically, against the oracle's own asynchronous emulation: on the tiny workload,
+    after 100 epochs (the model has learned: test RMSE near 0.30 against 0.99 for the zero
+    predictor, and still falling by about 2e-3 per epoch), test RMSE agrees within 1e-3
+    absolute, the criterion of the asynchronous mode; the oracle's emulations with
+    different scheduler seeds spread by about 1.3e-4 (random permutation) and 5e-4 (uniform
+    routing) there.  Under uniform routing which ratings receive how many of the call's
+    updates depends on how fast visits complete (items are not bound to once per epoch):
+    after 100 epochs, emulations that take turns by time land between 0.3087 (one to four
+    items served at once per worker) and 0.3114 (64 at once, no cost per visit or hop), so
+    one timing cannot stand for the device.  The GPU's uniform routing is therefore held
+    within 1e-3 of the band those emulations span (uniform turns; turns by time with 64, 16,
+    4 or 1 items served at once per worker, a visit's start-up worth 1 to 50 updates and a
+    hand-off 0 to 500); lost updates move the RMSE by far more (about 2e-3 per epoch's
+    worth here).
 """
 import numpy as np
 import pytest
@@ -17,6 +29,7 @@ import torch
 import oracle
 import paper_1312_0193_amd as nm
 import synth
+from parity import check, max_updates
 
 pytestmark = pytest.mark.gpu
 
@@ -85,7 +98,9 @@ def test_perm_trace_covers_every_visit_once_per_epoch_and_replays(case):
     t2 = tr[order]
     Wr, Hr, _ = oracle.replay(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
                               H0.numpy(), hp, P, seed, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
-    assert rel(W, Wr) < 2 * TOL_1EPOCH and rel(H, Hr) < 2 * TOL_1EPOCH, (rel(W, Wr), rel(H, Hr))
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), E)
+    check(W, Wr, norm_tol=2 * TOL_1EPOCH, updates=T, what="W")
+    check(H, Hr, norm_tol=2 * TOL_1EPOCH, updates=T, what="H")
 
 
 def test_perm_visiting_orders_differ_between_epochs():
@@ -129,25 +144,44 @@ def test_perm_many_epochs_across_launches():
     t2 = tr[order]
     Wr, Hr, _ = oracle.replay(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
                               H0.numpy(), hp, 8, 4, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
-    assert rel(W, Wr) < 1e-4 and rel(H, Hr) < 1e-4
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), 66)
+    check(W, Wr, norm_tol=1e-4, updates=T, what="W")
+    check(H, Hr, norm_tol=1e-4, updates=T, what="H")
 
 
-def test_perm_rmse_matches_oracle_emulation():
-    """Statistical parity with the oracle's asynchronous emulation (its own random
-    interleaving and routing) on the tiny workload after 10 epochs."""
+RMSE_EPOCHS = 100   # tiny workload: learned, still moving
+RMSE_TOL = 1e-3     # absolute, the asynchronous-mode criterion
+# timings of the uniform-routing emulations: None = uniform turns; else (items served at once
+# per worker, a visit's start-up and a hand-off in units of one update)
+UNIFORM_TIMINGS = (None, (64, 1.0, 0.0), (64, 5.0, 45.0), (64, 50.0, 100.0), (16, 25.0, 45.0), (4, 5.0, 45.0),
+                   (1, 50.0, 500.0))
+
+
+def tiny_setup():
     prob = synth.tiny()
     hpd = prob.hp
     W0, H0 = synth.init_factors(prob.m, prob.n, hpd["k"], 1)
     f = lambda x: float(np.float32(x))  # noqa: E731
     hp = oracle.Hyper(hpd["k"], f(hpd["lam"]), f(hpd["alpha"]), f(hpd["beta"]), f(hpd["gamma"]))
-    P, E = 16, 10
+    zero = float(np.sqrt(np.mean(prob.test_val.numpy().astype(np.float64) ** 2)))
+    return prob, W0, H0, hp, zero
+
+
+def test_perm_rmse_matches_oracle_emulation():
+    """Statistical parity with the oracle's asynchronous emulation (its own random
+    interleaving and routing) on the tiny workload at a learned point."""
+    prob, W0, H0, hp, zero = tiny_setup()
+    P, E = 16, RMSE_EPOCHS
     model, W, H = run(prob, W0, H0, hp, P, 1, [E])
     r_gpu, _ = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
     model.close()
     Wo, Ho, _ = oracle.train_perm(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
                                   H0.numpy(), hp, P, 1, E, 77)
     r_orc = oracle.rmse(prob.m, prob.n, prob.test_row.numpy(), prob.test_col.numpy(), prob.test_val.numpy(), Wo, Ho)
-    assert abs(r_gpu - r_orc) < 1e-3 * r_orc, (r_gpu, r_orc)
+    print(f"[parity] perm test RMSE after {E} epochs: gpu {r_gpu:.6f}, oracle emulation {r_orc:.6f}, "
+          f"zero predictor {zero:.6f}", flush=True)
+    assert r_orc < 0.45 * zero  # a learned point: the check can fail
+    assert abs(r_gpu - r_orc) < RMSE_TOL, (r_gpu, r_orc)
 
 
 # ---------------------------------------------------------------------------------------
@@ -182,26 +216,31 @@ def test_uniform_trace_replays_and_counts_updates():
     t2 = tr[order]
     Wr, Hr, _ = oracle.replay(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
                               H0.numpy(), hp, P, seed, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
-    assert rel(W, Wr) < 2e-5 and rel(H, Hr) < 2e-5, (rel(W, Wr), rel(H, Hr))
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), 2 * E)  # uniform routing: up to twice as many
+    check(W, Wr, norm_tol=2e-5, updates=T, what="W")
+    check(H, Hr, norm_tol=2e-5, updates=T, what="H")
 
 
 def test_uniform_rmse_matches_oracle_emulation():
-    prob = synth.tiny()
-    hpd = prob.hp
-    W0, H0 = synth.init_factors(prob.m, prob.n, hpd["k"], 1)
-    f = lambda x: float(np.float32(x))  # noqa: E731
-    hp = oracle.Hyper(hpd["k"], f(hpd["lam"]), f(hpd["alpha"]), f(hpd["beta"]), f(hpd["gamma"]))
-    P, E = 16, 10
+    prob, W0, H0, hp, zero = tiny_setup()
+    P, E = 16, RMSE_EPOCHS
     print("[case] uniform routing, tiny workload", flush=True)
     model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
                      beta=hp.beta, gamma=hp.gamma, workers=P, seed=1, sched="uniform")
     st = model.train(E)
     r_gpu, _ = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
     model.close()
-    Wo, Ho, _ = oracle.train_uniform(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(),
-                                     W0.numpy(), H0.numpy(), hp, P, 1, st.updates, 77)
-    r_orc = oracle.rmse(prob.m, prob.n, prob.test_row.numpy(), prob.test_col.numpy(), prob.test_val.numpy(), Wo, Ho)
-    assert abs(r_gpu - r_orc) < 2e-3 * r_orc, (r_gpu, r_orc)
+    band = []
+    for timing in UNIFORM_TIMINGS:
+        Wo, Ho, _ = oracle.train_uniform(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(),
+                                         W0.numpy(), H0.numpy(), hp, P, 1, st.updates, 77, timing=timing)
+        band.append(oracle.rmse(prob.m, prob.n, prob.test_row.numpy(), prob.test_col.numpy(), prob.test_val.numpy(),
+                                Wo, Ho))
+    lo, hi = min(band), max(band)
+    print(f"[parity] uniform test RMSE after {st.updates} updates: gpu {r_gpu:.6f}, oracle emulations "
+          f"[{lo:.6f}, {hi:.6f}], zero predictor {zero:.6f}", flush=True)
+    assert hi < 0.45 * zero
+    assert lo - RMSE_TOL < r_gpu < hi + RMSE_TOL, (r_gpu, band)
 
 
 def test_uniform_continues_per_pair_counts_across_calls():
@@ -278,7 +317,9 @@ def test_async_more_workers_than_items(sched):
     t2 = tr[order]
     Wr, Hr, _ = oracle.replay(prob.m, prob.n, prob.row.numpy(), prob.col.numpy(), prob.val.numpy(), W0.numpy(),
                               H0.numpy(), hp, P, seed, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
-    assert rel(W, Wr) < 2e-5 and rel(H, Hr) < 2e-5, (rel(W, Wr), rel(H, Hr))
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), 2 * E)
+    check(W, Wr, norm_tol=2e-5, updates=T, what="W")
+    check(H, Hr, norm_tol=2e-5, updates=T, what="H")
 
 
 @pytest.mark.parametrize("sched", ["perm", "uniform"])
@@ -299,3 +340,33 @@ def test_async_bf16_rmse_close_to_fp32(sched):
         out[dt], _ = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
         model.close()
     assert abs(out["bf16"] - out["fp32"]) < 1e-2 * out["fp32"], out
+
+
+def test_perm_visiting_orders_are_uniform_permutations():
+    """Each item's visiting order in an epoch is to be a uniformly random permutation of its
+    holders (section 3.4 draws the next holder uniformly from those not yet visited).  From
+    the trace of 2,000 items over 4 epochs, each visiting all 64 workers: how often each
+    rank stands at each position (64 x 64 cells, about 125 each) and how often each gap
+    between consecutive ranks (mod 64; 63 values, about 8,000 each) occurs are compared
+    with the uniform counts by chi-squared per degree of freedom.  For uniform permutations
+    both are 1 +- 0.02 and 1 +- 0.18; an order whose consecutive ranks follow each other
+    too often (a weak mixing of the rank bits) gives several times that."""
+    P, E = 64, 4
+    prob, W0, H0, hp = make(6_400, 2_000, 3_400_000, k=8, seed=17)
+    model, _, _ = run(prob, W0, H0, hp, P, 21, [E], record_trace=True)
+    tr = model.trace()
+    model.close()
+    vis = holders(prob, P)
+    assert len(vis) == P * prob.n  # every item has ratings on every worker here
+    tr = tr[np.lexsort((tr[:, 3], tr[:, 1]))]  # by item, then visit number
+    ranks = tr[:, 0].reshape(prob.n * E, P)  # worker = rank when every worker is a holder
+    assert np.array_equal(np.sort(ranks, axis=1), np.broadcast_to(np.arange(P), ranks.shape))
+    pos = np.zeros((P, P))
+    np.add.at(pos, (np.broadcast_to(np.arange(P), ranks.shape), ranks), 1)
+    gap = np.bincount(((ranks[:, 1:] - ranks[:, :-1]) % P).ravel(), minlength=P)[1:]
+    chi_pos = float(((pos - pos.mean()) ** 2 / pos.mean()).sum() / (P - 1) ** 2)
+    chi_gap = float(((gap - gap.mean()) ** 2 / gap.mean()).sum() / (P - 2))
+    print(f"[parity] visiting orders: position chi2/dof {chi_pos:.3f}, consecutive-gap chi2/dof {chi_gap:.3f}",
+          flush=True)
+    assert chi_pos < 1.15
+    assert chi_gap < 2.0

@@ -11,6 +11,7 @@ import torch
 import oracle
 import paper_1312_0193_amd as nm
 import synth
+from parity import check, max_updates
 
 pytestmark = pytest.mark.gpu
 
@@ -72,7 +73,9 @@ def test_ring_one_epoch_matches_oracle(m, n, nnz, k, P, deg, nw, slots):
     seed = 1234 + P
     model, W, H = gpu_run(prob, W0, H0, hp, P, seed, [1], waves_per_worker=nw, item_slots=slots)
     Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 1)
-    assert rel(W, Wo) < TOL_1EPOCH and rel(H, Ho) < TOL_1EPOCH, (rel(W, Wo), rel(H, Ho))
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), 1)
+    check(W, Wo, norm_tol=TOL_1EPOCH, updates=T, what="W")
+    check(H, Ho, norm_tol=TOL_1EPOCH, updates=T, what="H")
     # evaluation: same factors, FP64 on both sides
     tr, tc, tv = prob.test_row.numpy(), prob.test_col.numpy(), prob.test_val.numpy()
     r_gpu, j_gpu = model.evaluate(prob.test_row, prob.test_col, prob.test_val)
@@ -91,7 +94,9 @@ def test_ring_multi_epoch_and_split_calls():
     # the ring schedule is one fixed serial order: identical on every run and call split
     assert np.array_equal(W1, W2) and np.array_equal(H1, H2)
     Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 3)
-    assert rel(W1, Wo) < 3 * TOL_1EPOCH and rel(H1, Ho) < 3 * TOL_1EPOCH
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), 3)
+    check(W1, Wo, norm_tol=3 * TOL_1EPOCH, updates=T, what="W")
+    check(H1, Ho, norm_tol=3 * TOL_1EPOCH, updates=T, what="H")
     st = m2.train(0)
     assert st.epochs_done == 3 and st.updates == 0
 
@@ -110,7 +115,9 @@ def test_ring_independent_of_waves_and_slots():
         else:
             assert np.array_equal(W, ref[0]) and np.array_equal(H, ref[1]), (nw, slots)
     Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 2)
-    assert rel(ref[0], Wo) < 2 * TOL_1EPOCH and rel(ref[1], Ho) < 2 * TOL_1EPOCH
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), 2)
+    check(ref[0], Wo, norm_tol=2 * TOL_1EPOCH, updates=T, what="W")
+    check(ref[1], Ho, norm_tol=2 * TOL_1EPOCH, updates=T, what="H")
 
 
 def test_ring_independent_of_row_windows():
@@ -127,7 +134,9 @@ def test_ring_independent_of_row_windows():
         else:
             assert np.array_equal(W, ref[0]) and np.array_equal(H, ref[1]), win
     Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 2)
-    assert rel(ref[0], Wo) < 2 * TOL_1EPOCH and rel(ref[1], Ho) < 2 * TOL_1EPOCH
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), 2)
+    check(ref[0], Wo, norm_tol=2 * TOL_1EPOCH, updates=T, what="W")
+    check(ref[1], Ho, norm_tol=2 * TOL_1EPOCH, updates=T, what="H")
 
 
 def test_ring_many_epochs_in_one_call():
@@ -139,7 +148,9 @@ def test_ring_many_epochs_in_one_call():
     _, Wb, Hb = gpu_run(prob, W0, H0, hp, P, seed, [30, 40])
     assert np.array_equal(Wa, Wb) and np.array_equal(Ha, Hb)
     Wo, Ho = oracle_run(prob, W0, H0, hp, P, seed, 70)
-    assert rel(Wa, Wo) < 1e-4 and rel(Ha, Ho) < 1e-4
+    T = max_updates(prob.row.numpy(), prob.col.numpy(), 70)
+    check(Wa, Wo, norm_tol=1e-4, updates=T, what="W")
+    check(Ha, Ho, norm_tol=1e-4, updates=T, what="H")
 
 
 def test_ring_deterministic_across_contexts():
@@ -219,5 +230,7 @@ def test_trace_records_every_item_visit_and_replays():
     t2 = tr[order]
     Wr, Hr, _ = oracle.replay(prob.m, prob.n, row, col, prob.val.numpy(), W0.numpy(), H0.numpy(), hp, P, seed,
                               t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
-    assert rel(W, Wr) < 2 * TOL_1EPOCH and rel(H, Hr) < 2 * TOL_1EPOCH
+    T = max_updates(row, col, E)
+    check(W, Wr, norm_tol=2 * TOL_1EPOCH, updates=T, what="W")
+    check(H, Hr, norm_tol=2 * TOL_1EPOCH, updates=T, what="H")
     model.close()

@@ -205,3 +205,104 @@ def test_threaded_many_workers_learns_like_the_emulation():
     Jt = oracle.objective(p_.m, p_.n, row, col, val, W, H, hp.lam)
     Ju = oracle.objective(p_.m, p_.n, row, col, val, Wu, Hu, hp.lam)
     assert Jt < 0.4 * J0 and Ju < 0.4 * J0 and abs(Jt - Ju) < 0.5 * Ju, (J0, Jt, Ju)
+
+
+# ---------------------------------------------------------------- dynamic load balancing (section 3.3)
+
+def test_balanced_pick_prefers_the_shorter_queue():
+    assert oracle.balanced_pick(3, 5, 7, 2) == 7
+    assert oracle.balanced_pick(3, 2, 7, 5) == 3
+    assert oracle.balanced_pick(3, 4, 7, 4) == 3  # a tie keeps the first draw
+    assert oracle.balanced_pick(0, 0, 1, 0) == 0
+
+
+@pytest.mark.parametrize("P", [3, 7])
+def test_balanced_perm_still_visits_every_holder_once_per_epoch(P):
+    """Load balancing changes the order of an item's holders, never which ones it visits:
+    every (worker, item) pair that shares ratings once per epoch, and the trace replays."""
+    p_, W0, H0, hp = _small(seed=61, degrees="zipf")
+    row, col, val = _np(p_)
+    E = 4
+    W, H, st, tr = oracle.train_perm(p_.m, p_.n, row, col, val, W0, H0, hp, P, 2, E, 13, trace=True, balance=True)
+    rs = oracle.partition(p_.m, row, P)
+    q_of = np.searchsorted(rs, row, "right") - 1
+    pairs = sorted({(int(q), int(j)) for q, j in zip(q_of, col)})
+    assert st.updates == E * p_.nnz and st.violations == 0
+    for e in range(E):
+        assert sorted((int(a), int(b)) for a, b in tr[tr[:, 2] == e, :2]) == pairs
+    order = np.argsort(tr[:, 0], kind="stable")
+    t2 = tr[order]
+    Wr, Hr, _ = oracle.replay(p_.m, p_.n, row, col, val, W0, H0, hp, P, 2, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
+    assert np.array_equal(W, Wr) and np.array_equal(H, Hr)
+
+
+def _random_problem(P, n, per_row=40, seed=5):
+    m = P * 30
+    rng = np.random.default_rng(seed)
+    row = np.repeat(np.arange(m, dtype=np.int32), per_row)
+    col = rng.integers(0, n, row.size).astype(np.int32)
+    key = np.unique(row.astype(np.int64) * n + col)
+    row, col = (key // n).astype(np.int32), (key % n).astype(np.int32)
+    val = rng.standard_normal(row.size).astype(np.float32)
+    return m, row, col, val
+
+
+@pytest.mark.parametrize("sched_seed", [1, 2, 3])
+def test_balanced_uniform_routing_keeps_queues_short(sched_seed):
+    """Section 3.3's rule in the uniform routing of Algorithm 1: the recipient is the less
+    loaded of two uniform draws.  By the "power of two choices" result (Azar, Broder,
+    Karlin, Upfal 1994) the longest queue then stays near the mean instead of drifting far
+    above it as under one uniform draw; with 1,000 items among 16 workers (about 62 per
+    worker) the longest queue over 30 epochs of updates must come out below half of the
+    single-draw run's."""
+    P, n = 16, 1000
+    m, row, col, val = _random_problem(P, n)
+    hp = Hyper(2, 0.05, 0.0, 0.0, 1.0)  # s = 0: only the routing matters
+    W0, H0 = np.ones((m, 2)), np.ones((n, 2))
+    budget = 30 * row.size
+    _, _, st0 = oracle.train_uniform(m, n, row, col, val, W0, H0, hp, P, 1, budget, sched_seed)
+    _, _, st1 = oracle.train_uniform(m, n, row, col, val, W0, H0, hp, P, 1, budget, sched_seed, balance=True)
+    assert st0.updates >= budget and st1.updates >= budget
+    assert st1.max_queue < 0.5 * st0.max_queue, (st0.max_queue, st1.max_queue)
+    assert st1.max_queue >= n // P  # some worker holds at least the mean
+
+
+# ---------------------------------------------------------------- time-driven turns
+
+def test_timed_turns_with_one_worker_are_the_ring_order():
+    """With one worker serving one item at a time, time-driven turns take the queue in
+    FIFO order whatever the costs: the items cycle in ascending order, which is the ring
+    order of one worker."""
+    p_, W0, H0, hp = _small(m=40, n=30, nnz=500, seed=71)
+    row, col, val = _np(p_)
+    for timing in [(1, 0.0, 0.0), (1, 25.0, 45.0)]:
+        W, H, st = oracle.train_uniform(p_.m, p_.n, row, col, val, W0, H0, hp, 1, 3, 3 * p_.nnz, 7, timing=timing)
+        Wr, Hr, _ = oracle.train_ring(p_.m, p_.n, row, col, val, W0, H0, hp, 1, 3, 3)
+        assert np.array_equal(W, Wr) and np.array_equal(H, Hr), timing
+
+
+def test_timed_turns_follow_visit_costs():
+    """One worker serving two items at once: item A has one rating, item B twenty.  With
+    turns driven by time (costs in units of one update, no hand-off delay) A completes a
+    visit every unit while B completes one every twenty, so A is visited about twenty times
+    as often; under the uniform draw of turns the FIFO queue alternates them.  Both traces
+    replay exactly."""
+    m, n = 20, 2
+    row = np.array([0] + list(range(20)), dtype=np.int32)
+    col = np.array([0] + [1] * 20, dtype=np.int32)
+    val = np.ones(row.size, dtype=np.float32)
+    hp = Hyper(2, 0.05, 0.01, 0.0, 1.0)
+    W0, H0 = np.full((m, 2), 0.3), np.full((n, 2), 0.3)
+    budget = 400
+    counts = {}
+    for timing in (None, (2, 0.0, 0.0)):
+        W, H, st, tr = oracle.train_uniform(m, n, row, col, val, W0, H0, hp, 1, 1, budget, 5, trace=True,
+                                            timing=timing)
+        counts[timing] = np.bincount(tr[:, 1], minlength=2)
+        t2 = tr[np.argsort(tr[:, 0], kind="stable")]
+        Wr, Hr, _ = oracle.replay(m, n, row, col, val, W0, H0, hp, 1, 1, t2[:, 0], t2[:, 1], t2[:, 2], t2[:, 3])
+        assert np.array_equal(W, Wr) and np.array_equal(H, Hr)
+    a, b = counts[None]
+    assert abs(int(a) - int(b)) <= 1
+    a, b = counts[(2, 0.0, 0.0)]
+    assert 15 * b <= a <= 25 * b + 25, (a, b)
