@@ -167,6 +167,22 @@ nomad_status nomad_train_epochs(nomad_ctx *ctx, int32_t epochs, nomad_stats *out
 nomad_status nomad_eval_rmse(nomad_ctx *ctx, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
                              const float *d_val, double *rmse_out, double *objective_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): nomad_eval_rmse with every temporary in
+ * a fixed scratch array the library keeps on each device (about 512 KB, held until the
+ * process ends).  Nothing is allocated, cleared with a memset, or synchronised: the work
+ * is only queued on the context's stream.  Results go to d_out, a device array of three
+ * doubles: [0] the RMSE (NaN when nnz = 0), [1] J as nomad_eval_rmse defines it, [2] 1.0
+ * if some entry's index was out of range (the sums then skip it), else 0.0.
+ *   nnz       0 .. 134,217,728 (the scratch holds one partial sum per 8,192 entries, at
+ *             most 16,384 of them); larger is EINVAL.
+ * Every call on one device shares that device's scratch: calls whose work overlaps on a
+ * device (other streams, other threads, other contexts) race and give undefined results.
+ * ESTATE for a batch, a failed context or NULL; EINVAL for bad arguments; EDEVICE if a HIP
+ * launch fails. */
+nomad_status nomad_eval_rmse_noalloc(nomad_ctx *ctx, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
+                                     const float *d_val, double *d_out);
+
 /* Copy the current factors out as FP32: d_W m x k, d_H n x k (device, row-major). */
 nomad_status nomad_get_factors(nomad_ctx *ctx, float *d_W, float *d_H);
 

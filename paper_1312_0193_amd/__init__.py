@@ -79,6 +79,8 @@ def load() -> C.CDLL:
     lib.nomad_train_epochs.argtypes = [P, i32, C.POINTER(NomadStats)]
     lib.nomad_eval_rmse.restype = C.c_int
     lib.nomad_eval_rmse.argtypes = [P, i64, P, P, P, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.nomad_eval_rmse_noalloc.restype = C.c_int
+    lib.nomad_eval_rmse_noalloc.argtypes = [P, i64, P, P, P, P]
     lib.nomad_get_factors.restype = C.c_int
     lib.nomad_get_factors.argtypes = [P, P, P]
     lib.nomad_get_partition.restype = C.c_int
@@ -206,6 +208,20 @@ class Nomad:
         _check(load().nomad_eval_rmse(self._c(), int(row.numel()), _ptr(row), _ptr(col), _ptr(val), C.byref(r),
                                       C.byref(j)), self.ctx)
         return r.value, j.value
+
+    def evaluate_noalloc(self, row, col, val, out):
+        """nomad_eval_rmse_noalloc: queue the evaluation on the context's stream; `out` is a
+        float64 CUDA tensor of 3 elements that receives (RMSE, J, bad-index flag).  The
+        rating tensors must already be int32/int32/float32 CUDA tensors (nothing is copied
+        or allocated here)."""
+        import torch
+        if not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= 3 and out.is_contiguous()):
+            raise ValueError("out must be a contiguous CUDA float64 tensor of 3 elements")
+        for t, dt in ((row, torch.int32), (col, torch.int32), (val, torch.float32)):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise ValueError("row, col, val must be contiguous CUDA int32, int32, float32 tensors")
+        _check(load().nomad_eval_rmse_noalloc(self._c(), int(row.numel()), _ptr(row), _ptr(col), _ptr(val),
+                                              _ptr(out)), self.ctx)
 
     def factors(self):
         import torch

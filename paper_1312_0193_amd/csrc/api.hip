@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -72,6 +73,23 @@ struct nomad_ctx {
 namespace {
 
 thread_local std::string g_last_error;
+
+// Device address of the allocation-free evaluation's scratch array, per device: looked up
+// once per device (with that device current) by the first nomad_init on it.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+void prepare_noalloc_scratch(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void *ptr = nullptr;
+    const hipError_t e = nomad::noalloc_scratch_address(&ptr);
+    g_scratch_err[dev] = e;
+    if (e == hipSuccess) g_scratch_ptr[dev] = ptr;
+}
 
 nomad_status fail(nomad_ctx *ctx, nomad_status st, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
 nomad_status fail(nomad_ctx *ctx, nomad_status st, const char *fmt, ...) {
@@ -303,6 +321,7 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
 
     hipError_t e;
     if ((e = hipGetDevice(&c->device)) != hipSuccess) return bail(hip_fail(c, e, "nomad_init: device"));
+    prepare_noalloc_scratch(c->device);
     if ((e = hipMalloc(&c->W, (size_t)c->wbytes * (size_t)m * c->kp)) != hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: W"));
     if ((e = hipMalloc(&c->H, sizeof(float) * (size_t)n * c->kp)) != hipSuccess)
@@ -709,6 +728,37 @@ nomad_status nomad_eval_rmse(nomad_ctx *c, int64_t nnz, const int32_t *d_row, co
     }
     *rmse_out = nnz > 0 ? std::sqrt(sq / (double)nnz) : NAN;
     if (objective_out) *objective_out = nnz > 0 ? obj : 0.0;
+    return NOMAD_OK;
+}
+
+nomad_status nomad_eval_rmse_noalloc(nomad_ctx *c, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
+                                     const float *d_val, double *d_out) {
+    if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_eval_rmse_noalloc: NULL context");
+    if (!c->members.empty())
+        return fail(c, NOMAD_ESTATE, "nomad_eval_rmse_noalloc: a batch; use nomad_batch_problem for one of its problems");
+    if (c->failed)
+        return fail(c, NOMAD_ESTATE, "nomad_eval_rmse_noalloc: an earlier launch failed; the factors are undefined");
+    if (!d_out) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse_noalloc: d_out is NULL");
+    if (nnz < 0) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse_noalloc: nnz < 0");
+    if (nnz > nomad::noalloc_max_nnz())
+        return fail(c, NOMAD_EINVAL, "nomad_eval_rmse_noalloc: nnz=%lld exceeds %lld, the most entries whose partial "
+                    "sums its fixed %zu-byte scratch holds (use nomad_eval_rmse)", (long long)nnz,
+                    (long long)nomad::noalloc_max_nnz(), nomad::noalloc_scratch_bytes());
+    if (nnz > 0 && (!d_row || !d_col || !d_val)) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse_noalloc: NULL arrays");
+    void *ptr = nullptr;
+    if (c->device >= 0 && c->device < kMaxDevices) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        ptr = g_scratch_ptr[c->device];
+        if (!ptr)
+            return fail(c, NOMAD_EDEVICE, "nomad_eval_rmse_noalloc: no scratch address on device %d (%s)", c->device,
+                        hipGetErrorString(g_scratch_err[c->device]));
+    } else {
+        return fail(c, NOMAD_EDEVICE, "nomad_eval_rmse_noalloc: device %d is beyond the %d this build tracks",
+                    c->device, kMaxDevices);
+    }
+    HIPTRY(c, nomad::eval_sums_noalloc(c->W, c->wbytes, c->H, c->k, c->kp, c->m, c->n, nnz, d_row, d_col, d_val,
+                                       c->cfg.lambda, ptr, d_out, c->stream),
+           "nomad_eval_rmse_noalloc");
     return NOMAD_OK;
 }
 

@@ -98,6 +98,28 @@ __global__ __launch_bounds__(kThreads) void k_eval_final(const Comp *part, int n
     }
 }
 
+// The results of a reduction for a caller's device buffer: RMSE, J and the bad-index flag
+// (1.0 if an entry's index was out of range, else 0.0).
+__global__ void k_eval_out(const double *sums, const int32_t *bad, int64_t nnz, double *out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    out[0] = nnz > 0 ? sqrt(sums[0] / (double)nnz) : NAN;
+    out[1] = nnz > 0 ? sums[1] : 0.0;
+    out[2] = *bad ? 1.0 : 0.0;
+}
+
+__global__ void k_clear_word(int32_t *w) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *w = 0;
+}
+
+// Scratch of the allocation-free evaluation (nomad_eval_rmse_noalloc): one Neumaier pair
+// per block of the partial pass and per sum, the two final sums and the bad-index word.
+// Each device that runs the library holds its own copy until the process ends; its
+// address comes from hipGetSymbolAddress (the name itself is a host-side stand-in).
+constexpr int kNoallocMaxBlocks = 16384;
+constexpr int64_t kNoallocEntriesPerBlock = 8192;
+constexpr size_t kNoallocScratchBytes = sizeof(Comp) * 2 * kNoallocMaxBlocks + 2 * sizeof(double) + 64;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
 // FP32 rows of width k -> bfloat16 rows of width kp (nearest-even; the pad is left alone).
 __global__ void k_to_bf16(const float *src, int32_t k, uint16_t *dst, int32_t kp, int64_t rows) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -132,6 +154,35 @@ hipError_t from_bf16(const uint16_t *src, int32_t kp, float *dst, int32_t k, int
 }
 
 size_t eval_scratch_bytes() { return sizeof(Comp) * 2 * kBlocks + 2 * sizeof(double) + 64; }
+
+int64_t noalloc_max_nnz() { return (int64_t)kNoallocMaxBlocks * kNoallocEntriesPerBlock; }
+size_t noalloc_scratch_bytes() { return kNoallocScratchBytes; }
+
+hipError_t noalloc_scratch_address(void **ptr) {
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
+hipError_t eval_sums_noalloc(const void *W, int32_t wbytes, const float *H, int32_t k, int32_t kp, int64_t m,
+                             int64_t n, int64_t nnz, const int32_t *row, const int32_t *col, const float *val,
+                             double lambda, void *scratch_ptr, double *d_out, hipStream_t st) {
+    // one block of the partial pass per kNoallocEntriesPerBlock entries (the caller has
+    // checked nnz <= noalloc_max_nnz())
+    const int64_t want = (nnz + kNoallocEntriesPerBlock - 1) / kNoallocEntriesPerBlock;
+    const int blocks = (int)(want < 1 ? 1 : want);
+    Comp *part = (Comp *)scratch_ptr;
+    double *sums = (double *)(part + 2 * kNoallocMaxBlocks);
+    int32_t *bad = (int32_t *)(sums + 2);
+    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(64), 0, st, bad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_eval_partial, dim3(blocks), dim3(kThreads), 0, st, W, wbytes, H, k, kp, m, n, nnz, row,
+                       col, val, lambda, part, bad);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_eval_final, dim3(1), dim3(kThreads), 0, st, part, blocks, sums);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_eval_out, dim3(1), dim3(64), 0, st, sums, bad, nnz, d_out);
+    return hipGetLastError();
+}
 
 hipError_t eval_sums(const void *W, int32_t wbytes, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,
                      int64_t nnz, const int32_t *row, const int32_t *col, const float *val,

@@ -242,5 +242,15 @@ hipError_t eval_sums(const void *W, int32_t wbytes, const float *H, int32_t k, i
 hipError_t to_bf16(const float *src, int32_t k, uint16_t *dst, int32_t kp, int64_t rows, hipStream_t st);
 hipError_t from_bf16(const uint16_t *src, int32_t kp, float *dst, int32_t k, int64_t rows, hipStream_t st);
 size_t eval_scratch_bytes();
+// Allocation-free evaluation: the partial and final sums live in a file-scope device array
+// (one per device); its device address comes from noalloc_scratch_address, called with
+// that device current.  Results go to d_out (device: RMSE, J, bad-index flag); nothing is
+// allocated, set with a memset or synchronised.
+int64_t noalloc_max_nnz();
+size_t noalloc_scratch_bytes();
+hipError_t noalloc_scratch_address(void **ptr);
+hipError_t eval_sums_noalloc(const void *W, int32_t wbytes, const float *H, int32_t k, int32_t kp, int64_t m,
+                             int64_t n, int64_t nnz, const int32_t *row, const int32_t *col, const float *val,
+                             double lambda, void *scratch_ptr, double *d_out, hipStream_t stream);
 
 }  // namespace nomad
