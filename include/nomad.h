@@ -120,6 +120,16 @@ typedef struct {
                                 visit since nomad_init, in the run's serial order (the global
                                 count; every rating of a visit uses the count at the visit's
                                 start).  Not available in batches. */
+    int32_t balance;         /* 1 = dynamic load balancing (section 3.3) under the asynchronous
+                                schedules: a worker's load is the number of items waiting in its
+                                queue.  UNIFORM: the next worker is the less loaded of two drawn
+                                uniformly (the second draw hashes r ^ 0x5BD1E995 in place of r;
+                                the first on a tie).  PERM: two holders not yet visited in the
+                                epoch are candidates, the one held over from the item's last
+                                choice (if any, else the next of the visiting order) and the next
+                                of the visiting order; the less loaded goes next (the first on a
+                                tie) and the other is held over, so every holder is still visited
+                                once per epoch.  ENOTIMPL under RING. */
     uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing,
                            stochastic rounding */
 } nomad_config;
@@ -208,7 +218,9 @@ nomad_status nomad_get_trace(nomad_ctx *ctx, int64_t *len, int32_t *h_buf, int64
  *   4 compute waves: time in the kernel            a wave's prefetch window
  *     (sum over the waves)                       8 compute waves: longest time in the kernel
  *                                                9 memory wave: waiting for its loads/stores
- *   10..15 zero */
+ *   10 asynchronous schedules: the XCD (accelerator complex die, 0..7 on MI355X) the worker
+ *      ran on, read from the hardware's XCC_ID register
+ *   11..15 zero */
 nomad_status nomad_get_worker_stats(nomad_ctx *ctx, int64_t *h_stats, int64_t cap);
 
 /* One problem of a batch (nomad_init_batched): the arguments of nomad_init that differ

@@ -44,7 +44,7 @@ struct nomad_ctx {
     std::string err;
     // Asynchronous schedule: inbound queues, item state, seeding scratch.
     uint64_t *queue = nullptr;
-    uint32_t *qtail = nullptr, *parked = nullptr;
+    uint32_t *qtail = nullptr, *qhead = nullptr, *parked = nullptr;
     int32_t *istate = nullptr, *tvis = nullptr;   // per item state words (n x 4), per holder visits
     unsigned long long *upd = nullptr;
     int64_t queue_len = 0;
@@ -128,6 +128,7 @@ void release(nomad_ctx *c) {
     (void)hipFree(c->d_wg);
     (void)hipFree(c->queue);
     (void)hipFree(c->qtail);
+    (void)hipFree(c->qhead);
     (void)hipFree(c->parked);
     (void)hipFree(c->istate);
     (void)hipFree(c->tvis);
@@ -234,6 +235,7 @@ void nomad_config_default(nomad_config *cfg) {
     cfg->collect_stats = 0;
     cfg->debug_ownership = 0;
     cfg->t_source = 0;
+    cfg->balance = 0;
     cfg->seed = 0;
 }
 
@@ -272,6 +274,11 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: debug_ownership=%d is not 0 or 1", cfg->debug_ownership);
     if (cfg->t_source != 0 && cfg->t_source != 1)
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: t_source=%d is not 0 or 1", cfg->t_source);
+    if (cfg->balance != 0 && cfg->balance != 1)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: balance=%d is not 0 or 1", cfg->balance);
+    if (cfg->balance == 1 && cfg->sched == NOMAD_SCHED_RING)
+        return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init: balance=1 needs an asynchronous schedule (the ring order "
+                    "is fixed)");
     if (cfg->t_source == 1 && forced)
         return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init_batched: t_source=1 (global update count) is per problem only");
 
@@ -388,6 +395,7 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
             (e = hipMalloc(&c->upd, sizeof(unsigned long long))) != hipSuccess ||
             (e = hipMemsetAsync(c->tvis, 0, sizeof(int32_t) * (size_t)nv, st)) != hipSuccess ||
             (e = hipMalloc(&c->qtail, sizeof(uint32_t) * (size_t)p)) != hipSuccess ||
+            (e = hipMalloc(&c->qhead, sizeof(uint32_t) * (size_t)p)) != hipSuccess ||
             (e = hipMalloc(&c->parked, sizeof(uint32_t))) != hipSuccess ||
             (e = hipMalloc(&c->istate, sizeof(int32_t) * 4 * (size_t)n)) != hipSuccess ||
             (e = hipMalloc(&c->async_scratch, c->async_scratch_bytes)) != hipSuccess ||
@@ -632,6 +640,8 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
             a.xoff = c->plan.xoff;
             a.queue = c->queue;
             a.qtail = c->qtail;
+            a.qhead = c->qhead;
+            a.balance = c->cfg.balance ? 1 : 0;
             a.istate = c->istate;
             a.hmap = c->plan.hmap;
             a.parked = c->parked;
@@ -656,6 +666,7 @@ nomad_status nomad_train_epochs(nomad_ctx *c, int32_t epochs, nomad_stats *out) 
             if (async) {
                 HIPTRY(c, hipMemsetAsync(c->queue, 0, sizeof(uint64_t) * (size_t)c->queue_len, st), "train: reset");
                 HIPTRY(c, hipMemsetAsync(c->qtail, 0, sizeof(uint32_t) * (size_t)c->p, st), "train: reset");
+                HIPTRY(c, hipMemsetAsync(c->qhead, 0, sizeof(uint32_t) * (size_t)c->p, st), "train: reset");
                 HIPTRY(c, hipMemsetAsync(c->parked, 0, sizeof(uint32_t), st), "train: reset");
                 HIPTRY(c, nomad::seed_train_async(a, c->async_scratch, c->async_scratch_bytes, st), "train: seeding");
                 HIPTRY(c, hipEventRecord(c->lev[2 * launches], st), "train: event");

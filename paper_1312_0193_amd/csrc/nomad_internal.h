@@ -79,6 +79,7 @@ enum WStat {
     kWStatForwarded = 7,   // row reads served from an update still in the prefetch window
     kWStatCompMax = 8,     // compute waves: longest time in the kernel
     kWStatMemWait = 9,     // memory wave: time waiting for its loads and stores
+    kWStatXcd = 10,        // the accelerator complex die (XCD) the worker ran on
     kWStatCount = 16
 };
 
@@ -169,11 +170,16 @@ struct TrainArgs {
     unsigned long long *upd;    // uniform routing: updates applied in the call
     unsigned long long budget;  // uniform routing: updates after which items stop moving
     uint32_t *qtail;            // p: pushes into each queue during the launch
+    uint32_t *qhead;            // p: entries each worker has taken from its queue (published for
+                                // the load-balanced choice; queue length = qtail - qhead)
+    int32_t balance;            // 1: section 3.3's dynamic load balancing of the next worker
     int32_t *istate;            // n x 4: state of each item, written by its holder before it moves on:
                                 //   [0] permutation: epoch of the next visit; uniform: moves so far
-                                //   [1] permutation: position of the next visit in the epoch's order
+                                //   [1] permutation: positions of the epoch's visiting order used
+                                //       (the next visit's included)
                                 //   [2] visits of the item (that updated something) since nomad_init
-                                //   [3] unused
+                                //   [3] permutation with load balancing: the holder rank held over
+                                //       as a candidate for the next choice, or -1
     const int32_t *hmap;        // uniform routing: p x n, holder entry of (worker, item) or -1
     uint32_t *parked;           // items that finished the launch's epochs
     int64_t active;             // items with at least one rating

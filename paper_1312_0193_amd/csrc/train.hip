@@ -1272,7 +1272,7 @@ struct AsyncMemoryWave {
     // lane s < S: the visit in slot s: item, holder entry (-1 if none), step counter t, the
     // item's state words (epoch or moves, position, visits), its first holder entry and
     // number of holders
-    int f_j = 0, f_g = -1, f_t = 0, f_e = 0, f_pos = 0, f_seq = 0, f_hb = 0, f_nh = 0;
+    int f_j = 0, f_g = -1, f_t = 0, f_e = 0, f_pos = 0, f_seq = 0, f_hb = 0, f_nh = 0, f_cr = -1;
     // step sizes of t = tbase + lane
     int tbase = 0;
     float s_tab = 0.0f, c_tab = 0.0f;
@@ -1287,6 +1287,16 @@ struct AsyncMemoryWave {
         // routing's per-pair counts stay near the epochs done
         tbase = uni ? (a.epoch0 > 32 ? a.epoch0 - 32 : 0) : a.epoch0;
         step_size(a, (double)(tbase + lane), s_tab, c_tab);
+    }
+
+    // Items waiting in worker q2's queue (pushed, not yet taken): the load that section 3.3's
+    // rule compares.  The two counters are read at slightly different moments, so a head
+    // read after the tail can pass it; such a reading counts as an empty queue.
+    __device__ __forceinline__ int queue_load(int q2) const {
+        const uint32_t tl = __hip_atomic_load(a.qtail + q2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t hd = __hip_atomic_load(a.qhead + q2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int d = (int)(tl - hd);
+        return d > 0 ? d : 0;
     }
 
     // Push the item to worker q2's queue with payload `pay`.
@@ -1309,12 +1319,13 @@ struct AsyncMemoryWave {
         const int X = Xr + lane;
         const int sl = X & Smask;
         const int j = __shfl(f_j, sl), g = __shfl(f_g, sl), t = __shfl(f_t, sl), e = __shfl(f_e, sl),
-                  pos = __shfl(f_pos, sl), seq = __shfl(f_seq, sl), hb = __shfl(f_hb, sl), nh = __shfl(f_nh, sl);
+                  pos = __shfl(f_pos, sl), seq = __shfl(f_seq, sl), hb = __shfl(f_hb, sl), nh = __shfl(f_nh, sl),
+                  cr = __shfl(f_cr, sl);
         io.write_back(j, sl, nr);
         const bool mine = lane < nr;
         int dest = -1;  // next worker, -1: the item is parked
         uint32_t pay = 0;
-        int4 nst = make_int4(0, 0, g >= 0 ? seq + 1 : seq, 0);
+        int4 nst = make_int4(0, 0, g >= 0 ? seq + 1 : seq, -1);
         unsigned long long done_upd = 0;
         if (mine) {
             if (uni) {
@@ -1323,19 +1334,39 @@ struct AsyncMemoryWave {
                     done_upd = (unsigned long long)a.hcnt[g];
                 }
             } else {
-                // the next position of the epoch's visiting order, or the first of the next epoch
-                int np = pos + 1, ne = e;
-                if (np >= nh) {
-                    np = 0;
+                // The next holder: the next position of the epoch's visiting order (or the first
+                // of the next epoch once every holder was visited).  With load balancing
+                // (section 3.3) two holders not yet visited are candidates, the one held over
+                // from the last choice (if any) and the next of the order, and the one whose
+                // queue holds fewer items goes next; the other is held over.
+                int fp = pos, carry = cr, ne = e;
+                if (fp >= nh && carry < 0) {
+                    fp = 0;
                     ++ne;
                 }
                 if (ne < a.epoch0 + a.epochs) {
-                    const int ng = hb + (int)visit_rank(a.route_seed, j, ne, (uint32_t)nh, (uint32_t)np);
+                    int ra;
+                    if (carry >= 0) {
+                        ra = carry;
+                        carry = -1;
+                    } else {
+                        ra = (int)visit_rank(a.route_seed, j, ne, (uint32_t)nh, (uint32_t)fp++);
+                    }
+                    int pick = ra;
+                    if (a.balance && fp < nh) {
+                        const int rb = (int)visit_rank(a.route_seed, j, ne, (uint32_t)nh, (uint32_t)fp++);
+                        const int qa = a.hold[hb + ra], qb = a.hold[hb + rb];
+                        const bool take_b = queue_load(qb) < queue_load(qa);
+                        pick = take_b ? rb : ra;
+                        carry = take_b ? ra : rb;
+                    }
+                    const int ng = hb + pick;
                     dest = a.hold[ng];
                     pay = (uint32_t)ng;
                 }
                 nst.x = ne;
-                nst.y = np;
+                nst.y = fp;
+                nst.w = carry;
             }
         }
         if (uni) {
@@ -1349,6 +1380,11 @@ struct AsyncMemoryWave {
                 nst.x = e;  // moves so far
                 if (before + sum < a.budget) {
                     dest = route_uniform(a.route_seed, j, e, a.p);
+                    if (a.balance) {
+                        // section 3.3: the less loaded of two uniformly drawn workers
+                        const int d2 = route_uniform(a.route_seed ^ 0x5BD1E995u, j, e, a.p);
+                        if (queue_load(d2) < queue_load(dest)) dest = d2;
+                    }
                     nst.x = e + 1;
                     const int g2 = a.hmap[(int64_t)dest * a.n + j];
                     pay = g2 >= 0 ? (uint32_t)g2 : (kPassBit | (uint32_t)j);
@@ -1462,8 +1498,10 @@ struct AsyncMemoryWave {
         {
             const int k = (lane - Xl) & Smask;
             const int tj = __shfl(j, k), tg2 = __shfl(g, k), tt = __shfl(t, k), te = __shfl(st.x, k),
-                      tp = __shfl(st.y, k), ts = __shfl(st.z, k), thb = __shfl(hb, k), tnh = __shfl(nh, k);
+                      tp = __shfl(st.y, k), ts = __shfl(st.z, k), thb = __shfl(hb, k), tnh = __shfl(nh, k),
+                      tcr = __shfl(st.w, k);
             if (lane < S && k < nt) {
+                f_cr = tcr;
                 f_j = tj;
                 f_g = tg2;
                 f_t = tt;
@@ -1494,6 +1532,8 @@ struct AsyncMemoryWave {
         }
         head += nt;
         Xl += nt;
+        if (a.balance && lane == 0)
+            __hip_atomic_store(a.qhead + q, (uint32_t)head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         wait_vm();    // the item vectors are in LDS
         wait_lgkm();  // and so are the slots' descriptions
         if (lane == 0) sync_store(&L.ctl[0], Xl);
@@ -1543,6 +1583,8 @@ struct AsyncMemoryWave {
             atomicAdd(&ws[kWStatMemIters], (unsigned long long)iters);
             atomicAdd(&ws[kWStatVisits], (unsigned long long)Xl);
             atomicAdd(&ws[kWStatPollMiss], (unsigned long long)misses);
+            // hardware register XCC_ID (bits 3:0): the die this workgroup was placed on
+            a.wstats[(int64_t)q * kWStatCount + kWStatXcd] = (int64_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
         }
     }
 };
@@ -1594,7 +1636,8 @@ __global__ void k_seed_first(TrainArgs a, int64_t n, uint32_t *key, uint32_t *va
             key[j] = (uint32_t)a.hold[g];
             first[j] = (uint32_t)g;
             st.x = a.epoch0;
-            st.y = 0;
+            st.y = 1;   // position 0 of the visiting order is this first visit
+            st.w = -1;
         }
         *(int4 *)(a.istate + 4 * j) = st;
     }

@@ -18,8 +18,13 @@ column takes about 473,000 updates in sequence); the per-column errors and those
 heaviest columns are printed beside it.  The ownership invariant is checked on the device
 for all three schedules (zero violations, hand-offs counted), and the benchmark's test
 RMSE after six random-permutation epochs is compared with the oracle's emulations of the
-same schedule (tests/golden/medium_perm_rmse.json, three scheduler seeds) within the
-asynchronous criterion, 1e-3 absolute of the band they span.
+same schedule (tests/golden/medium_perm_rmse.json, three scheduler seeds).  The benchmark
+trains one epoch per call, and a launch ends only when every item has finished its epochs,
+so items stay within an epoch of each other as in the emulation: its RMSE must lie within
+1e-3 (the asynchronous criterion) of the band the emulations span.  Six epochs in one call
+let light items run epochs ahead of the heaviest (a chain of 473,267 updates per epoch
+that lasts about as long as the epoch): that RMSE is about 0.7% higher and is held within
+1e-2.
 """
 import json
 import os
@@ -170,14 +175,20 @@ def test_medium_perm_rmse_matches_oracle_emulation(medium):
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "medium_perm_rmse.json")
     gold = json.load(open(path))
     prob, W0, H0, hp, host = medium
-    mdl = model(prob, W0, H0, hp, sched="perm")
-    assert mdl.workers == gold["workers"]
-    mdl.train(gold["epochs"])
-    r, _ = mdl.evaluate(prob.test_row, prob.test_col, prob.test_val)
-    mdl.close()
     band = list(gold.get("test_rmse_by_sched_seed", {"": gold["test_rmse"]}).values())
     lo, hi = min(band), max(band)
-    print(f"[parity] medium perm test RMSE after {gold['epochs']} epochs: gpu {r:.6f}, oracle emulations "
-          f"[{lo:.6f}, {hi:.6f}] (initial {gold['initial_test_rmse']:.6f})", flush=True)
+    res = {}
+    for calls in ([1] * gold["epochs"], [gold["epochs"]]):
+        mdl = model(prob, W0, H0, hp, sched="perm")
+        assert mdl.workers == gold["workers"]
+        for e in calls:
+            mdl.train(e)
+        res[len(calls)], _ = mdl.evaluate(prob.test_row, prob.test_col, prob.test_val)
+        mdl.close()
+    r, r1 = res[gold["epochs"]], res[1]
+    print(f"[parity] medium perm test RMSE after {gold['epochs']} epochs: gpu {r:.6f} (one epoch per call, as the "
+          f"benchmark), {r1:.6f} (one call); oracle emulations [{lo:.6f}, {hi:.6f}] "
+          f"(initial {gold['initial_test_rmse']:.6f})", flush=True)
     assert r < 0.45 * gold["initial_test_rmse"]  # a learned point
     assert lo - 1e-3 < r < hi + 1e-3
+    assert abs(r1 - lo) < 1e-2
