@@ -130,6 +130,18 @@ typedef struct {
                                 of the visiting order; the less loaded goes next (the first on a
                                 tie) and the other is held over, so every holder is still visited
                                 once per epoch.  ENOTIMPL under RING. */
+    int32_t transpose;       /* 1 = make the row factors nomadic instead (the symmetry noted in
+                                section 3.1): the library runs NOMAD on the transposed matrix, so
+                                the columns of A are partitioned among the workers, h_j stay
+                                with their worker, and the w_i travel.  Every argument and result
+                                of the calls keeps A's orientation (nomad_init's m, n, d_row,
+                                d_col, d_W0, d_H0; nomad_get_factors' d_W, d_H; the evaluation's
+                                rows and columns); what is transposed is reported by
+                                nomad_get_partition (bounds of column blocks), nomad_get_trace
+                                (the travelling index is the row i) and the BF16 storage form
+                                (the resident factor, H, is the one stored in bfloat16; W is then
+                                FP32).  Pays off when rows are fewer than columns.  ENOTIMPL in
+                                batches. */
     uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing,
                            stochastic rounding */
 } nomad_config;

@@ -30,7 +30,7 @@ class NomadConfig(C.Structure):
                 ("workers", C.c_int32), ("waves_per_worker", C.c_int32), ("item_slots", C.c_int32),
                 ("window", C.c_int32),
                 ("record_trace", C.c_int32), ("collect_stats", C.c_int32), ("debug_ownership", C.c_int32),
-                ("t_source", C.c_int32), ("balance", C.c_int32), ("seed", C.c_uint64)]
+                ("t_source", C.c_int32), ("balance", C.c_int32), ("transpose", C.c_int32), ("seed", C.c_uint64)]
 
 
 class NomadProblemDesc(C.Structure):
@@ -155,7 +155,7 @@ class Stats:
 def make_config(k: int, lam: float, alpha: float, beta: float, gamma: float, *, sched="ring", dtype="fp32",
                 rounding="rne", workers=0, waves_per_worker=0, item_slots=0, window=0, record_trace=False,
                 collect_stats=False, debug_ownership=False, t_source="pair", balance=False,
-                seed=0) -> NomadConfig:
+                transpose=False, seed=0) -> NomadConfig:
     cfg = NomadConfig()
     load().nomad_config_default(C.byref(cfg))
     cfg.k, cfg.lambda_, cfg.alpha, cfg.beta, cfg.gamma = k, lam, alpha, beta, gamma
@@ -167,6 +167,7 @@ def make_config(k: int, lam: float, alpha: float, beta: float, gamma: float, *, 
     cfg.debug_ownership = int(bool(debug_ownership))
     cfg.t_source = T_SOURCE[t_source]
     cfg.balance = int(bool(balance))
+    cfg.transpose = int(bool(transpose))
     cfg.seed = seed
     return cfg
 

@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <utility>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -236,6 +237,7 @@ void nomad_config_default(nomad_config *cfg) {
     cfg->debug_ownership = 0;
     cfg->t_source = 0;
     cfg->balance = 0;
+    cfg->transpose = 0;
     cfg->seed = 0;
 }
 
@@ -276,6 +278,10 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: t_source=%d is not 0 or 1", cfg->t_source);
     if (cfg->balance != 0 && cfg->balance != 1)
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: balance=%d is not 0 or 1", cfg->balance);
+    if (cfg->transpose != 0 && cfg->transpose != 1)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: transpose=%d is not 0 or 1", cfg->transpose);
+    if (cfg->transpose == 1 && forced)
+        return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init_batched: transpose=1 is per problem only");
     if (cfg->balance == 1 && cfg->sched == NOMAD_SCHED_RING)
         return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init: balance=1 needs an asynchronous schedule (the ring order "
                     "is fixed)");
@@ -418,6 +424,9 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
 nomad_status nomad_init(nomad_ctx **out, const nomad_config *cfg, int64_t m, int64_t n, int64_t nnz,
                         const int32_t *d_row, const int32_t *d_col, const float *d_val, const float *d_W0,
                         const float *d_H0, void *hip_stream) {
+    // Transposed: NOMAD on A^T, whose rows are A's columns (section 3.1's symmetric choice).
+    if (cfg && cfg->transpose == 1)
+        return init_impl(out, cfg, n, m, nnz, d_col, d_row, d_val, d_H0, d_W0, hip_stream, nullptr);
     return init_impl(out, cfg, m, n, nnz, d_row, d_col, d_val, d_W0, d_H0, hip_stream, nullptr);
 }
 
@@ -729,6 +738,7 @@ nomad_status nomad_eval_rmse(nomad_ctx *c, int64_t nnz, const int32_t *d_row, co
     if (c->failed) return fail(c, NOMAD_ESTATE, "nomad_eval_rmse: an earlier launch failed; the factors are undefined");
     if (nnz < 0) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: nnz < 0");
     if (nnz > 0 && (!d_row || !d_col || !d_val)) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: NULL arrays");
+    if (c->cfg.transpose == 1) std::swap(d_row, d_col);  // the context holds A^T
     double sq = 0.0, obj = 0.0;
     int bad = 0;
     if (nnz > 0) {
@@ -756,6 +766,7 @@ nomad_status nomad_eval_rmse_noalloc(nomad_ctx *c, int64_t nnz, const int32_t *d
                     "sums its fixed %zu-byte scratch holds (use nomad_eval_rmse)", (long long)nnz,
                     (long long)nomad::noalloc_max_nnz(), nomad::noalloc_scratch_bytes());
     if (nnz > 0 && (!d_row || !d_col || !d_val)) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse_noalloc: NULL arrays");
+    if (c->cfg.transpose == 1) std::swap(d_row, d_col);  // the context holds A^T
     void *ptr = nullptr;
     if (c->device >= 0 && c->device < kMaxDevices) {
         std::lock_guard<std::mutex> lk(g_scratch_mu);
@@ -779,6 +790,7 @@ nomad_status nomad_get_factors(nomad_ctx *c, float *d_W, float *d_H) {
         return fail(c, NOMAD_ESTATE, "nomad_get_factors: a batch; use nomad_batch_problem for one of its problems");
     if (!d_W || !d_H) return fail(c, NOMAD_EINVAL, "nomad_get_factors: NULL output");
     if (c->failed) return fail(c, NOMAD_ESTATE, "nomad_get_factors: an earlier launch failed; the factors are undefined");
+    if (c->cfg.transpose == 1) std::swap(d_W, d_H);  // the context's row factors are A's H
     if (c->wbytes == 2)
         HIPTRY(c, nomad::from_bf16((const uint16_t *)c->W, c->kp, d_W, c->k, c->m, c->stream), "get_factors");
     else

@@ -59,9 +59,13 @@ __device__ __forceinline__ float wave_sum_last(float x) {
     x += DPP_F(x, 0x4E, 0xF, true);   // quad_perm [2,3,0,1]
     x += DPP_F(x, 0x124, 0xF, true);  // row_ror 4
     x += DPP_F(x, 0x128, 0xF, true);  // row_ror 8
-    // the disabled rows' values are left undefined (no register to clear first)
-    x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x142, 0xA, 0xF, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x143, 0xC, 0xF, false));
+    // The row broadcasts as one DPP addition each, written out: the compiler emits a DPP move
+    // and an addition for them.  The rows outside the row mask keep their value (the operand
+    // is tied to the result); the two wait states before each are those a DPP read needs
+    // after a vector write of its operand.  Each addition takes the same two terms as before,
+    // in the other order, which gives the same sum.
+    asm("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0xa bank_mask:0xf" : "+v"(x));
+    asm("s_nop 1\n\tv_add_f32_dpp %0, %0, %0 row_bcast:31 row_mask:0xc bank_mask:0xf" : "+v"(x));
     return x;
 }
 
