@@ -98,8 +98,9 @@ def _draw_from(cdf: torch.Tensor, count: int, g: torch.Generator, device) -> tor
 
 
 def _sample_cells(m: int, n: int, nnz: int, degrees: str, alpha: float,
-                  g: torch.Generator, device) -> tuple[torch.Tensor, torch.Tensor]:
-    """Distinct (row, col) cells, exactly nnz of them, in random order."""
+                  g: torch.Generator, device, cdf_c: Optional[torch.Tensor] = None) -> tuple[torch.Tensor, torch.Tensor]:
+    """Distinct (row, col) cells, exactly nnz of them, in random order.  cdf_c: column
+    weights (cumulative) to use instead of drawing them (zipf only)."""
     total = m * n
     if nnz > total:
         raise ValueError(f"nnz={nnz} exceeds m*n={total}")
@@ -112,11 +113,12 @@ def _sample_cells(m: int, n: int, nnz: int, degrees: str, alpha: float,
             keys = torch.unique(torch.cat([keys, draw]))
     elif degrees == "zipf":
         wr = _weights_zipf(m, alpha, g, device)
-        wc = _weights_zipf(n, alpha, g, device)
         cdf_r = torch.cumsum(wr, 0)
-        cdf_c = torch.cumsum(wc, 0)
         cdf_r[-1] = 1.0
-        cdf_c[-1] = 1.0
+        if cdf_c is None:
+            wc = _weights_zipf(n, alpha, g, device)
+            cdf_c = torch.cumsum(wc, 0)
+            cdf_c[-1] = 1.0
         keys = torch.empty(0, dtype=torch.int64, device=device)
         rounds = 0
         while keys.numel() < nnz:
@@ -136,16 +138,21 @@ def _sample_cells(m: int, n: int, nnz: int, degrees: str, alpha: float,
     return (keys // n).to(torch.int32), (keys % n).to(torch.int32)
 
 
-def _planted_values(row, col, m, n, rank, g, device, chunk=1 << 23) -> torch.Tensor:
-    """<u_i, v_j> with u, v ~ N(0, var 1/sqrt(rank)) entries (so Var<u,v> = 1)."""
-    std = rank ** -0.25
-    U = torch.randn(m, rank, generator=g, device=device, dtype=torch.float32) * std
-    V = torch.randn(n, rank, generator=g, device=device, dtype=torch.float32) * std
-    out = torch.empty(row.numel(), dtype=torch.float32, device=device)
+def _dot_rows(U, V, row, col, chunk=1 << 23) -> torch.Tensor:
+    """<U[row], V[col]> per cell, in chunks."""
+    out = torch.empty(row.numel(), dtype=torch.float32, device=U.device)
     for s in range(0, row.numel(), chunk):
         e = min(s + chunk, row.numel())
         out[s:e] = (U[row[s:e].long()] * V[col[s:e].long()]).sum(1)
     return out
+
+
+def _planted_values(row, col, m, n, rank, g, device) -> torch.Tensor:
+    """<u_i, v_j> with u, v ~ N(0, var 1/sqrt(rank)) entries (so Var<u,v> = 1)."""
+    std = rank ** -0.25
+    U = torch.randn(m, rank, generator=g, device=device, dtype=torch.float32) * std
+    V = torch.randn(n, rank, generator=g, device=device, dtype=torch.float32) * std
+    return _dot_rows(U, V, row, col)
 
 
 def planted_problem(m: int, n: int, nnz: int, rank: int, *, seed: int, degrees: str = "uniform",
@@ -158,6 +165,7 @@ def planted_problem(m: int, n: int, nnz: int, rank: int, *, seed: int, degrees: 
       "gaussian"  r = x + N(0, noise^2)
       "int15"     r = clip(round(3 + x + N(0, noise^2)), 1, 5)   (integer star ratings)
       "scaled100" r = clip(50 + 25 (x + N(0, noise^2)), 0, 100)
+      "sign"      r = +1 if x + N(0, noise^2) >= 0 else -1   (binary labels)
     where x = <u_i, v_j>.  The test set is a uniform subset of the drawn cells.
     """
     g = _gen(seed, device)
@@ -170,6 +178,8 @@ def planted_problem(m: int, n: int, nnz: int, rank: int, *, seed: int, degrees: 
         val = torch.clamp(torch.round(3.0 + x + eps), 1.0, 5.0)
     elif values == "scaled100":
         val = torch.clamp(50.0 + 25.0 * (x + eps), 0.0, 100.0)
+    elif values == "sign":
+        val = torch.where(x + eps >= 0.0, 1.0, -1.0).to(torch.float32)
     else:
         raise ValueError(values)
     if n_test is None:
@@ -219,16 +229,55 @@ def large(device="cpu") -> Problem:
                            hp=dict(k=100, lam=1.0, alpha=0.00075, beta=0.01, gamma=1.5, epochs=10))
 
 
-def very_tall(device="cpu", row_fraction: float = 1.0) -> Problem:
-    """Hugewiki-shaped: 50M x 39,780, 2.74B Zipf cells, real ratings (rank 50 + noise).
+VT_BLOCK_ROWS = 3_125_000
+VT_BLOCK_CELLS = 171_250_000
+VT_BLOCKS = 16
 
-    row_fraction < 1 draws the same recipe on a proportional row/nnz slice.
+
+def very_tall(device="cpu", blocks: int = VT_BLOCKS) -> Problem:
+    """Hugewiki-shaped: 50,000,000 x 39,780, 2.74 B cells, real ratings.
+
+    Drawn as 16 row blocks of 3,125,000 rows and 171,250,000 cells each.  Every block
+    follows the capped Chung-Lu recipe with Zipf(1.1) row weights over its own rows and
+    column weights shared by all blocks; values are <u_i, v_j> + N(0, 0.1^2) with planted
+    rank 50 (the v_j shared), 1.4% of each block held out.  `blocks` < 16 gives the first
+    `blocks` blocks (rows 0 .. blocks * 3,125,000), a row sample of the full matrix.
+    Blocks keep every sort below the 2^31 items one torch.unique call takes.
     """
-    m = int(50_000_000 * row_fraction)
-    nnz = int(2_740_000_000 * row_fraction)
-    return planted_problem(m, 39_780, nnz, 50, seed=5, degrees="zipf", alpha=1.1, values="gaussian",
-                           noise=0.1, test_frac=0.014, device=device, name="very_tall",
-                           hp=dict(k=100, lam=0.01, alpha=0.001, beta=0.0, gamma=1.5, epochs=5))
+    if not 1 <= blocks <= VT_BLOCKS:
+        raise ValueError(blocks)
+    n, rank, seed = 39_780, 50, 5
+    gc = _gen(seed, device)
+    wc = _weights_zipf(n, 1.1, gc, device)
+    cdf_c = torch.cumsum(wc, 0)
+    cdf_c[-1] = 1.0
+    V = torch.randn(n, rank, generator=gc, device=device, dtype=torch.float32) * rank ** -0.25
+    mb, cb = VT_BLOCK_ROWS, VT_BLOCK_CELLS
+    n_test_b = int(round(cb * 0.014))
+    n_train_b = cb - n_test_b
+    row = torch.empty(blocks * n_train_b, dtype=torch.int32, device=device)
+    col = torch.empty_like(row)
+    val = torch.empty(blocks * n_train_b, dtype=torch.float32, device=device)
+    trow = torch.empty(blocks * n_test_b, dtype=torch.int32, device=device)
+    tcol = torch.empty_like(trow)
+    tval = torch.empty(blocks * n_test_b, dtype=torch.float32, device=device)
+    for b in range(blocks):
+        g = _gen(seed * 1_000_003 + b + 1, device)
+        r, c = _sample_cells(mb, n, cb, "zipf", 1.1, g, device, cdf_c=cdf_c)
+        U = torch.randn(mb, rank, generator=g, device=device, dtype=torch.float32) * rank ** -0.25
+        x = _dot_rows(U, V, r, c)
+        v = x + torch.randn(cb, generator=g, device=device, dtype=torch.float32) * 0.1
+        r = r + b * mb
+        # cells come in random order: the first n_test_b of the block are held out
+        trow[b * n_test_b:(b + 1) * n_test_b] = r[:n_test_b]
+        tcol[b * n_test_b:(b + 1) * n_test_b] = c[:n_test_b]
+        tval[b * n_test_b:(b + 1) * n_test_b] = v[:n_test_b]
+        row[b * n_train_b:(b + 1) * n_train_b] = r[n_test_b:]
+        col[b * n_train_b:(b + 1) * n_train_b] = c[n_test_b:]
+        val[b * n_train_b:(b + 1) * n_train_b] = v[n_test_b:]
+        del r, c, U, x, v
+    return Problem(blocks * mb, n, row, col, val, trow, tcol, tval,
+                   dict(k=100, lam=0.01, alpha=0.001, beta=0.0, gamma=1.5, epochs=5), "very_tall")
 
 
 def batched_specs(count: int = 256, seed: int = 4) -> list[dict]:
@@ -258,9 +307,10 @@ def batched_problem(spec: dict, device="cpu") -> Problem:
 
 
 def small_case(m: int, n: int, nnz: int, *, seed: int, degrees="uniform", k=16, lam=0.05,
-               alpha=0.01, beta=1e-4, gamma=1.0, rank=4, test_frac=0.1, device="cpu") -> Problem:
+               alpha=0.01, beta=1e-4, gamma=1.0, rank=4, test_frac=0.1, device="cpu",
+               values="gaussian") -> Problem:
     """Parity-test helper: an arbitrary small planted problem."""
-    return planted_problem(m, n, nnz, rank, seed=seed, degrees=degrees, values="gaussian", noise=0.1,
+    return planted_problem(m, n, nnz, rank, seed=seed, degrees=degrees, values=values, noise=0.1,
                            test_frac=test_frac, device=device, name=f"small{m}x{n}",
                            hp=dict(k=k, lam=lam, alpha=alpha, beta=beta, gamma=gamma, epochs=1))
 
