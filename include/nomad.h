@@ -75,6 +75,16 @@ typedef enum {
  *     visits already under way complete, so nomad_stats.updates can exceed E * nnz. */
 typedef enum { NOMAD_SCHED_RING = 0, NOMAD_SCHED_PERM = 1, NOMAD_SCHED_UNIFORM = 2 } nomad_sched;
 
+/* Per-rating loss l(r, d) of a rating r at prediction d = <w_i, h_j> (section 2: the method
+ * takes any separable loss; the paper works with the square loss).  The updates of section
+ * 2.3 use the residual e = -dl/dd in place of r - d:
+ *   SQUARE    l = (r - d)^2 / 2, e = r - d;
+ *   LOGISTIC  l = log(1 + exp(-r d)) for labels r = +-1, e = r / (1 + exp(r d)) (computed in
+ *             FP32 with the fast exponential).
+ * nomad_eval_rmse's objective J sums l + lambda/2 (|w_i|^2 + |h_j|^2) over the ratings; its
+ * RMSE is that of d against r whatever the loss. */
+typedef enum { NOMAD_LOSS_SQUARE = 0, NOMAD_LOSS_LOGISTIC = 1 } nomad_loss;
+
 /* Storage type of W in device memory (H is always held in FP32); arithmetic is always
  * FP32.  NOMAD_BF16: W is rounded to bfloat16 once at nomad_init (nearest-even) and every
  * updated w_i is rounded to bfloat16 before it is stored, by the nomad_round rule:
@@ -142,6 +152,7 @@ typedef struct {
                                 (the resident factor, H, is the one stored in bfloat16; W is then
                                 FP32).  Pays off when rows are fewer than columns.  ENOTIMPL in
                                 batches. */
+    int32_t loss;            /* nomad_loss; batches use NOMAD_LOSS_SQUARE (ENOTIMPL otherwise) */
     uint64_t seed;      /* initial item placement g(j) = splitmix64(seed ^ j) mod p, routing,
                            stochastic rounding */
 } nomad_config;
@@ -185,7 +196,9 @@ nomad_status nomad_train_epochs(nomad_ctx *ctx, int32_t epochs, nomad_stats *out
  * with FP64 dot products and a deterministic compensated (Neumaier) sum.  If
  * objective_out is not NULL it also receives
  * J = 1/2 sum [ (A_ij - <w_i,h_j>)^2 + lambda (|w_i|^2 + |h_j|^2) ] over the same entries
- * (eq. obj_fcn in its per-rating form).  nnz = 0 gives NaN.  Indices are checked. */
+ * (eq. obj_fcn in its per-rating form), or with the logistic loss (nomad_config.loss)
+ * J = sum [ log(1 + exp(-A_ij <w_i,h_j>)) + lambda/2 (|w_i|^2 + |h_j|^2) ].  nnz = 0 gives
+ * NaN.  Indices are checked. */
 nomad_status nomad_eval_rmse(nomad_ctx *ctx, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
                              const float *d_val, double *rmse_out, double *objective_out);
 

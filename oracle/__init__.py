@@ -86,6 +86,18 @@ def _load():
         lib.orc_rmse.argtypes = [i64, i64, i64, P, P, P, i32, P, P, P]
         lib.orc_objective.restype = C.c_int
         lib.orc_objective.argtypes = [i64, i64, i64, P, P, P, i32, dbl, P, P, P]
+        lib.orc_objective_loss.restype = C.c_int
+        lib.orc_objective_loss.argtypes = [i64, i64, i64, P, P, P, i32, dbl, P, P, P, i32]
+        lib.orc_train_ring_loss.restype = C.c_int
+        lib.orc_train_ring_loss.argtypes = common + [i32, i32, P, P, P, i32]
+        lib.orc_replay_loss.restype = C.c_int
+        lib.orc_replay_loss.argtypes = common + [i64, P, P, P, P, P, P, P, i32]
+        lib.orc_residual.restype = dbl
+        lib.orc_residual.argtypes = [dbl, dbl, i32]
+        lib.orc_loss.restype = dbl
+        lib.orc_loss.argtypes = [dbl, dbl, i32]
+        lib.orc_update_loss.restype = None
+        lib.orc_update_loss.argtypes = [i32, P, P, dbl, dbl, dbl, i32]
         _lib = lib
     return _lib
 
@@ -154,10 +166,29 @@ def partition(m, row, p):
     return out
 
 
+LOSS = {"square": 0, "logistic": 1}
+
+
+def residual(r, d, loss="square") -> float:
+    return float(_load().orc_residual(float(r), float(d), LOSS[loss]))
+
+
+def loss_value(r, d, loss="square") -> float:
+    return float(_load().orc_loss(float(r), float(d), LOSS[loss]))
+
+
+def update_loss(w, h, r, s, lam, loss="square"):
+    """One update of copies of w and h (FP64) under the given loss."""
+    w = np.array(w, dtype=np.float64, copy=True)
+    h = np.array(h, dtype=np.float64, copy=True)
+    _load().orc_update_loss(w.size, _p(w), _p(h), float(r), float(s), float(lam), LOSS[loss])
+    return w, h
+
+
 def train_ring(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, epoch0=0,
-               interleave_seed=None):
+               interleave_seed=None, loss="square"):
     """Fixed token-passing order; with interleave_seed, the same orders under a random
-    asynchronous interleaving.  Returns (W, H, stats)."""
+    asynchronous interleaving (square loss only).  Returns (W, H, stats)."""
     row, col, val = _coo(row, col, val)
     W = _factors(W0, m, hp.k)
     H = _factors(H0, n, hp.k)
@@ -166,8 +197,9 @@ def train_ring(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, epochs, epoch0=0
     args = (m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha, hp.beta, hp.gamma,
             p, seed, epoch0, epochs)
     if interleave_seed is None:
-        _check(lib.orc_train_ring(*args, _p(W), _p(H), C.byref(st)))
+        _check(lib.orc_train_ring_loss(*args, _p(W), _p(H), C.byref(st), LOSS[loss]))
     else:
+        assert loss == "square"
         _check(lib.orc_train_ring_interleaved(*args, interleave_seed, _p(W), _p(H), C.byref(st)))
     return W, H, st
 
@@ -279,15 +311,15 @@ def train_threaded(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, max_updates,
     return W, H, st, sec.value
 
 
-def replay(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, tq, tj, tt, tseq):
+def replay(m, n, row, col, val, W0, H0, hp: Hyper, p, seed, tq, tj, tt, tseq, loss="square"):
     row, col, val = _coo(row, col, val)
     W = _factors(W0, m, hp.k)
     H = _factors(H0, n, hp.k)
     tq, tj, tt, tseq = (np.ascontiguousarray(np.asarray(a, dtype=np.int32)) for a in (tq, tj, tt, tseq))
     st = Stats()
-    _check(_load().orc_replay(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha, hp.beta,
-                              hp.gamma, p, seed, tq.size, _p(tq), _p(tj), _p(tt), _p(tseq), _p(W), _p(H),
-                              C.byref(st)))
+    _check(_load().orc_replay_loss(m, n, row.size, _p(row), _p(col), _p(val), hp.k, hp.lam, hp.alpha, hp.beta,
+                                   hp.gamma, p, seed, tq.size, _p(tq), _p(tj), _p(tt), _p(tseq), _p(W), _p(H),
+                                   C.byref(st), LOSS[loss]))
     return W, H, st
 
 
@@ -306,11 +338,11 @@ def rmse(m, n, row, col, val, W, H) -> float:
     return out.value
 
 
-def objective(m, n, row, col, val, W, H, lam) -> float:
+def objective(m, n, row, col, val, W, H, lam, loss="square") -> float:
     row, col, val = _coo(row, col, val)
     W = np.ascontiguousarray(W, dtype=np.float64)
     H = np.ascontiguousarray(H, dtype=np.float64)
     out = C.c_double()
-    _check(_load().orc_objective(m, n, row.size, _p(row), _p(col), _p(val), W.shape[1], float(lam),
-                                 _p(W), _p(H), C.byref(out)))
+    _check(_load().orc_objective_loss(m, n, row.size, _p(row), _p(col), _p(val), W.shape[1], float(lam),
+                                      _p(W), _p(H), C.byref(out), LOSS[loss]))
     return out.value

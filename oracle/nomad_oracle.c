@@ -17,6 +17,12 @@
  *                       gradient of the squared loss, so the update adds it), w_i (not w_j)
  *                       in the h-update, one residual shared by both updates, and the h
  *                       step uses the pre-update w_i (simultaneous update).
+ *   orc_residual, orc_loss, orc_update_loss -- the same update for a general separable
+ *                       loss (section 2 states the method for any; the conclusion writes the
+ *                       objective as a sum of per-rating terms): e = -d loss / d <w,h>.
+ *                       Square loss (the paper's) and the logistic loss of labels +-1.
+ *                       orc_train_ring_loss, orc_replay_loss and orc_objective_loss take
+ *                       the loss; the functions without the suffix use the square loss.
  *   orc_step         -- step-size schedule eq. (stepsize_method), section 5.1, with the
  *                       exponent generalised to gamma (the paper uses 1.5).
  *   orc_partition    -- row partition I_1..I_p of section 3.1, in the "same number of
@@ -104,17 +110,46 @@ double orc_step(double alpha, double beta, double gamma, double t)
     return alpha / (1.0 + beta * pow(t, gamma));
 }
 
-/* One SGD update on rating r of (w, h) with step s. */
-void orc_update(int32_t k, double *w, double *h, double r, double s, double lambda)
+/* The residual e = -d loss(r, d) / d d of one rating at prediction d = <w, h>.  The
+ * method takes any separable loss (section 2; the objective as a sum of per-rating terms in
+ * the conclusion); loss 0 is the square loss (r - d)^2 / 2 the paper works with, so
+ * e = r - d; loss 1 is the logistic loss log(1 + exp(-r d)) of labels r = +-1, so
+ * e = r / (1 + exp(r d)). */
+double orc_residual(double r, double d, int32_t loss)
+{
+    if (loss == 1) return r / (1.0 + exp(r * d));
+    return r - d;
+}
+
+/* The per-rating loss itself (without the regulariser): (r - d)^2 / 2, or
+ * log(1 + exp(-r d)) written as max(z, 0) + log1p(exp(-|z|)) with z = -r d. */
+double orc_loss(double r, double d, int32_t loss)
+{
+    if (loss == 1) {
+        double z = -r * d;
+        return (z > 0.0 ? z : 0.0) + log1p(exp(-fabs(z)));
+    }
+    return 0.5 * (r - d) * (r - d);
+}
+
+/* One SGD update on rating r of (w, h) with step s (section 2.3: one residual, both
+ * vectors from their values before the update), for the given loss. */
+void orc_update_loss(int32_t k, double *w, double *h, double r, double s, double lambda, int32_t loss)
 {
     double d = 0.0;
     for (int32_t l = 0; l < k; ++l) d += w[l] * h[l];
-    double e = r - d;
+    double e = orc_residual(r, d, loss);
     for (int32_t l = 0; l < k; ++l) {
         double wl = w[l], hl = h[l];
         w[l] = wl + s * (e * hl - lambda * wl);
         h[l] = hl + s * (e * wl - lambda * hl);
     }
+}
+
+/* The square-loss update. */
+void orc_update(int32_t k, double *w, double *h, double r, double s, double lambda)
+{
+    orc_update_loss(k, w, h, r, s, lambda, 0);
 }
 
 /* row_start[q] = smallest i with (#ratings in rows < i) >= ceil(q*nnz/p), q = 1..p-1;
@@ -178,6 +213,7 @@ typedef struct {
     int32_t *nhold;   /* number of workers holding ratings of item j */
     /* per item, its visits in ring order: ivis[istart[j]..istart[j+1]) index visits[] */
     int64_t *istart, *ivis;
+    int32_t loss;     /* the per-rating loss of the updates (orc_residual); 0 unless set */
 } layout;
 
 static int cmp_qsji(const void *a, const void *b)
@@ -310,7 +346,7 @@ static void apply_visit(const layout *L, const visit *V, int32_t k, double *W, d
         const rating *x = &L->ratings[e];
         int own_row = (x->i >= L->row_start[V->q] && x->i < L->row_start[V->q + 1]);
         if (st && (!own_row || !holder_ok)) st->violations++;
-        orc_update(k, W + (int64_t)x->i * k, h, x->r, s, lambda);
+        orc_update_loss(k, W + (int64_t)x->i * k, h, x->r, s, lambda, L->loss);
         if (st) st->updates++;
     }
     if (st && V->end > V->begin) st->visits++;
@@ -325,16 +361,18 @@ static int check_common(int32_t k, int32_t p, int32_t epochs)
 /* Fixed token-passing order.  For e in epochs, s in 0..p-1, q in 0..p-1: worker q
  * processes, in ascending item order, the items of group (q+s) mod p; t = epoch0 + e
  * (every rating is updated exactly once per epoch). */
-int orc_train_ring(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
-                   const float *val, int32_t k, double lambda, double alpha, double beta,
-                   double gamma, int32_t p, uint64_t seed, int32_t epoch0, int32_t epochs,
-                   double *W, double *H, orc_stats *st)
+int orc_train_ring_loss(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                        const float *val, int32_t k, double lambda, double alpha, double beta,
+                        double gamma, int32_t p, uint64_t seed, int32_t epoch0, int32_t epochs,
+                        double *W, double *H, orc_stats *st, int32_t loss)
 {
     int rc = check_common(k, p, epochs);
     if (rc) return rc;
+    if (loss != 0 && loss != 1) return ORC_EINVAL;
     layout L;
     rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
     if (rc) return rc;
+    L.loss = loss;
     if (st) memset(st, 0, sizeof(*st));
     /* cursor[q] walks worker q's visits, which are sorted by sub-step */
     int64_t *cursor = (int64_t *)malloc(sizeof(int64_t) * ((size_t)p + 1));
@@ -355,6 +393,15 @@ int orc_train_ring(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const 
     free(cursor);
     layout_free(&L);
     return ORC_OK;
+}
+
+int orc_train_ring(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                   const float *val, int32_t k, double lambda, double alpha, double beta,
+                   double gamma, int32_t p, uint64_t seed, int32_t epoch0, int32_t epochs,
+                   double *W, double *H, orc_stats *st)
+{
+    return orc_train_ring_loss(m, n, nnz, row, col, val, k, lambda, alpha, beta, gamma, p, seed, epoch0, epochs,
+                               W, H, st, 0);
 }
 
 /* The ring order with t = the number of updates applied before the visit (globally,
@@ -981,17 +1028,19 @@ out:
  * tj[x] with step index tt[x], as the tseq[x]-th visit of that item.  Records of one
  * worker are given in that worker's execution order.  A record runs once every earlier
  * record of its worker has run and the item has completed tseq[x] visits. */
-int orc_replay(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
-               const float *val, int32_t k, double lambda, double alpha, double beta,
-               double gamma, int32_t p, uint64_t seed, int64_t nrec, const int32_t *tq,
-               const int32_t *tj, const int32_t *tt, const int32_t *tseq, double *W, double *H,
-               orc_stats *st)
+int orc_replay_loss(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                    const float *val, int32_t k, double lambda, double alpha, double beta,
+                    double gamma, int32_t p, uint64_t seed, int64_t nrec, const int32_t *tq,
+                    const int32_t *tj, const int32_t *tt, const int32_t *tseq, double *W, double *H,
+                    orc_stats *st, int32_t loss)
 {
     int rc = check_common(k, p, 0);
     if (rc) return rc;
+    if (loss != 0 && loss != 1) return ORC_EINVAL;
     layout L;
     rc = layout_build(&L, m, n, nnz, row, col, val, p, seed);
     if (rc) return rc;
+    L.loss = loss;
     if (st) memset(st, 0, sizeof(*st));
     int64_t *wcount = (int64_t *)calloc((size_t)p + 1, sizeof(int64_t));
     int64_t *wptr = (int64_t *)calloc((size_t)p + 1, sizeof(int64_t));
@@ -1030,6 +1079,16 @@ out:
     return rc;
 }
 
+int orc_replay(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+               const float *val, int32_t k, double lambda, double alpha, double beta,
+               double gamma, int32_t p, uint64_t seed, int64_t nrec, const int32_t *tq,
+               const int32_t *tj, const int32_t *tt, const int32_t *tseq, double *W, double *H,
+               orc_stats *st)
+{
+    return orc_replay_loss(m, n, nnz, row, col, val, k, lambda, alpha, beta, gamma, p, seed, nrec, tq, tj, tt,
+                           tseq, W, H, st, 0);
+}
+
 /* ------------------------------------------------------------------------------- */
 /* Evaluation: FP64 dot products, Neumaier-compensated sums.                        */
 /* ------------------------------------------------------------------------------- */
@@ -1063,19 +1122,27 @@ int orc_rmse(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_
     return ORC_OK;
 }
 
-/* J(W,H) = 1/2 sum over ratings of [ (A_ij - <w_i,h_j>)^2 + lambda (|w_i|^2 + |h_j|^2) ]. */
-int orc_objective(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
-                  const float *val, int32_t k, double lambda, const double *W, const double *H,
-                  double *out)
+/* J(W,H) = sum over ratings of [ loss(A_ij, <w_i,h_j>) + lambda/2 (|w_i|^2 + |h_j|^2) ];
+ * with the square loss, 1/2 sum of [ (A_ij - <w_i,h_j>)^2 + lambda (|w_i|^2 + |h_j|^2) ]. */
+int orc_objective_loss(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                       const float *val, int32_t k, double lambda, const double *W, const double *H,
+                       double *out, int32_t loss)
 {
-    if (k <= 0) return ORC_EINVAL;
+    if (k <= 0 || (loss != 0 && loss != 1)) return ORC_EINVAL;
     double sum = 0.0, comp = 0.0;
     for (int64_t e = 0; e < nnz; ++e) {
         if (row[e] < 0 || row[e] >= m || col[e] < 0 || col[e] >= n) return ORC_EINVAL;
         const double *w = W + (int64_t)row[e] * k, *h = H + (int64_t)col[e] * k;
-        double err = (double)val[e] - dot(w, h, k);
-        neumaier_add(&sum, &comp, 0.5 * (err * err + lambda * (dot(w, w, k) + dot(h, h, k))));
+        double f = orc_loss((double)val[e], dot(w, h, k), loss);
+        neumaier_add(&sum, &comp, f + 0.5 * lambda * (dot(w, w, k) + dot(h, h, k)));
     }
     *out = sum + comp;
     return ORC_OK;
+}
+
+int orc_objective(int64_t m, int64_t n, int64_t nnz, const int32_t *row, const int32_t *col,
+                  const float *val, int32_t k, double lambda, const double *W, const double *H,
+                  double *out)
+{
+    return orc_objective_loss(m, n, nnz, row, col, val, k, lambda, W, H, out, 0);
 }

@@ -21,6 +21,7 @@ SCHED = {"ring": 0, "perm": 1, "uniform": 2}
 DTYPE = {"fp32": 0, "bf16": 1}
 ROUND = {"rne": 0, "stochastic": 1}
 T_SOURCE = {"pair": 0, "global": 1}
+LOSS = {"square": 0, "logistic": 1}
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESTATE", 5: "ENOTIMPL"}
 
 
@@ -30,7 +31,8 @@ class NomadConfig(C.Structure):
                 ("workers", C.c_int32), ("waves_per_worker", C.c_int32), ("item_slots", C.c_int32),
                 ("window", C.c_int32),
                 ("record_trace", C.c_int32), ("collect_stats", C.c_int32), ("debug_ownership", C.c_int32),
-                ("t_source", C.c_int32), ("balance", C.c_int32), ("transpose", C.c_int32), ("seed", C.c_uint64)]
+                ("t_source", C.c_int32), ("balance", C.c_int32), ("transpose", C.c_int32), ("loss", C.c_int32),
+                ("seed", C.c_uint64)]
 
 
 class NomadProblemDesc(C.Structure):
@@ -155,7 +157,7 @@ class Stats:
 def make_config(k: int, lam: float, alpha: float, beta: float, gamma: float, *, sched="ring", dtype="fp32",
                 rounding="rne", workers=0, waves_per_worker=0, item_slots=0, window=0, record_trace=False,
                 collect_stats=False, debug_ownership=False, t_source="pair", balance=False,
-                transpose=False, seed=0) -> NomadConfig:
+                transpose=False, loss="square", seed=0) -> NomadConfig:
     cfg = NomadConfig()
     load().nomad_config_default(C.byref(cfg))
     cfg.k, cfg.lambda_, cfg.alpha, cfg.beta, cfg.gamma = k, lam, alpha, beta, gamma
@@ -168,6 +170,7 @@ def make_config(k: int, lam: float, alpha: float, beta: float, gamma: float, *, 
     cfg.t_source = T_SOURCE[t_source]
     cfg.balance = int(bool(balance))
     cfg.transpose = int(bool(transpose))
+    cfg.loss = LOSS[loss]
     cfg.seed = seed
     return cfg
 

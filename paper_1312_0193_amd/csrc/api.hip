@@ -201,7 +201,7 @@ nomad_status choose_shape(const nomad_config *cfg, int32_t kp, int32_t wbytes, n
         return fail(ec, NOMAD_EINVAL, "nomad_init: %d compute waves, %d item slots and a window of %d rows need "
                     "%zu bytes of LDS for padded k=%d, device allows %d", nw, slots, window, lds, kp, max_lds);
     int32_t maxw = 0;
-    hipError_t he = nomad::train_max_workers(kp, nw, slots, window, wbytes, &maxw, async);
+    hipError_t he = nomad::train_max_workers(kp, nw, slots, window, wbytes, &maxw, async, cfg->loss);
     if (he != hipSuccess) return hip_fail(ec, he, "nomad_init: occupancy query");
     out->kp = kp;
     out->nw = nw;
@@ -238,6 +238,7 @@ void nomad_config_default(nomad_config *cfg) {
     cfg->t_source = 0;
     cfg->balance = 0;
     cfg->transpose = 0;
+    cfg->loss = NOMAD_LOSS_SQUARE;
     cfg->seed = 0;
 }
 
@@ -282,6 +283,10 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
         return fail(nullptr, NOMAD_EINVAL, "nomad_init: transpose=%d is not 0 or 1", cfg->transpose);
     if (cfg->transpose == 1 && forced)
         return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init_batched: transpose=1 is per problem only");
+    if (cfg->loss != NOMAD_LOSS_SQUARE && cfg->loss != NOMAD_LOSS_LOGISTIC)
+        return fail(nullptr, NOMAD_EINVAL, "nomad_init: loss=%d is not a nomad_loss", cfg->loss);
+    if (cfg->loss != NOMAD_LOSS_SQUARE && forced)
+        return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init_batched: batches use the square loss");
     if (cfg->balance == 1 && cfg->sched == NOMAD_SCHED_RING)
         return fail(nullptr, NOMAD_ENOTIMPL, "nomad_init: balance=1 needs an asynchronous schedule (the ring order "
                     "is fixed)");
@@ -440,6 +445,7 @@ static void fill_args(nomad_ctx *c, nomad::TrainArgs &a) {
     a.owner = c->holder;
     a.counters = c->counters;
     a.gstep = c->cfg.t_source == 1 ? 1 : 0;
+    a.loss = c->cfg.loss;
     a.W = c->W;
     a.H = c->H;
     a.recs = c->plan.recs;
@@ -742,7 +748,8 @@ nomad_status nomad_eval_rmse(nomad_ctx *c, int64_t nnz, const int32_t *d_row, co
     double sq = 0.0, obj = 0.0;
     int bad = 0;
     if (nnz > 0) {
-        HIPTRY(c, nomad::eval_sums(c->W, c->wbytes, c->H, c->k, c->kp, c->m, c->n, nnz, d_row, d_col, d_val, c->cfg.lambda, &sq,
+        HIPTRY(c, nomad::eval_sums(c->W, c->wbytes, c->H, c->k, c->kp, c->m, c->n, nnz, d_row, d_col, d_val,
+                                   c->cfg.lambda, c->cfg.loss, &sq,
                                    &obj, &bad, c->eval_scratch, c->eval_scratch_bytes, c->stream),
                "eval");
         if (bad) return fail(c, NOMAD_EINVAL, "nomad_eval_rmse: rating index out of range");
@@ -779,7 +786,7 @@ nomad_status nomad_eval_rmse_noalloc(nomad_ctx *c, int64_t nnz, const int32_t *d
                     c->device, kMaxDevices);
     }
     HIPTRY(c, nomad::eval_sums_noalloc(c->W, c->wbytes, c->H, c->k, c->kp, c->m, c->n, nnz, d_row, d_col, d_val,
-                                       c->cfg.lambda, ptr, d_out, c->stream),
+                                       c->cfg.lambda, c->cfg.loss, ptr, d_out, c->stream),
            "nomad_eval_rmse_noalloc");
     return NOMAD_OK;
 }

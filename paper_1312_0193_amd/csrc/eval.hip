@@ -1,5 +1,5 @@
-// Test RMSE (section 5.1) and objective J(W,H) (eq. obj_fcn, per-rating form) with FP64
-// dot products and compensated (Neumaier) sums.  The entry-to-thread assignment and the
+// Test RMSE (section 5.1) and objective J(W,H) (eq. obj_fcn, per-rating form, with the
+// context's per-rating loss) with FP64 dot products and compensated (Neumaier) sums.  The entry-to-thread assignment and the
 // reduction tree are fixed, so the result does not depend on timing.
 #include "nomad_internal.h"
 
@@ -35,8 +35,8 @@ __device__ __forceinline__ double w_at(const void *W, int32_t wbytes, int64_t x)
 __global__ __launch_bounds__(kThreads) void k_eval_partial(const void *W, int32_t wbytes, const float *H, int32_t k,
                                                           int32_t kp, int64_t m, int64_t n, int64_t nnz,
                                                           const int32_t *row, const int32_t *col,
-                                                          const float *val, double lambda, Comp *part,
-                                                          int32_t *bad) {
+                                                          const float *val, double lambda, int32_t loss,
+                                                          Comp *part, int32_t *bad) {
     __shared__ Comp sq[kThreads], ob[kThreads];
     Comp a{0.0, 0.0}, b{0.0, 0.0};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -57,7 +57,13 @@ __global__ __launch_bounds__(kThreads) void k_eval_partial(const void *W, int32_
         }
         const double err = (double)val[e] - d;
         neu_add(a, err * err);
-        neu_add(b, 0.5 * (err * err + lambda * (ww + hh)));
+        if (loss == 1) {
+            // logistic loss log(1 + exp(z)), z = -r d, as max(z, 0) + log1p(exp(-|z|))
+            const double z = -(double)val[e] * d;
+            neu_add(b, (z > 0.0 ? z : 0.0) + log1p(exp(-fabs(z))) + 0.5 * lambda * (ww + hh));
+        } else {
+            neu_add(b, 0.5 * (err * err + lambda * (ww + hh)));
+        }
     }
     sq[threadIdx.x] = a;
     ob[threadIdx.x] = b;
@@ -164,7 +170,7 @@ hipError_t noalloc_scratch_address(void **ptr) {
 
 hipError_t eval_sums_noalloc(const void *W, int32_t wbytes, const float *H, int32_t k, int32_t kp, int64_t m,
                              int64_t n, int64_t nnz, const int32_t *row, const int32_t *col, const float *val,
-                             double lambda, void *scratch_ptr, double *d_out, hipStream_t st) {
+                             double lambda, int32_t loss, void *scratch_ptr, double *d_out, hipStream_t st) {
     // one block of the partial pass per kNoallocEntriesPerBlock entries (the caller has
     // checked nnz <= noalloc_max_nnz())
     const int64_t want = (nnz + kNoallocEntriesPerBlock - 1) / kNoallocEntriesPerBlock;
@@ -176,7 +182,7 @@ hipError_t eval_sums_noalloc(const void *W, int32_t wbytes, const float *H, int3
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_eval_partial, dim3(blocks), dim3(kThreads), 0, st, W, wbytes, H, k, kp, m, n, nnz, row,
-                       col, val, lambda, part, bad);
+                       col, val, lambda, loss, part, bad);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_eval_final, dim3(1), dim3(kThreads), 0, st, part, blocks, sums);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -186,7 +192,7 @@ hipError_t eval_sums_noalloc(const void *W, int32_t wbytes, const float *H, int3
 
 hipError_t eval_sums(const void *W, int32_t wbytes, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,
                      int64_t nnz, const int32_t *row, const int32_t *col, const float *val,
-                     double lambda, double *h_sq_err, double *h_obj, int *h_bad_index, void *scratch,
+                     double lambda, int32_t loss, double *h_sq_err, double *h_obj, int *h_bad_index, void *scratch,
                      size_t scratch_bytes, hipStream_t st) {
     if (scratch_bytes < eval_scratch_bytes()) return hipErrorInvalidValue;
     Comp *part = (Comp *)scratch;
@@ -195,7 +201,7 @@ hipError_t eval_sums(const void *W, int32_t wbytes, const float *H, int32_t k, i
     hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_eval_partial, dim3(kBlocks), dim3(kThreads), 0, st, W, wbytes, H, k, kp, m, n, nnz, row,
-                       col, val, lambda, part, bad);
+                       col, val, lambda, loss, part, bad);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_eval_final, dim3(1), dim3(kThreads), 0, st, part, kBlocks, out);
     if ((e = hipGetLastError()) != hipSuccess) return e;

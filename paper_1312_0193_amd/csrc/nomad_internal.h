@@ -173,6 +173,7 @@ struct TrainArgs {
     uint32_t *qhead;            // p: entries each worker has taken from its queue (published for
                                 // the load-balanced choice; queue length = qtail - qhead)
     int32_t balance;            // 1: section 3.3's dynamic load balancing of the next worker
+    int32_t loss;               // per-rating loss: 0 square, 1 logistic (the kernels are compiled per loss)
     int32_t *istate;            // n x 4: state of each item, written by its holder before it moves on:
                                 //   [0] permutation: epoch of the next visit; uniform: moves so far
                                 //   [1] permutation: positions of the epoch's visiting order used
@@ -232,7 +233,7 @@ hipError_t launch_batch_epochs(TrainArgs *d_descs, int32_t nprob, int32_t epochs
                                hipStream_t stream);
 // Workers of `nw` compute waves that can be resident at once on the device.
 hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
-                             int32_t *max_workers, bool async = false);
+                             int32_t *max_workers, bool async = false, int32_t loss = 0);
 // The row window the asynchronous kernel's LDS layout is built for (its rows are in
 // registers; the layout keeps the ring kernel's shape).
 constexpr int kAsyncWindow = 8;
@@ -242,7 +243,7 @@ inline int32_t padded_k(int32_t k) { return k <= 64 ? 64 : (k <= 128 ? 128 : 256
 // eval.hip: FP64 RMSE / objective with a deterministic compensated sum.
 hipError_t eval_sums(const void *W, int32_t wbytes, const float *H, int32_t k, int32_t kp, int64_t m, int64_t n,
                      int64_t nnz, const int32_t *row, const int32_t *col, const float *val,
-                     double lambda, double *h_sq_err, double *h_obj, int *h_bad_index,
+                     double lambda, int32_t loss, double *h_sq_err, double *h_obj, int *h_bad_index,
                      void *scratch, size_t scratch_bytes, hipStream_t stream);
 // FP32 rows (width k) to bfloat16 rows (width kp; nearest-even), and back (exact).
 hipError_t to_bf16(const float *src, int32_t k, uint16_t *dst, int32_t kp, int64_t rows, hipStream_t st);
@@ -257,6 +258,6 @@ size_t noalloc_scratch_bytes();
 hipError_t noalloc_scratch_address(void **ptr);
 hipError_t eval_sums_noalloc(const void *W, int32_t wbytes, const float *H, int32_t k, int32_t kp, int64_t m,
                              int64_t n, int64_t nnz, const int32_t *row, const int32_t *col, const float *val,
-                             double lambda, void *scratch_ptr, double *d_out, hipStream_t stream);
+                             double lambda, int32_t loss, void *scratch_ptr, double *d_out, hipStream_t stream);
 
 }  // namespace nomad

@@ -47,6 +47,16 @@ __device__ __forceinline__ float rl_f(float v, int lane) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
 }
 
+// The residual e = -d loss(r, d) / d d of one rating at prediction d (section 2: the method
+// takes any separable loss; the updates of section 2.3 read e in place of r - d).  LOSS 0:
+// the square loss, e = r - d.  LOSS 1: the logistic loss log(1 + exp(-r d)) of labels +-1,
+// e = r / (1 + exp(r d)) (exp overflowing to infinity gives e = 0, its limit).
+template <int LOSS>
+__device__ __forceinline__ float residual(float r, float d) {
+    if constexpr (LOSS == 1) return r / (1.0f + __expf(r * d));
+    else return r - d;
+}
+
 // Sum of x over the wavefront, valid in lane 63 only: a butterfly within each 16-lane row
 // with DPP (every lane of row r then holds its row sum S_r), then the row broadcasts add
 // lane 15 into row 1 and lane 47 into row 3, and lane 31 into row 3, so that lane 63 holds
@@ -437,7 +447,7 @@ __device__ __forceinline__ void round_stored(const TrainArgs &a, int loff, float
     }
 }
 
-template <int VEC, int D, bool BF>
+template <int VEC, int D, bool BF, int LOSS>
 struct ComputeWave {
     static_assert(2 * (D - 2) <= 63 && D >= 4, "vmcnt range");
     static constexpr int ES = BF ? 2 : 4;  // bytes per stored element of W
@@ -611,7 +621,7 @@ struct ComputeWave {
             an = rec_next(an);
             vi = rec_read_rf(ai);
             ai = rec_next(ai);
-            const float se = rl_f(s * (rc.r - d), 63);
+            const float se = rl_f(s * residual<LOSS>(rc.r, d), 63);
             float nw[VEC];
 #pragma unroll
             for (int v = 0; v < VEC; ++v) {
@@ -1052,7 +1062,7 @@ __device__ __forceinline__ void row_gload(const char *p, float (&v)[VEC]) {
 // read 64 at a time into lane registers (one vector load; lane l holds the l-th); the row
 // of the next rating is loaded while the current one is updated (rows of one visit are
 // distinct, so the load never overtakes a store of the same row).
-template <int VEC, bool BF>
+template <int VEC, bool BF, int LOSS>
 struct AsyncComputeWave {
     static constexpr int ES = BF ? 2 : 4;
     const TrainArgs &a;
@@ -1097,7 +1107,7 @@ struct AsyncComputeWave {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) d = fmaf(wv[i], h[i], d);
         d = wave_sum_last(d);
-        const float se = rl_f(s * (rating - d), 63);
+        const float se = rl_f(s * residual<LOSS>(rating, d), 63);
         float nw[VEC];
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
@@ -1593,7 +1603,7 @@ struct AsyncMemoryWave {
     }
 };
 
-template <int VEC, int D, bool BF>
+template <int VEC, int D, bool BF, int LOSS>
 __global__ __launch_bounds__(1024) void k_worker_async(TrainArgs a) {
     extern __shared__ float4 lds4[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1605,7 +1615,7 @@ __global__ __launch_bounds__(1024) void k_worker_async(TrainArgs a) {
     __syncthreads();
     if (q >= a.p || a.epochs <= 0) return;
     if (wave < a.nw) {
-        AsyncComputeWave<VEC, BF> cw(a, L, q, wave, lane, a.rbase[(int64_t)q * a.nw + wave]);
+        AsyncComputeWave<VEC, BF, LOSS> cw(a, L, q, wave, lane, a.rbase[(int64_t)q * a.nw + wave]);
         cw.run();
     } else if (wave == a.nw) {
         AsyncMemoryWave mw(a, L, q, lane);
@@ -1666,7 +1676,7 @@ __global__ void k_seed_write(TrainArgs a, int64_t n, const uint32_t *key_s, cons
 }
 
 // One worker: workgroup q of the problem described by `a`.
-template <int VEC, int D, bool BF>
+template <int VEC, int D, bool BF, int LOSS>
 __device__ __forceinline__ void worker_body(const TrainArgs &a, int q) {
     extern __shared__ float4 lds4[];
     // The wave index is the same in every lane: say so, so that everything derived from it
@@ -1680,7 +1690,7 @@ __device__ __forceinline__ void worker_body(const TrainArgs &a, int q) {
     if (q >= a.p || a.epochs <= 0) return;
     if (wave < a.nw) {
         const int64_t i0 = a.rbase[(int64_t)q * a.nw + wave], i1 = a.rbase[(int64_t)q * a.nw + wave + 1];
-        ComputeWave<VEC, D, BF> cw(a, L, q, wave, lane, i0, i1 - i0);
+        ComputeWave<VEC, D, BF, LOSS> cw(a, L, q, wave, lane, i0, i1 - i0);
         cw.run();
     } else if (wave == a.nw) {
         MemoryWave mw(a, L, q, lane);
@@ -1688,9 +1698,9 @@ __device__ __forceinline__ void worker_body(const TrainArgs &a, int q) {
     }
 }
 
-template <int VEC, int D, bool BF>
+template <int VEC, int D, bool BF, int LOSS>
 __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
-    worker_body<VEC, D, BF>(a, blockIdx.x);
+    worker_body<VEC, D, BF, LOSS>(a, blockIdx.x);
 }
 
 // Several independent problems in one launch: workgroup g runs worker g - wg0 of problem
@@ -1699,56 +1709,63 @@ template <int VEC, int D, bool BF>
 __global__ __launch_bounds__(1024) void k_worker_batch(const TrainArgs *__restrict__ descs,
                                                        const int32_t *__restrict__ wg_prob) {
     const TrainArgs a = descs[wg_prob[blockIdx.x]];
-    worker_body<VEC, D, BF>(a, (int)blockIdx.x - a.wg0);
+    worker_body<VEC, D, BF, 0>(a, (int)blockIdx.x - a.wg0);  // batches use the square loss
 }
 
-// A batched launch when `descs` is given (a.p then = total workgroups), else one problem.
-template <int VEC, int D, bool BF>
+// A batched launch when `descs` is given (a.p then = total workgroups; square loss only),
+// else one problem.
+template <int VEC, int D, bool BF, int LOSS>
 hipError_t launch_t(const TrainArgs &a, const TrainArgs *descs, const int32_t *wg_prob, hipStream_t st) {
     const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D, BF ? 2 : 4);
-    if (descs)
-        hipLaunchKernelGGL((k_worker_batch<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, descs, wg_prob);
-    else
-        hipLaunchKernelGGL((k_worker<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    if constexpr (LOSS == 0) {
+        if (descs) {
+            hipLaunchKernelGGL((k_worker_batch<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, descs,
+                               wg_prob);
+            return hipGetLastError();
+        }
+    } else {
+        if (descs) return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL((k_worker<VEC, D, BF, LOSS>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
     return hipGetLastError();
 }
 
-template <int VEC, bool BF>
+template <int VEC, bool BF, int LOSS>
 const void *pick_d(int window) {
-    if (window <= 8) return (const void *)k_worker<VEC, 8, BF>;
-    if (window <= 16) return (const void *)k_worker<VEC, 16, BF>;
-    return (const void *)k_worker<VEC, 32, BF>;
+    if (window <= 8) return (const void *)k_worker<VEC, 8, BF, LOSS>;
+    if (window <= 16) return (const void *)k_worker<VEC, 16, BF, LOSS>;
+    return (const void *)k_worker<VEC, 32, BF, LOSS>;
 }
 
-template <bool BF>
+template <bool BF, int LOSS>
 const void *pick_kernel(int kp, int window) {
-    if (kp <= 64) return pick_d<1, BF>(window);
-    if (kp <= 128) return pick_d<2, BF>(window);
-    return pick_d<4, BF>(window);
+    if (kp <= 64) return pick_d<1, BF, LOSS>(window);
+    if (kp <= 128) return pick_d<2, BF, LOSS>(window);
+    return pick_d<4, BF, LOSS>(window);
 }
 
-template <int VEC, bool BF>
+template <int VEC, bool BF, int LOSS>
 hipError_t launch_v(const TrainArgs &a, const TrainArgs *d, const int32_t *g, hipStream_t st) {
-    if (a.window <= 8) return launch_t<VEC, 8, BF>(a, d, g, st);
-    if (a.window <= 16) return launch_t<VEC, 16, BF>(a, d, g, st);
-    return launch_t<VEC, 32, BF>(a, d, g, st);
+    if (a.window <= 8) return launch_t<VEC, 8, BF, LOSS>(a, d, g, st);
+    if (a.window <= 16) return launch_t<VEC, 16, BF, LOSS>(a, d, g, st);
+    return launch_t<VEC, 32, BF, LOSS>(a, d, g, st);
 }
 
-template <bool BF>
+template <bool BF, int LOSS>
 hipError_t launch_b(const TrainArgs &a, const TrainArgs *d, const int32_t *g, hipStream_t st) {
-    if (a.kp <= 64) return launch_v<1, BF>(a, d, g, st);
-    if (a.kp <= 128) return launch_v<2, BF>(a, d, g, st);
-    return launch_v<4, BF>(a, d, g, st);
+    if (a.kp <= 64) return launch_v<1, BF, LOSS>(a, d, g, st);
+    if (a.kp <= 128) return launch_v<2, BF, LOSS>(a, d, g, st);
+    return launch_v<4, BF, LOSS>(a, d, g, st);
 }
 
 }  // namespace
 
 namespace {
-template <bool BF>
+template <bool BF, int LOSS>
 const void *pick_async(int kp) {
-    if (kp <= 64) return (const void *)k_worker_async<1, kAsyncWindow, BF>;
-    if (kp <= 128) return (const void *)k_worker_async<2, kAsyncWindow, BF>;
-    return (const void *)k_worker_async<4, kAsyncWindow, BF>;
+    if (kp <= 64) return (const void *)k_worker_async<1, kAsyncWindow, BF, LOSS>;
+    if (kp <= 128) return (const void *)k_worker_async<2, kAsyncWindow, BF, LOSS>;
+    return (const void *)k_worker_async<4, kAsyncWindow, BF, LOSS>;
 }
 }  // namespace
 
@@ -1757,15 +1774,18 @@ size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window, in
 }
 
 hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
-                             int32_t *max_workers, bool async) {
+                             int32_t *max_workers, bool async, int32_t loss) {
     int dev = 0, cus = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     if (async) window = kAsyncWindow;
-    const void *kern = async ? (wbytes == 2 ? pick_async<true>(kp) : pick_async<false>(kp))
-                             : (wbytes == 2 ? pick_kernel<true>(kp, window) : pick_kernel<false>(kp, window));
+    const void *kern =
+        loss == 1 ? (async ? (wbytes == 2 ? pick_async<true, 1>(kp) : pick_async<false, 1>(kp))
+                           : (wbytes == 2 ? pick_kernel<true, 1>(kp, window) : pick_kernel<false, 1>(kp, window)))
+                  : (async ? (wbytes == 2 ? pick_async<true, 0>(kp) : pick_async<false, 0>(kp))
+                           : (wbytes == 2 ? pick_kernel<true, 0>(kp, window) : pick_kernel<false, 0>(kp, window)));
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 64 * (nw + 1), lds_bytes(kp, nw, slots, window, wbytes));
     if (e != hipSuccess) return e;
     *max_workers = nb * cus;
@@ -1773,28 +1793,31 @@ hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t wind
 }
 
 hipError_t launch_train(const TrainArgs &a, hipStream_t st) {
-    return a.wbytes == 2 ? launch_b<true>(a, nullptr, nullptr, st) : launch_b<false>(a, nullptr, nullptr, st);
+    if (a.loss == 1)
+        return a.wbytes == 2 ? launch_b<true, 1>(a, nullptr, nullptr, st) : launch_b<false, 1>(a, nullptr, nullptr, st);
+    return a.wbytes == 2 ? launch_b<true, 0>(a, nullptr, nullptr, st) : launch_b<false, 0>(a, nullptr, nullptr, st);
 }
 
 namespace {
-template <int VEC, int D, bool BF>
+template <int VEC, int D, bool BF, int LOSS>
 hipError_t launch_async_t(const TrainArgs &a, hipStream_t st) {
     const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D, BF ? 2 : 4);
-    hipLaunchKernelGGL((k_worker_async<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
     return hipGetLastError();
 }
-template <int VEC, bool BF>
+template <int VEC, bool BF, int LOSS>
 hipError_t launch_async_v(const TrainArgs &a, hipStream_t st) {
-    return launch_async_t<VEC, kAsyncWindow, BF>(a, st);  // the row window of the LDS layout is not used here
+    return launch_async_t<VEC, kAsyncWindow, BF, LOSS>(a, st);  // the row window of the LDS layout is not used here
 }
-template <bool BF>
+template <bool BF, int LOSS>
 hipError_t launch_async_k(const TrainArgs &a, hipStream_t st) {
-    if (a.kp <= 64) return launch_async_v<1, BF>(a, st);
-    if (a.kp <= 128) return launch_async_v<2, BF>(a, st);
-    return launch_async_v<4, BF>(a, st);
+    if (a.kp <= 64) return launch_async_v<1, BF, LOSS>(a, st);
+    if (a.kp <= 128) return launch_async_v<2, BF, LOSS>(a, st);
+    return launch_async_v<4, BF, LOSS>(a, st);
 }
 hipError_t launch_async_b(const TrainArgs &a, hipStream_t st) {
-    return a.wbytes == 2 ? launch_async_k<true>(a, st) : launch_async_k<false>(a, st);
+    if (a.loss == 1) return a.wbytes == 2 ? launch_async_k<true, 1>(a, st) : launch_async_k<false, 1>(a, st);
+    return a.wbytes == 2 ? launch_async_k<true, 0>(a, st) : launch_async_k<false, 0>(a, st);
 }
 }  // namespace
 
@@ -1864,7 +1887,7 @@ hipError_t launch_train_batch(const TrainArgs &shape, int32_t workgroups, const 
                               const int32_t *d_wg_prob, hipStream_t st) {
     TrainArgs a = shape;
     a.p = workgroups;
-    return a.wbytes == 2 ? launch_b<true>(a, d_descs, d_wg_prob, st) : launch_b<false>(a, d_descs, d_wg_prob, st);
+    return a.wbytes == 2 ? launch_b<true, 0>(a, d_descs, d_wg_prob, st) : launch_b<false, 0>(a, d_descs, d_wg_prob, st);
 }
 
 }  // namespace nomad
