@@ -50,6 +50,12 @@ GOLDEN_RMSE = os.path.join(ROOT, "tests", "golden", "medium_perm_rmse.json")
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_1312_0193_amd", "csrc", "train.hip")
+WORKLOADS = {
+    "medium": "medium: 480189x17770, 100M Zipf(1.1) cells, 1.4M held out, int 1-5 ratings, k=100, lambda=0.05",
+    "large": "large: 1000990x624961, 252.8M Zipf(1.1) cells, 1.4% held out, ratings 0-100, k=100, lambda=1",
+    "very_tall": "very tall: 50000000x39780, 2.74B Zipf(1.1) cells in 16 row blocks, 1.4% held out, real ratings, "
+                 "k=100, lambda=0.01",
+}
 KERNELS = {"perm": "k_worker_async", "uniform": "k_worker_async", "ring": "k_worker"}
 COPY_BYTES = 2 << 30  # calibration copy: 2 GiB read + 2 GiB written per dispatch
 
@@ -60,18 +66,19 @@ def kernel_source_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def counters_path(kernel: str, sched: str) -> str:
-    """The counter summary of `kernel` on the medium workload under schedule `sched`
-    (uniform routing has its own: the same kernel moves different bytes there)."""
+def counters_path(kernel: str, sched: str, workload: str = "medium", dtype: str = "fp32") -> str:
+    """The counter summary of `kernel` on `workload` under schedule `sched` (uniform routing
+    has its own: the same kernel moves different bytes there) and W storage `dtype`."""
     tag = "_uniform" if sched == "uniform" else ""
-    return os.path.join(ROOT, "profiles", f"{kernel}_medium{tag}_counters.txt")
+    dtag = "_bf16" if dtype == "bf16" else ""
+    return os.path.join(ROOT, "profiles", f"{kernel}_{workload}{tag}{dtag}_counters.txt")
 
 
-def measured_traffic(kernel: str, sched: str):
+def measured_traffic(kernel: str, sched: str, workload: str = "medium", dtype: str = "fp32"):
     """HBM bytes per training launch from the committed rocprofv3 counter summary, each
     counter scaled by what it reads for a plain copy of known size; None when the
     summary is missing or was taken on a different kernel source."""
-    path = counters_path(kernel, sched)
+    path = counters_path(kernel, sched, workload, dtype)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -177,6 +184,10 @@ def main():
                     help="perm: asynchronous random-permutation circulation; uniform: asynchronous uniform "
                          "routing (Algorithm 1 as printed; an epoch = |training ratings| updates); ring: fixed "
                          "token-passing order")
+    ap.add_argument("--workload", choices=["medium", "large", "very_tall"], default="medium",
+                    help="medium (the benchmark), large (Yahoo-shaped) or very_tall (Hugewiki-shaped, 2.7 B ratings)")
+    ap.add_argument("--dtype", choices=["fp32", "bf16"], default=None,
+                    help="storage of W (bf16: stochastic rounding); default fp32, bf16 for very_tall")
     ap.add_argument("--balance", action="store_true",
                     help="dynamic load balancing of the asynchronous schedules (section 3.3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -199,17 +210,21 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     t = time.perf_counter()
-    prob = synth.medium(device=dev)
+    gen = {"medium": (synth.medium, 2), "large": (synth.large, 3), "very_tall": (synth.very_tall, 5)}
+    make, seed = gen[args.workload]
+    prob = make(device=dev)
     hp = prob.hp
-    W0, H0 = synth.init_factors(prob.m, prob.n, hp["k"], 2, device=dev)
+    W0, H0 = synth.init_factors(prob.m, prob.n, hp["k"], seed, device=dev)
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # the generator's temporaries go back before the layout allocates
+    dtype = args.dtype or ("bf16" if args.workload == "very_tall" else "fp32")
+    dkw = dict(dtype="bf16", rounding="stochastic") if dtype == "bf16" else {}
     log(f"generated m={prob.m} n={prob.n} train={prob.nnz} test={prob.test_row.numel()} "
         f"in {time.perf_counter() - t:.1f} s")
-    seed = 2
     model = nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp["k"], lam=hp["lam"],
                      alpha=hp["alpha"], beta=hp["beta"], gamma=hp["gamma"], workers=args.workers, seed=seed,
                      waves_per_worker=args.waves, item_slots=args.item_slots, sched=args.sched,
-                     balance=args.balance)
+                     balance=args.balance, **dkw)
     P = model.workers
     st0 = model.train(0)
     log(f"layout {st0.layout_seconds:.3f} s, workers {P}")
@@ -235,11 +250,11 @@ def main():
     epochs_trained = args.warmup + args.steps
     log(f"test RMSE after {epochs_trained} epochs: {rmse:.5f}")
     V = visits_per_epoch(prob.row, prob.col, prob.n, model.partition())
-    B = bytes_per_update(hp["k"], 4, 4, V, nnz)
+    B = bytes_per_update(hp["k"], 2 if dtype == "bf16" else 4, 4, V, nnz)
     gold = json.load(open(GOLDEN_RMSE)) if os.path.exists(GOLDEN_RMSE) else None
     matched = None
-    if (gold and args.sched == "perm" and not args.balance and gold["workers"] == P
-            and gold["epochs"] == epochs_trained):
+    if (gold and args.workload == "medium" and dtype == "fp32" and args.sched == "perm" and not args.balance
+            and gold["workers"] == P and gold["epochs"] == epochs_trained):
         matched = {"oracle_test_rmse": gold["test_rmse"], "gap": rmse - gold["test_rmse"],
                    "epochs": gold["epochs"], "oracle": "random-permutation emulation, FP64, same inputs"}
     if matched is not None:
@@ -261,7 +276,7 @@ def main():
     avg_kernel = sum(ksec) / len(ksec)
     achieved = B * (updates / args.steps) / avg_kernel
     kernel = KERNELS[args.sched]
-    traffic = measured_traffic(kernel, args.sched)
+    traffic = measured_traffic(kernel, args.sched, args.workload, dtype)
     out = {
         "metric": METRIC,
         "value": value,
@@ -273,10 +288,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if dtype == "fp32" else "f32 (W stored bf16)",
         "data": "synthetic",
-        "config": {"workload": "medium: 480189x17770, 100M Zipf(1.1) cells, 1.4M held out, int 1-5 ratings, "
-                               f"k=100, lambda=0.05, {args.sched} schedule{' with load balancing' if args.balance else ''}, FP32",
+        "config": {"workload": f"{WORKLOADS[args.workload]}, {args.sched} schedule"
+                               f"{' with load balancing' if args.balance else ''}, "
+                               + ("FP32" if dtype == "fp32" else "W in BF16 (stochastic rounding), FP32 arithmetic"),
                    "global_batch": nnz, "workers": P, "waves_per_worker": model.cfg.waves_per_worker,
                    "item_slots": model.cfg.item_slots, "test_rmse": rmse, "matched_rmse": matched,
                    "epochs_trained": epochs_trained, "visits_per_epoch": V,
@@ -288,7 +304,8 @@ def main():
     model.close()
     if not args.no_cpu_baseline:
         W0c, H0c = W0.cpu(), H0.cpu()
-        out["cpu_baseline"] = cpu_baseline(prob, W0c, H0c, hp, P, seed, args.sched)
+        out["cpu_baseline"] = cpu_baseline(prob, W0c, H0c, hp, P, seed, args.sched,
+                                           row_fraction={"medium": 0.1, "large": 0.04, "very_tall": 0.004}[args.workload])
     print(json.dumps(out), flush=True)
 
 

@@ -124,7 +124,9 @@ typedef struct {
                                 a worker claims when it takes the item over (it must find the
                                 item free) and frees when it passes the item on (it must find
                                 its own claim), and every rating a compute wave updates must be
-                                of a row the wave owns.  Costs two atomics per visit. */
+                                of a row the wave owns (the ring order checks a wave's ratings
+                                once per launch, before its update loop, and counts a violation
+                                per epoch).  Costs two atomics per visit. */
     int32_t t_source;        /* what t counts in s_t: 0 = earlier updates of the same (i,j) pair
                                 (section 5.1; the default), 1 = all updates applied before the
                                 visit since nomad_init, in the run's serial order (the global

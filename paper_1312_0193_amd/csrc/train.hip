@@ -468,9 +468,7 @@ struct ComputeWave {
     int64_t bpos = 0;         // stream position of the next record batch
     int bent = 0;             // ring entry of the next record batch
     uint64_t forwarded = 0, t_wait = 0;
-    // ownership checks: a rating's row must lie in [own_lo, own_lo + own_span); a span of
-    // 2^32 - 1 admits every row (checks off)
-    uint32_t own_lo = 0, own_span = 0xFFFFFFFFu, viol = 0;
+    uint32_t viol = 0;  // ownership checks: ratings of rows the wave does not own
 
     __device__ ComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0, int64_t cnt_)
         : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC), rb(a_.kp * ES),
@@ -531,8 +529,21 @@ struct ComputeWave {
         if (total <= 0) return;
         const uint64_t t_start = tick(a.timing);
         if (a.owner) {
-            own_lo = (uint32_t)a.wave_start[(int64_t)q * a.nw + w];
-            own_span = (uint32_t)(a.wave_start[(int64_t)q * a.nw + w + 1] - a.wave_start[(int64_t)q * a.nw + w]);
+            // Ownership (section 3.1), checked once for the launch and outside the update
+            // loop: every rating of the wave's stream, which is the sequence of ratings it
+            // updates (each once per epoch), must be of a row the wave owns.
+            const int64_t lo = a.wave_start[(int64_t)q * a.nw + w], hi = a.wave_start[(int64_t)q * a.nw + w + 1];
+            uint32_t bad = 0;
+            for (int64_t p0 = 0; p0 < cnt; p0 += 64) {
+                const int64_t pos = p0 + lane;
+                bool b = false;
+                if (pos < cnt) {
+                    const int64_t r = rs[pos].row;
+                    b = r < lo || r >= hi;
+                }
+                bad += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(b));
+            }
+            viol = bad * (uint32_t)a.epochs;
         }
         load_batch();
         load_batch();
@@ -591,7 +602,6 @@ struct ComputeWave {
             const uint32_t ifwd = (uint32_t)__builtin_amdgcn_readfirstlane((int)vi.y);
             const int X = xbase + (int)(rc.info & kInfoXMask);
             const int slot = X & (a.slots - 1);
-            viol += (uint32_t)rc.row - own_lo >= own_span;
             if (rc.info & kInfoFirst) {
                 // This wave's part of visit X starts: wait for the item, from the memory
                 // wave (first wave of the visit) or from the wave before.
@@ -1082,6 +1092,69 @@ struct AsyncComputeWave {
     // The lane's part of row `row` (uniform).
     __device__ __forceinline__ char *lane_row(int row) const { return W + (int64_t)row * rb + lb; }
 
+    // Row addresses of a batch of records: lane l holds the address of record l's row,
+    // formed once per batch (one vector multiply-add for 64 rows), and row(x) takes record
+    // x's out of the lanes into scalar registers, where the row's load and, later, its store
+    // use it with the lane's offset (no 64-bit multiply per access).
+    struct RowAddr {
+        uint32_t lo, hi;
+        __device__ __forceinline__ uint64_t row(int x) const {
+            return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)hi, x) << 32) |
+                   (uint32_t)__builtin_amdgcn_readlane((int)lo, x);
+        }
+    };
+    // The lane's part of the row at uniform address `base`: global-memory accesses with the
+    // row's address in scalar registers and the lane's 32-bit byte offset.
+    typedef __attribute__((address_space(1))) char gchar;
+    __device__ __forceinline__ void gload(uint64_t base, float (&v)[VEC]) const {
+        const gchar *p = (const gchar *)base + lb;
+        if constexpr (!BF) {
+            if constexpr (VEC == 1) v[0] = *(const __attribute__((address_space(1))) float *)p;
+            if constexpr (VEC == 2) {
+                const f32x2v t = *(const __attribute__((address_space(1))) f32x2v *)p;
+                v[0] = t.x;
+                v[1] = t.y;
+            }
+            if constexpr (VEC == 4) {
+                const f32x4v t = *(const __attribute__((address_space(1))) f32x4v *)p;
+                v[0] = t.x;
+                v[1] = t.y;
+                v[2] = t.z;
+                v[3] = t.w;
+            }
+        } else if constexpr (VEC == 1) {
+            v[0] = __uint_as_float((uint32_t)*(const __attribute__((address_space(1))) uint16_t *)p << 16);
+        } else if constexpr (VEC == 2) {
+            const uint32_t t = *(const __attribute__((address_space(1))) uint32_t *)p;
+            v[0] = __uint_as_float(t << 16);
+            v[1] = __uint_as_float(t & 0xFFFF0000u);
+        } else {
+            const u32x2v t = *(const __attribute__((address_space(1))) u32x2v *)p;
+            v[0] = __uint_as_float(t.x << 16);
+            v[1] = __uint_as_float(t.x & 0xFFFF0000u);
+            v[2] = __uint_as_float(t.y << 16);
+            v[3] = __uint_as_float(t.y & 0xFFFF0000u);
+        }
+    }
+    __device__ __forceinline__ void gstore(uint64_t base, const float (&v)[VEC]) const {
+        gchar *p = (gchar *)base + lb;
+        if constexpr (!BF) {
+            if constexpr (VEC == 1) *(__attribute__((address_space(1))) float *)p = v[0];
+            if constexpr (VEC == 2) *(__attribute__((address_space(1))) f32x2v *)p = f32x2v{v[0], v[1]};
+            if constexpr (VEC == 4) *(__attribute__((address_space(1))) f32x4v *)p = f32x4v{v[0], v[1], v[2], v[3]};
+        } else if constexpr (VEC == 1) {
+            *(__attribute__((address_space(1))) uint16_t *)p = (uint16_t)(__float_as_uint(v[0]) >> 16);
+        } else if constexpr (VEC == 2) {
+            *(__attribute__((address_space(1))) uint32_t *)p = bf_pair<VEC>(v, 0);
+        } else {
+            *(__attribute__((address_space(1))) u32x2v *)p = u32x2v{bf_pair<VEC>(v, 0), bf_pair<VEC>(v, 2)};
+        }
+    }
+    __device__ __forceinline__ RowAddr row_addresses(int crow) const {
+        const uint64_t ad = (uint64_t)(uintptr_t)W + (uint64_t)(uint32_t)crow * (uint64_t)(uint32_t)rb;
+        return RowAddr{(uint32_t)ad, (uint32_t)(ad >> 32)};
+    }
+
     // Wait until visit X reaches this wave.  False when the worker stops with no such visit.
     __device__ __forceinline__ bool wait_visit(const int32_t *word, int X) {
         if (sync_load(word) > X) return true;
@@ -1101,8 +1174,8 @@ struct AsyncComputeWave {
     }
 
     // One update (section 2.3: one residual, both vectors from their values before it).
-    __device__ __forceinline__ void update(float (&h)[VEC], const float (&wv)[VEC], int row, float rating, float s,
-                                           float sl, int item, int t) {
+    __device__ __forceinline__ void update(float (&h)[VEC], const float (&wv)[VEC], int row, uint64_t rowp,
+                                           float rating, float s, float sl, int item, int t) {
         float d = 0.0f;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) d = fmaf(wv[i], h[i], d);
@@ -1118,7 +1191,7 @@ struct AsyncComputeWave {
             h[i] = fmaf(se, wv[i], fmaf(-sl, h[i], h[i]));
         }
         round_stored<VEC, BF>(a, loff, nw, row, item, t);
-        row_gstore<VEC, BF>(lane_row(row), nw);
+        gstore(rowp, nw);
     }
 
     // The wave's record range of visit X, left in LDS by the memory wave ([b, e); b = e when
@@ -1207,11 +1280,14 @@ struct AsyncComputeWave {
                     // conditional load or store makes it wait for everything).
                     constexpr int NB = 16;
                     float wbuf[NB][VEC];
-                    int rbuf[NB];
+                    int rbuf[NB];     // row indices (the stochastic rounding key uses them)
+                    uint64_t abuf[NB];  // row addresses (uniform)
+                    const RowAddr ra = row_addresses(crow);
 #pragma unroll
                     for (int k = 0; k < NB; ++k) {
                         rbuf[k] = __builtin_amdgcn_readlane(crow, k < nb ? k : nb - 1);
-                        row_gload<VEC, BF>(lane_row(rbuf[k]), wbuf[k]);
+                        abuf[k] = ra.row(k < nb ? k : nb - 1);
+                        gload(abuf[k], wbuf[k]);
                         // every lane, no branch; a different value each time, so that no
                         // store is merged into another
                         if (k + 1 < NB) a.dummy[(int64_t)q * kMaxWaves + w] = (float)k;
@@ -1220,17 +1296,18 @@ struct AsyncComputeWave {
                     for (; l + NB <= nb; l += NB) {
 #pragma unroll
                         for (int k = 0; k < NB; ++k) {
-                            update(h, wbuf[k], rbuf[k],
+                            update(h, wbuf[k], rbuf[k], abuf[k],
                                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, slam, item, t);
                             const int nl = l + k + NB;
                             rbuf[k] = __builtin_amdgcn_readlane(crow, nl < nb ? nl : nb - 1);
-                            row_gload<VEC, BF>(lane_row(rbuf[k]), wbuf[k]);
+                            abuf[k] = ra.row(nl < nb ? nl : nb - 1);
+                            gload(abuf[k], wbuf[k]);
                         }
                     }
 #pragma unroll
                     for (int k = 0; k < NB - 1; ++k)
                         if (l + k < nb)
-                            update(h, wbuf[k], rbuf[k],
+                            update(h, wbuf[k], rbuf[k], abuf[k],
                                    __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, slam, item, t);
                 }
                 nrat += (uint64_t)(e - b);
