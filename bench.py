@@ -37,13 +37,18 @@ def bytes_per_update(k: int, s_w: int, s_h: int, visits: int, nnz_train: int) ->
     return 12.0 + 2.0 * k * s_w + 2.0 * k * s_h * visits / nnz_train
 
 
-def visits_per_epoch(row, col, n: int, row_start) -> int:
-    """(worker, item) pairs that share ratings under the row partition `row_start`."""
+def visits_per_epoch(row, col, n: int, row_start, chunk: int = 1 << 28) -> int:
+    """(worker, item) pairs that share ratings under the row partition `row_start`: a flag
+    per pair, set chunk by chunk (torch's kernels take at most 2^31 elements at once)."""
     import torch
 
     rs = torch.as_tensor(row_start, dtype=torch.int64, device=row.device)
-    q = torch.searchsorted(rs, row.to(torch.int64), right=True) - 1
-    return int(torch.unique(q * n + col.to(torch.int64)).numel())
+    p = rs.numel() - 1
+    seen = torch.zeros(p * n, dtype=torch.bool, device=row.device)
+    for c0 in range(0, row.numel(), chunk):
+        q = torch.searchsorted(rs, row[c0:c0 + chunk].to(torch.int64), right=True) - 1
+        seen[q * n + col[c0:c0 + chunk].to(torch.int64)] = True
+    return int(seen.sum().item())
 
 
 GOLDEN_RMSE = os.path.join(ROOT, "tests", "golden", "medium_perm_rmse.json")
@@ -125,9 +130,12 @@ def host_cpu() -> dict:
     return info
 
 
-def cpu_baseline(prob, W0, H0, hp, P, seed, sched, row_fraction=0.1, max_threads=16):
-    """The FP64 oracle on a bounded sample: the ratings of the first row_fraction of the
-    rows (rows carry random Zipf weights, so this is a uniform row sample).
+def cpu_baseline(prob, W0, H0, hp, P, seed, sched, row_fraction=0.1, col_fraction=1.0, max_threads=16):
+    """The FP64 oracle on a bounded sample: the ratings in the leading block of rows
+    [0, row_fraction*m) x columns [0, col_fraction*n).  Rows and columns carry Zipf weights in
+    random order, so the block is a uniform sample of both.  The fractions are chosen per
+    workload so that a worker finds tens of ratings per visit of an item, as in the medium
+    workload: with fewer, the threaded run is mostly mutex hand-offs of empty visits.
       * threaded: Algorithm 1 literally on all host cores (one POSIX thread per worker,
         mutex-protected FIFO queues, uniform recipients), as many epochs' worth of updates as
         take about ten seconds; the headline CPU figure;
@@ -138,38 +146,109 @@ def cpu_baseline(prob, W0, H0, hp, P, seed, sched, row_fraction=0.1, max_threads
     import oracle
 
     m_s = max(1, int(prob.m * row_fraction))
-    row = prob.row.cpu().numpy()
-    sel = row < m_s
-    r, c, v = row[sel], prob.col.cpu().numpy()[sel], prob.val.cpu().numpy()[sel]
-    W = W0[:m_s].cpu().numpy()
-    H = H0.cpu().numpy()
+    n_s = max(1, int(prob.n * col_fraction))
+    # selected on the device, in chunks (torch indexes at most 2^31 elements at once): the
+    # full arrays never cross PCIe
+    parts = []
+    for c0 in range(0, prob.row.numel(), 1 << 28):
+        rr, cc, vv = (x[c0:c0 + (1 << 28)] for x in (prob.row, prob.col, prob.val))
+        sel = (rr < m_s) & (cc < n_s)
+        parts.append(tuple(x[sel].cpu() for x in (rr, cc, vv)))
+    r, c, v = (np.concatenate([p[i].numpy() for p in parts]) for i in range(3))
+    del parts
+    W = W0[:m_s].float().cpu().numpy()
+    H = H0[:n_s].float().cpu().numpy()
     f = lambda x: float(np.float32(x))  # noqa: E731
     h = oracle.Hyper(hp["k"], f(hp["lam"]), f(hp["alpha"]), f(hp["beta"]), f(hp["gamma"]))
     cpu = host_cpu()
     threads = max(1, min(int(cpu.get("nproc") or 1), max_threads))
-    log(f"cpu baseline: oracle on rows [0,{m_s}) = {r.size} ratings; threaded on {threads} cores")
+    log(f"cpu baseline: oracle on rows [0,{m_s}) x columns [0,{n_s}) = {r.size} ratings; "
+        f"threaded on {threads} cores")
     # a short run sizes the timed one to about ten seconds
-    _, _, st, tsec = oracle.train_threaded(m_s, prob.n, r, c, v, W, H, h, threads, seed, 2 * r.size, 1)
+    _, _, st, tsec = oracle.train_threaded(m_s, n_s, r, c, v, W, H, h, threads, seed, 2 * r.size, 1)
     budget = int(min(200, max(2, round(10.0 * st.updates / max(tsec, 1e-9) / max(r.size, 1))))) * r.size
-    _, _, st, tsec = oracle.train_threaded(m_s, prob.n, r, c, v, W, H, h, threads, seed, budget, 1)
+    _, _, st, tsec = oracle.train_threaded(m_s, n_s, r, c, v, W, H, h, threads, seed, budget, 1)
     t0 = time.perf_counter()
+    oracle.set_progress(2_000_000)  # the oracle reports its progress on stderr meanwhile
     if sched == "perm":
-        oracle.train_perm(m_s, prob.n, r, c, v, W, H, h, P, seed, 1, 1)
+        oracle.train_perm(m_s, n_s, r, c, v, W, H, h, P, seed, 1, 1)
     elif sched == "uniform":
-        oracle.train_uniform(m_s, prob.n, r, c, v, W, H, h, P, seed, r.size, 1)
+        oracle.train_uniform(m_s, n_s, r, c, v, W, H, h, P, seed, r.size, 1)
     else:
-        oracle.train_ring(m_s, prob.n, r, c, v, W, H, h, P, seed, 1)
+        oracle.train_ring(m_s, n_s, r, c, v, W, H, h, P, seed, 1)
     dt = time.perf_counter() - t0
+    oracle.set_progress(0)
     what = {"perm": "random-permutation schedule (asynchronous emulation)",
             "uniform": "uniform routing (asynchronous emulation, |sample| updates)", "ring": "ring order"}[sched]
     return {"value": st.updates / tsec, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": f"Algorithm 1 on {threads} POSIX threads (one worker each, FIFO queues, uniform "
                       f"recipients), FP64, {st.updates} updates over rows [0,{m_s}) of the workload "
-                      f"({r.size} ratings), layout excluded, {tsec:.1f} s",
+                      f"x columns [0,{n_s}) ({r.size} ratings), layout excluded, {tsec:.1f} s",
             "updates_per_core_s": st.updates / tsec / threads,
             "serial": {"value": r.size / dt, "unit": "updates/s", "cores": 1,
-                       "sample": f"1 epoch, {what}, {P} workers, FP64, same rows, layout included, {dt:.1f} s"},
+                       "sample": f"1 epoch, {what}, {P} workers, FP64, same sample, layout included, {dt:.1f} s"},
             "host": cpu}
+
+
+def bench_batched(args, dev):
+    """The batched workload: 256 independent problems (log-uniform sizes, k in {16,32,64}),
+    each in its own ring order, all in one launch per epoch (the library's default shape)."""
+    import torch
+
+    import paper_1312_0193_amd as nm
+    import synth
+
+    t = time.perf_counter()
+    specs = synth.batched_specs()
+    probs, descs = [], []
+    for sp in specs:
+        pr = synth.batched_problem(sp, device=dev)
+        W0, H0 = synth.init_factors(pr.m, pr.n, sp["k"], sp["seed"], device=dev)
+        probs.append(pr)
+        descs.append(dict(m=pr.m, n=pr.n, row=pr.row, col=pr.col, val=pr.val, W0=W0, H0=H0, k=sp["k"], lam=sp["lam"],
+                          alpha=sp["alpha"], beta=sp["beta"], gamma=sp["gamma"]))
+    torch.cuda.synchronize()
+    nnz = sum(pr.nnz for pr in probs)
+    log(f"generated {len(probs)} problems, {nnz} training ratings in {time.perf_counter() - t:.1f} s")
+    dtype = args.dtype or "fp32"
+    dkw = dict(dtype="bf16", rounding="stochastic") if dtype == "bf16" else {}
+    t = time.perf_counter()
+    batch = nm.NomadBatch(descs, **dkw)
+    log(f"batch laid out in {time.perf_counter() - t:.1f} s: {batch.cfg.workers} workers x "
+        f"{batch.cfg.waves_per_worker} compute waves")
+    # algorithmic bytes: each problem's own, with its own visits per epoch
+    s_w = 2 if dtype == "bf16" else 4
+    total_bytes = 0.0
+    for pr, sp, view in zip(probs, specs, batch.problems):
+        V = visits_per_epoch(pr.row, pr.col, pr.n, view.partition())
+        total_bytes += bytes_per_update(sp["k"], s_w, 4, V, pr.nnz) * pr.nnz
+    for w in range(args.warmup):
+        log(f"warmup epoch {w}: {batch.train(1).seconds * 1e3:.2f} ms")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ksec, updates = [], 0
+    for _ in range(args.steps):
+        st = batch.train(1)
+        ksec.append(st.seconds)
+        updates += st.updates
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log("epoch kernel ms: " + " ".join(f"{x * 1e3:.2f}" for x in ksec))
+    avg = sum(ksec) / len(ksec)
+    achieved = total_bytes / avg
+    out = {"metric": METRIC, "value": updates / wall, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32" if dtype == "fp32" else "f32 (W stored bf16)", "data": "synthetic",
+           "config": {"workload": "batched: 256 problems, rows 1k-200k, columns 500-20k, 50k-5M uniform cells each, "
+                                  "k in {16,32,64}, lambda in {0.01,0.05,0.1}, ring order per problem",
+                      "global_batch": nnz, "workers": batch.cfg.workers,
+                      "waves_per_worker": batch.cfg.waves_per_worker, "kernel_source": kernel_source_hash()},
+           "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK, "traffic": None, "bytes_per_update": total_bytes / nnz,
+                        "kernel": "k_worker_batch", "avg_kernel_ms": avg * 1e3}}
+    batch.close()
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -184,8 +263,9 @@ def main():
                     help="perm: asynchronous random-permutation circulation; uniform: asynchronous uniform "
                          "routing (Algorithm 1 as printed; an epoch = |training ratings| updates); ring: fixed "
                          "token-passing order")
-    ap.add_argument("--workload", choices=["medium", "large", "very_tall"], default="medium",
-                    help="medium (the benchmark), large (Yahoo-shaped) or very_tall (Hugewiki-shaped, 2.7 B ratings)")
+    ap.add_argument("--workload", choices=["medium", "large", "very_tall", "batched"], default="medium",
+                    help="medium (the benchmark), large (Yahoo-shaped), very_tall (Hugewiki-shaped, 2.7 B ratings) "
+                         "or batched (256 problems in one launch)")
     ap.add_argument("--dtype", choices=["fp32", "bf16"], default=None,
                     help="storage of W (bf16: stochastic rounding); default fp32, bf16 for very_tall")
     ap.add_argument("--balance", action="store_true",
@@ -209,6 +289,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.workload == "batched":
+        bench_batched(args, dev)
+        return
     t = time.perf_counter()
     gen = {"medium": (synth.medium, 2), "large": (synth.large, 3), "very_tall": (synth.very_tall, 5)}
     make, seed = gen[args.workload]
@@ -303,9 +386,8 @@ def main():
     }
     model.close()
     if not args.no_cpu_baseline:
-        W0c, H0c = W0.cpu(), H0.cpu()
-        out["cpu_baseline"] = cpu_baseline(prob, W0c, H0c, hp, P, seed, args.sched,
-                                           row_fraction={"medium": 0.1, "large": 0.04, "very_tall": 0.004}[args.workload])
+        rf, cf = {"medium": (0.1, 1.0), "large": (1.0, 0.01), "very_tall": (0.02, 0.05)}[args.workload]
+        out["cpu_baseline"] = cpu_baseline(prob, W0, H0, hp, P, seed, args.sched, rf, cf)
     print(json.dumps(out), flush=True)
 
 
