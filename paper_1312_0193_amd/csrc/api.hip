@@ -155,7 +155,8 @@ void release(nomad_ctx *c) {
 
 // Launch shape: compute waves, item slots and row window of a worker (LDS-fitted as the
 // configuration asks), and how many workers can be resident at once.
-nomad_status choose_shape(const nomad_config *cfg, int32_t kp, int32_t wbytes, nomad::Shape *out, nomad_ctx *ec) {
+nomad_status choose_shape(const nomad_config *cfg, int32_t kp, int32_t wbytes, nomad::Shape *out, nomad_ctx *ec,
+                          bool batch = false) {
     // Workers, compute waves per worker and item slots.  By default one worker runs on
     // every CU with eight compute waves (four under the asynchronous schedules), and holds
     // up to 64 items (fewer if LDS is short).
@@ -201,7 +202,7 @@ nomad_status choose_shape(const nomad_config *cfg, int32_t kp, int32_t wbytes, n
         return fail(ec, NOMAD_EINVAL, "nomad_init: %d compute waves, %d item slots and a window of %d rows need "
                     "%zu bytes of LDS for padded k=%d, device allows %d", nw, slots, window, lds, kp, max_lds);
     int32_t maxw = 0;
-    hipError_t he = nomad::train_max_workers(kp, nw, slots, window, wbytes, &maxw, async, cfg->loss);
+    hipError_t he = nomad::train_max_workers(kp, nw, slots, window, wbytes, &maxw, async, cfg->loss, batch);
     if (he != hipSuccess) return hip_fail(ec, he, "nomad_init: occupancy query");
     out->kp = kp;
     out->nw = nw;
@@ -875,7 +876,7 @@ nomad_status nomad_init_batched(nomad_ctx **out, int32_t nprob, const nomad_prob
     if (shape_cfg.window <= 0) shape_cfg.window = 8;
     nomad::Shape sh;
     {
-        const nomad_status ss = choose_shape(&shape_cfg, kp, common->dtype == NOMAD_BF16 ? 2 : 4, &sh, nullptr);
+        const nomad_status ss = choose_shape(&shape_cfg, kp, common->dtype == NOMAD_BF16 ? 2 : 4, &sh, nullptr, true);
         if (ss != NOMAD_OK) return ss;
     }
     int32_t T = common->workers > 0 ? common->workers : std::min(sh.maxw, nomad::kMaxWorkers);

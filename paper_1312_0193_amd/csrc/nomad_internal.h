@@ -232,8 +232,9 @@ hipError_t launch_batch_reset(const TrainArgs *d_descs, int32_t nprob, hipStream
 hipError_t launch_batch_epochs(TrainArgs *d_descs, int32_t nprob, int32_t epochs, int32_t advance,
                                hipStream_t stream);
 // Workers of `nw` compute waves that can be resident at once on the device.
+// `batch`: for the batched kernel (several problems in one launch).
 hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
-                             int32_t *max_workers, bool async = false, int32_t loss = 0);
+                             int32_t *max_workers, bool async = false, int32_t loss = 0, bool batch = false);
 // The row window the asynchronous kernel's LDS layout is built for (its rows are in
 // registers; the layout keeps the ring kernel's shape).
 constexpr int kAsyncWindow = 8;

@@ -1781,9 +1781,12 @@ __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
 }
 
 // Several independent problems in one launch: workgroup g runs worker g - wg0 of problem
-// wg_prob[g]; every problem has its own layout, factors and item counters.
+// wg_prob[g]; every problem has its own layout, factors and item counters.  Built for five
+// waves per SIMD (at most 96 registers a lane), so that two workers of eight compute waves
+// and a memory wave each (18 waves) share a CU: a batch gains more from workers than from
+// registers.
 template <int VEC, int D, bool BF>
-__global__ __launch_bounds__(1024) void k_worker_batch(const TrainArgs *__restrict__ descs,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_worker_batch(const TrainArgs *__restrict__ descs,
                                                        const int32_t *__restrict__ wg_prob) {
     const TrainArgs a = descs[wg_prob[blockIdx.x]];
     worker_body<VEC, D, BF, 0>(a, (int)blockIdx.x - a.wg0);  // batches use the square loss
@@ -1821,6 +1824,20 @@ const void *pick_kernel(int kp, int window) {
     return pick_d<4, BF, LOSS>(window);
 }
 
+template <int VEC, bool BF>
+const void *pick_batch_d(int window) {
+    if (window <= 8) return (const void *)k_worker_batch<VEC, 8, BF>;
+    if (window <= 16) return (const void *)k_worker_batch<VEC, 16, BF>;
+    return (const void *)k_worker_batch<VEC, 32, BF>;
+}
+
+template <bool BF>
+const void *pick_batch(int kp, int window) {
+    if (kp <= 64) return pick_batch_d<1, BF>(window);
+    if (kp <= 128) return pick_batch_d<2, BF>(window);
+    return pick_batch_d<4, BF>(window);
+}
+
 template <int VEC, bool BF, int LOSS>
 hipError_t launch_v(const TrainArgs &a, const TrainArgs *d, const int32_t *g, hipStream_t st) {
     if (a.window <= 8) return launch_t<VEC, 8, BF, LOSS>(a, d, g, st);
@@ -1851,7 +1868,7 @@ size_t train_lds_bytes(int32_t kp, int32_t nw, int32_t slots, int32_t window, in
 }
 
 hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t window, int32_t wbytes,
-                             int32_t *max_workers, bool async, int32_t loss) {
+                             int32_t *max_workers, bool async, int32_t loss, bool batch) {
     int dev = 0, cus = 0, nb = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -1859,6 +1876,7 @@ hipError_t train_max_workers(int32_t kp, int32_t nw, int32_t slots, int32_t wind
     if (e != hipSuccess) return e;
     if (async) window = kAsyncWindow;
     const void *kern =
+        batch ? (wbytes == 2 ? pick_batch<true>(kp, window) : pick_batch<false>(kp, window)) :
         loss == 1 ? (async ? (wbytes == 2 ? pick_async<true, 1>(kp) : pick_async<false, 1>(kp))
                            : (wbytes == 2 ? pick_kernel<true, 1>(kp, window) : pick_kernel<false, 1>(kp, window)))
                   : (async ? (wbytes == 2 ? pick_async<true, 0>(kp) : pick_async<false, 0>(kp))
