@@ -111,7 +111,8 @@ typedef struct {
     int32_t rounding;   /* nomad_round, used when dtype = NOMAD_BF16 */
     int32_t workers;    /* p, number of workers (workgroups, all resident at once);
                            0 = one per compute unit */
-    int32_t waves_per_worker; /* compute wavefronts of a worker, 1..15; 0 = 8 (ring), 4 (asynchronous) */
+    int32_t waves_per_worker; /* compute wavefronts of a worker, 1..15 (1..8 under the asynchronous
+                                 schedules); 0 = 8 (ring), 4 (asynchronous) */
     int32_t item_slots;  /* items a worker holds in LDS at once: a power of two, 1..64;
                             0 = as many as LDS allows, up to 64 */
     int32_t window;      /* rows a compute wave keeps in flight: 8, 16 or 32 (other values in
@@ -247,7 +248,12 @@ nomad_status nomad_get_trace(nomad_ctx *ctx, int64_t *len, int32_t *h_buf, int64
  *                                                9 memory wave: waiting for its loads/stores
  *   10 asynchronous schedules: the XCD (accelerator complex die, 0..7 on MI355X) the worker
  *      ran on, read from the hardware's XCC_ID register
- *   11..15 zero */
+ *   asynchronous schedules, memory wave, sums over the rounds of its loop:
+ *   11 free item slots                          14 visits passed on (a total, not per round)
+ *   12 items waiting in its queue (collect_stats 15 visits held: taken over, not yet passed
+ *      = 1 only)                                   on
+ *   13 rounds in which the next queue entry was not yet written while a later one was
+ *   (the ring order leaves 10..15 zero) */
 nomad_status nomad_get_worker_stats(nomad_ctx *ctx, int64_t *h_stats, int64_t cap);
 
 /* One problem of a batch (nomad_init_batched): the arguments of nomad_init that differ

@@ -20,6 +20,7 @@ struct nomad_ctx {
     int32_t k = 0, kp = 0, p = 0;
     int32_t nw = 0, slots = 0;         // compute waves and item slots per worker
     int32_t window = 0;                // rows a compute wave keeps in flight
+    int32_t keep_rows = 0;             // asynchronous schedules: some compute wave owns a single row
     int32_t cus = 0, max_lds = 0;
     hipStream_t stream = nullptr;
     int device = 0;                    // the device current at nomad_init
@@ -168,8 +169,9 @@ nomad_status choose_shape(const nomad_config *cfg, int32_t kp, int32_t wbytes, n
     const bool async = cfg->sched == NOMAD_SCHED_PERM || cfg->sched == NOMAD_SCHED_UNIFORM;
     const int32_t nw = cfg->waves_per_worker > 0 ? cfg->waves_per_worker
                                                  : (async ? nomad::kDefaultWavesAsync : nomad::kDefaultWaves);
-    if (nw < 1 || nw > nomad::kMaxWaves)
-        return fail(ec, NOMAD_EINVAL, "nomad_init: waves_per_worker=%d outside [1,%d]", nw, nomad::kMaxWaves);
+    if (nw < 1 || nw > (async ? nomad::kMaxWavesAsync : nomad::kMaxWaves))
+        return fail(ec, NOMAD_EINVAL, "nomad_init: waves_per_worker=%d outside [1,%d]%s", nw,
+                    async ? nomad::kMaxWavesAsync : nomad::kMaxWaves, async ? " (asynchronous schedules)" : "");
     if (cfg->window < 0 || cfg->window > nomad::kMaxWindow)
         return fail(ec, NOMAD_EINVAL, "nomad_init: window=%d outside [0,%d]", cfg->window, nomad::kMaxWindow);
     // Item slots and the compute waves' row windows share the LDS: by default deep windows
@@ -423,6 +425,11 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
     if ((e = hipMemcpy(c->row_start.data(), c->plan.row_start, sizeof(int64_t) * (p + 1), hipMemcpyDeviceToHost)) !=
         hipSuccess)
         return bail(hip_fail(c, e, "nomad_init: partition copy"));
+    // A row holding more than half of a compute wave's share of the ratings dominates its
+    // wave: most of the wave's visits are then a single rating on that row, and the kernel
+    // with the kept-row path for such visits is the one launched.
+    c->keep_rows = (cfg->sched == NOMAD_SCHED_PERM || cfg->sched == NOMAD_SCHED_UNIFORM) && nnz > 0 &&
+                   2.0 * (double)c->plan.max_row_degree * p * nw > (double)nnz;
     *out = c;
     return NOMAD_OK;
 }
@@ -458,6 +465,7 @@ static void fill_args(nomad_ctx *c, nomad::TrainArgs &a) {
     a.dummy = c->dummy;
     a.diag = c->diag;
     a.kp = c->kp;
+    a.keep_rows = c->keep_rows;
     a.wbytes = c->wbytes;
     a.rounding = c->cfg.rounding == NOMAD_ROUND_STOCHASTIC ? 1 : 0;
     a.sr_seed = (uint32_t)c->cfg.seed;

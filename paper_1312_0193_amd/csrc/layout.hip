@@ -567,6 +567,20 @@ hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t
         CK(tmp.need(need));
         CK(hipcub::DeviceScan::ExclusiveSum(tmp.p, need, (const int64_t *)deg, rowptr, m + 1, st));
     }
+    if (m > 0) {
+        // the largest row degree (read when the asynchronous kernel's variant is chosen)
+        size_t need = 0;
+        unsigned long long *none = nullptr;
+        CK(hipcub::DeviceReduce::Max(nullptr, need, deg, none, m, st));
+        const size_t off = (need + 255) & ~(size_t)255;
+        CK(tmp.need(off + sizeof(unsigned long long)));
+        unsigned long long *d_max = (unsigned long long *)((char *)tmp.p + off);
+        CK(hipcub::DeviceReduce::Max(tmp.p, need, deg, d_max, m, st));
+        unsigned long long h_max = 0;
+        CK(hipMemcpyAsync(&h_max, d_max, sizeof(h_max), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        pl->max_row_degree = (int64_t)h_max;
+    }
     hipLaunchKernelGGL(k_partition, dim3((p + 1 + 63) / 64), dim3(64), 0, st, rowptr, m, nnz, p, pl->row_start);
     CK(hipGetLastError());
     hipLaunchKernelGGL(k_wave_partition, dim3(grid_for(nwt + 1)), dim3(kThreads), 0, st, rowptr, pl->row_start, m,

@@ -29,6 +29,8 @@ namespace nomad {
 
 constexpr int kMaxK = 256;          // largest latent dimension
 constexpr int kMaxWaves = 15;       // compute waves per worker (plus one memory wave)
+constexpr int kMaxWavesAsync = 8;   // the same under the asynchronous schedules (their kernel is
+                                    // built for nine waves, so that each may use 168 registers)
 constexpr int kDefaultWaves = 8;
 // Asynchronous schedules: fewer compute waves per worker leave the SIMDs to the waves that
 // carry the long runs of heavy items (on a Zipf workload 4 waves beat 8 by a fifth).
@@ -80,6 +82,12 @@ enum WStat {
     kWStatCompMax = 8,     // compute waves: longest time in the kernel
     kWStatMemWait = 9,     // memory wave: time waiting for its loads and stores
     kWStatXcd = 10,        // the accelerator complex die (XCD) the worker ran on
+    kWStatRoom = 11,       // memory wave: free item slots, summed over its rounds
+    kWStatQueueLen = 12,   // memory wave: items waiting in its queue, summed over rounds (timed)
+    kWStatBlocked = 13,    // memory wave: rounds whose next queue entry was not yet written
+                           // while a later one was
+    kWStatPassed = 14,     // memory wave: visits passed on
+    kWStatHeld = 15,       // memory wave: visits held (taken, not yet passed on), summed over rounds
     kWStatCount = 16
 };
 
@@ -108,6 +116,7 @@ struct Plan {
     VisitRec *visits = nullptr;
     int64_t nvisits = 0;            // (worker, item) visits per epoch
     int64_t max_worker_visits = 0;
+    int64_t max_row_degree = 0;     // ratings of the densest row
     // Asynchronous schedules (build_async_tables).  A worker's "local item" x is the item of
     // its visit vbase[q] + x; the ring order's record streams are grouped by local item.
     int32_t *hold = nullptr;   // nvisits holder entries, grouped by item (workers ascending): the worker
@@ -191,6 +200,8 @@ struct TrainArgs {
                                 // item or 0xFFFFFFFF
     unsigned long long *counters;  // [0] ownership violations, [1] hops, [2] global update count
     int32_t gstep;              // 1: t = global count of updates before the visit (step-size option)
+    int32_t keep_rows;          // asynchronous schedules: some compute wave owns a single row (its
+                                // single-rating visits keep that row in LDS; see train.hip)
     int32_t *trace;             // optional: 4 ints per visit
     int64_t *trace_len;         // optional counter
     int64_t trace_cap;

@@ -1072,7 +1072,7 @@ __device__ __forceinline__ void row_gload(const char *p, float (&v)[VEC]) {
 // read 64 at a time into lane registers (one vector load; lane l holds the l-th); the row
 // of the next rating is loaded while the current one is updated (rows of one visit are
 // distinct, so the load never overtakes a store of the same row).
-template <int VEC, bool BF, int LOSS>
+template <int VEC, bool BF, int LOSS, bool KEEP>
 struct AsyncComputeWave {
     static constexpr int ES = BF ? 2 : 4;
     const TrainArgs &a;
@@ -1084,10 +1084,22 @@ struct AsyncComputeWave {
     const uint32_t lb;    // the lane's byte offset inside a row
     uint64_t nrat = 0, t_wait = 0;
     uint32_t viol = 0;    // ownership checks: ratings of rows the wave does not own
+    // KEEP (layouts with a row that holds more than half of a compute wave's share of the
+    // ratings): the row of the last update of this wave's last batch, its stored value in the
+    // wave's row region of the LDS layout (unused otherwise here) and its index in `kept`
+    // (-1: none kept).  A visit whose only rating for this wave is on that row takes the row
+    // from here instead of memory: only this wave writes its rows, so the kept copy is the
+    // row's current value.  A row rated by nearly every item dominates its wave, which then
+    // gets from nearly every item a visit of one rating on that row.  The kernel is compiled
+    // with and without this path: its mere presence costs the other layouts a few percent.
+    __device__ __forceinline__ lds_float *keep() const {
+        return to_lds((float *)(L.rows + (size_t)w * (kAsyncWindow + 1) * kp * ES));
+    }
 
     __device__ AsyncComputeWave(const TrainArgs &a_, const Lds &L_, int q_, int w_, int lane_, int64_t r0)
         : a(a_), L(L_), q(q_), w(w_), lane(lane_), kp(a_.kp), loff(lane_ * VEC), rb(a_.kp * ES), rs(a_.recs + r0),
           items(to_lds(L_.items) + lane_ * VEC), W((char *)a_.W), lb((uint32_t)(lane_ * VEC * ES)) {}
+    int kept = -1;  // the kept row's index (a scalar register: the check costs no LDS round trip)
 
     // The lane's part of row `row` (uniform).
     __device__ __forceinline__ char *lane_row(int row) const { return W + (int64_t)row * rb + lb; }
@@ -1174,6 +1186,8 @@ struct AsyncComputeWave {
     }
 
     // One update (section 2.3: one residual, both vectors from their values before it).
+    // TO_KEEP: also keep the stored row in LDS as this wave's kept row.
+    template <bool TO_KEEP = false>
     __device__ __forceinline__ void update(float (&h)[VEC], const float (&wv)[VEC], int row, uint64_t rowp,
                                            float rating, float s, float sl, int item, int t) {
         float d = 0.0f;
@@ -1192,6 +1206,10 @@ struct AsyncComputeWave {
         }
         round_stored<VEC, BF>(a, loff, nw, row, item, t);
         gstore(rowp, nw);
+        if constexpr (TO_KEEP) {
+            lstore<VEC>(keep() + loff, nw);
+            kept = row;
+        }
     }
 
     // The wave's record range of visit X, left in LDS by the memory wave ([b, e); b = e when
@@ -1272,6 +1290,18 @@ struct AsyncComputeWave {
                         if (lane < pn) pre = *(const u32x2v *)(rs + pb + lane);
                         pre_X = px;
                     }
+                    if constexpr (KEEP) {
+                        if (nb == 1 && __builtin_amdgcn_readfirstlane(crow) == kept) {
+                            // one rating, on the row kept from this wave's last batch: no load
+                            const RowAddr ra = row_addresses(crow);
+                            float wv[VEC];
+                            lload<VEC>(keep() + loff, wv);
+                            update<true>(h, wv, kept, ra.row(0),
+                                         __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(crat))), s, slam,
+                                         item, t);
+                            continue;
+                        }
+                    }
                     // Sixteen row buffers: the row of rating l + 16 is loaded while rating l is
                     // updated.  Groups of four updates run in a branch-free body with
                     // unconditional loads (indices past the batch clamped to its last rating),
@@ -1304,11 +1334,17 @@ struct AsyncComputeWave {
                             gload(abuf[k], wbuf[k]);
                         }
                     }
+                    if constexpr (KEEP) kept = -1;  // kept only when the batch's last update is below
 #pragma unroll
                     for (int k = 0; k < NB - 1; ++k)
-                        if (l + k < nb)
-                            update(h, wbuf[k], rbuf[k], abuf[k],
-                                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k)), s, slam, item, t);
+                        if (l + k < nb) {
+                            const float rk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(crat), l + k));
+                            if (KEEP && l + k == nb - 1)
+                                update<KEEP>(h, wbuf[k], __builtin_amdgcn_readlane(crow, l + k), abuf[k], rk, s, slam,
+                                             item, t);
+                            else
+                                update(h, wbuf[k], rbuf[k], abuf[k], rk, s, slam, item, t);
+                        }
                 }
                 nrat += (uint64_t)(e - b);
                 lstore<VEC>(items + (size_t)sl * kp, h);
@@ -1368,6 +1404,9 @@ struct AsyncMemoryWave {
     int tbase = 0;
     float s_tab = 0.0f, c_tab = 0.0f;
     uint64_t iters = 0, misses = 0, hops = 0, viol = 0;
+    // sums over rounds: free slots, queue length (with collect_stats), rounds whose first
+    // queue entry was not yet written while a later one was, visits passed on, visits held
+    uint64_t s_room = 0, s_qlen = 0, s_hol = 0, s_nr = 0, s_held = 0;
 
     __device__ AsyncMemoryWave(const TrainArgs &a_, const Lds &L_, int q_, int lane_)
         : a(a_), L(L_), io(a_, L_, q_, lane_), q(q_), lane(lane_), S(a_.slots), uni(a_.sched == 2),
@@ -1406,6 +1445,7 @@ struct AsyncMemoryWave {
         int nr = sync_load(&L.flag[a.nw - 1]) - Xr;
         if (nr > 64) nr = 64;
         if (nr <= 0) return false;
+        s_nr += (uint64_t)nr;
         const int Smask = S - 1;
         const int X = Xr + lane;
         const int sl = X & Smask;
@@ -1501,6 +1541,13 @@ struct AsyncMemoryWave {
     __device__ __forceinline__ bool take_over() {
         int room = Xr + S - Xl;
         if (room > 64) room = 64;
+        s_held += (uint64_t)(Xl - Xr);
+        if (room > 0) s_room += (uint64_t)room;
+        if (a.timing && cap > 0) {
+            const int ql = (int)(__hip_atomic_load(a.qtail + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) -
+                                 (uint32_t)head);
+            s_qlen += (uint64_t)(ql > 0 ? ql : 0);
+        }
         if (room <= 0 || cap <= 0) return false;
         const int Smask = S - 1;
         uint64_t ent = 0;
@@ -1509,9 +1556,11 @@ struct AsyncMemoryWave {
             ent = __hip_atomic_load(a.queue + qb + (head + lane) % cap, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             valid = (uint32_t)(ent >> 32) == (uint32_t)(head + lane + 1);
         }
-        const int nt = leading_run(__builtin_amdgcn_ballot_w64(valid));
+        const uint64_t vb = __builtin_amdgcn_ballot_w64(valid);
+        const int nt = leading_run(vb);
         if (nt <= 0) {
             ++misses;
+            s_hol += vb != 0;
             return false;
         }
         const bool mine = lane < nt;
@@ -1674,14 +1723,19 @@ struct AsyncMemoryWave {
             atomicAdd(&ws[kWStatMemIters], (unsigned long long)iters);
             atomicAdd(&ws[kWStatVisits], (unsigned long long)Xl);
             atomicAdd(&ws[kWStatPollMiss], (unsigned long long)misses);
+            atomicAdd(&ws[kWStatRoom], (unsigned long long)s_room);
+            atomicAdd(&ws[kWStatQueueLen], (unsigned long long)s_qlen);
+            atomicAdd(&ws[kWStatBlocked], (unsigned long long)s_hol);
+            atomicAdd(&ws[kWStatPassed], (unsigned long long)s_nr);
+            atomicAdd(&ws[kWStatHeld], (unsigned long long)s_held);
             // hardware register XCC_ID (bits 3:0): the die this workgroup was placed on
             a.wstats[(int64_t)q * kWStatCount + kWStatXcd] = (int64_t)__builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20);
         }
     }
 };
 
-template <int VEC, int D, bool BF, int LOSS>
-__global__ __launch_bounds__(1024) void k_worker_async(TrainArgs a) {
+template <int VEC, int D, bool BF, int LOSS, bool KEEP>
+__global__ __launch_bounds__(64 * (kMaxWavesAsync + 1)) void k_worker_async(TrainArgs a) {
     extern __shared__ float4 lds4[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
@@ -1692,7 +1746,7 @@ __global__ __launch_bounds__(1024) void k_worker_async(TrainArgs a) {
     __syncthreads();
     if (q >= a.p || a.epochs <= 0) return;
     if (wave < a.nw) {
-        AsyncComputeWave<VEC, BF, LOSS> cw(a, L, q, wave, lane, a.rbase[(int64_t)q * a.nw + wave]);
+        AsyncComputeWave<VEC, BF, LOSS, KEEP> cw(a, L, q, wave, lane, a.rbase[(int64_t)q * a.nw + wave]);
         cw.run();
     } else if (wave == a.nw) {
         AsyncMemoryWave mw(a, L, q, lane);
@@ -1857,9 +1911,9 @@ hipError_t launch_b(const TrainArgs &a, const TrainArgs *d, const int32_t *g, hi
 namespace {
 template <bool BF, int LOSS>
 const void *pick_async(int kp) {
-    if (kp <= 64) return (const void *)k_worker_async<1, kAsyncWindow, BF, LOSS>;
-    if (kp <= 128) return (const void *)k_worker_async<2, kAsyncWindow, BF, LOSS>;
-    return (const void *)k_worker_async<4, kAsyncWindow, BF, LOSS>;
+    if (kp <= 64) return (const void *)k_worker_async<1, kAsyncWindow, BF, LOSS, false>;
+    if (kp <= 128) return (const void *)k_worker_async<2, kAsyncWindow, BF, LOSS, false>;
+    return (const void *)k_worker_async<4, kAsyncWindow, BF, LOSS, false>;
 }
 }  // namespace
 
@@ -1897,7 +1951,11 @@ namespace {
 template <int VEC, int D, bool BF, int LOSS>
 hipError_t launch_async_t(const TrainArgs &a, hipStream_t st) {
     const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D, BF ? 2 : 4);
-    hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    if (a.nw < 1 || a.nw > kMaxWavesAsync) return hipErrorInvalidValue;  // the kernel's launch bound
+    if (a.keep_rows)
+        hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS, true>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    else
+        hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS, false>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
     return hipGetLastError();
 }
 template <int VEC, bool BF, int LOSS>

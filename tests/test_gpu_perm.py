@@ -370,3 +370,44 @@ def test_perm_visiting_orders_are_uniform_permutations():
           flush=True)
     assert chi_pos < 1.15
     assert chi_gap < 2.0
+
+
+@pytest.mark.parametrize("sched", ["perm", "uniform"])
+def test_async_dense_rows_replay(sched):
+    """Rows rated by every item: their waves get a visit of one rating on the same row from
+    nearly every item, which takes the row kept from the wave's last update instead of
+    reloading it.  The trace still replays in the oracle."""
+    base, W0, H0, hp = make(800, 300, 8_000, k=32, seed=51)
+    row, col, val = base.row.numpy(), base.col.numpy(), base.val.numpy()
+    have = set(zip(row.tolist(), col.tolist()))
+    extra = [(r, j) for r in (0, 1, 5) for j in range(base.n) if (r, j) not in have]
+    g = np.random.default_rng(51)
+    row = np.concatenate([row, np.array([r for r, _ in extra], dtype=np.int32)])
+    col = np.concatenate([col, np.array([j for _, j in extra], dtype=np.int32)])
+    val = np.concatenate([val, (0.5 * g.standard_normal(len(extra))).astype(np.float32)])
+    perm = g.permutation(row.size)
+    row, col, val = row[perm], col[perm], val[perm]
+    P, seed, E = 8, 6, 3
+    print(f"[case] dense rows, {sched}, nnz={row.size} P={P}", flush=True)
+    model = nm.Nomad(base.m, base.n, torch.from_numpy(row), torch.from_numpy(col), torch.from_numpy(val), W0, H0,
+                     k=hp.k, lam=hp.lam, alpha=hp.alpha, beta=hp.beta, gamma=hp.gamma, workers=P, seed=seed,
+                     sched=sched, record_trace=True)
+    st = model.train(E)
+    tr = model.trace()
+    W, H = (x.cpu().double().numpy() for x in model.factors())
+    model.close()
+    if sched == "perm":
+        assert st.updates == E * row.size
+    t2 = tr[np.argsort(tr[:, 0], kind="stable")]
+    Wr, Hr, _ = oracle.replay(base.m, base.n, row, col, val, W0.numpy(), H0.numpy(), hp, P, seed, t2[:, 0],
+                              t2[:, 1], t2[:, 2], t2[:, 3])
+    T = max_updates(row, col, 2 * E)
+    check(W, Wr, norm_tol=2e-5, updates=T, what="W (dense rows)")
+    check(H, Hr, norm_tol=2e-5, updates=T, what="H (dense rows)")
+
+
+def test_async_waves_limit():
+    prob, W0, H0, hp = make(200, 50, 2_000, k=16, seed=2)
+    with pytest.raises(nm.NomadError):
+        nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
+                 beta=hp.beta, gamma=hp.gamma, workers=4, seed=1, sched="perm", waves_per_worker=9)
