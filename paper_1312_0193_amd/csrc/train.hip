@@ -416,11 +416,14 @@ __device__ __forceinline__ void row_gstore(char *p, const float (&v)[VEC]) {
 // (the hardware conversion, two elements per instruction) or stochastic: the low 16 bits
 // plus random bits, truncated; the bits of element l come from the half (l mod 2) of a
 // hash of (key of the rating, l / 2), the key hashing (seed, row, item, epoch).
-template <int VEC, bool BF>
+// RND: the rounding rule when known at compile time (0 nearest-even, 1 stochastic), or -1
+// to read it from the arguments (a branch per update: it splits an unrolled loop into one
+// scheduling region per update).
+template <int VEC, bool BF, int RND = -1>
 __device__ __forceinline__ void round_stored(const TrainArgs &a, int loff, float (&v)[VEC], int row, int item,
                                          int t) {
     if constexpr (BF) {
-        if (a.rounding == 0) {
+        if (RND == 0 || (RND < 0 && a.rounding == 0)) {
             if constexpr (VEC == 1) {
                 v[0] = (float)(__bf16)v[0];
             } else {
@@ -447,7 +450,7 @@ __device__ __forceinline__ void round_stored(const TrainArgs &a, int loff, float
     }
 }
 
-template <int VEC, int D, bool BF, int LOSS>
+template <int VEC, int D, bool BF, int LOSS, int RND>
 struct ComputeWave {
     static_assert(2 * (D - 2) <= 63 && D >= 4, "vmcnt range");
     static constexpr int ES = BF ? 2 : 4;  // bytes per stored element of W
@@ -485,7 +488,7 @@ struct ComputeWave {
                row_mask);
     }
     __device__ __forceinline__ void round_row(float (&v)[VEC], int row, int item, int t) const {
-        round_stored<VEC, BF>(a, loff, v, row, item, t);
+        round_stored<VEC, BF, RND>(a, loff, v, row, item, t);
     }
     __device__ __forceinline__ void placeholder_store() {
         if (lane == 0) a.dummy[(int64_t)q * kMaxWaves + w] = 0.0f;
@@ -1072,7 +1075,7 @@ __device__ __forceinline__ void row_gload(const char *p, float (&v)[VEC]) {
 // read 64 at a time into lane registers (one vector load; lane l holds the l-th); the row
 // of the next rating is loaded while the current one is updated (rows of one visit are
 // distinct, so the load never overtakes a store of the same row).
-template <int VEC, bool BF, int LOSS, bool KEEP>
+template <int VEC, bool BF, int LOSS, bool KEEP, int RND>
 struct AsyncComputeWave {
     static constexpr int ES = BF ? 2 : 4;
     const TrainArgs &a;
@@ -1204,7 +1207,7 @@ struct AsyncComputeWave {
             nw[i] = fmaf(-sl, wv[i], fmaf(se, h[i], wv[i]));
             h[i] = fmaf(se, wv[i], fmaf(-sl, h[i], h[i]));
         }
-        round_stored<VEC, BF>(a, loff, nw, row, item, t);
+        round_stored<VEC, BF, RND>(a, loff, nw, row, item, t);
         gstore(rowp, nw);
         if constexpr (TO_KEEP) {
             lstore<VEC>(keep() + loff, nw);
@@ -1734,7 +1737,7 @@ struct AsyncMemoryWave {
     }
 };
 
-template <int VEC, int D, bool BF, int LOSS, bool KEEP>
+template <int VEC, int D, bool BF, int LOSS, bool KEEP, int RND>
 __global__ __launch_bounds__(64 * (kMaxWavesAsync + 1)) void k_worker_async(TrainArgs a) {
     extern __shared__ float4 lds4[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1746,7 +1749,7 @@ __global__ __launch_bounds__(64 * (kMaxWavesAsync + 1)) void k_worker_async(Trai
     __syncthreads();
     if (q >= a.p || a.epochs <= 0) return;
     if (wave < a.nw) {
-        AsyncComputeWave<VEC, BF, LOSS, KEEP> cw(a, L, q, wave, lane, a.rbase[(int64_t)q * a.nw + wave]);
+        AsyncComputeWave<VEC, BF, LOSS, KEEP, RND> cw(a, L, q, wave, lane, a.rbase[(int64_t)q * a.nw + wave]);
         cw.run();
     } else if (wave == a.nw) {
         AsyncMemoryWave mw(a, L, q, lane);
@@ -1806,8 +1809,9 @@ __global__ void k_seed_write(TrainArgs a, int64_t n, const uint32_t *key_s, cons
     }
 }
 
-// One worker: workgroup q of the problem described by `a`.
-template <int VEC, int D, bool BF, int LOSS>
+// One worker: workgroup q of the problem described by `a` (RND: the bfloat16 rounding rule,
+// fixed at compile time so that the update loop has no branch on it).
+template <int VEC, int D, bool BF, int LOSS, int RND>
 __device__ __forceinline__ void worker_body(const TrainArgs &a, int q) {
     extern __shared__ float4 lds4[];
     // The wave index is the same in every lane: say so, so that everything derived from it
@@ -1821,7 +1825,7 @@ __device__ __forceinline__ void worker_body(const TrainArgs &a, int q) {
     if (q >= a.p || a.epochs <= 0) return;
     if (wave < a.nw) {
         const int64_t i0 = a.rbase[(int64_t)q * a.nw + wave], i1 = a.rbase[(int64_t)q * a.nw + wave + 1];
-        ComputeWave<VEC, D, BF, LOSS> cw(a, L, q, wave, lane, i0, i1 - i0);
+        ComputeWave<VEC, D, BF, LOSS, RND> cw(a, L, q, wave, lane, i0, i1 - i0);
         cw.run();
     } else if (wave == a.nw) {
         MemoryWave mw(a, L, q, lane);
@@ -1829,9 +1833,9 @@ __device__ __forceinline__ void worker_body(const TrainArgs &a, int q) {
     }
 }
 
-template <int VEC, int D, bool BF, int LOSS>
+template <int VEC, int D, bool BF, int LOSS, int RND>
 __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
-    worker_body<VEC, D, BF, LOSS>(a, blockIdx.x);
+    worker_body<VEC, D, BF, LOSS, RND>(a, blockIdx.x);
 }
 
 // Several independent problems in one launch: workgroup g runs worker g - wg0 of problem
@@ -1839,36 +1843,41 @@ __global__ __launch_bounds__(1024) void k_worker(TrainArgs a) {
 // waves per SIMD (at most 96 registers a lane), so that two workers of eight compute waves
 // and a memory wave each (18 waves) share a CU: a batch gains more from workers than from
 // registers.
-template <int VEC, int D, bool BF>
+template <int VEC, int D, bool BF, int RND>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void k_worker_batch(const TrainArgs *__restrict__ descs,
                                                        const int32_t *__restrict__ wg_prob) {
     const TrainArgs a = descs[wg_prob[blockIdx.x]];
-    worker_body<VEC, D, BF, 0>(a, (int)blockIdx.x - a.wg0);  // batches use the square loss
+    worker_body<VEC, D, BF, 0, RND>(a, (int)blockIdx.x - a.wg0);  // batches use the square loss
 }
 
 // A batched launch when `descs` is given (a.p then = total workgroups; square loss only),
 // else one problem.
-template <int VEC, int D, bool BF, int LOSS>
-hipError_t launch_t(const TrainArgs &a, const TrainArgs *descs, const int32_t *wg_prob, hipStream_t st) {
+template <int VEC, int D, bool BF, int LOSS, int RND>
+hipError_t launch_r(const TrainArgs &a, const TrainArgs *descs, const int32_t *wg_prob, hipStream_t st) {
     const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D, BF ? 2 : 4);
     if constexpr (LOSS == 0) {
         if (descs) {
-            hipLaunchKernelGGL((k_worker_batch<VEC, D, BF>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, descs,
+            hipLaunchKernelGGL((k_worker_batch<VEC, D, BF, RND>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, descs,
                                wg_prob);
             return hipGetLastError();
         }
     } else {
         if (descs) return hipErrorInvalidValue;
     }
-    hipLaunchKernelGGL((k_worker<VEC, D, BF, LOSS>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    hipLaunchKernelGGL((k_worker<VEC, D, BF, LOSS, RND>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
     return hipGetLastError();
+}
+template <int VEC, int D, bool BF, int LOSS>
+hipError_t launch_t(const TrainArgs &a, const TrainArgs *descs, const int32_t *wg_prob, hipStream_t st) {
+    if (BF && a.rounding == 1) return launch_r<VEC, D, BF, LOSS, 1>(a, descs, wg_prob, st);
+    return launch_r<VEC, D, BF, LOSS, 0>(a, descs, wg_prob, st);
 }
 
 template <int VEC, bool BF, int LOSS>
 const void *pick_d(int window) {
-    if (window <= 8) return (const void *)k_worker<VEC, 8, BF, LOSS>;
-    if (window <= 16) return (const void *)k_worker<VEC, 16, BF, LOSS>;
-    return (const void *)k_worker<VEC, 32, BF, LOSS>;
+    if (window <= 8) return (const void *)k_worker<VEC, 8, BF, LOSS, 0>;
+    if (window <= 16) return (const void *)k_worker<VEC, 16, BF, LOSS, 0>;
+    return (const void *)k_worker<VEC, 32, BF, LOSS, 0>;
 }
 
 template <bool BF, int LOSS>
@@ -1880,9 +1889,9 @@ const void *pick_kernel(int kp, int window) {
 
 template <int VEC, bool BF>
 const void *pick_batch_d(int window) {
-    if (window <= 8) return (const void *)k_worker_batch<VEC, 8, BF>;
-    if (window <= 16) return (const void *)k_worker_batch<VEC, 16, BF>;
-    return (const void *)k_worker_batch<VEC, 32, BF>;
+    if (window <= 8) return (const void *)k_worker_batch<VEC, 8, BF, 0>;
+    if (window <= 16) return (const void *)k_worker_batch<VEC, 16, BF, 0>;
+    return (const void *)k_worker_batch<VEC, 32, BF, 0>;
 }
 
 template <bool BF>
@@ -1911,9 +1920,9 @@ hipError_t launch_b(const TrainArgs &a, const TrainArgs *d, const int32_t *g, hi
 namespace {
 template <bool BF, int LOSS>
 const void *pick_async(int kp) {
-    if (kp <= 64) return (const void *)k_worker_async<1, kAsyncWindow, BF, LOSS, false>;
-    if (kp <= 128) return (const void *)k_worker_async<2, kAsyncWindow, BF, LOSS, false>;
-    return (const void *)k_worker_async<4, kAsyncWindow, BF, LOSS, false>;
+    if (kp <= 64) return (const void *)k_worker_async<1, kAsyncWindow, BF, LOSS, false, 0>;
+    if (kp <= 128) return (const void *)k_worker_async<2, kAsyncWindow, BF, LOSS, false, 0>;
+    return (const void *)k_worker_async<4, kAsyncWindow, BF, LOSS, false, 0>;
 }
 }  // namespace
 
@@ -1952,10 +1961,15 @@ template <int VEC, int D, bool BF, int LOSS>
 hipError_t launch_async_t(const TrainArgs &a, hipStream_t st) {
     const size_t lds = lds_bytes(a.kp, a.nw, a.slots, D, BF ? 2 : 4);
     if (a.nw < 1 || a.nw > kMaxWavesAsync) return hipErrorInvalidValue;  // the kernel's launch bound
-    if (a.keep_rows)
-        hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS, true>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
-    else
-        hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS, false>), dim3(a.p), dim3(64 * (a.nw + 1)), lds, st, a);
+    // variants: with the kept-row path or not; bfloat16 storage per rounding rule
+    const dim3 g(a.p), b(64 * (a.nw + 1));
+    if (BF && a.rounding == 1) {
+        if (a.keep_rows) hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS, true, 1>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS, false, 1>), g, b, lds, st, a);
+    } else {
+        if (a.keep_rows) hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS, true, 0>), g, b, lds, st, a);
+        else hipLaunchKernelGGL((k_worker_async<VEC, D, BF, LOSS, false, 0>), g, b, lds, st, a);
+    }
     return hipGetLastError();
 }
 template <int VEC, bool BF, int LOSS>
