@@ -130,6 +130,24 @@ def host_cpu() -> dict:
     return info
 
 
+def block_sample(prob, row_fraction, col_fraction, chunk=1 << 28):
+    """The ratings of rows [0, row_fraction*m) x columns [0, col_fraction*n), as host arrays,
+    in their original order: (m_s, n_s, row, col, val).  Selected where the problem lives
+    (the device), in chunks (torch indexes at most 2^31 elements at once), so the full arrays
+    never cross PCIe."""
+    import numpy as np
+
+    m_s = max(1, int(prob.m * row_fraction))
+    n_s = max(1, int(prob.n * col_fraction))
+    parts = []
+    for c0 in range(0, prob.row.numel(), chunk):
+        rr, cc, vv = (x[c0:c0 + chunk] for x in (prob.row, prob.col, prob.val))
+        sel = (rr < m_s) & (cc < n_s)
+        parts.append(tuple(x[sel].cpu().numpy() for x in (rr, cc, vv)))
+    r, c, v = (np.concatenate([p[i] for p in parts]) if parts else np.zeros(0) for i in range(3))
+    return m_s, n_s, r, c, v
+
+
 def cpu_baseline(prob, W0, H0, hp, P, seed, sched, row_fraction=0.1, col_fraction=1.0, max_threads=16):
     """The FP64 oracle on a bounded sample: the ratings in the leading block of rows
     [0, row_fraction*m) x columns [0, col_fraction*n).  Rows and columns carry Zipf weights in
@@ -145,17 +163,7 @@ def cpu_baseline(prob, W0, H0, hp, P, seed, sched, row_fraction=0.1, col_fractio
 
     import oracle
 
-    m_s = max(1, int(prob.m * row_fraction))
-    n_s = max(1, int(prob.n * col_fraction))
-    # selected on the device, in chunks (torch indexes at most 2^31 elements at once): the
-    # full arrays never cross PCIe
-    parts = []
-    for c0 in range(0, prob.row.numel(), 1 << 28):
-        rr, cc, vv = (x[c0:c0 + (1 << 28)] for x in (prob.row, prob.col, prob.val))
-        sel = (rr < m_s) & (cc < n_s)
-        parts.append(tuple(x[sel].cpu() for x in (rr, cc, vv)))
-    r, c, v = (np.concatenate([p[i].numpy() for p in parts]) for i in range(3))
-    del parts
+    m_s, n_s, r, c, v = block_sample(prob, row_fraction, col_fraction)
     W = W0[:m_s].float().cpu().numpy()
     H = H0[:n_s].float().cpu().numpy()
     f = lambda x: float(np.float32(x))  # noqa: E731

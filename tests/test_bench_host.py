@@ -1,5 +1,5 @@
-"""Host logic of bench.py (no GPU): algorithmic bytes, the counter summaries it reads,
-and the one-GPU guard."""
+"""Host logic of bench.py (no GPU): algorithmic bytes, visit counts, the CPU baseline's
+sample, the counter summaries it reads, and the one-GPU guard."""
 import os
 import subprocess
 import sys
@@ -55,3 +55,30 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_visits_per_epoch_in_chunks_matches_one_pass():
+    import torch
+
+    g = torch.Generator().manual_seed(3)
+    row = torch.randint(0, 500, (20_000,), generator=g, dtype=torch.int32)
+    col = torch.randint(0, 90, (20_000,), generator=g, dtype=torch.int32)
+    rs = [0, 70, 200, 330, 500]
+    q = torch.searchsorted(torch.tensor(rs), row.long(), right=True) - 1
+    expect = int(torch.unique(q * 90 + col.long()).numel())
+    assert bench.visits_per_epoch(row, col, 90, rs) == expect
+    assert bench.visits_per_epoch(row, col, 90, rs, chunk=777) == expect
+
+
+def test_block_sample_keeps_the_leading_block_in_order():
+    import numpy as np
+
+    import synth
+
+    p = synth.small_case(300, 120, 6_000, seed=9, degrees="zipf")
+    m_s, n_s, r, c, v = bench.block_sample(p, 0.5, 0.25, chunk=1_000)
+    assert (m_s, n_s) == (150, 30)
+    row, col, val = p.row.numpy(), p.col.numpy(), p.val.numpy()
+    sel = (row < 150) & (col < 30)
+    assert np.array_equal(r, row[sel]) and np.array_equal(c, col[sel]) and np.array_equal(v, val[sel])
+    assert r.size > 0
