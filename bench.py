@@ -368,6 +368,7 @@ def main():
     achieved = B * (updates / args.steps) / avg_kernel
     kernel = KERNELS[args.sched]
     traffic = measured_traffic(kernel, args.sched, args.workload, dtype)
+    shape = model.config()  # the launch shape in use (the library's choices filled in)
     out = {
         "metric": METRIC,
         "value": value,
@@ -384,8 +385,8 @@ def main():
         "config": {"workload": f"{WORKLOADS[args.workload]}, {args.sched} schedule"
                                f"{' with load balancing' if args.balance else ''}, "
                                + ("FP32" if dtype == "fp32" else "W in BF16 (stochastic rounding), FP32 arithmetic"),
-                   "global_batch": nnz, "workers": P, "waves_per_worker": model.cfg.waves_per_worker,
-                   "item_slots": model.cfg.item_slots, "test_rmse": rmse, "matched_rmse": matched,
+                   "global_batch": nnz, "workers": P, "waves_per_worker": shape.waves_per_worker,
+                   "item_slots": shape.item_slots, "test_rmse": rmse, "matched_rmse": matched,
                    "epochs_trained": epochs_trained, "visits_per_epoch": V,
                    "kernel_source": kernel_source_hash()},
         "roofline": {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",

@@ -112,7 +112,9 @@ typedef struct {
     int32_t workers;    /* p, number of workers (workgroups, all resident at once);
                            0 = one per compute unit */
     int32_t waves_per_worker; /* compute wavefronts of a worker, 1..15 (1..8 under the asynchronous
-                                 schedules); 0 = 8 (ring), 4 (asynchronous) */
+                                 schedules); 0 = 8 (ring), 4 (asynchronous; 6 when some row holds
+                                 more than half of a four-wave share of the ratings, i.e. its
+                                 degree exceeds nnz / (8 x workers)) */
     int32_t item_slots;  /* items a worker holds in LDS at once: a power of two, 1..64;
                             0 = as many as LDS allows, up to 64 */
     int32_t window;      /* rows a compute wave keeps in flight: 8, 16 or 32 (other values in
@@ -227,6 +229,11 @@ nomad_status nomad_get_factors(nomad_ctx *ctx, float *d_W, float *d_H);
 /* Row partition: h_row_start[0..p] (host, p+1 int64), worker q owns rows
  * [h_row_start[q], h_row_start[q+1]).  *p_out receives p. */
 nomad_status nomad_get_partition(nomad_ctx *ctx, int32_t *p_out, int64_t *h_row_start, int64_t cap);
+
+/* The configuration the context runs with: the one given to nomad_init with the library's
+ * choices filled in (workers, waves_per_worker, item_slots, window).  *h_cfg: host.  For a
+ * batch: its shared configuration (workers = the total). */
+nomad_status nomad_get_config(nomad_ctx *ctx, nomad_config *h_cfg);
 
 /* Visit trace of the last nomad_train_epochs call with record_trace = 1.  Each record is
  * four int32: (worker q, item j, step index t, visit sequence number of item j since

@@ -244,6 +244,12 @@ class Nomad:
         _check(load().nomad_get_partition(self._c(), C.byref(p), rs.ctypes.data_as(C.c_void_p), rs.size), self.ctx)
         return rs
 
+    def config(self) -> NomadConfig:
+        """nomad_get_config: the configuration in use (the library's choices filled in)."""
+        cfg = NomadConfig()
+        _check(load().nomad_get_config(self._c(), C.byref(cfg)), self.ctx)
+        return cfg
+
     @property
     def workers(self) -> int:
         p = C.c_int32()

@@ -318,7 +318,21 @@ static nomad_status init_impl(nomad_ctx **out, const nomad_config *cfg, int64_t 
     if (forced) {
         sh = *forced;
     } else {
-        const nomad_status ss = choose_shape(cfg, c->kp, c->wbytes, &sh, c);
+        nomad_config shaped = *cfg;
+        const bool async = cfg->sched == NOMAD_SCHED_PERM || cfg->sched == NOMAD_SCHED_UNIFORM;
+        if (async && cfg->waves_per_worker <= 0 && nnz > 0) {
+            // a row holding more than half of a four-wave share of the ratings: six waves
+            int64_t md = 0;
+            int dev = 0, cus = 0;
+            hipError_t e0 = nomad::max_row_degree(d_row, nnz, m, c->stream, &md);
+            if (e0 == hipSuccess) e0 = hipGetDevice(&dev);
+            if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            if (e0 != hipSuccess) return bail(hip_fail(c, e0, "nomad_init: row degrees"));
+            const double pw = cfg->workers > 0 ? cfg->workers : cus;
+            if (2.0 * (double)md * pw * nomad::kDefaultWavesAsync > (double)nnz)
+                shaped.waves_per_worker = nomad::kDenseWavesAsync;
+        }
+        const nomad_status ss = choose_shape(&shaped, c->kp, c->wbytes, &sh, c);
         if (ss != NOMAD_OK) return bail(ss);
     }
     const int32_t nw = sh.nw, slots = sh.slots, window = sh.window, maxw = sh.maxw, cus = sh.cus, max_lds = sh.max_lds;
@@ -832,6 +846,13 @@ nomad_status nomad_get_partition(nomad_ctx *c, int32_t *p_out, int64_t *h_row_st
     return NOMAD_OK;
 }
 
+nomad_status nomad_get_config(nomad_ctx *c, nomad_config *h_cfg) {
+    if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_config: NULL context");
+    if (!h_cfg) return fail(c, NOMAD_EINVAL, "nomad_get_config: h_cfg is NULL");
+    *h_cfg = c->cfg;
+    return NOMAD_OK;
+}
+
 nomad_status nomad_get_trace(nomad_ctx *c, int64_t *len, int32_t *h_buf, int64_t cap) {
     if (!c) return fail(nullptr, NOMAD_ESTATE, "nomad_get_trace: NULL context");
     if (!c->members.empty())
@@ -929,6 +950,10 @@ nomad_status nomad_init_batched(nomad_ctx **out, int32_t nprob, const nomad_prob
         return st;
     };
     c->cfg = *common;
+    c->cfg.workers = T;
+    c->cfg.waves_per_worker = sh.nw;
+    c->cfg.item_slots = sh.slots;
+    c->cfg.window = sh.window;
     c->stream = (hipStream_t)hip_stream;
     c->shape = sh;
     c->kp = kp;

@@ -520,6 +520,40 @@ done:
     return rc;
 }
 
+// Ratings per row (rows outside [0, m) are skipped here; the layout reports them).
+__global__ void k_row_count(const int32_t *row, int64_t nnz, int64_t m, uint32_t *cnt) {
+    GRID_LOOP(e, nnz) {
+        const int32_t i = row[e];
+        if (i >= 0 && i < m) atomicAdd(&cnt[i], 1u);
+    }
+}
+
+hipError_t max_row_degree(const int32_t *d_row, int64_t nnz, int64_t m, hipStream_t st, int64_t *out) {
+    *out = 0;
+    if (m <= 0 || nnz <= 0) return hipSuccess;
+    uint32_t *cnt = nullptr;
+    void *tmp = nullptr;
+    size_t need = 0;
+    uint32_t h_max = 0;
+    hipError_t e = hipMalloc(&cnt, sizeof(uint32_t) * (size_t)m);
+    if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size_t)m, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_row_count, dim3(grid_for(nnz)), dim3(kThreads), 0, st, d_row, nnz, m, cnt);
+        e = hipGetLastError();
+    }
+    uint32_t *none = nullptr;
+    if (e == hipSuccess) e = hipcub::DeviceReduce::Max(nullptr, need, cnt, none, m, st);
+    const size_t off = (need + 255) & ~(size_t)255;
+    if (e == hipSuccess) e = hipMalloc(&tmp, off + sizeof(uint32_t));
+    if (e == hipSuccess) e = hipcub::DeviceReduce::Max(tmp, need, cnt, (uint32_t *)((char *)tmp + off), m, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h_max, (char *)tmp + off, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(tmp);
+    (void)hipFree(cnt);
+    if (e == hipSuccess) *out = (int64_t)h_max;
+    return e;
+}
+
 hipError_t build_plan(Plan *pl, int64_t m, int64_t n, int64_t nnz, const int32_t *d_row, const int32_t *d_col,
                       const float *d_val, int32_t p, int32_t nw, int32_t window, uint64_t seed, hipStream_t st,
                       int *err_code, char *msg, size_t msg_len) {

@@ -35,6 +35,11 @@ constexpr int kDefaultWaves = 8;
 // Asynchronous schedules: fewer compute waves per worker leave the SIMDs to the waves that
 // carry the long runs of heavy items (on a Zipf workload 4 waves beat 8 by a fifth).
 constexpr int kDefaultWavesAsync = 4;
+// The default under the asynchronous schedules when a row holds more than half of a
+// four-wave share of the ratings: such rows make some workers host a visit from nearly every
+// item, and more waves spread those workers' other rows (measured on the Yahoo-shaped
+// workload: 0.65 s per epoch with four waves, 0.52 s with six, 0.54 s with eight).
+constexpr int kDenseWavesAsync = 6;
 constexpr int kMaxItemSlots = 64;   // items a worker holds in LDS at once
 constexpr int kMaxWorkers = 4096;
 constexpr int kMaxEpochsPerLaunch = 64;  // a call runs longer epoch counts as several launches
@@ -209,6 +214,8 @@ struct TrainArgs {
 
 // Host-side entry points of the translation units (all stream-ordered).
 
+// layout.hip: the ratings of the densest row (stream-ordered, then synchronous).
+hipError_t max_row_degree(const int32_t *d_row, int64_t nnz, int64_t m, hipStream_t stream, int64_t *out);
 // layout.hip: build the layout; err_code receives 0 or a nomad_status value.
 hipError_t build_plan(Plan *plan, int64_t m, int64_t n, int64_t nnz, const int32_t *d_row,
                       const int32_t *d_col, const float *d_val, int32_t p, int32_t nw, int32_t window,

@@ -411,3 +411,29 @@ def test_async_waves_limit():
     with pytest.raises(nm.NomadError):
         nm.Nomad(prob.m, prob.n, prob.row, prob.col, prob.val, W0, H0, k=hp.k, lam=hp.lam, alpha=hp.alpha,
                  beta=hp.beta, gamma=hp.gamma, workers=4, seed=1, sched="perm", waves_per_worker=9)
+
+
+def test_async_default_waves_follow_the_densest_row():
+    """The default compute waves under the asynchronous schedules: six when a row holds more
+    than half of a four-wave share of the ratings (degree > nnz / (8 p)), else four; an
+    explicit count is kept.  nomad_get_config reports the shape in use."""
+    sparse, W0, H0, hp = make(2_000, 400, 20_000, k=16, seed=61)  # max degree ~ 30 < 20000 / 64
+    kw = dict(k=hp.k, lam=hp.lam, alpha=hp.alpha, beta=hp.beta, gamma=hp.gamma, workers=8, seed=1, sched="perm")
+    m = nm.Nomad(sparse.m, sparse.n, sparse.row, sparse.col, sparse.val, W0, H0, **kw)
+    assert m.config().waves_per_worker == 4 and m.config().workers == 8
+    m.close()
+    row, col = sparse.row.numpy(), sparse.col.numpy()
+    have = set(zip(row.tolist(), col.tolist()))
+    extra = [j for j in range(sparse.n) if (7, j) not in have]  # row 7 rated by every item
+    row2 = np.concatenate([row, np.full(len(extra), 7, dtype=np.int32)])
+    col2 = np.concatenate([col, np.array(extra, dtype=np.int32)])
+    val2 = np.concatenate([sparse.val.numpy(), np.ones(len(extra), dtype=np.float32)])
+    assert 400 * 8 * 8 > row2.size  # degree 400 > nnz / (8 p)
+    m = nm.Nomad(sparse.m, sparse.n, torch.from_numpy(row2), torch.from_numpy(col2), torch.from_numpy(val2), W0, H0,
+                 **kw)
+    assert m.config().waves_per_worker == 6
+    m.close()
+    m = nm.Nomad(sparse.m, sparse.n, torch.from_numpy(row2), torch.from_numpy(col2), torch.from_numpy(val2), W0, H0,
+                 waves_per_worker=3, **kw)
+    assert m.config().waves_per_worker == 3
+    m.close()
