@@ -43,7 +43,7 @@ typedef enum {
     NOMAD_ENOMEM = 2,   /* device or host allocation failed */
     NOMAD_EDEVICE = 3,  /* a HIP call failed, or the workers cannot all be resident */
     NOMAD_ESTATE = 4,   /* call not valid in the context's state (e.g. NULL context) */
-    NOMAD_ENOTIMPL = 5  /* option combination not provided by this build */
+    NOMAD_ENOTIMPL = 5  /* an option combination the library does not provide */
 } nomad_status;
 
 /* Order in which items travel between workers.

@@ -805,7 +805,7 @@ nomad_status nomad_eval_rmse_noalloc(nomad_ctx *c, int64_t nnz, const int32_t *d
             return fail(c, NOMAD_EDEVICE, "nomad_eval_rmse_noalloc: no scratch address on device %d (%s)", c->device,
                         hipGetErrorString(g_scratch_err[c->device]));
     } else {
-        return fail(c, NOMAD_EDEVICE, "nomad_eval_rmse_noalloc: device %d is beyond the %d this build tracks",
+        return fail(c, NOMAD_EDEVICE, "nomad_eval_rmse_noalloc: device %d is beyond the %d the library tracks",
                     c->device, kMaxDevices);
     }
     HIPTRY(c, nomad::eval_sums_noalloc(c->W, c->wbytes, c->H, c->k, c->kp, c->m, c->n, nnz, d_row, d_col, d_val,
